@@ -1,0 +1,424 @@
+"""Seeded synthetic workloads shaped after the paper's five systems (Table 5) and
+its timing workload (Table 2): cells, grids, plane-wave states, eigenvalues,
+occupations, PAW projections, synthetic PAW tables, q-points and the imaginary
+frequency grid.
+
+This module holds inputs only. It draws random numbers and lays out the
+problem; it evaluates none of the response-function arithmetic (no pair
+densities, no chi0, no weights, no log-determinants). Both the CPU oracle and
+the GPU library receive exactly the arrays produced here.
+
+Conventions
+-----------
+* Hartree atomic units (bohr, Ha).
+* Lattice rows ``A[i]`` are the cell vectors a_i; reciprocal rows satisfy
+  a_i . b_j = 2 pi delta_ij.
+* Miller triples m give G = m1 b1 + m2 b2 + m3 b3; on an N-point axis an index
+  m maps to grid position m mod N.
+* Plane-wave coefficients C_n(Q) multiply e^{i (k+G_Q).r} with no 1/sqrt(Omega);
+  rows of C are orthonormal (sum_Q C_n(Q)^* C_m(Q) = delta_nm).
+* PAW projections are stored per band as one row over all atoms,
+  ``P[n, off[a] + i]`` = <p~_i^a | psi~_n>.
+* Q^a_ij(K) (the augmentation form factor of the PAW pair density) needs
+  partial waves that are not available, so a separable Gaussian model stands
+  in: Q^a_ij(K) = s^a_ij exp(-|K|^2 sigma^2 / 2) e^{-i K.R_a}, s^a real
+  symmetric. The nabla analogue D^a (used only in the q -> 0 limit) is real
+  antisymmetric per Cartesian direction.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+# ----------------------------------------------------------------------------
+# geometry helpers (input layout only)
+# ----------------------------------------------------------------------------
+def reciprocal_rows(A: np.ndarray) -> np.ndarray:
+    """Rows b_i with a_i . b_j = 2 pi delta_ij."""
+    return TWO_PI * np.linalg.inv(np.asarray(A, dtype=np.float64)).T
+
+
+def cart(miller: np.ndarray, B: np.ndarray, shift=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Cartesian shift + m1 b1 + m2 b2 + m3 b3, summed in a fixed order."""
+    m = np.asarray(miller, dtype=np.float64)
+    out = np.empty(m.shape[:-1] + (3,))
+    for c in range(3):
+        out[..., c] = shift[c] + m[..., 0] * B[0, c] + m[..., 1] * B[1, c] + m[..., 2] * B[2, c]
+    return out
+
+
+def _box(mmax: Sequence[int]) -> np.ndarray:
+    r = [np.arange(-int(M), int(M) + 1) for M in mmax]
+    g = np.stack(np.meshgrid(*r, indexing="ij"), axis=-1).reshape(-1, 3)
+    return g.astype(np.int32)
+
+
+def _sphere_box(A, radius: float, shift) -> np.ndarray:
+    """Every Miller triple whose |shift + G| could be <= radius."""
+    # |m_i| <= (radius + |shift|) * |a_i| / (2 pi)
+    a_len = np.linalg.norm(np.asarray(A, dtype=np.float64), axis=1)
+    s = float(np.linalg.norm(shift))
+    mmax = np.floor((radius + s) * a_len / TWO_PI).astype(int) + 1
+    return _box(mmax)
+
+
+def sphere_sq_lengths(A, shift, radius):
+    B = reciprocal_rows(A)
+    m = _sphere_box(A, radius, shift)
+    k = cart(m, B, shift)
+    k2 = k[:, 0] * k[:, 0] + k[:, 1] * k[:, 1] + k[:, 2] * k[:, 2]
+    return m, k2
+
+
+def ecut_for_count(A, q, target: int) -> float:
+    """Smallest chi cutoff whose sphere |q+G|^2/2 <= Ecut holds >= target vectors.
+
+    The value returned is the midpoint between that shell and the next one, so
+    the sphere it selects does not depend on rounding at the boundary.
+    """
+    radius = 1.0
+    while True:
+        m, k2 = sphere_sq_lengths(A, q, radius)
+        inside = np.sort(k2[k2 <= radius * radius])
+        if inside.size > target + 64:
+            break
+        radius *= 1.3
+    st = inside[target - 1]
+    above = inside[inside > st * (1 + 1e-12) + 1e-14]
+    snext = above[0]
+    return 0.25 * (st + snext)
+
+
+def wavefunction_sphere(A, kpt, ecut_wf: float) -> np.ndarray:
+    """Miller list of the plane-wave basis |k+Q|^2/2 <= ecut_wf, ordered by |k+Q| then lexicographically."""
+    radius = np.sqrt(2.0 * ecut_wf)
+    m, k2 = sphere_sq_lengths(A, kpt, radius)
+    sel = k2 <= 2.0 * ecut_wf
+    m, k2 = m[sel], k2[sel]
+    order = np.lexsort((m[:, 2], m[:, 1], m[:, 0], k2))
+    return np.ascontiguousarray(m[order], dtype=np.int32)
+
+
+# ----------------------------------------------------------------------------
+# containers
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class StateSet:
+    """One k (or k+q) state set."""
+    kpt: np.ndarray          # (3,) Cartesian, bohr^-1
+    weight: float            # w_k (1/N_k)
+    miller: np.ndarray       # int32 [NQ, 3]
+    C: np.ndarray            # complex128 [nb, NQ], orthonormal rows
+    eps: np.ndarray          # float64 [nb], ascending
+    f: np.ndarray            # float64 [nb], in [0, 2], non-increasing
+    P: np.ndarray            # complex128 [nb, sum Np]
+
+    @property
+    def nbands(self):
+        return self.C.shape[0]
+
+
+@dataclasses.dataclass
+class Paw:
+    nproj: List[int]         # Np per atom
+    s: List[np.ndarray]      # real symmetric (Np, Np) per atom
+    R: np.ndarray            # (Na, 3) Cartesian positions
+    D: List[np.ndarray]      # real (3, Np, Np), antisymmetric per direction
+    sigma: float = 0.5
+
+    @property
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.nproj)]).astype(np.int32)
+
+    @property
+    def qoffsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum([n * n for n in self.nproj])]).astype(np.int32)
+
+
+@dataclasses.dataclass
+class QPoint:
+    q: np.ndarray            # (3,) Cartesian
+    ecut: float              # chi cutoff (Ha); sphere |q+G|^2/2 <= ecut
+    weight: float = 1.0      # w_q
+    optical: bool = False    # q -> 0 limit along qhat
+    qhat: np.ndarray = dataclasses.field(default_factory=lambda: np.array([1.0, 0.0, 0.0]))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    A: np.ndarray            # (3, 3) lattice rows (bohr)
+    grid: tuple              # (N1, N2, N3)
+    kpoints: List[StateSet]  # state sets at k; k+q uses the same set (see below)
+    paw: Paw
+    qpoints: List[QPoint]
+    omega: np.ndarray        # [nw] imaginary frequencies (Ha)
+    omega_weight: np.ndarray # [nw] quadrature weights for d omega
+    seed: int
+    kq: Optional[List[StateSet]] = None   # distinct k+q sets; None -> same as kpoints
+
+    @property
+    def volume(self) -> float:
+        return float(abs(np.linalg.det(self.A)))
+
+    def kq_sets(self) -> List[StateSet]:
+        return self.kq if self.kq is not None else self.kpoints
+
+    def digest(self) -> str:
+        h = hashlib.sha256()
+        for s in self.kpoints + (self.kq or []):
+            for arr in (s.miller, s.C, s.eps, s.f, s.P):
+                h.update(np.ascontiguousarray(arr).tobytes())
+        h.update(np.ascontiguousarray(self.omega).tobytes())
+        return h.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------
+# draws
+# ----------------------------------------------------------------------------
+def orthonormal_coefficients(rng, A, kpt, miller, nb):
+    """Re, Im ~ N(0,1) x exp(-|k+Q|^2/8), then orthonormal rows by QR with diag(R) > 0."""
+    B = reciprocal_rows(A)
+    kq = cart(miller, B, kpt)
+    env = np.exp(-(kq[:, 0] ** 2 + kq[:, 1] ** 2 + kq[:, 2] ** 2) / 8.0)
+    NQ = miller.shape[0]
+    if nb > NQ:
+        raise ValueError(f"{nb} bands need at least as many plane waves (have {NQ})")
+    X = (rng.standard_normal((nb, NQ)) + 1j * rng.standard_normal((nb, NQ))) * env[None, :]
+    Qm, R = np.linalg.qr(X.T)            # X^T = Qm R, Qm: NQ x nb
+    d = np.diag(R)
+    ph = d / np.abs(d)
+    Qm = Qm * ph[None, :]
+    return np.ascontiguousarray(Qm.T)
+
+
+def gapped_levels(rng, n_occ, n_unocc, occ_range=(-0.8, -0.3), unocc_range=(0.0, 3.0)):
+    eo = np.sort(rng.uniform(occ_range[0], occ_range[1], n_occ))
+    eu = np.sort(rng.uniform(unocc_range[0], unocc_range[1], n_unocc))
+    eps = np.concatenate([eo, eu])
+    f = np.concatenate([np.full(n_occ, 2.0), np.zeros(n_unocc)])
+    return eps, f
+
+
+def fermi_levels(rng, n_below, n_above, T=0.01, mu=0.0):
+    eb = np.sort(rng.uniform(-0.8, 0.0, n_below))
+    ea = np.sort(rng.uniform(0.0, 3.0, n_above))
+    eps = np.concatenate([eb, ea])
+    x = np.clip((eps - mu) / T, -700.0, 700.0)
+    f = 2.0 / (1.0 + np.exp(x))
+    return eps, f
+
+
+def draw_projections(rng, nb, nproj_total):
+    """P with Re, Im ~ N(0, 0.1) each."""
+    return 0.1 * rng.standard_normal((nb, nproj_total)) + 0.1j * rng.standard_normal((nb, nproj_total))
+
+
+def draw_paw(rng, A, nproj: Sequence[int]) -> Paw:
+    s, D = [], []
+    for n in nproj:
+        Bm = rng.standard_normal((n, n))
+        s.append(0.5 * (Bm + Bm.T))
+    R = rng.uniform(0.0, 1.0, (len(nproj), 3)) @ np.asarray(A, dtype=np.float64)
+    for n in nproj:
+        Cm = rng.standard_normal((3, n, n))
+        D.append(0.1 * 0.5 * (Cm - np.transpose(Cm, (0, 2, 1))))
+    return Paw(nproj=list(nproj), s=s, R=R, D=D)
+
+
+def frequency_grid(nw: int, w0: float = 1.0):
+    """Gauss-Legendre nodes on [-1, 1] mapped to [0, inf) by omega = w0 x/(1-x), x = (t+1)/2.
+
+    Returns (omega, weight) with weight = d omega per node, so that
+    int_0^inf g(omega) d omega ~= sum_i weight_i g(omega_i).
+    """
+    t, w = np.polynomial.legendre.leggauss(nw)
+    x = 0.5 * (t + 1.0)
+    omega = w0 * x / (1.0 - x)
+    weight = 0.5 * w * w0 / (1.0 - x) ** 2
+    return omega, weight
+
+
+# ----------------------------------------------------------------------------
+# synthetic PAW tables evaluated on a caller-supplied G list
+# ----------------------------------------------------------------------------
+def paw_q_table(paw: Paw, A, q, gmiller) -> np.ndarray:
+    """Q[qoff[a] + i*Np + j, G] = s^a_ij exp(-|q+G|^2 sigma^2/2) exp(-i (q+G).R_a), complex128."""
+    B = reciprocal_rows(A)
+    K = cart(gmiller, B, q)
+    K2 = K[:, 0] ** 2 + K[:, 1] ** 2 + K[:, 2] ** 2
+    g = np.exp(-0.5 * K2 * paw.sigma ** 2)
+    rows = []
+    for a, n in enumerate(paw.nproj):
+        phase = np.exp(-1j * (K @ paw.R[a]))
+        rows.append((paw.s[a].reshape(n * n, 1) * (g * phase)[None, :]))
+    return np.ascontiguousarray(np.concatenate(rows, axis=0).astype(np.complex128))
+
+
+def paw_d_table(paw: Paw) -> np.ndarray:
+    """D[c, qoff[a] + i*Np + j] = D^a_c,ij (real), the PAW nabla correction."""
+    cols = [paw.D[a].reshape(3, n * n) for a, n in enumerate(paw.nproj)]
+    return np.ascontiguousarray(np.concatenate(cols, axis=1).astype(np.float64))
+
+
+# ----------------------------------------------------------------------------
+# configurations
+# ----------------------------------------------------------------------------
+def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
+              extra_kq=False, w0=1.0):
+    """Draw in the fixed order: C, eps_occ, eps_unocc, P, s^a, R_a, D^a (per k for the first four)."""
+    rng = np.random.default_rng(seed)
+    A = np.asarray(A, dtype=np.float64)
+    ecut_max = max(qp.ecut for qp in qpoints)
+    ecut_wf = 4.0 * ecut_max
+    nproj_total = int(sum(nproj))
+    sets = []
+    pend = []
+    for ik, k in enumerate(kpts):
+        miller = wavefunction_sphere(A, k, ecut_wf)
+        nb = levels(None, dry=True)
+        C = orthonormal_coefficients(rng, A, k, miller, nb)
+        eps, f = levels(rng)
+        pend.append((k, kweights[ik], miller, C, eps, f))
+    for (k, w, miller, C, eps, f) in pend:
+        P = draw_projections(rng, C.shape[0], nproj_total)
+        sets.append(StateSet(kpt=np.asarray(k, dtype=np.float64), weight=float(w), miller=miller,
+                             C=C, eps=eps, f=f, P=P))
+    paw = draw_paw(rng, A, nproj)
+    kq = None
+    if extra_kq:
+        kq = []
+        for s in sets:
+            C2 = orthonormal_coefficients(rng, A, s.kpt, s.miller, s.nbands)
+            eps2, f2 = levels(rng)
+            P2 = draw_projections(rng, s.nbands, nproj_total)
+            kq.append(StateSet(kpt=s.kpt.copy(), weight=s.weight, miller=s.miller, C=C2,
+                               eps=eps2, f=f2, P=P2))
+    omega, ow = frequency_grid(nw, w0)
+    wl = Workload(name=name, A=A, grid=tuple(int(x) for x in grid), kpoints=sets, paw=paw,
+                  qpoints=qpoints, omega=omega, omega_weight=ow, seed=seed, kq=kq)
+    check_alias_free(wl)
+    return wl
+
+
+def _gapped(n_occ, n_unocc):
+    def levels(rng, dry=False):
+        if dry:
+            return n_occ + n_unocc
+        return gapped_levels(rng, n_occ, n_unocc)
+    return levels
+
+
+def _fermi(n_below, n_above, T):
+    def levels(rng, dry=False):
+        if dry:
+            return n_below + n_above
+        return fermi_levels(rng, n_below, n_above, T)
+    return levels
+
+
+def max_abs_miller(m: np.ndarray) -> np.ndarray:
+    return np.abs(np.asarray(m)).max(axis=0)
+
+
+def check_alias_free(wl: Workload):
+    """Pair products of two plane-wave sets are exact on the grid for every chi G-vector."""
+    N = np.asarray(wl.grid)
+    for qp in wl.qpoints:
+        gm, _ = sphere_sq_lengths(wl.A, qp.q, np.sqrt(2.0 * qp.ecut))
+        _, k2 = sphere_sq_lengths(wl.A, qp.q, np.sqrt(2.0 * qp.ecut))
+        gm = gm[k2 <= 2.0 * qp.ecut]
+        mc = max_abs_miller(gm)
+        for s, t in zip(wl.kpoints, wl.kq_sets()):
+            tot = max_abs_miller(s.miller) + max_abs_miller(t.miller) + mc
+            if np.any(tot > N - 1):
+                raise ValueError(f"grid {tuple(N)} aliases: |m_k|+|m_kq|+|m_chi| = {tuple(tot)}")
+            if np.any(2 * max_abs_miller(s.miller) >= N):
+                raise ValueError("wavefunction sphere does not fit the grid")
+
+
+def config0(seed: int = 0, n_occ: int = 4, n_unocc: int = 60, nw: int = 8, extra_kq=False) -> Workload:
+    """Tiny plain FP64 case: cubic L=10 bohr, 16^3 grid, Gamma, q=(0.1,0,0) 2pi/L,
+    4 occupied + 60 unoccupied states, 2 atoms x 4 projectors, ~120 G, 8 frequencies."""
+    L = 10.0
+    A = np.eye(3) * L
+    q = np.array([0.1 * TWO_PI / L, 0.0, 0.0])
+    ecut = ecut_for_count(A, q, 120)
+    qps = [QPoint(q=q, ecut=ecut)]
+    return _assemble("cfg0-tiny", A, (16, 16, 16), seed, [np.zeros(3)], [1.0],
+                     _gapped(n_occ, n_unocc), [4, 4], qps, nw, extra_kq=extra_kq)
+
+
+def config1(seed: int = 1, n_occ: int = 16, n_unocc: int = 800, nw: int = 16,
+            target_ng: int = 1500, grid=(48, 48, 48), which_q=(0, 1, 2)) -> Workload:
+    """O2-in-box scale: 12x12x13 bohr, 48^3 grid, Gamma, 16 occupied + 800 unoccupied,
+    2 atoms x 13 projectors, ~1500 G, 16 frequencies, q = 0 (optical), 0.1, 0.2 x 2pi/12 along x."""
+    A = np.diag([12.0, 12.0, 13.0])
+    qs = []
+    for i in which_q:
+        if i == 0:
+            q = np.zeros(3)
+            qs.append(QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), optical=True,
+                             qhat=np.array([1.0, 0.0, 0.0]), weight=1.0 / 3))
+        else:
+            q = np.array([0.1 * i * TWO_PI / 12.0, 0.0, 0.0])
+            qs.append(QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), weight=1.0 / 3))
+    return _assemble("cfg1-o2box", A, grid, seed, [np.zeros(3)], [1.0],
+                     _gapped(n_occ, n_unocc), [13, 13], qs, nw)
+
+
+def config2(seed: int = 2, n_below: int = 120, n_above: int = 3000, nk: int = 8, nw: int = 16,
+            target_ng: int = 4000, T: float = 0.01) -> Workload:
+    """Metal-slab scale: 9x9x36 bohr, 40x40x160 grid, 2x2x2 Gamma-centred k (independent sets,
+    w_k = 1/8), 120 + 3000 Fermi-smeared states (T = 0.01 Ha), 20 atoms x 18 projectors,
+    ~4000 G, 16 frequencies, q = (0.1 2pi/9, 0, 0)."""
+    A = np.diag([9.0, 9.0, 36.0])
+    B = reciprocal_rows(A)
+    frac = [(i, j, k) for i in (0, 1) for j in (0, 1) for k in (0, 1)][:nk]
+    kpts = [0.5 * (i * B[0] + j * B[1] + k * B[2]) for (i, j, k) in frac]
+    q = np.array([0.1 * TWO_PI / 9.0, 0.0, 0.0])
+    qps = [QPoint(q=q, ecut=ecut_for_count(A, q, target_ng))]
+    return _assemble("cfg2-slab", A, (40, 40, 160), seed, kpts, [1.0 / len(kpts)] * len(kpts),
+                     _fermi(n_below, n_above, T), [18] * 20, qps, nw)
+
+
+def config3_qpoints(seed: int = 3, nq: int = 64):
+    A = np.diag([9.0, 9.0, 36.0])
+    B = reciprocal_rows(A)
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 1.0, nq)
+    targets = np.rint(200.0 * 15.0 ** u).astype(int)
+    mp = [(2 * i - 5) / 8.0 for i in range(1, 5)]
+    fr = [(a, b, c) for a in mp for b in mp for c in mp][:nq]
+    qps = []
+    for t, (a, b, c) in zip(targets, fr):
+        q = a * B[0] + b * B[1] + c * B[2]
+        qps.append(QPoint(q=q, ecut=ecut_for_count(A, q, int(t)), weight=1.0 / nq))
+    return A, qps
+
+
+def config3(seed: int = 3, n_occ: int = 60, n_unocc: int = 1500, nq: int = 64, nw: int = 16) -> Workload:
+    """Batching form: 9x9x36 bohr, 40x40x160 grid, Gamma, 60 + 1500 states, 64 q-points of a
+    4x4x4 Monkhorst-Pack mesh without Gamma, G-sphere sizes log-uneven in [200, 3000]."""
+    A, qps = config3_qpoints(seed, nq)
+    return _assemble("cfg3-batched", A, (40, 40, 160), seed, [np.zeros(3)], [1.0],
+                     _gapped(n_occ, n_unocc), [18] * 20, qps, nw)
+
+
+def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), target_ng=15,
+         q_frac=(0.1, 0.0, 0.0), nw=8, seed=11, optical=False, extra_kq=False, ecut_wf_scale=None):
+    """Small cases on tiny grids for direct-sum checks and ragged shapes."""
+    A = np.diag(np.asarray(L, dtype=np.float64))
+    B = reciprocal_rows(A)
+    q = q_frac[0] * B[0] + q_frac[1] * B[1] + q_frac[2] * B[2]
+    if optical:
+        q = np.zeros(3)
+    qp = QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), optical=optical)
+    return _assemble("tiny", A, grid, seed, [np.zeros(3)], [1.0], _gapped(n_occ, n_unocc),
+                     list(nproj), [qp], nw, extra_kq=extra_kq)
