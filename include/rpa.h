@@ -1,0 +1,192 @@
+/*
+ * rpa.h - C ABI of the MI355X (gfx950) library for the RPA correlation energy
+ * in the projector augmented wave method: the non-interacting response
+ * function chi0(q; G, G'; i w) and E_c(q).
+ *
+ * Method: J. Yan, L. Li, C. O'Grady, "Graphics Processing Unit Acceleration
+ * of the Random Phase Approximation in the Projector Augmented Wave Method",
+ * arXiv 1307.8052. Equation names below are that paper's labels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Hartree atomic units. Cell rows A[i] are the lattice vectors a_i (bohr);
+ *    reciprocal rows b_j satisfy a_i . b_j = 2 pi delta_ij; a Miller triple m
+ *    is G = m1 b1 + m2 b2 + m3 b3 and sits at grid position m mod N.
+ *  - complex128 arrays are interleaved (re, im) doubles, row-major.
+ *  - Pointers marked DEVICE are caller-owned device memory on the context's
+ *    device; pointers marked HOST are caller-owned host memory read during
+ *    the call only. The library never frees or keeps caller pointers.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Device work is
+ *    stream-ordered and asynchronous; host arrays are consumed before return.
+ *  - Every call validates on the host before any launch and returns an
+ *    rpa_status; nothing aborts or throws across the ABI. A failed kernel
+ *    launch or an earlier asynchronous fault is reported as RPA_ERR_HIP.
+ *    rpa_last_error() gives a per-thread detail string for the last failure.
+ *  - Calls on one context are not re-entrant: one host thread at a time.
+ */
+#ifndef RPA_MI355X_H
+#define RPA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpa_ctx rpa_ctx;
+
+typedef enum {
+    RPA_OK = 0,
+    RPA_ERR_INPUT = -1,       /* bad value: NULL pointer, non-monotone eps/f, q+G = 0 off the optical limit */
+    RPA_ERR_SHAPE = -2,       /* inconsistent sizes (bands, projector offsets, Miller ranges) */
+    RPA_ERR_ALIAS = -3,       /* grid too small for an alias-free pair product on the G-sphere */
+    RPA_ERR_NOMEM = -4,       /* device allocation failed or workspace cap below the minimum */
+    RPA_ERR_NOT_PD = -5,      /* 1 - v^1/2 chi0 v^1/2 not positive definite at some frequency */
+    RPA_ERR_HIP = -6,         /* HIP runtime error */
+    RPA_ERR_UNSUPPORTED = -7  /* grid length not a product of 2, 3, 5 or too large for LDS staging */
+} rpa_status;
+
+typedef enum {
+    RPA_FP64 = 0,        /* FP64 FFTs, FP64 MFMA rank-k update */
+    RPA_SPLIT_BF16 = 1,  /* FP32 FFTs; rank-k update on BF16 MFMA with hi/lo split, FP32 accumulate */
+    RPA_SPLIT_FP16 = 2   /* FP32 FFTs; rank-k update on FP16 MFMA with hi/lo split, FP32 accumulate */
+} rpa_precision;
+
+/* Unit cell and FFT grid. n[i] is the number of grid points along a_i; each
+ * must be >= 2 and a product of the primes 2, 3 and 5. */
+typedef struct {
+    double A[3][3];
+    int n[3];
+} rpa_cell;
+
+/* One state set at k (or at k+q) - Eq. get_wfs and Eq. n_G_2.
+ *  C        DEVICE complex128 [nbands][nQ]: plane-wave coefficients C_n(Q) of the
+ *           periodic part; psi~_n(r) = e^{ik.r} sum_Q C_n(Q) e^{i G_Q.r}. Rows are
+ *           expected orthonormal (sum_Q C_n^* C_m = delta_nm); no 1/sqrt(Omega).
+ *  miller   HOST int32 [nQ][3]: Miller index of each Q; every |m_i| < n[i]/2.
+ *  eps      HOST [nbands]: Kohn-Sham eigenvalues (Ha), ascending.
+ *  f        HOST [nbands]: occupations in [0, 2] (spin included), non-increasing.
+ *  proj_off HOST int32 [natoms+1]: projector offsets; atom a owns columns
+ *           proj_off[a] .. proj_off[a+1]-1 of P.
+ *  P        DEVICE complex128 [nbands][proj_off[natoms]]: P^a_ni = <p~^a_i|psi~_n>.
+ *  kpt      Cartesian k (bohr^-1); enters only the optical-limit momentum.
+ *  weight   Brillouin-zone weight w_k of this k-point (1/N_k).            */
+typedef struct {
+    int nbands;
+    int nQ;
+    const int32_t* miller;
+    const void* C;
+    const double* eps;
+    const double* f;
+    int natoms;
+    const int32_t* proj_off;
+    const void* P;
+    double kpt[3];
+    double weight;
+} rpa_states;
+
+/* One q-point - Eq. rpa_c, Eq. n_G_2, Eq. n_q0.
+ *  q        Cartesian q (bohr^-1).
+ *  optical  1: q -> 0 limit along qhat (q must be 0). Row G = 0 of every pair
+ *           density is replaced by Eq. n_q0 and v^1/2 at G = 0 is sqrt(4 pi).
+ *  NG, gmiller  HOST int32 [NG][3]: the G-sphere (any order; chi0 comes out in
+ *           this order). rpa_gsphere() produces the canonical one.
+ *  Qpaw     DEVICE complex128 [sum_a Np_a^2][NG]: Q^a_ij(q+G), row
+ *           qoff_a + i*Np_a + j with qoff_a = sum_{b<a} Np_b^2.
+ *  Dpaw     HOST double [3][sum_a Np_a^2]: PAW nabla correction D^a_ij
+ *           (Eq. Q_q0) per Cartesian direction; read only when optical = 1.
+ *  weight   w_q, used by rpa_ec_batched to form sum_q w_q E_c(q).          */
+typedef struct {
+    double q[3];
+    int optical;
+    double qhat[3];
+    int NG;
+    const int32_t* gmiller;
+    const void* Qpaw;
+    const double* Dpaw;
+    double weight;
+} rpa_qspec;
+
+/* Imaginary-frequency quadrature (HOST): nodes omega[nw] > 0 and weights of
+ * d omega, so that E_c(q) = sum_i weight_i F(omega_i) / 2 pi (Eq. rpa). */
+typedef struct {
+    int nw;
+    const double* omega;
+    const double* weight;
+} rpa_freq;
+
+/* Create a context on HIP device `device` for one cell and grid. The context
+ * owns device workspaces (grown on demand up to workspace_cap_bytes; 0 means
+ * no cap) and caches. Errors: RPA_ERR_INPUT (NULL out or cell),
+ * RPA_ERR_UNSUPPORTED (grid), RPA_ERR_HIP. */
+int rpa_create(rpa_ctx** out, const rpa_cell* cell, int device, size_t workspace_cap_bytes);
+
+/* Release every resource of the context (after synchronizing its device). */
+int rpa_destroy(rpa_ctx* ctx);
+
+/* The chi G-sphere {G : |q+G|^2/2 <= ecut} (Sec. 2.1), ordered by |q+G|^2,
+ * then (m1, m2, m3) lexicographically. Host only. Writes up to `capacity`
+ * triples to miller_out (HOST int32 [capacity][3], may be NULL) and the
+ * count to *ng_out; RPA_ERR_SHAPE if capacity is too small (count still set). */
+int rpa_gsphere(const rpa_cell* cell, const double q[3], double ecut, int32_t* miller_out,
+                int capacity, int* ng_out);
+
+/* Pair densities rho_nm(q+G) (Eq. n_G_2 with Eq. fft; Eq. n_q0 row when
+ * optical) for an explicit pair list: n from set k, m from set kq.
+ *  pair_n, pair_m HOST int32 [npairs].
+ *  rho_out DEVICE complex128 [npairs][NG].
+ * Computed in the precision's FFT type (FP64 or FP32) and widened. */
+int rpa_pair_density(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, const rpa_qspec* qs,
+                     int npairs, const int32_t* pair_n, const int32_t* pair_m, rpa_precision prec,
+                     void* rho_out, void* stream);
+
+/* chi0_GG'(q, i w) of Eq. chi0 summed over nk (k, k+q) state-set pairs, grouped
+ * as in Eq. zher_multi: pairs (n, m) with f_n - f_m > 1e-8 carry the real
+ * weight a_nm(w) = (w_k/Omega)(f_n - f_m) 2 (e_n - e_m)/(w^2 + (e_n - e_m)^2)
+ * (resonant and anti-resonant terms of each transition paired).
+ *  k, kq    HOST arrays of nk state sets (kq[i] may equal k[i]).
+ *  chi0_out DEVICE complex128 [nw][NG][NG], full Hermitian, gmiller order. */
+int rpa_chi0(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+             const rpa_freq* fr, rpa_precision prec, void* chi0_out, void* stream);
+
+/* E_c(q) from a given chi0 (Eq. rpa, Table 1 step 13):
+ * F(w) = ln det(1 - K) + Tr K with K = v^1/2 chi0 v^1/2, v^1/2_G = sqrt(4 pi)/|q+G|,
+ * ln det from an FP64 Cholesky factorisation; E_c = sum_i weight_i F(w_i)/2 pi.
+ *  chi0   DEVICE complex128 [nw][NG][NG] (lower triangle read).
+ *  ec_dev DEVICE double [1]; F_dev DEVICE double [nw] or NULL.
+ * A non-positive pivot is reported on the next synchronizing call of this
+ * context as RPA_ERR_NOT_PD via rpa_check(); the returned values are then NaN. */
+int rpa_ec_from_chi0(rpa_ctx* ctx, const rpa_qspec* qs, const rpa_freq* fr, const void* chi0,
+                     double* ec_dev, double* F_dev, void* stream);
+
+/* chi0 then E_c(q) in one call, without materialising the output chi0. */
+int rpa_ec(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+           const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, void* stream);
+
+/* Synchronize `stream` and report device-side failures of earlier calls on
+ * this context (RPA_ERR_NOT_PD with the frequency index in rpa_last_error). */
+int rpa_check(rpa_ctx* ctx, void* stream);
+
+/* Stage profiler. rpa_profile(ctx, 1) clears the totals and starts recording a
+ * pair of HIP events on the launch stream around every kernel group of the
+ * calls that follow (0 stops). rpa_profile_get() synchronizes on the recorded
+ * events and returns the summed elapsed milliseconds and the number of timed
+ * groups of one stage: "orbitals", "pair_xy", "pair_z_gather", "paw",
+ * "optical", "weights", "herk" (the rank-k update of chi0, one launch per pair
+ * chunk and frequency set) or "cholesky" (the whole E_c stage).
+ * RPA_ERR_INPUT for an unknown stage name. */
+int rpa_profile(rpa_ctx* ctx, int enable);
+int rpa_profile_get(rpa_ctx* ctx, const char* stage, double* ms, long long* launches);
+
+/* Static text for a status code. */
+const char* rpa_status_string(int status);
+
+/* Detail of the last failure on the calling thread (never NULL). */
+const char* rpa_last_error(const rpa_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPA_MI355X_H */

@@ -1,0 +1,287 @@
+"""MI355X (gfx950) library for the RPA correlation energy in the PAW method:
+chi0(q; G, G'; i w) from pair densities and E_c(q) (arXiv 1307.8052).
+
+This module only marshals arguments to the C ABI of ``include/rpa.h``; every
+step of the computation runs in the HIP library. Device arrays are torch
+tensors on a ROCm device; the work is ordered on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _capi
+from ._capi import PRECISION, RpaCell, RpaFreq, RpaQSpec, RpaStates
+
+__all__ = ["RpaError", "Context", "States", "QSpec", "Freq", "gsphere", "PRECISION", "library_path"]
+
+
+def library_path() -> str:
+    return _capi.LIB_PATH
+
+
+class RpaError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        msg = _capi.lib().rpa_status_string(status).decode()
+        super().__init__(f"[{status}] {msg}: {detail}")
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        detail = _capi.lib().rpa_last_error(ctx).decode(errors="replace")
+        raise RpaError(status, detail)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr_i32(a: np.ndarray):
+    return a.ctypes.data_as(_capi.P_i32)
+
+
+def _ptr_f64(a: np.ndarray):
+    return a.ctypes.data_as(_capi.P_f64)
+
+
+def _dev_c128(t, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.complex128))
+    return t.to(device=device, dtype=torch.complex128).contiguous()
+
+
+def _cell(A, grid) -> RpaCell:
+    c = RpaCell()
+    a = _f64(A).reshape(9)
+    for i in range(9):
+        c.A[i] = float(a[i])
+    for i in range(3):
+        c.n[i] = int(grid[i])
+    return c
+
+
+def gsphere(A, grid, q, ecut: float) -> np.ndarray:
+    """The chi G-sphere |q+G|^2/2 <= ecut in the library's canonical order (host only)."""
+    L = _capi.lib()
+    cell = _cell(A, grid)
+    qv = _f64(q)
+    ng = ctypes.c_int(0)
+    _check(L.rpa_gsphere(ctypes.byref(cell), _ptr_f64(qv), float(ecut), None, 0, ctypes.byref(ng)))
+    out = np.zeros((max(ng.value, 1), 3), dtype=np.int32)
+    _check(L.rpa_gsphere(ctypes.byref(cell), _ptr_f64(qv), float(ecut), _ptr_i32(out), ng.value, ctypes.byref(ng)))
+    return out[: ng.value]
+
+
+class States:
+    """One k (or k+q) state set; C and P live on the device, the rest on the host."""
+
+    def __init__(self, C, miller, eps, f, P=None, proj_off=None, kpt=(0.0, 0.0, 0.0), weight=1.0,
+                 device="cuda"):
+        torch = _torch()
+        self.device = device
+        self.C = _dev_c128(C, device)
+        self.miller = _i32(miller).reshape(-1, 3)
+        self.eps = _f64(eps)
+        self.f = _f64(f)
+        self.proj_off = _i32(proj_off if proj_off is not None else [0])
+        natoms = len(self.proj_off) - 1
+        if P is None or natoms <= 0:
+            self.P = torch.zeros((self.C.shape[0], 1), dtype=torch.complex128, device=device)
+            self.natoms = 0
+        else:
+            self.P = _dev_c128(P, device)
+            self.natoms = natoms
+        self.kpt = _f64(kpt)
+        self.weight = float(weight)
+
+    @classmethod
+    def from_synth(cls, s, paw, device="cuda"):
+        return cls(s.C, s.miller, s.eps, s.f, s.P, paw.offsets, s.kpt, s.weight, device)
+
+    def struct(self) -> RpaStates:
+        st = RpaStates()
+        st.nbands = int(self.C.shape[0])
+        st.nQ = int(self.C.shape[1])
+        st.miller = _ptr_i32(self.miller)
+        st.C = ctypes.c_void_p(self.C.data_ptr())
+        st.eps = _ptr_f64(self.eps)
+        st.f = _ptr_f64(self.f)
+        st.natoms = int(self.natoms)
+        st.proj_off = _ptr_i32(self.proj_off)
+        st.P = ctypes.c_void_p(self.P.data_ptr())
+        for i in range(3):
+            st.kpt[i] = float(self.kpt[i])
+        st.weight = self.weight
+        return st
+
+
+class QSpec:
+    """One q-point: its G-sphere, the PAW table Q(q+G) on the device and, at q -> 0, the nabla table."""
+
+    def __init__(self, q, gmiller, Qpaw=None, optical=False, qhat=(1.0, 0.0, 0.0), Dpaw=None, weight=1.0,
+                 device="cuda"):
+        self.q = _f64(q)
+        self.gmiller = _i32(gmiller).reshape(-1, 3)
+        self.optical = bool(optical)
+        self.qhat = _f64(qhat)
+        self.Qpaw = _dev_c128(Qpaw, device) if Qpaw is not None else None
+        self.Dpaw = _f64(Dpaw) if Dpaw is not None else None
+        self.weight = float(weight)
+
+    @property
+    def NG(self) -> int:
+        return int(self.gmiller.shape[0])
+
+    def struct(self) -> RpaQSpec:
+        s = RpaQSpec()
+        for i in range(3):
+            s.q[i] = float(self.q[i])
+            s.qhat[i] = float(self.qhat[i])
+        s.optical = int(self.optical)
+        s.NG = self.NG
+        s.gmiller = _ptr_i32(self.gmiller)
+        s.Qpaw = ctypes.c_void_p(self.Qpaw.data_ptr()) if self.Qpaw is not None else None
+        s.Dpaw = _ptr_f64(self.Dpaw) if self.Dpaw is not None else None
+        s.weight = self.weight
+        return s
+
+
+class Freq:
+    def __init__(self, omega, weight):
+        self.omega = _f64(omega)
+        self.weight = _f64(weight)
+
+    @property
+    def nw(self) -> int:
+        return int(self.omega.size)
+
+    def struct(self) -> RpaFreq:
+        fr = RpaFreq()
+        fr.nw = self.nw
+        fr.omega = _ptr_f64(self.omega)
+        fr.weight = _ptr_f64(self.weight)
+        return fr
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISION[p]
+    return int(p)
+
+
+class Context:
+    """A library context for one cell and FFT grid on one device."""
+
+    def __init__(self, A, grid, device: int = 0, workspace_cap: int = 0):
+        self._L = _capi.lib()
+        self.A = _f64(A).reshape(3, 3)
+        self.grid = tuple(int(x) for x in grid)
+        self.device_index = int(device)
+        self.device = f"cuda:{self.device_index}"
+        self._cell = _cell(self.A, self.grid)
+        h = ctypes.c_void_p()
+        _check(self._L.rpa_create(ctypes.byref(h), ctypes.byref(self._cell), self.device_index, int(workspace_cap)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.rpa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls -------------------------------------------------------------
+    @staticmethod
+    def _arrays(sets):
+        arr = (RpaStates * len(sets))()
+        for i, s in enumerate(sets):
+            arr[i] = s.struct()
+        return arr
+
+    def pair_density(self, k: States, kq: States, qs: QSpec, pair_n, pair_m, precision="fp64"):
+        torch = _torch()
+        pn = _i32(pair_n)
+        pm = _i32(pair_m)
+        out = torch.empty((pn.size, qs.NG), dtype=torch.complex128, device=self.device)
+        ks, kqs, q = k.struct(), kq.struct(), qs.struct()
+        _check(self._L.rpa_pair_density(self._h, ctypes.byref(ks), ctypes.byref(kqs), ctypes.byref(q), int(pn.size),
+                                        _ptr_i32(pn), _ptr_i32(pm), _prec(precision),
+                                        ctypes.c_void_p(out.data_ptr()), _stream()), self._h)
+        return out
+
+    def chi0(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, freq: Freq, precision="fp64"):
+        torch = _torch()
+        out = torch.empty((freq.nw, qs.NG, qs.NG), dtype=torch.complex128, device=self.device)
+        a, b, q, fr = self._arrays(ks), self._arrays(kqs), qs.struct(), freq.struct()
+        _check(self._L.rpa_chi0(self._h, a, b, len(ks), ctypes.byref(q), ctypes.byref(fr), _prec(precision),
+                                ctypes.c_void_p(out.data_ptr()), _stream()), self._h)
+        return out
+
+    def ec(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, freq: Freq, precision="fp64"):
+        """E_c(q) (device double [1]) and F(w) (device double [nw]); asynchronous."""
+        torch = _torch()
+        ec = torch.empty(1, dtype=torch.float64, device=self.device)
+        F = torch.empty(freq.nw, dtype=torch.float64, device=self.device)
+        a, b, q, fr = self._arrays(ks), self._arrays(kqs), qs.struct(), freq.struct()
+        _check(self._L.rpa_ec(self._h, a, b, len(ks), ctypes.byref(q), ctypes.byref(fr), _prec(precision),
+                              ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()), _stream()), self._h)
+        return ec, F
+
+    def ec_from_chi0(self, qs: QSpec, freq: Freq, chi0):
+        torch = _torch()
+        chi0 = chi0.to(device=self.device, dtype=torch.complex128).contiguous()
+        ec = torch.empty(1, dtype=torch.float64, device=self.device)
+        F = torch.empty(freq.nw, dtype=torch.float64, device=self.device)
+        q, fr = qs.struct(), freq.struct()
+        _check(self._L.rpa_ec_from_chi0(self._h, ctypes.byref(q), ctypes.byref(fr), ctypes.c_void_p(chi0.data_ptr()),
+                                        ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()), _stream()),
+               self._h)
+        return ec, F
+
+    STAGES = ("orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights", "herk", "cholesky")
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-stage HIP-event timing; totals are cleared."""
+        _check(self._L.rpa_profile(self._h, int(bool(enable))), self._h)
+
+    def profile_get(self) -> dict:
+        """{stage: (milliseconds, timed launch groups)} since the last profile() call."""
+        out = {}
+        for st in self.STAGES:
+            ms = ctypes.c_double(0)
+            n = ctypes.c_longlong(0)
+            _check(self._L.rpa_profile_get(self._h, st.encode(), ctypes.byref(ms), ctypes.byref(n)), self._h)
+            out[st] = (ms.value, n.value)
+        return out
+
+    def check(self):
+        """Synchronize and raise RpaError for device-side failures (e.g. a non-positive pivot)."""
+        _check(self._L.rpa_check(self._h, _stream()), self._h)

@@ -1,0 +1,117 @@
+// Internal interfaces between the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft.hpp"
+
+namespace rpa {
+
+// Tile edge of the rank-k update and of the Cholesky blocks; the padded
+// G dimension NGp is a multiple of it.
+constexpr int kTile = 64;
+
+// Workgroup size of every FFT-stage kernel.
+constexpr int kFftThreads = 256;
+
+// Geometry of the pruned pair-density transform for one q.
+struct PairGeom {
+    int N1, N2, N3;       // grid
+    int K1, K2;           // kept Miller ranges along a1 and a2 (the sphere's extent)
+    int ncols;            // K1*K2 columns (m1, m2) of the sphere's bounding box
+    int NG, NGp;          // sphere size and its padded size
+    FftPlan p1, p2, p3;
+};
+
+// ----------------------------------------------------------------- FFT stages
+template <typename T>
+hipError_t launch_fill_zero(cplx<T>* p, size_t n, hipStream_t s);
+
+template <typename T>
+hipError_t launch_orb_scatter(const double* C, int nbands, int nQ, const int32_t* map, size_t vol,
+                              cplx<T>* phi, hipStream_t s);
+
+// In-place batched 1-D inverse transforms along one axis of [nb][N3][N2][N1] arrays.
+template <typename T>
+hipError_t launch_fft_axis(cplx<T>* data, int nb, int N1, int N2, int N3, int axis, const FftPlan& plan,
+                           const cplx<T>* tw, int dir, hipStream_t s);
+
+template <typename T>
+hipError_t launch_pair_xy(const cplx<T>* phik, const cplx<T>* phikq, const int32_t* pn, const int32_t* pm,
+                          int npairs, const PairGeom& g, const int32_t* kx_grid, const int32_t* ky_grid,
+                          const cplx<T>* tw1, const cplx<T>* tw2, cplx<T>* tbuf, hipStream_t s);
+
+template <typename T>
+hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
+                                const int32_t* col_g, const int32_t* col_kz, const cplx<T>* tw3, T* rho_re,
+                                T* rho_im, hipStream_t s);
+
+// ------------------------------------------------------------ linear algebra
+template <typename T>
+hipError_t launch_paw_y(const double* Pk, int ldP, const int32_t* nlist, int nn, const int32_t* proj_off,
+                        const int32_t* qoff, int natoms, int nprojtot, const double* Q, int NG, int NGp,
+                        T* Yre, T* Yim, hipStream_t s);
+
+template <typename T>
+hipError_t launch_paw_add(const T* Yre, const T* Yim, const int32_t* pn, int nlo, const int32_t* pm,
+                          const double* Pkq, int ldP, int nprojtot, int npairs, int NG, int NGp, T* rho_re,
+                          T* rho_im, hipStream_t s);
+
+template <typename T>
+hipError_t launch_optical_row(const double* Ck, const double* Ckq, int nQ, const double* wq, const double* Pk,
+                              const double* Pkq, int ldP, const double* Dq, const int32_t* proj_off,
+                              const int32_t* qoff, int natoms, const double* epsk, const double* epskq,
+                              const int32_t* pn, const int32_t* pm, int npairs, int g0, int NGp, T* rho_re,
+                              T* rho_im, hipStream_t s);
+
+hipError_t launch_weights(const double* epsk, const double* epskq, const double* fk, const double* fkq,
+                          const int32_t* pn, const int32_t* pm, int npairs, const double* omega, int nw,
+                          double prefac, double* a, int lda, hipStream_t s);
+
+// C[b] (lower tiles of the nT x nT block region at (r0, r0)) +=
+//   sum_k w[b][k] A[b][k][c0 + i] conj(A[b][k][c0 + j]); w == nullptr means alpha.
+struct HerkArgs {
+    const double* Are; const double* Aim; long long sA; int ldA; int colA; int K;
+    const double* w; long long sw; double alpha;
+    double* Cre; double* Cim; long long sC; int ldC; int r0;
+    int nT; int nbatch;
+};
+hipError_t launch_herk_f64(const HerkArgs& h, hipStream_t s);
+
+// Split-precision rank-k update (FP32 operands, hi/lo BF16 or FP16 products on
+// MFMA, FP32 accumulation, FP64 output accumulation).
+struct HerkSplitArgs {
+    const float* Are; const float* Aim; int ldA; int K;
+    const double* w; int lda;
+    double* Cre; double* Cim; long long sC; int ldC;
+    int nT; int nw;
+    int fp16;            // 0 = BF16, 1 = FP16 (scaled)
+    const float* wscale; // per-frequency power-of-two scale for FP16 (nullptr for BF16)
+};
+hipError_t launch_herk_split(const HerkSplitArgs& h, hipStream_t s);
+
+// -K = -v_i v_j chi_ij on the lower triangle (in place, planar), zero padding,
+// and Tr K per frequency.
+hipError_t launch_build_negk(double* Cre, double* Cim, int ldC, int NG, int NGp, int nw,
+                             const double* vsqrt, double* trk, hipStream_t s);
+hipError_t launch_build_negk_from_full(const double* chi, int NG, double* Cre, double* Cim, int NGp, int nw,
+                                       const double* vsqrt, double* trk, hipStream_t s);
+
+hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, double* Lre, double* Lim,
+                             double* logdet, int* fail, hipStream_t s);
+hipError_t launch_chol_trsm(const double* Cre, const double* Cim, int ldC, int j0, int NGp, int nw,
+                            const double* Lre, const double* Lim, double* Pre, double* Pim, hipStream_t s);
+hipError_t launch_finalize(const double* logdet, const double* trk, const int* fail, const double* wgt, int nw,
+                           double* F, double* ec, hipStream_t s);
+
+hipError_t launch_zero(double* d, int nd, int* iv, int ni, hipStream_t s);
+
+// planar (re, im) [npairs][NGp] of type T -> interleaved complex128 [npairs][NG]
+template <typename T>
+hipError_t launch_rho_out(const T* rre, const T* rim, int npairs, int NG, int NGp, double* out, hipStream_t s);
+
+hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out,
+                          hipStream_t s);
+
+}  // namespace rpa

@@ -1,0 +1,610 @@
+// Dense stages of the chi0 / E_c path:
+//   PAW correction of the pair densities (Eq. n_G_2, Table 1 steps 7-9),
+//   optical-limit row at q = 0 (Eq. n_q0, Eq. nabla, Eq. Q_q0, step 10),
+//   real transition weights (Eq. chi0, Eq. A_iw),
+//   grouped complex rank-k update of chi0 (Eq. zher_multi, step 11) on FP64 MFMA,
+//   E_c(q) from a blocked FP64 Cholesky factorisation of 1 - K (Eq. rpa, step 13).
+//
+// Matrices of the rank-k update and of the factorisation are planar (separate
+// real and imaginary arrays), row-major, with a padded leading dimension that is
+// a multiple of the 64-wide tile.
+#include "internal.hpp"
+
+namespace rpa {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ cplx<double> ld_c128(const double* p, size_t i) { return mk(p[2 * i], p[2 * i + 1]); }
+
+// ------------------------------------------------------------------- PAW
+// Y[s][aj][g] = sum_i conj(P_k[n_s][a, i]) Q[qoff_a + i Np_a + j][g]
+template <typename T>
+__global__ void k_paw_y(const double* __restrict__ Pk, int ldP, const int32_t* __restrict__ nlist,
+                        const int32_t* __restrict__ proj_off, const int32_t* __restrict__ qoff, int natoms,
+                        int nprojtot, const double* __restrict__ Q, int NG, int NGp, T* __restrict__ Yre,
+                        T* __restrict__ Yim) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int aj = blockIdx.y;
+    const int s = blockIdx.z;
+    if (g >= NGp) return;
+    int a = 0;
+    while (a + 1 < natoms && proj_off[a + 1] <= aj) ++a;
+    const int lo = proj_off[a], np = proj_off[a + 1] - lo, j = aj - lo;
+    const size_t n = nlist[s];
+    cplx<double> acc = mk(0.0, 0.0);
+    if (g < NG) {
+        for (int i = 0; i < np; ++i) {
+            const cplx<double> p = ld_c128(Pk, n * ldP + lo + i);
+            const cplx<double> q = ld_c128(Q, (size_t)(qoff[a] + i * np + j) * NG + g);
+            acc = acc + cmulc(p, q);
+        }
+    }
+    const size_t o = ((size_t)s * nprojtot + aj) * NGp + g;
+    Yre[o] = T(acc.x);
+    Yim[o] = T(acc.y);
+}
+
+// rho[p][g] += sum_aj Y[n_p - nlo][aj][g] P_kq[m_p][aj]
+constexpr int kPawPairs = 8;
+template <typename T>
+__global__ __launch_bounds__(256) void k_paw_add(const T* __restrict__ Yre, const T* __restrict__ Yim,
+                                                 const int32_t* __restrict__ pn, int nlo,
+                                                 const int32_t* __restrict__ pm,
+                                                 const double* __restrict__ Pkq, int ldP, int nprojtot, int npairs,
+                                                 int NG, int NGp, T* __restrict__ rre, T* __restrict__ rim) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* pr = reinterpret_cast<T*>(smem);
+    T* pi = pr + kPawPairs * nprojtot;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p0 = blockIdx.y * kPawPairs;
+    const int np = min(kPawPairs, npairs - p0);
+    for (int e = threadIdx.x; e < np * nprojtot; e += blockDim.x) {
+        const int pp = e / nprojtot, aj = e - pp * nprojtot;
+        const cplx<double> v = ld_c128(Pkq, (size_t)pm[p0 + pp] * ldP + aj);
+        pr[e] = T(v.x);
+        pi[e] = T(v.y);
+    }
+    __syncthreads();
+    if (g >= NG) return;
+    for (int pp = 0; pp < np; ++pp) {
+        const size_t yb = (size_t)(pn[p0 + pp] - nlo) * nprojtot * NGp + g;
+        T sr = T(0), si = T(0);
+        for (int aj = 0; aj < nprojtot; ++aj) {
+            const T yr = Yre[yb + (size_t)aj * NGp], yi = Yim[yb + (size_t)aj * NGp];
+            const T xr = pr[pp * nprojtot + aj], xi = pi[pp * nprojtot + aj];
+            sr += yr * xr - yi * xi;
+            si += yr * xi + yi * xr;
+        }
+        const size_t o = (size_t)(p0 + pp) * NGp + g;
+        rre[o] += sr;
+        rim[o] += si;
+    }
+}
+
+// ---------------------------------------------------------------- optical
+// rho[p][g0] = [sum_Q conj(Ck_n) Ckq_m wq - i sum_a sum_ij conj(Pk_ni) Dq_ij Pkq_mj] / (e_m - e_n)
+template <typename T>
+__global__ __launch_bounds__(256) void k_optical_row(const double* __restrict__ Ck, const double* __restrict__ Ckq,
+                                                     int nQ, const double* __restrict__ wq,
+                                                     const double* __restrict__ Pk, const double* __restrict__ Pkq,
+                                                     int ldP, const double* __restrict__ Dq,
+                                                     const int32_t* __restrict__ proj_off,
+                                                     const int32_t* __restrict__ qoff, int natoms,
+                                                     const double* __restrict__ epsk, const double* __restrict__ epskq,
+                                                     const int32_t* __restrict__ pn, const int32_t* __restrict__ pm,
+                                                     int g0, int NGp, T* __restrict__ rre, T* __restrict__ rim) {
+    __shared__ double red[4][256];
+    const int p = blockIdx.x;
+    const size_t n = pn[p], m = pm[p];
+    double mr = 0, mi = 0, dr = 0, di = 0;
+    for (int q = threadIdx.x; q < nQ; q += blockDim.x) {
+        const cplx<double> c = cmulc(ld_c128(Ck, n * nQ + q), ld_c128(Ckq, m * nQ + q));
+        mr += c.x * wq[q];
+        mi += c.y * wq[q];
+    }
+    const int nq2 = qoff[natoms];
+    for (int e = threadIdx.x; e < nq2; e += blockDim.x) {
+        int a = 0;
+        while (a + 1 < natoms && qoff[a + 1] <= e) ++a;
+        const int np = proj_off[a + 1] - proj_off[a];
+        const int r = e - qoff[a], i = r / np, j = r - i * np;
+        const cplx<double> t = cmulc(ld_c128(Pk, n * ldP + proj_off[a] + i), ld_c128(Pkq, m * ldP + proj_off[a] + j));
+        dr += t.x * Dq[e];
+        di += t.y * Dq[e];
+    }
+    red[0][threadIdx.x] = mr;
+    red[1][threadIdx.x] = mi;
+    red[2][threadIdx.x] = dr;
+    red[3][threadIdx.x] = di;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double den = epskq[m] - epsk[n];
+        // numerator = mom - i * paw
+        const double nr = red[0][0] + red[3][0];
+        const double ni = red[1][0] - red[2][0];
+        rre[(size_t)p * NGp + g0] = T(nr / den);
+        rim[(size_t)p * NGp + g0] = T(ni / den);
+    }
+}
+
+// ---------------------------------------------------------------- weights
+__global__ void k_weights(const double* __restrict__ epsk, const double* __restrict__ epskq,
+                          const double* __restrict__ fk, const double* __restrict__ fkq, const int32_t* __restrict__ pn,
+                          const int32_t* __restrict__ pm, int npairs, const double* __restrict__ omega, int nw,
+                          double prefac, double* __restrict__ a, int lda) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= lda) return;
+    if (p >= npairs) {
+        for (int w = 0; w < nw; ++w) a[(size_t)w * lda + p] = 0.0;
+        return;
+    }
+    const double d = epsk[pn[p]] - epskq[pm[p]];
+    const double df = fk[pn[p]] - fkq[pm[p]];
+    for (int w = 0; w < nw; ++w) {
+        const double om = omega[w];
+        a[(size_t)w * lda + p] = prefac * df * 2.0 * d / (om * om + d * d);
+    }
+}
+
+// ------------------------------------------------------------ FP64 HERK
+// One 64x64 lower tile (I >= J) of one batch entry per workgroup; four waves,
+// each a 32x32 quadrant as 2x2 blocks of v_mfma_f64_16x16x4f64.
+// Fragment layouts (16x16x4 f64): A lane l holds A[l%16][l/16], B lane l holds
+// B[l/16][l%16], D lane l element r holds D[l/16 + 4*r][l%16] (rows interleave
+// across the four lane groups, unlike the 16-bit-input MFMAs).
+constexpr int kHerkBK = 16;
+
+__device__ __forceinline__ void tile_of(int t, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+__global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
+    __shared__ double sAr[kHerkBK][kTile], sAi[kHerkBK][kTile], sBr[kHerkBK][kTile], sBi[kHerkBK][kTile];
+    int I, J;
+    tile_of(blockIdx.x, I, J);
+    const int b = blockIdx.y;
+    const double* Are = h.Are + (size_t)b * h.sA;
+    const double* Aim = h.Aim + (size_t)b * h.sA;
+    const double* w = h.w ? h.w + (size_t)b * h.sw : nullptr;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int ci = h.colA + I * kTile, cj = h.colA + J * kTile;
+    v4d accR[2][2], accI[2][2];
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+            accR[x][y] = v4d{0, 0, 0, 0};
+            accI[x][y] = v4d{0, 0, 0, 0};
+        }
+    for (int k0 = 0; k0 < h.K; k0 += kHerkBK) {
+        for (int e = tid; e < kHerkBK * kTile; e += 256) {
+            const int kk = e >> 6, c = e & 63, k = k0 + kk;
+            double ar = 0, ai = 0, br = 0, bi = 0;
+            if (k < h.K) {
+                const size_t row = (size_t)k * h.ldA;
+                const double wk = w ? w[k] : h.alpha;
+                ar = Are[row + ci + c] * wk;
+                ai = Aim[row + ci + c] * wk;
+                br = Are[row + cj + c];
+                bi = Aim[row + cj + c];
+            }
+            sAr[kk][c] = ar;
+            sAi[kk][c] = ai;
+            sBr[kk][c] = br;
+            sBi[kk][c] = bi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kHerkBK; kk += 4) {
+            const int kr = kk + (lane >> 4), cc = lane & 15;
+            double a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                a_r[x] = sAr[kr][wr + x * 16 + cc];
+                a_i[x] = sAi[kr][wr + x * 16 + cc];
+                a_n[x] = -a_r[x];
+                b_r[x] = sBr[kr][wc + x * 16 + cc];
+                b_i[x] = sBi[kr][wc + x * 16 + cc];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    accR[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_r[y], accR[x][y], 0, 0, 0);
+                    accR[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_i[y], accR[x][y], 0, 0, 0);
+                    accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_r[y], accI[x][y], 0, 0, 0);
+                    accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[x], b_i[y], accI[x][y], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    double* Cre = h.Cre + (size_t)b * h.sC;
+    double* Cim = h.Cim + (size_t)b * h.sC;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = h.r0 + I * kTile + wr + x * 16 + (lane >> 4) + 4 * r;
+                const int col = h.r0 + J * kTile + wc + y * 16 + (lane & 15);
+                const size_t o = (size_t)row * h.ldC + col;
+                Cre[o] += accR[x][y][r];
+                Cim[o] += accI[x][y][r];
+            }
+}
+
+// ------------------------------------------------------- E_c: 1 - K setup
+__global__ void k_trace_k(const double* __restrict__ Cre, int ldC, long long sC, int NG,
+                          const double* __restrict__ vsqrt, double* __restrict__ trk) {
+    __shared__ double red[256];
+    const int w = blockIdx.x;
+    double s = 0;
+    for (int i = threadIdx.x; i < NG; i += blockDim.x) s += vsqrt[i] * vsqrt[i] * Cre[(size_t)w * sC + (size_t)i * ldC + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) trk[w] = red[0];
+}
+
+__global__ void k_trace_full(const double* __restrict__ chi, int NG, const double* __restrict__ vsqrt,
+                             double* __restrict__ trk) {
+    __shared__ double red[256];
+    const int w = blockIdx.x;
+    double s = 0;
+    for (int i = threadIdx.x; i < NG; i += blockDim.x)
+        s += vsqrt[i] * vsqrt[i] * chi[2 * ((size_t)w * NG * NG + (size_t)i * NG + i)];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) trk[w] = red[0];
+}
+
+// lower triangle (row i, cols j <= i) := -v_i v_j chi_ij, zero outside NG
+__global__ void k_negk(double* __restrict__ Cre, double* __restrict__ Cim, int ldC, long long sC, int NG,
+                       const double* __restrict__ vsqrt) {
+    const int i = blockIdx.x, w = blockIdx.y;
+    double* rr = Cre + (size_t)w * sC + (size_t)i * ldC;
+    double* ri = Cim + (size_t)w * sC + (size_t)i * ldC;
+    const double vi = i < NG ? vsqrt[i] : 0.0;
+    for (int j = threadIdx.x; j <= i; j += blockDim.x) {
+        const double s = (i < NG && j < NG) ? -vi * vsqrt[j] : 0.0;
+        rr[j] = rr[j] * s;
+        ri[j] = ri[j] * s;
+    }
+}
+
+__global__ void k_negk_full(const double* __restrict__ chi, int NG, double* __restrict__ Cre,
+                            double* __restrict__ Cim, int ldC, long long sC, const double* __restrict__ vsqrt) {
+    const int i = blockIdx.x, w = blockIdx.y;
+    double* rr = Cre + (size_t)w * sC + (size_t)i * ldC;
+    double* ri = Cim + (size_t)w * sC + (size_t)i * ldC;
+    for (int j = threadIdx.x; j <= i; j += blockDim.x) {
+        double re = 0, im = 0;
+        if (i < NG && j < NG) {
+            const double s = -vsqrt[i] * vsqrt[j];
+            const size_t o = 2 * ((size_t)w * NG * NG + (size_t)i * NG + j);
+            re = chi[o] * s;
+            im = chi[o + 1] * s;
+        }
+        rr[j] = re;
+        ri[j] = im;
+    }
+}
+
+__global__ void k_zero_d(double* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+__global__ void k_zero_i(int* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// ------------------------------------------------------ blocked Cholesky
+// The factorised matrix is 1 + A with A = -K held in C; the identity is never
+// formed: pivot j is 1 + A_jj and contributes log1p(A_jj) to ln det(1 - K),
+// which keeps ln det accurate when K is small (large frequencies).
+//
+// Panel: factor the 64x64 diagonal block at j0 in LDS, accumulate its log-det,
+// and store the inverse of its lower-triangular factor for the row solve.
+__global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ Cre, const double* __restrict__ Cim,
+                                                    int ldC, long long sC, int j0, double* __restrict__ Lre,
+                                                    double* __restrict__ Lim, double* __restrict__ logdet,
+                                                    int* __restrict__ fail) {
+    __shared__ double sr[kTile][kTile + 1], si[kTile][kTile + 1];
+    __shared__ double vr[kTile][kTile + 1], vi[kTile][kTile + 1];
+    __shared__ double pinv, ldacc;
+    __shared__ int bad;
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const double* cr = Cre + (size_t)w * sC;
+    const double* ci = Cim + (size_t)w * sC;
+    for (int e = tid; e < kTile * kTile; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        const bool low = c <= r;
+        sr[r][c] = low ? cr[(size_t)(j0 + r) * ldC + j0 + c] : 0.0;
+        si[r][c] = low ? ci[(size_t)(j0 + r) * ldC + j0 + c] : 0.0;
+        vr[r][c] = 0.0;
+        vi[r][c] = 0.0;
+    }
+    if (tid == 0) { ldacc = 0.0; bad = 0; }
+    __syncthreads();
+    for (int c = 0; c < kTile; ++c) {
+        if (tid == 0) {
+            const double d = sr[c][c];
+            if (!(1.0 + d > 0.0) && !bad) bad = j0 + c + 1;
+            ldacc += log1p(d);
+            const double s = sqrt(1.0 + d);
+            sr[c][c] = s;
+            si[c][c] = 0.0;
+            pinv = 1.0 / s;
+        }
+        __syncthreads();
+        for (int r = c + 1 + tid; r < kTile; r += blockDim.x) {
+            sr[r][c] *= pinv;
+            si[r][c] *= pinv;
+        }
+        __syncthreads();
+        const int m = kTile - 1 - c;
+        for (int e = tid; e < m * m; e += blockDim.x) {
+            const int r = c + 1 + e / m, cc = c + 1 + e % m;
+            if (cc <= r) {
+                // A[r][cc] -= L[r][c] conj(L[cc][c])
+                const double ar = sr[r][c], ai = si[r][c], br = sr[cc][c], bi = si[cc][c];
+                sr[r][cc] -= ar * br + ai * bi;
+                si[r][cc] -= ai * br - ar * bi;
+            }
+        }
+        __syncthreads();
+    }
+    // inverse of the lower-triangular factor, one column per thread
+    if (tid < kTile) {
+        const int c = tid;
+        vr[c][c] = 1.0 / sr[c][c];
+        vi[c][c] = 0.0;
+        for (int r = c + 1; r < kTile; ++r) {
+            double xr = 0, xi = 0;
+            for (int k = c; k < r; ++k) {
+                xr += sr[r][k] * vr[k][c] - si[r][k] * vi[k][c];
+                xi += sr[r][k] * vi[k][c] + si[r][k] * vr[k][c];
+            }
+            const double inv = 1.0 / sr[r][r];
+            vr[r][c] = -xr * inv;
+            vi[r][c] = -xi * inv;
+        }
+    }
+    __syncthreads();
+    double* lr = Lre + (size_t)w * kTile * kTile;
+    double* li = Lim + (size_t)w * kTile * kTile;
+    for (int e = tid; e < kTile * kTile; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        lr[e] = vr[r][c];
+        li[e] = vi[r][c];
+    }
+    if (tid == 0) {
+        logdet[w] += ldacc;
+        if (bad && !fail[w]) fail[w] = bad;
+    }
+}
+
+// Row solve of the panel below the diagonal block: X = A21 (L11^-1)^H, written
+// transposed (X[c][r], rows contiguous) as the operand of the trailing update.
+constexpr int kTrsmRows = 32;
+__global__ __launch_bounds__(256) void k_chol_trsm(const double* __restrict__ Cre, const double* __restrict__ Cim,
+                                                   int ldC, long long sC, int j0, int NGp,
+                                                   const double* __restrict__ Lre, const double* __restrict__ Lim,
+                                                   double* __restrict__ Pre, double* __restrict__ Pim) {
+    __shared__ double lr[kTile][kTile + 1], li[kTile][kTile + 1];
+    __shared__ double ar[kTrsmRows][kTile + 1], ai[kTrsmRows][kTile + 1];
+    const int w = blockIdx.y, tid = threadIdx.x;
+    const int r0 = j0 + kTile + blockIdx.x * kTrsmRows;
+    const double* cr = Cre + (size_t)w * sC;
+    const double* ci = Cim + (size_t)w * sC;
+    for (int e = tid; e < kTile * kTile; e += blockDim.x) {
+        lr[e >> 6][e & 63] = Lre[(size_t)w * kTile * kTile + e];
+        li[e >> 6][e & 63] = Lim[(size_t)w * kTile * kTile + e];
+    }
+    for (int e = tid; e < kTrsmRows * kTile; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        const int row = r0 + r;
+        ar[r][c] = row < NGp ? cr[(size_t)row * ldC + j0 + c] : 0.0;
+        ai[r][c] = row < NGp ? ci[(size_t)row * ldC + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    double* pr = Pre + (size_t)w * kTile * NGp;
+    double* pi = Pim + (size_t)w * kTile * NGp;
+    for (int e = tid; e < kTrsmRows * kTile; e += blockDim.x) {
+        const int r = e % kTrsmRows, c = e / kTrsmRows;
+        const int row = r0 + r;
+        // X[r][c] = sum_{k<=c} A[r][k] conj(Linv[c][k])
+        double xr = 0, xi = 0;
+        for (int k = 0; k <= c; ++k) {
+            xr += ar[r][k] * lr[c][k] + ai[r][k] * li[c][k];
+            xi += ai[r][k] * lr[c][k] - ar[r][k] * li[c][k];
+        }
+        if (row < NGp) {
+            pr[(size_t)c * NGp + row] = xr;
+            pi[(size_t)c * NGp + row] = xi;
+        }
+    }
+}
+
+__global__ void k_finalize(const double* __restrict__ logdet, const double* __restrict__ trk,
+                           const int* __restrict__ fail, const double* __restrict__ wgt, int nw, double* __restrict__ F,
+                           double* __restrict__ ec) {
+    if (threadIdx.x != 0) return;
+    double e = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        const double f = fail[w] ? __builtin_nan("") : logdet[w] + trk[w];
+        if (F) F[w] = f;
+        e += wgt[w] * f;
+    }
+    *ec = e / (2.0 * kPi);
+}
+
+template <typename T>
+__global__ void k_rho_out(const T* __restrict__ rre, const T* __restrict__ rim, int NG, int NGp,
+                          double* __restrict__ out) {
+    const size_t p = blockIdx.y;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < NG; g += gridDim.x * blockDim.x) {
+        out[2 * (p * NG + g)] = (double)rre[p * NGp + g];
+        out[2 * (p * NG + g) + 1] = (double)rim[p * NGp + g];
+    }
+}
+
+__global__ void k_chi_out(const double* __restrict__ Cre, const double* __restrict__ Cim, int ldC, long long sC,
+                          int NG, double* __restrict__ out) {
+    const int i = blockIdx.x, w = blockIdx.y;
+    const double* cr = Cre + (size_t)w * sC;
+    const double* ci = Cim + (size_t)w * sC;
+    double* o = out + 2 * ((size_t)w * NG * NG + (size_t)i * NG);
+    for (int j = threadIdx.x; j < NG; j += blockDim.x) {
+        double re, im;
+        if (j <= i) { re = cr[(size_t)i * ldC + j]; im = ci[(size_t)i * ldC + j]; }
+        else { re = cr[(size_t)j * ldC + i]; im = -ci[(size_t)j * ldC + i]; }
+        o[2 * j] = re;
+        o[2 * j + 1] = im;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_paw_y(const double* Pk, int ldP, const int32_t* nlist, int nn, const int32_t* proj_off,
+                        const int32_t* qoff, int natoms, int nprojtot, const double* Q, int NG, int NGp, T* Yre,
+                        T* Yim, hipStream_t s) {
+    if (!nn || !nprojtot) return hipSuccess;
+    dim3 grid((unsigned)((NGp + 255) / 256), (unsigned)nprojtot, (unsigned)nn);
+    hipLaunchKernelGGL(k_paw_y<T>, grid, dim3(256), 0, s, Pk, ldP, nlist, proj_off, qoff, natoms, nprojtot, Q, NG, NGp,
+                       Yre, Yim);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_paw_add(const T* Yre, const T* Yim, const int32_t* pn, int nlo, const int32_t* pm, const double* Pkq,
+                          int ldP, int nprojtot, int npairs, int NG, int NGp, T* rre, T* rim, hipStream_t s) {
+    if (!npairs || !nprojtot) return hipSuccess;
+    dim3 grid((unsigned)((NG + 255) / 256), (unsigned)((npairs + kPawPairs - 1) / kPawPairs));
+    const size_t lds = 2 * (size_t)kPawPairs * nprojtot * sizeof(T);
+    hipLaunchKernelGGL(k_paw_add<T>, grid, dim3(256), lds, s, Yre, Yim, pn, nlo, pm, Pkq, ldP, nprojtot, npairs, NG,
+                       NGp, rre, rim);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_optical_row(const double* Ck, const double* Ckq, int nQ, const double* wq, const double* Pk,
+                              const double* Pkq, int ldP, const double* Dq, const int32_t* proj_off,
+                              const int32_t* qoff, int natoms, const double* epsk, const double* epskq,
+                              const int32_t* pn, const int32_t* pm, int npairs, int g0, int NGp, T* rre, T* rim,
+                              hipStream_t s) {
+    if (!npairs) return hipSuccess;
+    hipLaunchKernelGGL(k_optical_row<T>, dim3((unsigned)npairs), dim3(256), 0, s, Ck, Ckq, nQ, wq, Pk, Pkq, ldP, Dq,
+                       proj_off, qoff, natoms, epsk, epskq, pn, pm, g0, NGp, rre, rim);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(const double* epsk, const double* epskq, const double* fk, const double* fkq,
+                          const int32_t* pn, const int32_t* pm, int npairs, const double* omega, int nw, double prefac,
+                          double* a, int lda, hipStream_t s) {
+    if (!lda) return hipSuccess;
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)((lda + 255) / 256)), dim3(256), 0, s, epsk, epskq, fk, fkq, pn, pm,
+                       npairs, omega, nw, prefac, a, lda);
+    return hipGetLastError();
+}
+
+hipError_t launch_herk_f64(const HerkArgs& h, hipStream_t s) {
+    if (h.nT <= 0 || h.nbatch <= 0 || h.K <= 0) return hipSuccess;
+    const unsigned ntiles = (unsigned)(h.nT * (h.nT + 1) / 2);
+    hipLaunchKernelGGL(k_herk_f64, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_negk(double* Cre, double* Cim, int ldC, int NG, int NGp, int nw, const double* vsqrt,
+                             double* trk, hipStream_t s) {
+    const long long sC = (long long)ldC * ldC;
+    hipLaunchKernelGGL(k_trace_k, dim3((unsigned)nw), dim3(256), 0, s, Cre, ldC, sC, NG, vsqrt, trk);
+    hipLaunchKernelGGL(k_negk, dim3((unsigned)NGp, (unsigned)nw), dim3(256), 0, s, Cre, Cim, ldC, sC, NG, vsqrt);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_negk_from_full(const double* chi, int NG, double* Cre, double* Cim, int NGp, int nw,
+                                       const double* vsqrt, double* trk, hipStream_t s) {
+    const long long sC = (long long)NGp * NGp;
+    hipLaunchKernelGGL(k_trace_full, dim3((unsigned)nw), dim3(256), 0, s, chi, NG, vsqrt, trk);
+    hipLaunchKernelGGL(k_negk_full, dim3((unsigned)NGp, (unsigned)nw), dim3(256), 0, s, chi, NG, Cre, Cim, NGp, sC,
+                       vsqrt);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, double* Lre, double* Lim,
+                             double* logdet, int* fail, hipStream_t s) {
+    hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)nw), dim3(256), 0, s, Cre, Cim, ldC, (long long)ldC * ldC, j0, Lre,
+                       Lim, logdet, fail);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_trsm(const double* Cre, const double* Cim, int ldC, int j0, int NGp, int nw, const double* Lre,
+                            const double* Lim, double* Pre, double* Pim, hipStream_t s) {
+    const int rows = NGp - j0 - kTile;
+    if (rows <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rows + kTrsmRows - 1) / kTrsmRows), (unsigned)nw);
+    hipLaunchKernelGGL(k_chol_trsm, grid, dim3(256), 0, s, Cre, Cim, ldC, (long long)ldC * ldC, j0, NGp, Lre, Lim, Pre,
+                       Pim);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* logdet, const double* trk, const int* fail, const double* wgt, int nw,
+                           double* F, double* ec, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, logdet, trk, fail, wgt, nw, F, ec);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* d, int nd, int* iv, int ni, hipStream_t s) {
+    if (nd) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(256), 0, s, d, nd);
+    if (ni) hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(256), 0, s, iv, ni);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_chi_out, dim3((unsigned)NG, (unsigned)nw), dim3(256), 0, s, Cre, Cim, ldC,
+                       (long long)ldC * ldC, NG, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rho_out(const T* rre, const T* rim, int npairs, int NG, int NGp, double* out, hipStream_t s) {
+    if (!npairs) return hipSuccess;
+    hipLaunchKernelGGL(k_rho_out<T>, dim3((unsigned)((NG + 255) / 256), (unsigned)npairs), dim3(256), 0, s, rre, rim,
+                       NG, NGp, out);
+    return hipGetLastError();
+}
+
+#define RPA_INST(T)                                                                                                  \
+    template hipError_t launch_rho_out<T>(const T*, const T*, int, int, int, double*, hipStream_t);                  \
+    template hipError_t launch_paw_y<T>(const double*, int, const int32_t*, int, const int32_t*, const int32_t*, int, \
+                                        int, const double*, int, int, T*, T*, hipStream_t);                          \
+    template hipError_t launch_paw_add<T>(const T*, const T*, const int32_t*, int, const int32_t*, const double*,    \
+                                          int, int, int, int, int, T*, T*, hipStream_t);                              \
+    template hipError_t launch_optical_row<T>(const double*, const double*, int, const double*, const double*,       \
+                                              const double*, int, const double*, const int32_t*, const int32_t*,     \
+                                              int, const double*, const double*, const int32_t*, const int32_t*,     \
+                                              int, int, int, T*, T*, hipStream_t);
+RPA_INST(double)
+RPA_INST(float)
+#undef RPA_INST
+
+}  // namespace rpa

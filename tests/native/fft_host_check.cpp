@@ -1,0 +1,31 @@
+// Host-side check of the FFT building blocks of the HIP library: the same
+// header, compiled for the CPU, transforms lines that the test compares with
+// numpy's FFT.
+#include <cmath>
+#include <vector>
+#include "../../paper_1307_8052_amd/csrc/fft.hpp"
+
+using rpa::cplx;
+
+extern "C" int fft_lines_host(int N, int dir, int nlines, const double* in, double* out) {
+    rpa::FftPlan plan;
+    if (!rpa::make_plan(N, &plan)) return -1;
+    std::vector<cplx<double>> a(nlines * N), b(nlines * N), tw(N);
+    for (int t = 0; t < N; ++t) tw[t] = rpa::mk(std::cos(2 * M_PI * t / N), -std::sin(2 * M_PI * t / N));
+    for (int i = 0; i < nlines * N; ++i) a[i] = rpa::mk(in[2 * i], in[2 * i + 1]);
+    auto addr = [N](int l, int e) { return l * N + e; };
+    cplx<double>* src = a.data();
+    cplx<double>* dst = b.data();
+    int Ns = 1;
+    for (int s = 0; s < plan.nstages; ++s) {
+        int R = plan.radix[s];
+        if (dir < 0)
+            rpa::stockham_dispatch<-1>(R, src, dst, N, Ns, nlines, (s & 1) != 0, addr, tw.data(), 0, 1);
+        else
+            rpa::stockham_dispatch<+1>(R, src, dst, N, Ns, nlines, (s & 1) == 0, addr, tw.data(), 0, 1);
+        std::swap(src, dst);
+        Ns *= R;
+    }
+    for (int i = 0; i < nlines * N; ++i) { out[2 * i] = src[i].x; out[2 * i + 1] = src[i].y; }
+    return 0;
+}

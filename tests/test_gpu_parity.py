@@ -1,0 +1,171 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Sizes: tiny grids (direct checks, ragged sphere boxes, distinct k and k+q
+sets), the 16^3 configuration with 4 + 60 states, and reduced-band variants
+of the 48^3 configuration. Tolerances:
+  FP64 path   - pair densities and chi0 within 1e-12 of the largest element,
+                E_c within 1e-10 Ha;
+  split path  - pair densities (FP32 FFT) within 2e-6 relative, chi0 within
+                2e-4 of the largest element, E_c within 1e-6 Ha.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import gpu_inputs, oracle_q
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rpa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1307_8052_amd as m
+    return m
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+WORKLOADS = {
+    "tiny8": lambda: synth.tiny(grid=(8, 8, 8)),
+    "tiny6x8x10": lambda: synth.tiny(grid=(6, 8, 10), L=(6.0, 7.0, 9.0), target_ng=9),
+    "tiny12_distinct_kq": lambda: synth.tiny(grid=(12, 12, 12), L=(8.0, 8.5, 9.0), n_occ=3, n_unocc=7,
+                                             target_ng=40, extra_kq=True),
+    "tiny10_optical": lambda: synth.tiny(grid=(10, 10, 10), n_occ=2, n_unocc=4, optical=True, target_ng=12),
+    "cfg0": lambda: synth.config0(),
+}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_pair_density(rpa, name, prec):
+    wl = WORKLOADS[name]()
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    s, t = wl.kpoints[0], wl.kq_sets()[0]
+    ref_g = oracle.gsphere(wl.A, wl.qpoints[0].q, wl.qpoints[0].ecut)
+    assert np.array_equal(gm, ref_g)
+    pairs = oracle.pair_list(s.f, t.f)
+    Q = synth.paw_q_table(wl.paw, wl.A, wl.qpoints[0].q, ref_g)
+    _, rho_ref = oracle.pair_densities(wl.A, wl.grid, s, t, ref_g, Q, wl.paw.offsets, wl.qpoints[0].optical,
+                                       wl.qpoints[0].qhat, synth.paw_d_table(wl.paw))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        rho = ctx.pair_density(ks[0], kqs[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    print(f"{name} {prec}: pairs={pairs[0].size} NG={len(gm)} rel={_rel(rho, rho_ref):.3e}", flush=True)
+    assert _rel(rho, rho_ref) < tol
+
+
+def test_pair_density_unsorted_pairs_and_diagonal(rpa):
+    """Arbitrary pair order (including n = m) and the G = 0 normalisation of the pseudo part."""
+    wl = synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=5, q_frac=(0.0, 0.0, 0.0), nproj=(1,), target_ng=7)
+    wl.qpoints[0].q = np.zeros(3)
+    s = wl.kpoints[0]
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    qs.Qpaw = qs.Qpaw * 0
+    pn = np.array([3, 0, 6, 2, 2, 5], dtype=np.int32)
+    pm = np.array([1, 0, 6, 4, 2, 1], dtype=np.int32)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        rho = ctx.pair_density(ks[0], ks[0], qs, pn, pm).cpu().numpy()
+    phi = oracle.orbitals(s.C, s.miller, wl.grid)
+    ref = oracle.pseudo_pair_density(phi, phi, (pn.astype(np.int64), pm.astype(np.int64)), gm, wl.grid)
+    assert _rel(rho, ref) < 1e-12
+    g0 = int(np.nonzero(np.all(gm == 0, axis=1))[0][0])
+    assert np.allclose(rho[:, g0], (pn == pm).astype(float), atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["tiny8", "tiny12_distinct_kq", "tiny10_optical", "cfg0"])
+def test_chi0_and_ec_fp64(rpa, name):
+    wl = WORKLOADS[name]()
+    ref = oracle_q(wl)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        chi = ctx.chi0(ks, kqs, qs, fr, "fp64").cpu().numpy()
+        ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
+        ctx.check()
+        ec = float(ec.cpu()[0])
+        F = F.cpu().numpy()
+    r = _rel(chi, ref["chi"])
+    print(f"{name}: NG={len(gm)} chi rel={r:.3e} E={ec:.12f} ref={ref['E']:.12f} dE={ec - ref['E']:.3e}", flush=True)
+    assert r < 1e-12
+    assert np.max(np.abs(F - ref["F"])) < 1e-10
+    assert abs(ec - ref["E"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_chi0_and_ec_split(rpa, prec):
+    wl = synth.config0()
+    ref = oracle_q(wl)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
+        ec, F = ctx.ec(ks, kqs, qs, fr, prec)
+        ctx.check()
+        ec = float(ec.cpu()[0])
+    r = _rel(chi, ref["chi"])
+    print(f"cfg0 {prec}: chi rel={r:.3e} E={ec:.10f} ref={ref['E']:.10f} dE={ec - ref['E']:.3e}", flush=True)
+    assert r < 2e-4
+    assert abs(ec - ref["E"]) < 1e-6
+
+
+def test_ec_from_oracle_chi0(rpa):
+    wl = synth.config0(n_occ=2, n_unocc=20)
+    ref = oracle_q(wl)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, F = ctx.ec_from_chi0(qs, fr, torch.from_numpy(ref["chi"]))
+        ctx.check()
+    assert abs(float(ec.cpu()[0]) - ref["E"]) < 1e-12
+    assert np.max(np.abs(F.cpu().numpy() - ref["F"])) < 1e-12
+
+
+def test_not_positive_definite_is_reported(rpa):
+    """A chi0 with one positive weight large enough to make 1 - K indefinite."""
+    wl = synth.config0(n_occ=1, n_unocc=3)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    NG = len(gm)
+    chi = np.zeros((wl.omega.size, NG, NG), dtype=np.complex128)
+    v = np.zeros(NG, dtype=np.complex128)
+    v[3] = 1.0
+    chi[2] = 50.0 * np.outer(v, v)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.ec_from_chi0(qs, fr, torch.from_numpy(chi))
+        with pytest.raises(rpa.RpaError) as ei:
+            ctx.check()
+    assert ei.value.status == -5 and "frequency index 2" in str(ei.value)
+
+
+def test_alias_and_shape_errors_before_launch(rpa):
+    wl = synth.config0(n_occ=1, n_unocc=3)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, (12, 12, 12)) as ctx:
+        with pytest.raises(rpa.RpaError) as ei:
+            ctx.ec(ks, kqs, qs, fr)
+        assert ei.value.status in (-3,)
+    bad = rpa.States(wl.kpoints[0].C, wl.kpoints[0].miller, wl.kpoints[0].eps[::-1].copy(), wl.kpoints[0].f,
+                     wl.kpoints[0].P, wl.paw.offsets)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        with pytest.raises(rpa.RpaError) as ei:
+            ctx.ec([bad], [bad], qs, fr)
+        assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("iq", [0, 1])
+def test_o2box_reduced_bands(rpa, iq):
+    """48^3 grid, ~1500 G-vectors, optical and finite q, with 4 occupied + 40 unoccupied states."""
+    wl = synth.config1(n_occ=4, n_unocc=40, which_q=(0, 1))
+    ref = oracle_q(wl, iq)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl, iq)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
+        ec2, F2 = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        ctx.check()
+        ec, ec2 = float(ec.cpu()[0]), float(ec2.cpu()[0])
+    print(f"o2box q{iq}: NG={len(gm)} E64={ec:.12f} Esplit={ec2:.12f} ref={ref['E']:.12f}", flush=True)
+    assert abs(ec - ref["E"]) < 1e-10
+    assert abs(ec2 - ref["E"]) < 1e-6
