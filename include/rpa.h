@@ -164,6 +164,34 @@ int rpa_ec_from_chi0(rpa_ctx* ctx, const rpa_qspec* qs, const rpa_freq* fr, cons
 int rpa_ec(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
            const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, void* stream);
 
+/* E_c(q) for nq q-points that share the same (k, k+q) state-set pairs (as with
+ * Gamma-only sampling) - Eq. rpa_c's q sum. Orbitals are built once; each q
+ * has its own G-sphere, PAW table and chi0. Outputs: ec_dev DEVICE double
+ * [nq + 1] holds E_c(q_j) and, at index nq, sum_j w_qj E_c(q_j); F_dev DEVICE
+ * double [nq][nw] or NULL.
+ * use_graph = 1: the whole launch sequence is captured once into a hipGraph
+ * (with buffers owned by that graph) and replayed by later calls whose host
+ * inputs (sizes, Miller lists, eigenvalues, occupations, frequencies, q, PAW
+ * nabla table) and device pointers are unchanged; device array contents may
+ * change between replays. Replays must use the same stream; a call with other
+ * inputs re-captures. */
+int rpa_ec_batched(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs,
+                   const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
+                   void* stream);
+
+/* Rank-k kernel choice of the split precisions per padded sphere size
+ * (NG rounded up to 64): variant 1 = 64x64 tiles staged from FP32 rho,
+ * variant 2 = 128x128 tiles from the K-blocked pre-split rho. Without an
+ * entry, NG >= 385 uses variant 2.
+ *  rpa_autotune     times both variants on synthetic operands of the given
+ *                   shape on `stream` (synchronizes) and records the faster.
+ *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only).
+ *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */
+int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, void* stream);
+int rpa_tune_set(rpa_ctx* ctx, rpa_precision prec, int NG, int variant);
+int rpa_tune_get(rpa_ctx* ctx, rpa_precision prec, int NG, int* variant);
+int rpa_tune_cache_io(rpa_ctx* ctx, const char* path, int save);
+
 /* Synchronize `stream` and report device-side failures of earlier calls on
  * this context (RPA_ERR_NOT_PD with the frequency index in rpa_last_error). */
 int rpa_check(rpa_ctx* ctx, void* stream);

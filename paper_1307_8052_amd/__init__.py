@@ -255,6 +255,42 @@ class Context:
                               ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()), _stream()), self._h)
         return ec, F
 
+    def ec_batched(self, ks: Sequence[States], kqs: Sequence[States], qspecs: Sequence[QSpec], freq: Freq,
+                   precision="fp64", use_graph: bool = False, out=None):
+        """E_c(q) for every q of qspecs sharing the same state sets; returns (ec [nq + 1], F [nq, nw]) on the
+        device, ec[nq] = sum_q w_q E_c(q). With use_graph the launch sequence is captured once and replayed
+        while the inputs (host values and device pointers) stay the same; pass the same `out` tensors to replay."""
+        torch = _torch()
+        nq = len(qspecs)
+        if out is None:
+            out = (torch.empty(nq + 1, dtype=torch.float64, device=self.device),
+                   torch.empty((nq, freq.nw), dtype=torch.float64, device=self.device))
+        ec, F = out
+        a, b, fr = self._arrays(ks), self._arrays(kqs), freq.struct()
+        qarr = (RpaQSpec * nq)()
+        for i, q in enumerate(qspecs):
+            qarr[i] = q.struct()
+        _check(self._L.rpa_ec_batched(self._h, a, b, len(ks), nq, qarr, ctypes.byref(fr), _prec(precision),
+                                      ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()),
+                                      int(bool(use_graph)), _stream()), self._h)
+        return ec, F
+
+    def autotune(self, NG: int, npairs: int, nw: int = 16, precision="split_bf16") -> int:
+        """Time the split rank-k kernel variants for this shape; returns the recorded variant."""
+        _check(self._L.rpa_autotune(self._h, _prec(precision), int(NG), int(npairs), int(nw), _stream()), self._h)
+        return self.tune_get(NG, precision)
+
+    def tune_set(self, NG: int, variant: int, precision="split_bf16"):
+        _check(self._L.rpa_tune_set(self._h, _prec(precision), int(NG), int(variant)), self._h)
+
+    def tune_get(self, NG: int, precision="split_bf16") -> int:
+        v = ctypes.c_int(0)
+        _check(self._L.rpa_tune_get(self._h, _prec(precision), int(NG), ctypes.byref(v)), self._h)
+        return v.value
+
+    def tune_cache(self, path: str, save: bool):
+        _check(self._L.rpa_tune_cache_io(self._h, path.encode(), int(bool(save))), self._h)
+
     def ec_from_chi0(self, qs: QSpec, freq: Freq, chi0):
         torch = _torch()
         chi0 = chi0.to(device=self.device, dtype=torch.complex128).contiguous()

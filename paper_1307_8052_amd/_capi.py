@@ -76,6 +76,13 @@ SIGNATURES = {
                                  c_void_p, c_void_p, c_void_p]),
     "rpa_ec": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
                        ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p, c_void_p]),
+    "rpa_ec_batched": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int, c_int,
+                               ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p, c_int,
+                               c_void_p]),
+    "rpa_autotune": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
+    "rpa_tune_set": (c_int, [c_void_p, c_int, c_int, c_int]),
+    "rpa_tune_get": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int)]),
+    "rpa_tune_cache_io": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "rpa_check": (c_int, [c_void_p, c_void_p]),
     "rpa_profile": (c_int, [c_void_p, c_int]),
     "rpa_profile_get": (c_int, [c_void_p, ctypes.c_char_p, ctypes.POINTER(c_double),

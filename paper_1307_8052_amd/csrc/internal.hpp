@@ -87,9 +87,25 @@ struct HerkSplitArgs {
     double* Cre; double* Cim; long long sC; int ldC;
     int nT; int nw;
     int fp16;            // 0 = BF16, 1 = FP16 (scaled)
-    const float* wscale; // per-frequency power-of-two scale for FP16 (nullptr for BF16)
+    const float* wscale; // FP16: [nw] scales of X_w and [nw] the scale of rho (nullptr for BF16)
 };
 hipError_t launch_herk_split(const HerkSplitArgs& h, hipStream_t s);
+// FP16 operand scales from the chunk's rho (n = K * ld elements per part) and weights; `part`
+// holds 256 floats of scratch.
+hipError_t launch_split_scales(const float* rre, const float* rim, size_t n, const double* a, int lda, int K, int nw,
+                               float* scales, float* part, hipStream_t s);
+
+// Large-tile split update: operands pre-packed K-blocked ([K/32][NGq][32]) by
+// launch_pack_split; NGq = NGp rounded up to 128; 128x128 lower tiles.
+struct HerkSplit2Args {
+    const float* Xre; const float* Xim; const unsigned short* B[4]; int NGq; int K;
+    const double* w; int lda;
+    double* Cre; double* Cim; long long sC; int ldC;
+    int ntiles; int nw; int fp16; const float* scales;
+};
+hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
+                             int fp16, float* Xre, float* Xim, unsigned short* const B[4], hipStream_t s);
+hipError_t launch_herk_split2(const HerkSplit2Args& h, hipStream_t s);
 
 // -K = -v_i v_j chi_ij on the lower triangle (in place, planar), zero padding,
 // and Tr K per frequency.
@@ -106,6 +122,10 @@ hipError_t launch_finalize(const double* logdet, const double* trk, const int* f
                            double* F, double* ec, hipStream_t s);
 
 hipError_t launch_zero(double* d, int nd, int* iv, int ni, hipStream_t s);
+// out[0] = sum_j w[j] x[j]
+hipError_t launch_weighted_sum(const double* x, const double* w, int n, double* out, hipStream_t s);
+// deterministic pseudo-random fill in [-1, 1) (tuning inputs)
+hipError_t launch_fill_pattern(float* f, size_t nf, double* d, size_t nd, hipStream_t s);
 
 // planar (re, im) [npairs][NGp] of type T -> interleaved complex128 [npairs][NG]
 template <typename T>

@@ -1,0 +1,289 @@
+// Split-precision grouped rank-k update of chi0 (Eq. zher_multi), large-tile
+// form.
+//
+// Per pair chunk, k_pack_split rewrites rho once into two K-blocked copies,
+// [K/32][NGq][32] with the 32 pairs of a block contiguous per G:
+//   X  FP32 (re, im), the operand that each frequency scales by a(w);
+//   B  16-bit hi/lo (re_hi, re_lo, im_hi, im_lo) of rho, split once.
+// k_herk_split2 then computes one 128x128 lower tile of chi0(w) per
+// workgroup (four waves, 64x64 each as 4x4 blocks of 16x16): every K-step it
+// loads 32 pairs of X, multiplies by a(w), splits into hi/lo in registers and
+// stages both operands in LDS, and issues 12 v_mfma_f32_16x16x32 per block
+// (Re = Xr Br^T + Xi Bi^T, Im = Xi Br^T - Xr Bi^T, three split products each).
+// The next K-step's global loads are in flight while the MFMAs run.
+//
+// Workgroups are numbered so that the nw frequencies of one tile go to the
+// same XCD (consecutive workgroup ids are dealt round-robin to the 8 XCDs),
+// so the operand rows of a tile are fetched into one L2 and reused nw times.
+#include "internal.hpp"
+
+namespace rpa {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+typedef u16 v8u16 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 128;       // workgroup tile edge
+constexpr int KS = 32;        // pairs per K-step (MFMA K)
+constexpr int LDR = 40;       // LDS row stride in 16-bit elements (80 bytes)
+constexpr int kXcds = 8;
+
+template <bool F16> struct H;
+template <> struct H<false> {
+    typedef v8bf v8;
+    static __device__ __forceinline__ u16 bits(float x) {
+        __bf16 h = (__bf16)x;
+        return __builtin_bit_cast(u16, h);
+    }
+    static __device__ __forceinline__ float back(u16 b) { return (float)__builtin_bit_cast(__bf16, b); }
+    static __device__ __forceinline__ v4f mfma(v8 a, v8 b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct H<true> {
+    typedef v8h v8;
+    static __device__ __forceinline__ u16 bits(float x) {
+        _Float16 h = (_Float16)x;
+        return __builtin_bit_cast(u16, h);
+    }
+    static __device__ __forceinline__ float back(u16 b) { return (float)__builtin_bit_cast(_Float16, b); }
+    static __device__ __forceinline__ v4f mfma(v8 a, v8 b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <bool F16>
+__device__ __forceinline__ void split(float x, u16& hi, u16& lo) {
+    hi = H<F16>::bits(x);
+    lo = H<F16>::bits(x - H<F16>::back(hi));
+}
+
+// rho planar [K][ldr] -> X blocked FP32 and B blocked 16-bit hi/lo; one
+// workgroup per (64 G, 32 pairs); entries past K or past ldr are zero.
+template <bool F16>
+__global__ __launch_bounds__(256) void k_pack_split(const float* __restrict__ rre, const float* __restrict__ rim,
+                                                     int K, int ldr, int NGq, const float* __restrict__ scales,
+                                                     int nw, float* __restrict__ Xre, float* __restrict__ Xim,
+                                                     u16* __restrict__ B0, u16* __restrict__ B1,
+                                                     u16* __restrict__ B2, u16* __restrict__ B3) {
+    __shared__ float tr[KS][65], ti[KS][65];
+    const int g0 = blockIdx.x * 64, kb = blockIdx.y, k0 = kb * KS;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < KS * 64; e += 256) {
+        const int kk = e >> 6, c = e & 63, k = k0 + kk, g = g0 + c;
+        float vr = 0.f, vi = 0.f;
+        if (k < K && g < ldr) {
+            vr = rre[(size_t)k * ldr + g];
+            vi = rim[(size_t)k * ldr + g];
+        }
+        tr[kk][c] = vr;
+        ti[kk][c] = vi;
+    }
+    __syncthreads();
+    const float sb = (F16 && scales) ? scales[nw] : 1.0f;
+    const int c = tid >> 2, kq = (tid & 3) * 8;
+    const size_t o = ((size_t)kb * NGq + g0 + c) * KS + kq;
+    v8u16 hr, lr, hi_, li;
+    float xr[8], xi[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        xr[e] = tr[kq + e][c];
+        xi[e] = ti[kq + e][c];
+        u16 a, b;
+        split<F16>(xr[e] * sb, a, b);
+        hr[e] = a;
+        lr[e] = b;
+        split<F16>(xi[e] * sb, a, b);
+        hi_[e] = a;
+        li[e] = b;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        Xre[o + e] = xr[e];
+        Xim[o + e] = xi[e];
+    }
+    *reinterpret_cast<v8u16*>(B0 + o) = hr;
+    *reinterpret_cast<v8u16*>(B1 + o) = lr;
+    *reinterpret_cast<v8u16*>(B2 + o) = hi_;
+    *reinterpret_cast<v8u16*>(B3 + o) = li;
+}
+
+__device__ __forceinline__ void tile_of(int t, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+template <bool F16>
+__global__ __launch_bounds__(256, 1) void k_herk_split2(HerkSplit2Args h) {
+    typedef typename H<F16>::v8 hv;
+    __shared__ __align__(16) u16 sA[4][TM][LDR];
+    __shared__ __align__(16) u16 sB[4][TM][LDR];
+
+    // XCD-aware numbering: ids b, b+8, b+16, ... run on one XCD
+    const int b = blockIdx.x;
+    const int xcd = b % kXcds, local = b / kXcds;
+    const int tile = (local / h.nw) * kXcds + xcd;
+    const int w = local % h.nw;
+    if (tile >= h.ntiles) return;
+    int I, J;
+    tile_of(tile, I, J);
+    const int ci = I * TM, cj = J * TM;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const double* aw = h.w + (size_t)w * h.lda;
+    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
+    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
+
+    // staging assignment: thread -> (row r, 16 consecutive pairs)
+    const int sr = tid >> 1, sk = (tid & 1) * 16;
+    float pxr[16], pxi[16];
+    v8u16 pb[4][2];
+    auto fetch = [&](int kb) {
+        const size_t oa = ((size_t)kb * h.NGq + ci + sr) * KS + sk;
+        const size_t ob = ((size_t)kb * h.NGq + cj + sr) * KS + sk;
+#pragma unroll
+        for (int e = 0; e < 16; e += 4) {
+            const v4f a = *reinterpret_cast<const v4f*>(h.Xre + oa + e);
+            const v4f c = *reinterpret_cast<const v4f*>(h.Xim + oa + e);
+            pxr[e] = a[0]; pxr[e + 1] = a[1]; pxr[e + 2] = a[2]; pxr[e + 3] = a[3];
+            pxi[e] = c[0]; pxi[e + 1] = c[1]; pxi[e + 2] = c[2]; pxi[e + 3] = c[3];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pb[q][0] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
+            pb[q][1] = *reinterpret_cast<const v8u16*>(h.B[q] + ob + 8);
+        }
+    };
+
+    v4f accR[4][4], accI[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            accR[x][y] = v4f{0, 0, 0, 0};
+            accI[x][y] = v4f{0, 0, 0, 0};
+        }
+
+    const int nkb = (h.K + KS - 1) / KS;
+    fetch(0);
+    for (int kb = 0; kb < nkb; ++kb) {
+        __syncthreads();
+        {
+            // X_w = rho a(w) sa, split into hi/lo
+            v8u16 xrh[2], xrl[2], xih[2], xil[2];
+            const int kbase = kb * KS + sk;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int k = kbase + e;
+                const float wk = k < h.K ? (float)aw[k] * sa : 0.f;
+                u16 a, c;
+                split<F16>(pxr[e] * wk, a, c);
+                xrh[e >> 3][e & 7] = a;
+                xrl[e >> 3][e & 7] = c;
+                split<F16>(pxi[e] * wk, a, c);
+                xih[e >> 3][e & 7] = a;
+                xil[e >> 3][e & 7] = c;
+            }
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                *reinterpret_cast<v8u16*>(&sA[0][sr][sk + 8 * hf]) = xrh[hf];
+                *reinterpret_cast<v8u16*>(&sA[1][sr][sk + 8 * hf]) = xrl[hf];
+                *reinterpret_cast<v8u16*>(&sA[2][sr][sk + 8 * hf]) = xih[hf];
+                *reinterpret_cast<v8u16*>(&sA[3][sr][sk + 8 * hf]) = xil[hf];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[q][sr][sk + 8 * hf]) = pb[q][hf];
+            }
+        }
+        __syncthreads();
+        if (kb + 1 < nkb) fetch(kb + 1);
+
+        const int rr = lane & 15, kq = 8 * (lane >> 4);
+        hv bf[4][4], bn[4][2];  // [col block][re_hi, re_lo, im_hi, im_lo], -im
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bf[y][q] = *reinterpret_cast<const hv*>(&sB[q][wc + 16 * y + rr][kq]);
+            bn[y][0] = -bf[y][2];
+            bn[y][1] = -bf[y][3];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            hv af[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) af[q] = *reinterpret_cast<const hv*>(&sA[q][wr + 16 * x + rr][kq]);
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                v4f r = accR[x][y], im = accI[x][y];
+                // small terms first, then the hi*hi products
+                r = H<F16>::mfma(af[1], bf[y][0], r);
+                r = H<F16>::mfma(af[0], bf[y][1], r);
+                r = H<F16>::mfma(af[3], bf[y][2], r);
+                r = H<F16>::mfma(af[2], bf[y][3], r);
+                r = H<F16>::mfma(af[0], bf[y][0], r);
+                r = H<F16>::mfma(af[2], bf[y][2], r);
+                im = H<F16>::mfma(af[3], bf[y][0], im);
+                im = H<F16>::mfma(af[2], bf[y][1], im);
+                im = H<F16>::mfma(af[1], bn[y][0], im);
+                im = H<F16>::mfma(af[0], bn[y][1], im);
+                im = H<F16>::mfma(af[2], bf[y][0], im);
+                im = H<F16>::mfma(af[0], bn[y][0], im);
+                accR[x][y] = r;
+                accI[x][y] = im;
+            }
+        }
+    }
+
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    double* Cre = h.Cre + (size_t)w * h.sC;
+    double* Cim = h.Cim + (size_t)w * h.sC;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                if (row < h.ldC && col < h.ldC) {
+                    const size_t o = (size_t)row * h.ldC + col;
+                    Cre[o] += (double)accR[x][y][r] * inv;
+                    Cim[o] += (double)accI[x][y][r] * inv;
+                }
+            }
+}
+
+}  // namespace
+
+hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
+                             int fp16, float* Xre, float* Xim, u16* const B[4], hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    dim3 grid((unsigned)(NGq / 64), (unsigned)((K + KS - 1) / KS));
+    if (fp16)
+        hipLaunchKernelGGL(k_pack_split<true>, grid, dim3(256), 0, s, rre, rim, K, ldr, NGq, scales, nw, Xre, Xim, B[0],
+                           B[1], B[2], B[3]);
+    else
+        hipLaunchKernelGGL(k_pack_split<false>, grid, dim3(256), 0, s, rre, rim, K, ldr, NGq, scales, nw, Xre, Xim,
+                           B[0], B[1], B[2], B[3]);
+    return hipGetLastError();
+}
+
+hipError_t launch_herk_split2(const HerkSplit2Args& h, hipStream_t s) {
+    if (h.ntiles <= 0 || h.nw <= 0 || h.K <= 0) return hipSuccess;
+    const int per_xcd = (h.ntiles + kXcds - 1) / kXcds;
+    const unsigned blocks = (unsigned)(per_xcd * h.nw * kXcds);
+    if (h.fp16)
+        hipLaunchKernelGGL(k_herk_split2<true>, dim3(blocks), dim3(256), 0, s, h);
+    else
+        hipLaunchKernelGGL(k_herk_split2<false>, dim3(blocks), dim3(256), 0, s, h);
+    return hipGetLastError();
+}
+
+}  // namespace rpa

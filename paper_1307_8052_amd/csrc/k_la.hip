@@ -308,6 +308,29 @@ __global__ void k_negk_full(const double* __restrict__ chi, int NG, double* __re
     }
 }
 
+__global__ void k_weighted_sum(const double* __restrict__ x, const double* __restrict__ w, int n,
+                               double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += w[j] * x[j];
+    *out = s;
+}
+
+__device__ __forceinline__ float hash_unit(unsigned long long i) {
+    unsigned long long z = i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (float)((z >> 40) * (1.0 / 16777216.0)) * 2.0f - 1.0f;
+}
+
+__global__ void k_fill_pattern(float* __restrict__ f, size_t nf, double* __restrict__ d, size_t nd) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += (size_t)gridDim.x * blockDim.x)
+        f[i] = hash_unit(i);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (size_t)gridDim.x * blockDim.x)
+        d[i] = -1e-3 * (1.5 + hash_unit(i + nf));
+}
+
 __global__ void k_zero_d(double* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
 }
@@ -576,6 +599,16 @@ hipError_t launch_finalize(const double* logdet, const double* trk, const int* f
 hipError_t launch_zero(double* d, int nd, int* iv, int ni, hipStream_t s) {
     if (nd) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(256), 0, s, d, nd);
     if (ni) hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(256), 0, s, iv, ni);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum(const double* x, const double* w, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_weighted_sum, dim3(1), dim3(64), 0, s, x, w, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(float* f, size_t nf, double* d, size_t nd, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_pattern, dim3(1024), dim3(256), 0, s, f, nf, d, nd);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -68,6 +69,15 @@ struct rpa_ctx {
     std::vector<hipEvent_t> pool;
     double prof_ms[16] = {0};
     long long prof_n[16] = {0};
+    int last_nq = 0;
+    // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 2 = 128x128 tiles
+    std::map<uint64_t, int> tune;
+    std::map<uint64_t, double> tune_ms;
+    // the captured batch graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+    bool capturing = false;
 };
 
 namespace {
@@ -94,7 +104,7 @@ struct ProfScope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     ProfScope(rpa_ctx* c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
-        if (c->prof && (a = prof_event(c))) (void)hipEventRecord(a, s);
+        if (c->prof && !c->capturing && (a = prof_event(c))) (void)hipEventRecord(a, s);
     }
     ~ProfScope() {
         if (!a) return;
@@ -117,6 +127,29 @@ void prof_collect(rpa_ctx* c) {
     }
     c->recs.clear();
 }
+
+// ---------------------------------------------------------------- tuning / graphs
+uint64_t tune_key(rpa_precision p, int NGp) { return ((uint64_t)(uint32_t)p << 32) | (uint32_t)NGp; }
+
+void drop_graph(rpa_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_key = 0;
+}
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void bytes(const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    }
+    template <typename V> void val(const V& v) { bytes(&v, sizeof(v)); }
+};
 
 // ---------------------------------------------------------------- buffers
 int get_buf(rpa_ctx* c, const char* name, size_t bytes, hipStream_t s, void** out) {
@@ -165,7 +198,7 @@ struct Upload {
     }
 };
 
-int do_upload(rpa_ctx* c, Upload& u, hipStream_t s) {
+int do_upload(rpa_ctx* c, Upload& u, hipStream_t s, const char* bufname) {
     if (u.total == 0) return RPA_OK;
     if (c->staged_valid) HIP_TRY(hipEventSynchronize(c->staged));
     if (c->pinned_bytes < u.total) {
@@ -176,7 +209,7 @@ int do_upload(rpa_ctx* c, Upload& u, hipStream_t s) {
         c->pinned_bytes = u.total;
     }
     void* dev = nullptr;
-    int rc = get_buf(c, "tables", u.total, s, &dev);
+    int rc = get_buf(c, bufname, u.total, s, &dev);
     if (rc) return rc;
     for (auto& it : u.items) {
         if (it.bytes) std::memcpy(static_cast<char*>(c->pinned) + it.off, it.src, it.bytes);
@@ -424,102 +457,132 @@ std::vector<cplx<T>> twiddles(int N) {
 }
 
 // ------------------------------------------------------------ the engine
-struct Engine {
-    rpa_ctx* c;
-    hipStream_t s;
-    rpa_precision prec;
-    const rpa_qspec* qs;
-    QPlan qp;
-    int nw = 0;
-
-    // device table pointers
-    void* d_kx = nullptr; void* d_ky = nullptr; void* d_cs = nullptr; void* d_cg = nullptr; void* d_ckz = nullptr;
-    void* d_vs = nullptr; void* d_om = nullptr; void* d_ow = nullptr;
-    void* d_tw[3] = {nullptr, nullptr, nullptr};
-    void* d_qoff = nullptr; void* d_poff = nullptr;
-
-    // host tables kept alive until upload
-    std::vector<int32_t> qoff, poff;
-    std::vector<double> om, ow;
-    std::vector<cplx<double>> tw64[3];
-    std::vector<cplx<float>> tw32[3];
-
-    bool fp64() const { return prec == RPA_FP64; }
-};
-
+// One call = one Batch: tables shared by every q (frequencies, twiddles, PAW
+// offsets), one KSet per (k, k+q) state-set pair (pair list, index maps,
+// eigenvalues) and one QJob per q-point (sphere tables, Coulomb, chi0
+// accumulator, rank-k kernel variant). Planning and uploads happen first; the
+// kernel sequence afterwards touches only pre-sized buffers, so it can be
+// captured into a graph.
 struct KSet {
     const rpa_states* k;
     const rpa_states* kq;
     std::vector<int32_t> pn, pm;
     std::vector<int32_t> mapk, mapkq;
     std::vector<double> epsk, epskq, fk, fkq;
-    std::vector<double> wq, Dq;
+    std::vector<int32_t> nlist_all;  // n = 0 .. nbands-1
     void* d_pn = nullptr; void* d_pm = nullptr;
     void* d_mapk = nullptr; void* d_mapkq = nullptr;
     void* d_epsk = nullptr; void* d_epskq = nullptr; void* d_fk = nullptr; void* d_fkq = nullptr;
-    void* d_wq = nullptr; void* d_Dq = nullptr;
-    std::vector<int32_t> nlist_all;  // n = 0 .. nbands-1
     void* d_nlist = nullptr;
 };
 
-int chunk_size(const Engine& E, size_t elem) {
-    const PairGeom& g = E.qp.g;
-    const size_t per = (size_t)g.N3 * g.ncols * 2 * elem + 2 * (size_t)g.NGp * elem + (size_t)E.nw * 8;
+struct QJob {
+    const rpa_qspec* qs = nullptr;
+    QPlan qp;
+    void* d_kx = nullptr; void* d_ky = nullptr; void* d_cs = nullptr; void* d_cg = nullptr; void* d_ckz = nullptr;
+    void* d_vs = nullptr;
+    // optical limit: plane-wave momentum weights per k set and qhat.D
+    std::vector<std::vector<double>> wq;
+    std::vector<void*> d_wq;
+    std::vector<double> Dq;
+    void* d_Dq = nullptr;
+    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64 tiles, 2 split 128x128 tiles
+    int Pc = 0;        // pair chunk
+    size_t chi_off = 0;
+    double* cr = nullptr;
+    double* ci = nullptr;
+    double* ec = nullptr;
+    double* F = nullptr;
+};
+
+struct Batch {
+    rpa_ctx* c = nullptr;
+    hipStream_t s = nullptr;
+    rpa_precision prec = RPA_FP64;
+    int nw = 0;
+    std::vector<double> om, ow;
+    std::vector<int32_t> qoff, poff;
+    std::vector<cplx<double>> tw64[3];
+    std::vector<cplx<float>> tw32[3];
+    void* d_om = nullptr; void* d_ow = nullptr; void* d_tw[3] = {nullptr, nullptr, nullptr};
+    void* d_qoff = nullptr; void* d_poff = nullptr;
+    void* d_wq = nullptr;            // q weights (batched calls)
+    std::string prefix;              // buffer-name prefix (graph-owned and tuning buffers)
+    std::vector<KSet> ks;
+    std::vector<QJob> qj;
+    bool fp64() const { return prec == RPA_FP64; }
+    size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
+};
+
+int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
+    if (prec == RPA_FP64) return 0;
+    auto it = c->tune.find(tune_key(prec, NGp));
+    if (it != c->tune.end()) return it->second;
+    return ((NGp + 127) / 128 >= 4) ? 2 : 1;
+}
+
+int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
+    const PairGeom& g = qp.g;
+    const size_t per = (size_t)g.N3 * g.ncols * 2 * elem + 2 * (size_t)g.NGp * elem + (size_t)nw * 8 +
+                       (size_t)(g.NGp + 127) / 128 * 128 * 16;
     size_t budget = (size_t)6 << 30;
-    if (E.c->cap) budget = std::min(budget, E.c->cap / 3);
+    if (c->cap) budget = std::min(budget, c->cap / 4);
     size_t pc = budget / per;
     pc = std::max<size_t>(pc, 64);
     pc = std::min<size_t>(pc, 1 << 20);
     return (int)pc;
 }
 
-template <typename T>
-int run_orbitals(Engine& E, const rpa_states* s, void* d_map, const char* name, cplx<T>** out) {
-    rpa_ctx* c = E.c;
-    const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
-    void* p = nullptr;
-    int rc = get_buf(c, name, (size_t)s->nbands * vol * sizeof(cplx<T>), E.s, &p);
-    if (rc) return rc;
-    cplx<T>* phi = static_cast<cplx<T>*>(p);
-    ProfScope ps_(c, S_ORB, E.s);
-    HIP_TRY(launch_fill_zero<T>(phi, (size_t)s->nbands * vol, E.s));
-    HIP_TRY(launch_orb_scatter<T>(static_cast<const double*>(s->C), s->nbands, s->nQ,
-                                  static_cast<const int32_t*>(d_map), vol, phi, E.s));
-    for (int ax = 0; ax < 3; ++ax)
-        HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
-                                   static_cast<const cplx<T>*>(E.d_tw[ax]), +1, E.s));
-    *out = phi;
-    return RPA_OK;
-}
-
-int prepare_common(Engine& E, Upload& up) {
-    rpa_ctx* c = E.c;
-    const QPlan& q = E.qp;
-    up.add(q.kx, &E.d_kx);
-    up.add(q.ky, &E.d_ky);
-    up.add(q.col_start, &E.d_cs);
-    up.add(q.col_g, &E.d_cg);
-    up.add(q.col_kz, &E.d_ckz);
-    up.add(q.vsqrt, &E.d_vs);
-    up.add(E.om, &E.d_om);
-    up.add(E.ow, &E.d_ow);
-    for (int ax = 0; ax < 3; ++ax) {
-        if (E.fp64()) {
-            E.tw64[ax] = twiddles<double>(c->N[ax]);
-            up.add(E.tw64[ax], &E.d_tw[ax]);
-        } else {
-            E.tw32[ax] = twiddles<float>(c->N[ax]);
-            up.add(E.tw32[ax], &E.d_tw[ax]);
-        }
+int begin(Batch& B, rpa_ctx* c, const rpa_freq* fr, rpa_precision prec, void* stream) {
+    B.c = c;
+    B.s = static_cast<hipStream_t>(stream);
+    B.prec = prec;
+    if (prec != RPA_FP64 && prec != RPA_SPLIT_BF16 && prec != RPA_SPLIT_FP16)
+        return fail(RPA_ERR_INPUT, "unknown precision");
+    HIP_TRY(hipSetDevice(c->device));
+    if (fr) {
+        int rc = check_freq(fr);
+        if (rc) return rc;
+        B.nw = fr->nw;
+        B.om.assign(fr->omega, fr->omega + fr->nw);
+        B.ow.assign(fr->weight, fr->weight + fr->nw);
     }
     return RPA_OK;
 }
 
-int prepare_kset(Engine& E, KSet& K, Upload& up, bool need_pairs_from_f, const int32_t* pn_in = nullptr,
-                 const int32_t* pm_in = nullptr, int np_in = 0) {
+int prepare_common(Batch& B, const rpa_states* k, Upload& up) {
+    rpa_ctx* c = B.c;
+    if (B.nw) {
+        up.add(B.om, &B.d_om);
+        up.add(B.ow, &B.d_ow);
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        if (B.fp64()) {
+            B.tw64[ax] = twiddles<double>(c->N[ax]);
+            up.add(B.tw64[ax], &B.d_tw[ax]);
+        } else {
+            B.tw32[ax] = twiddles<float>(c->N[ax]);
+            up.add(B.tw32[ax], &B.d_tw[ax]);
+        }
+    }
+    const int na = k->natoms;
+    B.poff.assign(na + 1, 0);
+    B.qoff.assign(na + 1, 0);
+    for (int a = 0; a <= na && na > 0; ++a) B.poff[a] = k->proj_off[a];
+    for (int a = 0; a < na; ++a) {
+        const int np = k->proj_off[a + 1] - k->proj_off[a];
+        B.qoff[a + 1] = B.qoff[a] + np * np;
+    }
+    up.add(B.poff, &B.d_poff);
+    up.add(B.qoff, &B.d_qoff);
+    return RPA_OK;
+}
+
+int prepare_kset(Batch& B, KSet& K, Upload& up, const int32_t* pn_in = nullptr, const int32_t* pm_in = nullptr,
+                 int np_in = -1) {
     const rpa_states* k = K.k;
     const rpa_states* kq = K.kq;
-    if (need_pairs_from_f) {
+    if (np_in < 0) {
         pair_list(k, kq, K.pn, K.pm);
     } else {
         K.pn.assign(pn_in, pn_in + np_in);
@@ -528,12 +591,12 @@ int prepare_kset(Engine& E, KSet& K, Upload& up, bool need_pairs_from_f, const i
             if (K.pn[i] < 0 || K.pn[i] >= k->nbands || K.pm[i] < 0 || K.pm[i] >= kq->nbands)
                 return fail(RPA_ERR_SHAPE, "pair index out of range");
     }
-    K.mapk = scatter_map(E.c, k);
+    K.mapk = scatter_map(B.c, k);
     up.add(K.pn, &K.d_pn);
     up.add(K.pm, &K.d_pm);
     up.add(K.mapk, &K.d_mapk);
     if (!same_set(k, kq)) {
-        K.mapkq = scatter_map(E.c, kq);
+        K.mapkq = scatter_map(B.c, kq);
         up.add(K.mapkq, &K.d_mapkq);
     }
     K.epsk.assign(k->eps, k->eps + k->nbands);
@@ -547,267 +610,358 @@ int prepare_kset(Engine& E, KSet& K, Upload& up, bool need_pairs_from_f, const i
     K.nlist_all.resize(k->nbands);
     std::iota(K.nlist_all.begin(), K.nlist_all.end(), 0);
     up.add(K.nlist_all, &K.d_nlist);
-    if (E.qs->optical) {
-        double B[3][3];
-        std::memcpy(B, E.c->B, sizeof(B));
-        K.wq.resize(k->nQ);
-        double qh[3] = {E.qs->qhat[0], E.qs->qhat[1], E.qs->qhat[2]};
+    return RPA_OK;
+}
+
+int prepare_q(Batch& B, QJob& Q, Upload& up) {
+    const QPlan& q = Q.qp;
+    up.add(q.kx, &Q.d_kx);
+    up.add(q.ky, &Q.d_ky);
+    up.add(q.col_start, &Q.d_cs);
+    up.add(q.col_g, &Q.d_cg);
+    up.add(q.col_kz, &Q.d_ckz);
+    up.add(q.vsqrt, &Q.d_vs);
+    if (Q.qs->optical) {
+        double qh[3] = {Q.qs->qhat[0], Q.qs->qhat[1], Q.qs->qhat[2]};
         const double nrm = std::sqrt(qh[0] * qh[0] + qh[1] * qh[1] + qh[2] * qh[2]);
         if (!(nrm > 0)) return fail(RPA_ERR_INPUT, "optical limit needs a nonzero qhat");
         for (int d = 0; d < 3; ++d) qh[d] /= nrm;
-        for (int i = 0; i < k->nQ; ++i) {
-            double kv[3];
-            kvec(B, k->kpt, k->miller + 3 * i, kv);
-            K.wq[i] = qh[0] * kv[0] + qh[1] * kv[1] + qh[2] * kv[2];
+        Q.wq.resize(B.ks.size());
+        Q.d_wq.assign(B.ks.size(), nullptr);
+        for (size_t i = 0; i < B.ks.size(); ++i) {
+            const rpa_states* k = B.ks[i].k;
+            Q.wq[i].resize(k->nQ);
+            for (int j = 0; j < k->nQ; ++j) {
+                double kv[3];
+                kvec(B.c->B, k->kpt, k->miller + 3 * j, kv);
+                Q.wq[i][j] = qh[0] * kv[0] + qh[1] * kv[1] + qh[2] * kv[2];
+            }
+            up.add(Q.wq[i], &Q.d_wq[i]);
         }
-        up.add(K.wq, &K.d_wq);
-        const int nq2 = (int)E.qoff.back();
-        K.Dq.assign(std::max(nq2, 1), 0.0);
-        if (nq2 > 0)
-            for (int e = 0; e < nq2; ++e)
-                K.Dq[e] = qh[0] * E.qs->Dpaw[e] + qh[1] * E.qs->Dpaw[nq2 + e] + qh[2] * E.qs->Dpaw[2 * nq2 + e];
-        up.add(K.Dq, &K.d_Dq);
+        const int nq2 = (int)B.qoff.back();
+        Q.Dq.assign(std::max(nq2, 1), 0.0);
+        for (int e = 0; e < nq2; ++e)
+            Q.Dq[e] = qh[0] * Q.qs->Dpaw[e] + qh[1] * Q.qs->Dpaw[nq2 + e] + qh[2] * Q.qs->Dpaw[2 * nq2 + e];
+        up.add(Q.Dq, &Q.d_Dq);
     }
+    return RPA_OK;
+}
+
+void* buf(Batch& B, const char* name) { return B.c->bufs[B.prefix + name].p; }
+
+// Work buffers, sized once for every q of the batch (never grown while launching).
+struct WorkSizes {
+    size_t tbuf = 0, rho = 0, weights = 0, paw_y = 0, pack = 0, scales = 0, chi = 0;
+    size_t cholL = 0, cholP = 0, small = 0, phi_k = 0, phi_kq = 0;
+};
+
+int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
+    rpa_ctx* c = B.c;
+    const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
+    const size_t el = B.elem();
+    size_t chi_off = 0;
+    for (auto& K : B.ks) {
+        W.phi_k = std::max(W.phi_k, (size_t)K.k->nbands * vol * 2 * el);
+        if (!same_set(K.k, K.kq)) W.phi_kq = std::max(W.phi_kq, (size_t)K.kq->nbands * vol * 2 * el);
+    }
+    for (auto& Q : B.qj) {
+        const PairGeom& g = Q.qp.g;
+        int P = 0;
+        int nn_max = 1;
+        for (auto& K : B.ks) {
+            P = std::max(P, (int)K.pn.size());
+            if (!K.pn.empty()) nn_max = std::max(nn_max, K.k->nbands);
+        }
+        Q.Pc = std::max(1, std::min(P, chunk_size(c, Q.qp, B.nw, el)));
+        const int Pc = Q.Pc;
+        const int nproj = B.poff.empty() ? 0 : B.poff.back();
+        // band window of a chunk: at most all bands of the k set
+        int win = 1;
+        for (auto& K : B.ks) {
+            for (size_t p0 = 0; p0 < K.pn.size(); p0 += Pc) {
+                const size_t p1 = std::min(K.pn.size(), p0 + Pc);
+                int lo = K.pn[p0], hi = K.pn[p0];
+                for (size_t i = p0; i < p1; ++i) {
+                    lo = std::min(lo, (int)K.pn[i]);
+                    hi = std::max(hi, (int)K.pn[i]);
+                }
+                win = std::max(win, hi - lo + 1);
+            }
+        }
+        (void)nn_max;
+        W.tbuf = std::max(W.tbuf, (size_t)Pc * g.N3 * g.ncols * 2 * el);
+        W.rho = std::max(W.rho, 2 * (size_t)Pc * g.NGp * el);
+        const int lda = (Pc + 3) / 4 * 4;
+        W.weights = std::max(W.weights, (size_t)std::max(B.nw, 1) * lda * sizeof(double));
+        if (nproj > 0) W.paw_y = std::max(W.paw_y, 2 * (size_t)win * nproj * g.NGp * el);
+        if (!B.fp64()) {
+            const int NGq = (g.NGp + 127) / 128 * 128;
+            const size_t blk = (size_t)((Pc + 31) / 32) * NGq * 32;
+            W.pack = std::max(W.pack, blk * (2 * sizeof(float) + 4 * sizeof(unsigned short)));
+            W.scales = std::max(W.scales, (size_t)(B.nw + 1 + 256) * sizeof(float));
+        }
+        if (need_ec || need_chi) {
+            Q.chi_off = chi_off;
+            chi_off += 2 * (size_t)B.nw * g.NGp * g.NGp * sizeof(double);
+        }
+        if (need_ec) {
+            W.cholL = std::max(W.cholL, 2 * (size_t)B.nw * kTile * kTile * sizeof(double));
+            W.cholP = std::max(W.cholP, 2 * (size_t)B.nw * kTile * g.NGp * sizeof(double));
+        }
+        Q.variant = default_variant(c, B.prec, g.NGp);
+    }
+    W.chi = chi_off;
+    if (need_ec) W.small = B.qj.size() * (size_t)B.nw * (2 * sizeof(double) + sizeof(int)) + 64;
+    struct NB {
+        const char* n;
+        size_t b;
+    } list[] = {{"phi_k", W.phi_k}, {"phi_kq", W.phi_kq}, {"tbuf", W.tbuf}, {"rho", W.rho},
+                {"weights", W.weights}, {"paw_y", W.paw_y}, {"split_pack", W.pack}, {"split_scales", W.scales},
+                {"chi", W.chi}, {"chol_L", W.cholL}, {"chol_panel", W.cholP}, {"ec_small", W.small}};
+    for (auto& e : list) {
+        if (!e.b) continue;
+        void* p = nullptr;
+        int rc = get_buf(c, (B.prefix + e.n).c_str(), e.b, B.s, &p);
+        if (rc) return rc;
+    }
+    if (W.chi) {
+        char* base = static_cast<char*>(buf(B, "chi"));
+        for (auto& Q : B.qj) {
+            const size_t mat = (size_t)B.nw * Q.qp.NGp * Q.qp.NGp;
+            Q.cr = reinterpret_cast<double*>(base + Q.chi_off);
+            Q.ci = Q.cr + mat;
+        }
+    }
+    return RPA_OK;
+}
+
+template <typename T>
+int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const char* name, cplx<T>** out) {
+    rpa_ctx* c = B.c;
+    const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
+    cplx<T>* phi = static_cast<cplx<T>*>(buf(B, name));
+    ProfScope ps_(c, S_ORB, B.s);
+    HIP_TRY(launch_fill_zero<T>(phi, (size_t)s->nbands * vol, B.s));
+    HIP_TRY(launch_orb_scatter<T>(static_cast<const double*>(s->C), s->nbands, s->nQ,
+                                  static_cast<const int32_t*>(d_map), vol, phi, B.s));
+    for (int ax = 0; ax < 3; ++ax)
+        HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
+                                   static_cast<const cplx<T>*>(B.d_tw[ax]), +1, B.s));
+    *out = phi;
     return RPA_OK;
 }
 
 // rho for pairs [p0, p0 + np) of K into planar buffers rre/rim [np][NGp]
 template <typename T>
-int pair_chunk(Engine& E, KSet& K, const cplx<T>* phik, const cplx<T>* phikq, int p0, int np, T* rre, T* rim) {
-    rpa_ctx* c = E.c;
-    const PairGeom& g = E.qp.g;
-    void* tb = nullptr;
-    int rc = get_buf(c, "tbuf", (size_t)np * g.N3 * g.ncols * sizeof(cplx<T>), E.s, &tb);
-    if (rc) return rc;
+int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const cplx<T>* phikq, int p0, int np,
+                  T* rre, T* rim) {
+    rpa_ctx* c = B.c;
+    const PairGeom& g = Q.qp.g;
+    cplx<T>* tb = static_cast<cplx<T>*>(buf(B, "tbuf"));
     const int32_t* pn = static_cast<const int32_t*>(K.d_pn) + p0;
     const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
     {
-    ProfScope ps_(c, S_PAIR_XY, E.s);
-    HIP_TRY(launch_pair_xy<T>(phik, phikq, pn, pm, np, g, static_cast<const int32_t*>(E.d_kx),
-                              static_cast<const int32_t*>(E.d_ky), static_cast<const cplx<T>*>(E.d_tw[0]),
-                              static_cast<const cplx<T>*>(E.d_tw[1]), static_cast<cplx<T>*>(tb), E.s));
+        ProfScope ps_(c, S_PAIR_XY, B.s);
+        HIP_TRY(launch_pair_xy<T>(phik, phikq, pn, pm, np, g, static_cast<const int32_t*>(Q.d_kx),
+                                  static_cast<const int32_t*>(Q.d_ky), static_cast<const cplx<T>*>(B.d_tw[0]),
+                                  static_cast<const cplx<T>*>(B.d_tw[1]), tb, B.s));
     }
     {
-    ProfScope ps_(c, S_PAIR_Z, E.s);
-    HIP_TRY(launch_pair_z_gather<T>(static_cast<const cplx<T>*>(tb), np, g, static_cast<const int32_t*>(E.d_cs),
-                                    static_cast<const int32_t*>(E.d_cg), static_cast<const int32_t*>(E.d_ckz),
-                                    static_cast<const cplx<T>*>(E.d_tw[2]), rre, rim, E.s));
+        ProfScope ps_(c, S_PAIR_Z, B.s);
+        HIP_TRY(launch_pair_z_gather<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
+                                        static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
+                                        static_cast<const cplx<T>*>(B.d_tw[2]), rre, rim, B.s));
     }
     const int nproj = nproj_total(K.k);
     if (nproj > 0) {
-        // Y for the band window [nlo, nhi] of this chunk
         int nlo = K.pn[p0], nhi = K.pn[p0];
         for (int i = p0; i < p0 + np; ++i) {
             nlo = std::min(nlo, (int)K.pn[i]);
             nhi = std::max(nhi, (int)K.pn[i]);
         }
         const int nn = nhi - nlo + 1;
-        void* y = nullptr;
-        rc = get_buf(c, "paw_y", 2 * (size_t)nn * nproj * g.NGp * sizeof(T), E.s, &y);
-        if (rc) return rc;
-        T* Yre = static_cast<T*>(y);
+        T* Yre = static_cast<T*>(buf(B, "paw_y"));
         T* Yim = Yre + (size_t)nn * nproj * g.NGp;
-        ProfScope ps_(c, S_PAW, E.s);
+        ProfScope ps_(c, S_PAW, B.s);
         HIP_TRY(launch_paw_y<T>(static_cast<const double*>(K.k->P), nproj, static_cast<const int32_t*>(K.d_nlist) + nlo,
-                                nn, static_cast<const int32_t*>(E.d_poff), static_cast<const int32_t*>(E.d_qoff),
-                                K.k->natoms, nproj, static_cast<const double*>(E.qs->Qpaw), g.NG, g.NGp, Yre, Yim,
-                                E.s));
+                                nn, static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Yre, Yim,
+                                B.s));
         HIP_TRY(launch_paw_add<T>(Yre, Yim, pn, nlo, pm, static_cast<const double*>(K.kq->P), nproj, nproj, np, g.NG,
-                                  g.NGp, rre, rim, E.s));
+                                  g.NGp, rre, rim, B.s));
     }
-    if (E.qs->optical && E.qp.g0 >= 0) {
-        ProfScope ps_(c, S_OPTICAL, E.s);
+    if (Q.qs->optical && Q.qp.g0 >= 0) {
+        ProfScope ps_(c, S_OPTICAL, B.s);
         HIP_TRY(launch_optical_row<T>(static_cast<const double*>(K.k->C), static_cast<const double*>(K.kq->C), K.k->nQ,
-                                      static_cast<const double*>(K.d_wq), static_cast<const double*>(K.k->P),
-                                      static_cast<const double*>(K.kq->P), nproj, static_cast<const double*>(K.d_Dq),
-                                      static_cast<const int32_t*>(E.d_poff), static_cast<const int32_t*>(E.d_qoff),
+                                      static_cast<const double*>(Q.d_wq[ik]), static_cast<const double*>(K.k->P),
+                                      static_cast<const double*>(K.kq->P), nproj, static_cast<const double*>(Q.d_Dq),
+                                      static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
                                       K.k->natoms, static_cast<const double*>(K.d_epsk),
-                                      static_cast<const double*>(K.d_epskq), pn, pm, np, E.qp.g0, g.NGp, rre, rim,
-                                      E.s));
+                                      static_cast<const double*>(K.d_epskq), pn, pm, np, Q.qp.g0, g.NGp, rre, rim,
+                                      B.s));
     }
     return RPA_OK;
 }
 
-int begin(Engine& E, rpa_ctx* c, const rpa_qspec* qs, const rpa_freq* fr, rpa_precision prec, void* stream) {
-    E.c = c;
-    E.s = static_cast<hipStream_t>(stream);
-    E.prec = prec;
-    E.qs = qs;
-    if (prec != RPA_FP64 && prec != RPA_SPLIT_BF16 && prec != RPA_SPLIT_FP16)
-        return fail(RPA_ERR_INPUT, "unknown precision");
-    HIP_TRY(hipSetDevice(c->device));
-    int rc = plan_q(c, qs, E.qp, fr != nullptr);
-    if (rc) return rc;
-    if (fr) {
-        rc = check_freq(fr);
-        if (rc) return rc;
-        E.nw = fr->nw;
-        E.om.assign(fr->omega, fr->omega + fr->nw);
-        E.ow.assign(fr->weight, fr->weight + fr->nw);
-    }
-    return RPA_OK;
-}
-
-int set_paw_tables(Engine& E, const rpa_states* k, Upload& up) {
-    const int na = k->natoms;
-    E.poff.assign(na + 1, 0);
-    E.qoff.assign(na + 1, 0);
-    for (int a = 0; a <= na && na > 0; ++a) E.poff[a] = k->proj_off[a];
-    for (int a = 0; a < na; ++a) {
-        const int np = k->proj_off[a + 1] - k->proj_off[a];
-        E.qoff[a + 1] = E.qoff[a] + np * np;
-    }
-    up.add(E.poff, &E.d_poff);
-    up.add(E.qoff, &E.d_qoff);
-    return RPA_OK;
-}
-
-// accumulate chi0 (planar, lower tiles) over all k pairs into "chi" buffers
+// chi0(w) += rho diag(a(w)) rho^H for one chunk, with the job's kernel variant
 template <typename T>
-int accumulate_chi0(Engine& E, const rpa_states* ks, const rpa_states* kqs, int nk, double** chiRe, double** chiIm) {
-    rpa_ctx* c = E.c;
-    const PairGeom& g = E.qp.g;
-    const int NGp = g.NGp;
-    std::vector<KSet> sets(nk);
-    Upload up;
-    int rc = prepare_common(E, up);
-    if (rc) return rc;
-    rc = set_paw_tables(E, &ks[0], up);
-    if (rc) return rc;
-    for (int i = 0; i < nk; ++i) {
-        sets[i].k = &ks[i];
-        sets[i].kq = &kqs[i];
-        rc = check_pair(c, &ks[i], &kqs[i], E.qs);
-        if (rc) return rc;
-        rc = prepare_kset(E, sets[i], up, true);
-        if (rc) return rc;
+int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const double* aw, int lda) {
+    rpa_ctx* c = B.c;
+    const int NGp = Q.qp.NGp;
+    ProfScope ps_(c, S_HERK, B.s);
+    if constexpr (sizeof(T) == 8) {
+        HerkArgs h{};
+        h.Are = reinterpret_cast<const double*>(rre);
+        h.Aim = reinterpret_cast<const double*>(rim);
+        h.sA = 0;
+        h.ldA = NGp;
+        h.colA = 0;
+        h.K = np;
+        h.w = aw;
+        h.sw = lda;
+        h.alpha = 0;
+        h.Cre = Q.cr;
+        h.Cim = Q.ci;
+        h.sC = (long long)NGp * NGp;
+        h.ldC = NGp;
+        h.r0 = 0;
+        h.nT = NGp / kTile;
+        h.nbatch = B.nw;
+        HIP_TRY(launch_herk_f64(h, B.s));
+    } else {
+        const bool fp16 = B.prec == RPA_SPLIT_FP16;
+        float* scales = nullptr;
+        if (fp16) {
+            scales = static_cast<float*>(buf(B, "split_scales"));
+            HIP_TRY(launch_split_scales(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim),
+                                        (size_t)np * NGp, aw, lda, np, B.nw, scales, scales + B.nw + 1, B.s));
+        }
+        if (Q.variant == 2) {
+            const int NGq = (NGp + 127) / 128 * 128;
+            const size_t blk = (size_t)((np + 31) / 32) * NGq * 32;
+            float* Xre = static_cast<float*>(buf(B, "split_pack"));
+            float* Xim = Xre + blk;
+            unsigned short* Bp[4];
+            for (int q = 0; q < 4; ++q) Bp[q] = reinterpret_cast<unsigned short*>(Xim + blk) + q * blk;
+            HIP_TRY(launch_pack_split(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim), np,
+                                      NGp, NGq, scales, B.nw, fp16, Xre, Xim, Bp, B.s));
+            HerkSplit2Args h{};
+            h.Xre = Xre;
+            h.Xim = Xim;
+            for (int q = 0; q < 4; ++q) h.B[q] = Bp[q];
+            h.NGq = NGq;
+            h.K = np;
+            h.w = aw;
+            h.lda = lda;
+            h.Cre = Q.cr;
+            h.Cim = Q.ci;
+            h.sC = (long long)NGp * NGp;
+            h.ldC = NGp;
+            const int nT = NGq / 128;
+            h.ntiles = nT * (nT + 1) / 2;
+            h.nw = B.nw;
+            h.fp16 = fp16;
+            h.scales = scales;
+            HIP_TRY(launch_herk_split2(h, B.s));
+        } else {
+            HerkSplitArgs h{};
+            h.Are = reinterpret_cast<const float*>(rre);
+            h.Aim = reinterpret_cast<const float*>(rim);
+            h.ldA = NGp;
+            h.K = np;
+            h.w = aw;
+            h.lda = lda;
+            h.Cre = Q.cr;
+            h.Cim = Q.ci;
+            h.sC = (long long)NGp * NGp;
+            h.ldC = NGp;
+            h.nT = NGp / kTile;
+            h.nw = B.nw;
+            h.fp16 = fp16;
+            h.wscale = scales;
+            HIP_TRY(launch_herk_split(h, B.s));
+        }
     }
-    rc = do_upload(c, up, E.s);
-    if (rc) return rc;
+    return RPA_OK;
+}
 
-    void* chi = nullptr;
-    const size_t mat = (size_t)E.nw * NGp * NGp;
-    rc = get_buf(c, "chi", 2 * mat * sizeof(double), E.s, &chi);
-    if (rc) return rc;
-    double* cr = static_cast<double*>(chi);
-    double* ci = cr + mat;
-    HIP_TRY(launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(cr), mat, E.s));
-
-    for (int i = 0; i < nk; ++i) {
-        KSet& K = sets[i];
+// chi0 of every q of the batch (planar lower tiles in each job's accumulator)
+template <typename T>
+int enqueue_chi0(Batch& B) {
+    rpa_ctx* c = B.c;
+    for (auto& Q : B.qj) {
+        const size_t mat = (size_t)B.nw * Q.qp.NGp * Q.qp.NGp;
+        HIP_TRY(launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(Q.cr), mat, B.s));
+    }
+    for (size_t ik = 0; ik < B.ks.size(); ++ik) {
+        KSet& K = B.ks[ik];
         const int P = (int)K.pn.size();
         if (P == 0) continue;
         cplx<T>* phik = nullptr;
         cplx<T>* phikq = nullptr;
-        rc = run_orbitals<T>(E, K.k, K.d_mapk, "phi_k", &phik);
+        int rc = enqueue_orbitals<T>(B, K.k, K.d_mapk, "phi_k", &phik);
         if (rc) return rc;
         if (same_set(K.k, K.kq)) {
             phikq = phik;
         } else {
-            rc = run_orbitals<T>(E, K.kq, K.d_mapkq, "phi_kq", &phikq);
+            rc = enqueue_orbitals<T>(B, K.kq, K.d_mapkq, "phi_kq", &phikq);
             if (rc) return rc;
         }
-        const int Pc = std::min(P, chunk_size(E, sizeof(T)));
-        const int lda = (Pc + 3) / 4 * 4;
-        void* rho = nullptr;
-        rc = get_buf(c, "rho", 2 * (size_t)Pc * NGp * sizeof(T), E.s, &rho);
-        if (rc) return rc;
-        T* rre = static_cast<T*>(rho);
-        T* rim = rre + (size_t)Pc * NGp;
-        void* aw = nullptr;
-        rc = get_buf(c, "weights", (size_t)E.nw * lda * sizeof(double), E.s, &aw);
-        if (rc) return rc;
         const double prefac = K.k->weight / c->volume;
-        for (int p0 = 0; p0 < P; p0 += Pc) {
-            const int np = std::min(Pc, P - p0);
-            rc = pair_chunk<T>(E, K, phik, phikq, p0, np, rre, rim);
-            if (rc) return rc;
-            {
-            ProfScope ps_(c, S_WEIGHTS, E.s);
-            HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
-                                   static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
-                                   static_cast<const int32_t*>(K.d_pn) + p0, static_cast<const int32_t*>(K.d_pm) + p0,
-                                   np, static_cast<const double*>(E.d_om), E.nw, prefac, static_cast<double*>(aw),
-                                   lda, E.s));
-            }
-            ProfScope ps_(c, S_HERK, E.s);
-            if constexpr (sizeof(T) == 8) {
-                HerkArgs h{};
-                h.Are = reinterpret_cast<const double*>(rre);
-                h.Aim = reinterpret_cast<const double*>(rim);
-                h.sA = 0;
-                h.ldA = NGp;
-                h.colA = 0;
-                h.K = np;
-                h.w = static_cast<const double*>(aw);
-                h.sw = lda;
-                h.alpha = 0;
-                h.Cre = cr;
-                h.Cim = ci;
-                h.sC = (long long)NGp * NGp;
-                h.ldC = NGp;
-                h.r0 = 0;
-                h.nT = NGp / kTile;
-                h.nbatch = E.nw;
-                HIP_TRY(launch_herk_f64(h, E.s));
-            } else {
-                HerkSplitArgs h{};
-                h.Are = reinterpret_cast<const float*>(rre);
-                h.Aim = reinterpret_cast<const float*>(rim);
-                h.ldA = NGp;
-                h.K = np;
-                h.w = static_cast<const double*>(aw);
-                h.lda = lda;
-                h.Cre = cr;
-                h.Cim = ci;
-                h.sC = (long long)NGp * NGp;
-                h.ldC = NGp;
-                h.nT = NGp / kTile;
-                h.nw = E.nw;
-                h.fp16 = E.prec == RPA_SPLIT_FP16;
-                h.wscale = nullptr;
-                HIP_TRY(launch_herk_split(h, E.s));
+        for (auto& Q : B.qj) {
+            const int Pc = Q.Pc;
+            const int lda = (Pc + 3) / 4 * 4;
+            T* rre = static_cast<T*>(buf(B, "rho"));
+            T* rim = rre + (size_t)Pc * Q.qp.NGp;
+            double* aw = static_cast<double*>(buf(B, "weights"));
+            for (int p0 = 0; p0 < P; p0 += Pc) {
+                const int np = std::min(Pc, P - p0);
+                rc = enqueue_pairs<T>(B, Q, K, (int)ik, phik, phikq, p0, np, rre, rim);
+                if (rc) return rc;
+                {
+                    ProfScope ps_(c, S_WEIGHTS, B.s);
+                    HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
+                                           static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
+                                           static_cast<const int32_t*>(K.d_pn) + p0,
+                                           static_cast<const int32_t*>(K.d_pm) + p0, np,
+                                           static_cast<const double*>(B.d_om), B.nw, prefac, aw, lda, B.s));
+                }
+                rc = enqueue_update<T>(B, Q, np, rre, rim, aw, lda);
+                if (rc) return rc;
             }
         }
     }
-    *chiRe = cr;
-    *chiIm = ci;
     return RPA_OK;
 }
 
-// E_c from the planar lower-triangular chi0 accumulator (overwritten)
-int ec_stage(Engine& E, double* cr, double* ci, double* ec_dev, double* F_dev, bool from_full, const void* chi_full) {
-    rpa_ctx* c = E.c;
-    const int NG = E.qp.NG, NGp = E.qp.NGp, nw = E.nw;
-    void* sm = nullptr;
-    int rc = get_buf(c, "ec_small", (size_t)nw * (2 * sizeof(double) + sizeof(int)) + 64, E.s, &sm);
-    if (rc) return rc;
-    double* logdet = static_cast<double*>(sm);
+// E_c of job qi from its accumulator (overwritten by -K and its factor)
+int enqueue_ec(Batch& B, int qi, bool from_full, const void* chi_full) {
+    rpa_ctx* c = B.c;
+    QJob& Q = B.qj[qi];
+    const int NG = Q.qp.NG, NGp = Q.qp.NGp, nw = B.nw;
+    double* cr = Q.cr;
+    double* ci = Q.ci;
+    char* sm = static_cast<char*>(buf(B, "ec_small"));
+    double* logdet = reinterpret_cast<double*>(sm) + (size_t)qi * 2 * nw;
     double* trk = logdet + nw;
-    int* failv = reinterpret_cast<int*>(trk + nw);
-    void* lb = nullptr;
-    rc = get_buf(c, "chol_L", 2 * (size_t)nw * kTile * kTile * sizeof(double), E.s, &lb);
-    if (rc) return rc;
-    double* Lre = static_cast<double*>(lb);
+    int* failv = reinterpret_cast<int*>(reinterpret_cast<double*>(sm) + B.qj.size() * 2 * nw) + (size_t)qi * nw;
+    double* Lre = static_cast<double*>(buf(B, "chol_L"));
     double* Lim = Lre + (size_t)nw * kTile * kTile;
-    void* pb = nullptr;
-    rc = get_buf(c, "chol_panel", 2 * (size_t)nw * kTile * NGp * sizeof(double), E.s, &pb);
-    if (rc) return rc;
-    double* Pre = static_cast<double*>(pb);
+    double* Pre = static_cast<double*>(buf(B, "chol_panel"));
     double* Pim = Pre + (size_t)nw * kTile * NGp;
-    ProfScope ps_(c, S_CHOL, E.s);
-    HIP_TRY(launch_zero(logdet, 2 * nw, failv, nw, E.s));
+    ProfScope ps_(c, S_CHOL, B.s);
+    HIP_TRY(launch_zero(logdet, 2 * nw, failv, nw, B.s));
     if (from_full) {
         HIP_TRY(launch_build_negk_from_full(static_cast<const double*>(chi_full), NG, cr, ci, NGp, nw,
-                                            static_cast<const double*>(E.d_vs), trk, E.s));
+                                            static_cast<const double*>(Q.d_vs), trk, B.s));
     } else {
-        HIP_TRY(launch_build_negk(cr, ci, NGp, NG, NGp, nw, static_cast<const double*>(E.d_vs), trk, E.s));
+        HIP_TRY(launch_build_negk(cr, ci, NGp, NG, NGp, nw, static_cast<const double*>(Q.d_vs), trk, B.s));
     }
     for (int j0 = 0; j0 < NGp; j0 += kTile) {
-        HIP_TRY(launch_chol_panel(cr, ci, NGp, j0, nw, Lre, Lim, logdet, failv, E.s));
+        HIP_TRY(launch_chol_panel(cr, ci, NGp, j0, nw, Lre, Lim, logdet, failv, B.s));
         const int r0 = j0 + kTile;
         if (r0 >= NGp) break;
-        HIP_TRY(launch_chol_trsm(cr, ci, NGp, j0, NGp, nw, Lre, Lim, Pre, Pim, E.s));
+        HIP_TRY(launch_chol_trsm(cr, ci, NGp, j0, NGp, nw, Lre, Lim, Pre, Pim, B.s));
         HerkArgs h{};
         h.Are = Pre;
         h.Aim = Pim;
@@ -825,12 +979,17 @@ int ec_stage(Engine& E, double* cr, double* ci, double* ec_dev, double* F_dev, b
         h.r0 = r0;
         h.nT = (NGp - r0) / kTile;
         h.nbatch = nw;
-        HIP_TRY(launch_herk_f64(h, E.s));
+        HIP_TRY(launch_herk_f64(h, B.s));
     }
-    HIP_TRY(launch_finalize(logdet, trk, failv, static_cast<const double*>(E.d_ow), nw, F_dev, ec_dev, E.s));
-    c->last_fail = failv;
-    c->last_nw = nw;
+    HIP_TRY(launch_finalize(logdet, trk, failv, static_cast<const double*>(B.d_ow), nw, Q.F, Q.ec, B.s));
     return RPA_OK;
+}
+
+void remember_fail_flags(Batch& B) {
+    char* sm = static_cast<char*>(buf(B, "ec_small"));
+    B.c->last_fail = reinterpret_cast<int*>(reinterpret_cast<double*>(sm) + B.qj.size() * 2 * B.nw);
+    B.c->last_nw = B.nw;
+    B.c->last_nq = (int)B.qj.size();
 }
 
 int check_common(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs) {
@@ -840,6 +999,91 @@ int check_common(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk
     for (int i = 1; i < nk; ++i)
         if (k[i].natoms != k[0].natoms) return fail(RPA_ERR_SHAPE, "atom count differs between k-points");
     return RPA_OK;
+}
+
+// plan every (k, q) of a call: validation, tables, one upload, buffer sizes
+int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, int nq,
+               bool need_ec, bool need_chi, const char* table_buf, const int32_t* pn = nullptr,
+               const int32_t* pm = nullptr, int npairs = -1) {
+    rpa_ctx* c = B.c;
+    Upload up;
+    int rc = prepare_common(B, &k[0], up);
+    if (rc) return rc;
+    B.ks.resize(nk);
+    for (int i = 0; i < nk; ++i) {
+        B.ks[i].k = &k[i];
+        B.ks[i].kq = &kq[i];
+        for (int j = 0; j < nq; ++j) {
+            rc = check_pair(c, &k[i], &kq[i], &qs[j]);
+            if (rc) return rc;
+        }
+        rc = prepare_kset(B, B.ks[i], up, pn, pm, npairs);
+        if (rc) return rc;
+    }
+    B.qj.resize(nq);
+    for (int j = 0; j < nq; ++j) {
+        QJob& Q = B.qj[j];
+        Q.qs = &qs[j];
+        rc = plan_q(c, &qs[j], Q.qp, need_ec);
+        if (rc) return rc;
+        rc = prepare_q(B, Q, up);
+        if (rc) return rc;
+    }
+    rc = do_upload(c, up, B.s, table_buf);
+    if (rc) return rc;
+    WorkSizes W;
+    return presize(B, need_ec, need_chi, W);
+}
+// key of a batched call: every host value the captured launches baked in, and
+// every device pointer they read or write
+uint64_t batch_key(const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs, const rpa_freq* fr,
+                   rpa_precision prec, const double* ec, const double* F, void* stream) {
+    Fnv h;
+    h.val(nk);
+    h.val(nq);
+    h.val(prec);
+    h.val(ec);
+    h.val(F);
+    h.val(stream);
+    auto st = [&](const rpa_states* s) {
+        h.val(s->nbands);
+        h.val(s->nQ);
+        h.val(s->C);
+        h.val(s->P);
+        h.val(s->natoms);
+        h.bytes(s->miller, sizeof(int32_t) * 3 * (size_t)s->nQ);
+        h.bytes(s->eps, sizeof(double) * s->nbands);
+        h.bytes(s->f, sizeof(double) * s->nbands);
+        if (s->natoms > 0) h.bytes(s->proj_off, sizeof(int32_t) * (s->natoms + 1));
+        h.bytes(s->kpt, sizeof(s->kpt));
+        h.val(s->weight);
+    };
+    for (int i = 0; i < nk; ++i) {
+        st(&k[i]);
+        st(&kq[i]);
+    }
+    for (int j = 0; j < nq; ++j) {
+        const rpa_qspec& q = qs[j];
+        h.bytes(q.q, sizeof(q.q));
+        h.val(q.optical);
+        h.bytes(q.qhat, sizeof(q.qhat));
+        h.val(q.NG);
+        h.bytes(q.gmiller, sizeof(int32_t) * 3 * (size_t)q.NG);
+        h.val(q.Qpaw);
+        h.val(q.weight);
+        if (q.optical && q.Dpaw && k[0].natoms > 0) {
+            int nq2 = 0;
+            for (int a = 0; a < k[0].natoms; ++a) {
+                const int np = k[0].proj_off[a + 1] - k[0].proj_off[a];
+                nq2 += np * np;
+            }
+            h.bytes(q.Dpaw, sizeof(double) * 3 * (size_t)nq2);
+        }
+    }
+    h.val(fr->nw);
+    h.bytes(fr->omega, sizeof(double) * fr->nw);
+    h.bytes(fr->weight, sizeof(double) * fr->nw);
+    return h.h;
 }
 
 }  // namespace
@@ -895,6 +1139,7 @@ int rpa_destroy(rpa_ctx* c) {
     if (!c) return RPA_OK;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    drop_graph(c);
     prof_collect(c);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     for (auto& kv : c->bufs)
@@ -952,47 +1197,34 @@ int rpa_pair_density(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, cons
     int rc = check_common(c, k, kq, 1, qs);
     if (rc) return rc;
     if (npairs < 0 || (npairs > 0 && (!pn || !pm || !rho_out))) return fail(RPA_ERR_INPUT, "bad pair list");
-    Engine E;
-    rc = begin(E, c, qs, nullptr, prec, stream);
+    Batch B;
+    rc = begin(B, c, nullptr, prec, stream);
     if (rc) return rc;
-    rc = check_pair(c, k, kq, qs);
-    if (rc) return rc;
-    if (npairs == 0) return RPA_OK;
-    Upload up;
-    KSet K;
-    K.k = k;
-    K.kq = kq;
-    prepare_common(E, up);
-    set_paw_tables(E, k, up);
-    rc = prepare_kset(E, K, up, false, pn, pm, npairs);
-    if (rc) return rc;
-    // the PAW band window of a chunk is [min n, max n]; keep pairs n-sorted per chunk
-    rc = do_upload(c, up, E.s);
+    if (npairs == 0) return check_pair(c, k, kq, qs);
+    rc = plan_batch(B, k, kq, 1, qs, 1, false, false, "tables", pn, pm, npairs);
     if (rc) return rc;
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
+        KSet& K = B.ks[0];
+        QJob& Q = B.qj[0];
         cplx<T>* phik = nullptr;
         cplx<T>* phikq = nullptr;
-        int r = run_orbitals<T>(E, k, K.d_mapk, "phi_k", &phik);
+        int r = enqueue_orbitals<T>(B, k, K.d_mapk, "phi_k", &phik);
         if (r) return r;
         if (same_set(k, kq)) phikq = phik;
         else {
-            r = run_orbitals<T>(E, kq, K.d_mapkq, "phi_kq", &phikq);
+            r = enqueue_orbitals<T>(B, kq, K.d_mapkq, "phi_kq", &phikq);
             if (r) return r;
         }
-        const int NGp = E.qp.NGp;
-        const int Pc = std::min(npairs, chunk_size(E, sizeof(T)));
-        void* rho = nullptr;
-        r = get_buf(c, "rho", 2 * (size_t)Pc * NGp * sizeof(T), E.s, &rho);
-        if (r) return r;
-        T* rre = static_cast<T*>(rho);
+        const int NGp = Q.qp.NGp, Pc = Q.Pc;
+        T* rre = static_cast<T*>(buf(B, "rho"));
         T* rim = rre + (size_t)Pc * NGp;
         for (int p0 = 0; p0 < npairs; p0 += Pc) {
             const int np = std::min(Pc, npairs - p0);
-            r = pair_chunk<T>(E, K, phik, phikq, p0, np, rre, rim);
+            r = enqueue_pairs<T>(B, Q, K, 0, phik, phikq, p0, np, rre, rim);
             if (r) return r;
-            HIP_TRY(launch_rho_out<T>(rre, rim, np, E.qp.NG, NGp, static_cast<double*>(rho_out) + 2 * (size_t)p0 * E.qp.NG,
-                                      E.s));
+            HIP_TRY(launch_rho_out<T>(rre, rim, np, Q.qp.NG, NGp,
+                                      static_cast<double*>(rho_out) + 2 * (size_t)p0 * Q.qp.NG, B.s));
         }
         return RPA_OK;
     };
@@ -1004,15 +1236,16 @@ int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, cons
     int rc = check_common(c, k, kq, nk, qs);
     if (rc) return rc;
     if (!chi0_out) return fail(RPA_ERR_INPUT, "NULL chi0_out");
-    Engine E;
-    rc = begin(E, c, qs, fr, prec, stream);
-    if (rc) return rc;
     if (!fr) return fail(RPA_ERR_INPUT, "NULL frequency grid");
-    double *cr = nullptr, *ci = nullptr;
-    rc = prec == RPA_FP64 ? accumulate_chi0<double>(E, k, kq, nk, &cr, &ci)
-                          : accumulate_chi0<float>(E, k, kq, nk, &cr, &ci);
+    Batch B;
+    rc = begin(B, c, fr, prec, stream);
     if (rc) return rc;
-    HIP_TRY(launch_chi_out(cr, ci, E.qp.NGp, E.qp.NG, E.nw, static_cast<double*>(chi0_out), E.s));
+    rc = plan_batch(B, k, kq, nk, qs, 1, false, true, "tables");
+    if (rc) return rc;
+    rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
+    if (rc) return rc;
+    QJob& Q = B.qj[0];
+    HIP_TRY(launch_chi_out(Q.cr, Q.ci, Q.qp.NGp, Q.qp.NG, B.nw, static_cast<double*>(chi0_out), B.s));
     return RPA_OK;
 }
 
@@ -1021,36 +1254,226 @@ int rpa_ec(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const 
     int rc = check_common(c, k, kq, nk, qs);
     if (rc) return rc;
     if (!ec_dev) return fail(RPA_ERR_INPUT, "NULL ec_dev");
-    Engine E;
-    rc = begin(E, c, qs, fr, prec, stream);
-    if (rc) return rc;
     if (!fr) return fail(RPA_ERR_INPUT, "NULL frequency grid");
-    double *cr = nullptr, *ci = nullptr;
-    rc = prec == RPA_FP64 ? accumulate_chi0<double>(E, k, kq, nk, &cr, &ci)
-                          : accumulate_chi0<float>(E, k, kq, nk, &cr, &ci);
+    Batch B;
+    rc = begin(B, c, fr, prec, stream);
     if (rc) return rc;
-    return ec_stage(E, cr, ci, ec_dev, F_dev, false, nullptr);
+    rc = plan_batch(B, k, kq, nk, qs, 1, true, false, "tables");
+    if (rc) return rc;
+    rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
+    if (rc) return rc;
+    B.qj[0].ec = ec_dev;
+    B.qj[0].F = F_dev;
+    rc = enqueue_ec(B, 0, false, nullptr);
+    if (rc) return rc;
+    remember_fail_flags(B);
+    return RPA_OK;
 }
 
 int rpa_ec_from_chi0(rpa_ctx* c, const rpa_qspec* qs, const rpa_freq* fr, const void* chi0, double* ec_dev,
                      double* F_dev, void* stream) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
-    if (!chi0 || !ec_dev) return fail(RPA_ERR_INPUT, "NULL chi0 or ec_dev");
-    Engine E;
-    int rc = begin(E, c, qs, fr, RPA_FP64, stream);
-    if (rc) return rc;
+    if (!chi0 || !ec_dev || !qs) return fail(RPA_ERR_INPUT, "NULL chi0, qspec or ec_dev");
     if (!fr) return fail(RPA_ERR_INPUT, "NULL frequency grid");
+    Batch B;
+    int rc = begin(B, c, fr, RPA_FP64, stream);
+    if (rc) return rc;
+    B.qj.resize(1);
+    QJob& Q = B.qj[0];
+    Q.qs = qs;
+    rc = plan_q(c, qs, Q.qp, true);
+    if (rc) return rc;
     Upload up;
-    up.add(E.qp.vsqrt, &E.d_vs);
-    up.add(E.ow, &E.d_ow);
-    rc = do_upload(c, up, E.s);
+    up.add(Q.qp.vsqrt, &Q.d_vs);
+    up.add(B.ow, &B.d_ow);
+    rc = do_upload(c, up, B.s, "tables");
     if (rc) return rc;
-    void* chi = nullptr;
-    const size_t mat = (size_t)E.nw * E.qp.NGp * E.qp.NGp;
-    rc = get_buf(c, "chi", 2 * mat * sizeof(double), E.s, &chi);
+    WorkSizes W;
+    rc = presize(B, true, false, W);
     if (rc) return rc;
-    double* cr = static_cast<double*>(chi);
-    return ec_stage(E, cr, cr + mat, ec_dev, F_dev, true, chi0);
+    Q.ec = ec_dev;
+    Q.F = F_dev;
+    rc = enqueue_ec(B, 0, true, chi0);
+    if (rc) return rc;
+    remember_fail_flags(B);
+    return RPA_OK;
+}
+
+int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs,
+                   const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
+                   void* stream) {
+    if (nq <= 0 || !qs) return fail(RPA_ERR_INPUT, "need at least one q-point");
+    int rc = check_common(c, k, kq, nk, qs);
+    if (rc) return rc;
+    if (!ec_dev) return fail(RPA_ERR_INPUT, "NULL ec_dev");
+    if (!fr) return fail(RPA_ERR_INPUT, "NULL frequency grid");
+    Batch B;
+    rc = begin(B, c, fr, prec, stream);
+    if (rc) return rc;
+    const uint64_t key = use_graph ? batch_key(k, kq, nk, nq, qs, fr, prec, ec_dev, F_dev, stream) : 0;
+    if (use_graph && c->graph_exec && c->graph_key == key) {
+        HIP_TRY(hipGraphLaunch(c->graph_exec, B.s));
+        return RPA_OK;
+    }
+    if (use_graph) {
+        drop_graph(c);
+        B.prefix = "g:";
+    }
+    const std::string tables = B.prefix + "tables";
+    rc = plan_batch(B, k, kq, nk, qs, nq, true, false, tables.c_str());
+    if (rc) return rc;
+    std::vector<double> wq(nq);
+    for (int j = 0; j < nq; ++j) wq[j] = qs[j].weight;
+    auto enqueue_all = [&]() -> int {
+        int r = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
+        if (r) return r;
+        for (int j = 0; j < nq; ++j) {
+            B.qj[j].ec = ec_dev + j;
+            B.qj[j].F = F_dev ? F_dev + (size_t)j * B.nw : nullptr;
+            r = enqueue_ec(B, j, false, nullptr);
+            if (r) return r;
+        }
+        HIP_TRY(launch_weighted_sum(ec_dev, static_cast<const double*>(B.d_wq), nq, ec_dev + nq, B.s));
+        return RPA_OK;
+    };
+    {
+        Upload up;
+        up.add(wq, &B.d_wq);
+        rc = do_upload(c, up, B.s, (B.prefix + "qweights").c_str());
+        if (rc) return rc;
+    }
+    if (!use_graph) {
+        rc = enqueue_all();
+        if (rc) return rc;
+        remember_fail_flags(B);
+        return RPA_OK;
+    }
+    hipGraph_t graph = nullptr;
+    c->capturing = true;
+    HIP_TRY(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_all();
+    hipError_t e = hipStreamEndCapture(B.s, &graph);
+    c->capturing = false;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(RPA_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(RPA_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    c->graph = graph;
+    c->graph_exec = exec;
+    c->graph_key = key;
+    HIP_TRY(hipGraphLaunch(exec, B.s));
+    remember_fail_flags(B);
+    return RPA_OK;
+}
+
+int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
+    if (!c) return fail(RPA_ERR_INPUT, "NULL context");
+    if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
+    if (variant != 1 && variant != 2) return fail(RPA_ERR_INPUT, "split variants are 1 (64x64) and 2 (128x128)");
+    const int NGp = (NG + kTile - 1) / kTile * kTile;
+    c->tune[tune_key(prec, NGp)] = variant;
+    return RPA_OK;
+}
+
+int rpa_tune_get(rpa_ctx* c, rpa_precision prec, int NG, int* variant) {
+    if (!c || !variant) return fail(RPA_ERR_INPUT, "NULL argument");
+    *variant = default_variant(c, prec, (NG + kTile - 1) / kTile * kTile);
+    return RPA_OK;
+}
+
+int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, void* stream) {
+    if (!c) return fail(RPA_ERR_INPUT, "NULL context");
+    if (prec == RPA_FP64) return RPA_OK;
+    if (NG <= 0 || npairs <= 0 || nw <= 0) return fail(RPA_ERR_INPUT, "bad tuning shape");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int NGp = (NG + kTile - 1) / kTile * kTile;
+    Batch B;
+    B.c = c;
+    B.s = s;
+    B.prec = prec;
+    B.nw = nw;
+    B.prefix = "tune:";
+    B.qj.resize(1);
+    QJob& Q = B.qj[0];
+    Q.qp.NG = NG;
+    Q.qp.NGp = NGp;
+    const int lda = (npairs + 3) / 4 * 4;
+    const int NGq = (NGp + 127) / 128 * 128;
+    const size_t blk = (size_t)((npairs + 31) / 32) * NGq * 32;
+    void *rho, *aw, *chi, *pack, *sc;
+    int rc = get_buf(c, "tune:rho", 2 * (size_t)npairs * NGp * sizeof(float), s, &rho);
+    if (!rc) rc = get_buf(c, "tune:weights", (size_t)nw * lda * sizeof(double), s, &aw);
+    if (!rc) rc = get_buf(c, "tune:chi", 2 * (size_t)nw * NGp * NGp * sizeof(double), s, &chi);
+    if (!rc) rc = get_buf(c, "tune:split_pack", blk * (2 * sizeof(float) + 4 * sizeof(unsigned short)), s, &pack);
+    if (!rc) rc = get_buf(c, "tune:split_scales", (size_t)(nw + 1 + 256) * sizeof(float), s, &sc);
+    if (rc) return rc;
+    HIP_TRY(launch_fill_pattern(static_cast<float*>(rho), 2 * (size_t)npairs * NGp, static_cast<double*>(aw),
+                                (size_t)nw * lda, s));
+    Q.cr = static_cast<double*>(chi);
+    Q.ci = Q.cr + (size_t)nw * NGp * NGp;
+    const float* rre = static_cast<const float*>(rho);
+    const float* rim = rre + (size_t)npairs * NGp;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    int bestv = 1;
+    for (int v = 1; v <= 2; ++v) {
+        Q.variant = v;
+        double tmin = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRY(hipEventRecord(e0, s));
+            rc = enqueue_update<float>(B, Q, npairs, rre, rim, static_cast<const double*>(aw), lda);
+            if (rc) break;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tmin = std::min(tmin, (double)ms);
+        }
+        if (rc) break;
+        if (tmin < best) {
+            best = tmin;
+            bestv = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    c->tune[tune_key(prec, NGp)] = bestv;
+    c->tune_ms[tune_key(prec, NGp)] = best;
+    return RPA_OK;
+}
+
+int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
+    if (!c || !path) return fail(RPA_ERR_INPUT, "NULL argument");
+    if (save) {
+        FILE* f = std::fopen(path, "w");
+        if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64 tiles, 2 = 128x128 tiles)\n");
+        for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
+        std::fclose(f);
+        return RPA_OK;
+    }
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(RPA_ERR_INPUT, std::string("cannot read ") + path);
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#') continue;
+        int p, ng, v;
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || v == 2) && ng > 0)
+            c->tune[tune_key((rpa_precision)p, ng)] = v;
+    }
+    std::fclose(f);
+    return RPA_OK;
 }
 
 int rpa_profile(rpa_ctx* c, int enable) {
@@ -1084,12 +1507,14 @@ int rpa_check(rpa_ctx* c, void* stream) {
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     HIP_TRY(hipGetLastError());
     if (!c->last_fail || c->last_nw <= 0) return RPA_OK;
-    std::vector<int> f(c->last_nw);
-    HIP_TRY(hipMemcpy(f.data(), c->last_fail, sizeof(int) * c->last_nw, hipMemcpyDeviceToHost));
-    for (int w = 0; w < c->last_nw; ++w)
-        if (f[w])
-            return fail(RPA_ERR_NOT_PD, "1 - K not positive definite at frequency index " + std::to_string(w) +
-                                            " (pivot " + std::to_string(f[w] - 1) + ")");
+    const int n = c->last_nw * std::max(c->last_nq, 1);
+    std::vector<int> f(n);
+    HIP_TRY(hipMemcpy(f.data(), c->last_fail, sizeof(int) * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+        if (f[i])
+            return fail(RPA_ERR_NOT_PD, "1 - K not positive definite at q index " + std::to_string(i / c->last_nw) +
+                                            ", frequency index " + std::to_string(i % c->last_nw) + " (pivot " +
+                                            std::to_string(f[i] - 1) + ")");
     return RPA_OK;
 }
 

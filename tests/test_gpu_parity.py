@@ -163,9 +163,87 @@ def test_o2box_reduced_bands(rpa, iq):
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl, iq)
     with rpa.Context(wl.A, wl.grid) as ctx:
         ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
-        ec2, F2 = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        ec16, _ = ctx.ec(ks, kqs, qs, fr, "split_fp16")
+        ecb, _ = ctx.ec(ks, kqs, qs, fr, "split_bf16")
         ctx.check()
-        ec, ec2 = float(ec.cpu()[0]), float(ec2.cpu()[0])
-    print(f"o2box q{iq}: NG={len(gm)} E64={ec:.12f} Esplit={ec2:.12f} ref={ref['E']:.12f}", flush=True)
+        ec, ec16, ecb = float(ec.cpu()[0]), float(ec16.cpu()[0]), float(ecb.cpu()[0])
+    print(f"o2box q{iq}: NG={len(gm)} E64={ec:.12f} Efp16={ec16:.12f} Ebf16={ecb:.12f} ref={ref['E']:.12f}",
+          flush=True)
     assert abs(ec - ref["E"]) < 1e-10
-    assert abs(ec2 - ref["E"]) < 1e-6
+    # |E_c| is 5-30 Ha here, so 1e-6 Ha is a relative 3e-8 for the FP16 hi/lo split (22 bits per operand)
+    assert abs(ec16 - ref["E"]) < 1e-6
+    # BF16 hi/lo keeps 16 bits per operand: looser bound, stated
+    assert abs(ecb - ref["E"]) < 5e-6
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_kernel_variants(rpa, variant, prec):
+    """Both split rank-k kernels (64x64 and 128x128 tiles) against the oracle on the 16^3 workload
+    (NG = 126) and a tiny grid (NG = 15: one 128-tile, half of it padding)."""
+    for wl in (synth.config0(), synth.tiny(grid=(8, 8, 8))):
+        ref = oracle_q(wl)
+        ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+        with rpa.Context(wl.A, wl.grid) as ctx:
+            ctx.tune_set(len(gm), variant, prec)
+            assert ctx.tune_get(len(gm), prec) == variant
+            chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
+            ec, F = ctx.ec(ks, kqs, qs, fr, prec)
+            ctx.check()
+        r = _rel(chi, ref["chi"])
+        dE = float(ec.cpu()[0]) - ref["E"]
+        print(f"variant {variant} {prec} NG={len(gm)}: chi rel={r:.3e} dE={dE:.3e}", flush=True)
+        assert r < 2e-4
+        assert abs(dE) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_fp16"])
+def test_batched_graph_replays_match_per_q_calls(rpa, prec):
+    """Several q-points in one call, captured into a graph and replayed three times with eager work and
+    synchronisations in between; every replay equals the per-q results, and the weighted sum is formed."""
+    wl = synth.tiny(grid=(12, 12, 12), L=(8.0, 8.5, 9.0), n_occ=3, n_unocc=9, target_ng=40)
+    Bm = 2 * np.pi * np.linalg.inv(wl.A).T
+    qpts = [synth.QPoint(q=f * Bm[0] + g * Bm[1], ecut=synth.ecut_for_count(wl.A, f * Bm[0] + g * Bm[1], t),
+                         weight=w)
+            for f, g, t, w in ((0.1, 0.0, 40, 0.5), (0.25, 0.1, 25, 0.3), (0.0, 0.3, 60, 0.2))]
+    wl.qpoints = qpts
+    ks = [rpa.States.from_synth(wl.kpoints[0], wl.paw, "cuda:0")]
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    qspecs = []
+    for qp in qpts:
+        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+        qspecs.append(rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        per_q = []
+        for qs in qspecs:
+            e, _ = ctx.ec(ks, ks, qs, fr, prec)
+            per_q.append(float(e.cpu()[0]))
+        ec0, F0 = ctx.ec_batched(ks, ks, qspecs, fr, prec, use_graph=False)
+        ctx.check()
+        eager = ec0.cpu().numpy().copy()
+        assert np.allclose(eager[:3], per_q, rtol=0, atol=1e-13)
+        assert abs(eager[3] - sum(q.weight * e for q, e in zip(qspecs, per_q))) < 1e-13
+        out = None
+        for rep in range(3):
+            out = ctx.ec_batched(ks, ks, qspecs, fr, prec, use_graph=True, out=out)
+            ctx.check()
+            got = out[0].cpu().numpy().copy()
+            print(f"{prec} replay {rep}: {got}", flush=True)
+            assert np.array_equal(got, eager), (rep, got, eager)
+            # eager work between replays reuses the same context
+            e, _ = ctx.ec(ks, ks, qspecs[1], fr, prec)
+            torch.cuda.synchronize()
+            assert float(e.cpu()[0]) == per_q[1]
+        # the oracle for each q
+        for qs, qp, e in zip(qspecs, qpts, per_q):
+            wl1 = synth.Workload(name="t", A=wl.A, grid=wl.grid, kpoints=wl.kpoints, paw=wl.paw, qpoints=[qp],
+                                 omega=wl.omega, omega_weight=wl.omega_weight, seed=0)
+            ref = oracle_q(wl1)
+            assert abs(e - ref["E"]) < (1e-10 if prec == "fp64" else 1e-6)
+
+
+def test_autotune_records_a_variant(rpa):
+    with rpa.Context(np.eye(3) * 10.0, (16, 16, 16)) as ctx:
+        v = ctx.autotune(NG=700, npairs=512, nw=4, precision="split_bf16")
+        assert v in (1, 2)
+        assert ctx.tune_get(700, "split_bf16") == v
