@@ -50,21 +50,22 @@ def make_inputs(rpa, wl, device):
     return ks, qspecs, fr
 
 
-def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False):
-    outs = []
+def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False, use_graph=False):
+    """`steps` passes of E_c(q) over all q-points (one batched call per step)."""
+    out = None
     torch.cuda.synchronize()
     if profile:
         ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        outs = [ctx.ec(ks, ks, qs, fr, prec) for qs in qspecs]
+        out = ctx.ec_batched(ks, ks, qspecs, fr, prec, use_graph=use_graph, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.check()
     prof = ctx.profile_get() if profile else None
     if profile:
         ctx.profile(False)
-    ecs = [float(e.cpu()[0]) for e, _ in outs]
+    ecs = [float(x) for x in out[0].cpu().numpy()[: len(qspecs)]]
     return (t1 - t0), ecs, prof
 
 
@@ -147,6 +148,11 @@ def main():
     value = flops_step * args.steps / dt / 1e12
     log(f"split: {ms_step:.2f} ms/step, {value:.2f} TFLOP/s, E_c = {ec_split}")
     log("stage ms (timed region): " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in prof.items()))
+    # the same step replayed from a captured graph (launch overhead removed)
+    run_steps(torch, ctx, ks, qspecs, fr, args.precision, 1, use_graph=True)
+    dtg, ec_graph, _ = run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.steps, use_graph=True)
+    ms_step_graph = dtg / args.steps * 1e3
+    log(f"split (graph replay): {ms_step_graph:.2f} ms/step")
 
     # FP64 path on the same inputs
     k64 = args.fp64_steps if args.fp64_steps is not None else args.steps
@@ -196,6 +202,9 @@ def main():
         "ms_per_q": ms_step / len(NGs),
         "ec_split": ec_split, "ec_fp64": ec64,
         "ec_split_minus_fp64_ha": [a - b for a, b in zip(ec_split, ec64)],
+        "ec_split_minus_fp64_rel": [(a - b) / abs(b) for a, b in zip(ec_split, ec64)],
+        "ms_per_step_graph": ms_step_graph,
+        "ec_graph_equals_eager": ec_graph == ec_split,
         "speedup_vs_fp64": ms_step64 / ms_step,
         "stage_ms": stage_ms,
         "fp64": fp64,

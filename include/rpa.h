@@ -179,6 +179,23 @@ int rpa_ec_batched(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int 
                    const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
                    void* stream);
 
+/* Gradient of E_c(q) (FP64 path, one (k, k+q) state-set pair): given the
+ * upstream derivative dEc (DEVICE double [1], e.g. 1.0), writes
+ *  deps_k  DEVICE double [nbands_k]           dE/d eps_n at k
+ *  dC_k    DEVICE complex128 [nbands_k][nQ_k]  dE/dRe C + i dE/dIm C
+ *  dP_k    DEVICE complex128 [nbands_k][nproj] (may be NULL without PAW atoms)
+ * and the same for the k+q set; when kq is the same set as k (same C, P and
+ * Miller pointers) both roles are summed into the k outputs and the kq
+ * outputs are ignored. Occupations are held fixed; C and P are free
+ * variables (no re-orthonormalisation). E_c(q) is written to ec_dev.
+ * The pair densities are recomputed chunk by chunk, (1 - K)^-1 is formed
+ * from the Cholesky factor, and rho_bar = sum_w c_w 2 a(w) W(w) rho is taken
+ * back through the optical row, the PAW term, the pruned pair FFT and the
+ * orbital FFT. RPA_ERR_UNSUPPORTED if N1*N2 > 4096. */
+int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, const rpa_qspec* qs,
+                    const rpa_freq* fr, const double* dEc, double* ec_dev, double* deps_k, void* dC_k, void* dP_k,
+                    double* deps_kq, void* dC_kq, void* dP_kq, void* stream);
+
 /* Rank-k kernel choice of the split precisions per padded sphere size
  * (NG rounded up to 64): variant 1 = 64x64 tiles staged from FP32 rho,
  * variant 2 = 128x128 tiles from the K-blocked pre-split rho. Without an

@@ -16,7 +16,8 @@ import numpy as np
 from . import _capi
 from ._capi import PRECISION, RpaCell, RpaFreq, RpaQSpec, RpaStates
 
-__all__ = ["RpaError", "Context", "States", "QSpec", "Freq", "gsphere", "PRECISION", "library_path"]
+__all__ = ["RpaError", "Context", "States", "QSpec", "Freq", "gsphere", "PRECISION", "library_path",
+           "ec_autograd"]
 
 
 def library_path() -> str:
@@ -275,6 +276,35 @@ class Context:
                                       int(bool(use_graph)), _stream()), self._h)
         return ec, F
 
+    def ec_backward(self, k: States, kq: States, qs: QSpec, freq: Freq, dEc=1.0):
+        """E_c(q) and its gradient (FP64) for one (k, k+q) pair of state sets.
+
+        Returns (ec [1], grads) with grads = dict(eps_k, C_k, P_k[, eps_kq, C_kq, P_kq]) as device tensors;
+        complex gradients are dE/dRe + i dE/dIm. With kq the same set as k only the k entries are returned
+        (both roles summed)."""
+        torch = _torch()
+        dev = self.device
+        dE = torch.as_tensor(dEc, dtype=torch.float64, device=dev).reshape(1).contiguous()
+        ec = torch.empty(1, dtype=torch.float64, device=dev)
+        same = kq is k
+
+        def outs(s):
+            return (torch.empty(s.C.shape[0], dtype=torch.float64, device=dev),
+                    torch.empty_like(s.C), torch.empty_like(s.P))
+        ek, Ck, Pk = outs(k)
+        eq, Cq, Pq = (None, None, None) if same else outs(kq)
+        a, b, q, fr = k.struct(), kq.struct(), qs.struct(), freq.struct()
+
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _check(self._L.rpa_ec_backward(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(q), ctypes.byref(fr),
+                                       ptr(dE), ptr(ec), ptr(ek), ptr(Ck), ptr(Pk), ptr(eq), ptr(Cq), ptr(Pq),
+                                       _stream()), self._h)
+        grads = {"eps_k": ek, "C_k": Ck, "P_k": Pk}
+        if not same:
+            grads.update(eps_kq=eq, C_kq=Cq, P_kq=Pq)
+        return ec, grads
+
     def autotune(self, NG: int, npairs: int, nw: int = 16, precision="split_bf16") -> int:
         """Time the split rank-k kernel variants for this shape; returns the recorded variant."""
         _check(self._L.rpa_autotune(self._h, _prec(precision), int(NG), int(npairs), int(nw), _stream()), self._h)
@@ -321,3 +351,35 @@ class Context:
     def check(self):
         """Synchronize and raise RpaError for device-side failures (e.g. a non-positive pivot)."""
         _check(self._L.rpa_check(self._h, _stream()), self._h)
+
+
+def _ec_function():
+    import torch
+
+    class EcFunction(torch.autograd.Function):
+        """E_c(q) as a differentiable function of the eigenvalues (float64), the plane-wave coefficients
+        (complex128) and the PAW projections (complex128) of one state set used at k and k+q. The forward
+        pass and the hand-written adjoint both run in the HIP library; the pair densities are recomputed
+        in the adjoint pass."""
+
+        @staticmethod
+        def forward(fctx, C, eps, P, context, template, qs, freq):
+            st = States(C.detach(), template.miller, eps.detach().cpu().numpy(), template.f, P.detach(),
+                        template.proj_off, template.kpt, template.weight, device=context.device)
+            fctx.objs = (context, st, qs, freq)
+            fctx.eps_device = eps.device
+            ec, _ = context.ec([st], [st], qs, freq, "fp64")
+            return ec[0].clone()
+
+        @staticmethod
+        def backward(fctx, grad):
+            context, st, qs, freq = fctx.objs
+            _, g = context.ec_backward(st, st, qs, freq, dEc=grad.detach().to(torch.float64))
+            return g["C_k"], g["eps_k"].to(fctx.eps_device), g["P_k"], None, None, None, None
+
+    return EcFunction
+
+
+def ec_autograd(context, C, eps, P, template: "States", qs: "QSpec", freq: "Freq"):
+    """Differentiable E_c(q) (see EcFunction): C, P complex128 device tensors, eps float64 tensor."""
+    return _ec_function().apply(C, eps, P, context, template, qs, freq)

@@ -79,6 +79,9 @@ SIGNATURES = {
     "rpa_ec_batched": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int, c_int,
                                ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p, c_int,
                                c_void_p]),
+    "rpa_ec_backward": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates),
+                                ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rpa_autotune": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
     "rpa_tune_set": (c_int, [c_void_p, c_int, c_int, c_int]),
     "rpa_tune_get": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int)]),

@@ -116,7 +116,8 @@ hipError_t launch_build_negk_from_full(const double* chi, int NG, double* Cre, d
 
 hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, double* Lre, double* Lim,
                              double* logdet, int* fail, hipStream_t s);
-hipError_t launch_chol_trsm(const double* Cre, const double* Cim, int ldC, int j0, int NGp, int nw,
+// Both also write the factor L (lower triangle, diagonal real) back into C.
+hipError_t launch_chol_trsm(double* Cre, double* Cim, int ldC, int j0, int NGp, int nw,
                             const double* Lre, const double* Lim, double* Pre, double* Pim, hipStream_t s);
 hipError_t launch_finalize(const double* logdet, const double* trk, const int* fail, const double* wgt, int nw,
                            double* F, double* ec, hipStream_t s);
@@ -133,5 +134,52 @@ hipError_t launch_rho_out(const T* rre, const T* rim, int npairs, int NG, int NG
 
 hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out,
                           hipStream_t s);
+
+// ------------------------------------------------------------------ adjoint
+// C[b] = beta C[b] + alpha op(A[b]) op(B[b]); A(i,k) at i*aI + k*aK, B(k,j) at
+// k*bK + j*bJ, C(i,j) at i*ldC + j; conj flags conjugate an operand; beta 0 or 1.
+struct GemmArgs {
+    int M, N, K, nbatch;
+    const double* Ar; const double* Ai; long long sA; long long aI, aK; int conjA;
+    const double* Br; const double* Bi; long long sB; long long bK, bJ; int conjB;
+    double* Cr; double* Ci; long long sC; long long ldC; double alpha; int beta;
+};
+hipError_t launch_gemm_c64(const GemmArgs& g, hipStream_t s);
+hipError_t launch_identity(double* Xr, double* Xi, int n, int ld, int nb, hipStream_t s);
+hipError_t launch_build_w(double* Mr, double* Mi, int NG, int NGp, int nw, const double* vs, hipStream_t s);
+hipError_t launch_freq_coeffs(const double* dE, const double* ow, int nw, double* cw, hipStream_t s);
+hipError_t launch_grad_weights(const double* rr, const double* ri, const double* yr, const double* yi, int NG, int NGp,
+                               const double* a, int lda, int w, const double* cw, double* gr, double* gi, double* dEda,
+                               int npairs, hipStream_t s);
+hipError_t launch_pair_eps(const double* dEda, int lda, int nw, const double* epsk, const double* epskq,
+                           const double* fk, const double* fkq, const int32_t* pn, const int32_t* pm, int npairs,
+                           const double* omega, double prefac, double* u, hipStream_t s);
+hipError_t launch_optical_adj(const double* rr, const double* ri, double* gr, double* gi, int g0, int NGp,
+                              const double* epsk, const double* epskq, const int32_t* pn, const int32_t* pm,
+                              int npairs, double* u, double* gnum, hipStream_t s);
+hipError_t launch_paw_u(const double* Pkq, int ldP, int mlo, int nm, const int32_t* proj_off, const int32_t* qoff,
+                        int natoms, int nproj, const double* Q, int NG, int NGp, double* Ur, double* Ui, hipStream_t s);
+hipError_t launch_paw_adj(const double* gr, const double* gi, int NG, int NGp, const double* Yr, const double* Yi,
+                          int nlo, const double* Ur, const double* Ui, int mlo, int nproj, const int32_t* pn,
+                          const int32_t* pm, int npairs, double* Zm, double* Zn, hipStream_t s);
+hipError_t launch_paw_reduce(const double* Z, const int32_t* start, const int32_t* list, int nb, int nproj, double* dP,
+                             int band0, const double* gnum, const double* Pother, const int32_t* other,
+                             const double* Dq, const int32_t* proj_off, const int32_t* qoff, int natoms, int side,
+                             hipStream_t s);
+hipError_t launch_eps_reduce(const double* u, const int32_t* start, const int32_t* list, int nbands, double sign,
+                             double* de, hipStream_t s);
+hipError_t launch_optical_c(const double* gnum, const int32_t* start, const int32_t* list, const int32_t* other,
+                            const double* Cother, int nQ, const double* wq, int side, int nb, double* dC,
+                            hipStream_t s);
+hipError_t launch_zadj(const double* gr, const double* gi, int NGp, int npairs, const PairGeom& g,
+                       const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, const cplx<double>* tw3,
+                       cplx<double>* tadj, hipStream_t s);
+hipError_t launch_xyadj(const cplx<double>* tadj, const PairGeom& g, const int32_t* start, const int32_t* list,
+                        const int32_t* other, const cplx<double>* phio, int band0, int nb, int side,
+                        const int32_t* kx, const int32_t* ky, const cplx<double>* tw1, const cplx<double>* tw2,
+                        cplx<double>* phibar, hipStream_t s);
+hipError_t launch_gather_c(const cplx<double>* ph, size_t vol, const int32_t* map, int nQ, int nb, double* dC,
+                           hipStream_t s);
+hipError_t launch_zero_d(double* p, size_t n, hipStream_t s);
 
 }  // namespace rpa

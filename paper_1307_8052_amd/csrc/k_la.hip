@@ -345,7 +345,7 @@ __global__ void k_zero_i(int* p, int n) {
 //
 // Panel: factor the 64x64 diagonal block at j0 in LDS, accumulate its log-det,
 // and store the inverse of its lower-triangular factor for the row solve.
-__global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ Cre, const double* __restrict__ Cim,
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, double* __restrict__ Cim,
                                                     int ldC, long long sC, int j0, double* __restrict__ Lre,
                                                     double* __restrict__ Lim, double* __restrict__ logdet,
                                                     int* __restrict__ fail) {
@@ -354,8 +354,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ C
     __shared__ double pinv, ldacc;
     __shared__ int bad;
     const int w = blockIdx.x, tid = threadIdx.x;
-    const double* cr = Cre + (size_t)w * sC;
-    const double* ci = Cim + (size_t)w * sC;
+    double* cr = Cre + (size_t)w * sC;
+    double* ci = Cim + (size_t)w * sC;
     for (int e = tid; e < kTile * kTile; e += blockDim.x) {
         const int r = e >> 6, c = e & 63;
         const bool low = c <= r;
@@ -417,6 +417,11 @@ __global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ C
         const int r = e >> 6, c = e & 63;
         lr[e] = vr[r][c];
         li[e] = vi[r][c];
+        // the factor itself replaces the lower triangle of the block
+        if (c <= r) {
+            cr[(size_t)(j0 + r) * ldC + j0 + c] = sr[r][c];
+            ci[(size_t)(j0 + r) * ldC + j0 + c] = si[r][c];
+        }
     }
     if (tid == 0) {
         logdet[w] += ldacc;
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(const double* __restrict__ C
 // Row solve of the panel below the diagonal block: X = A21 (L11^-1)^H, written
 // transposed (X[c][r], rows contiguous) as the operand of the trailing update.
 constexpr int kTrsmRows = 32;
-__global__ __launch_bounds__(256) void k_chol_trsm(const double* __restrict__ Cre, const double* __restrict__ Cim,
+__global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ Cre, double* __restrict__ Cim,
                                                    int ldC, long long sC, int j0, int NGp,
                                                    const double* __restrict__ Lre, const double* __restrict__ Lim,
                                                    double* __restrict__ Pre, double* __restrict__ Pim) {
@@ -435,8 +440,8 @@ __global__ __launch_bounds__(256) void k_chol_trsm(const double* __restrict__ Cr
     __shared__ double ar[kTrsmRows][kTile + 1], ai[kTrsmRows][kTile + 1];
     const int w = blockIdx.y, tid = threadIdx.x;
     const int r0 = j0 + kTile + blockIdx.x * kTrsmRows;
-    const double* cr = Cre + (size_t)w * sC;
-    const double* ci = Cim + (size_t)w * sC;
+    double* cr = Cre + (size_t)w * sC;
+    double* ci = Cim + (size_t)w * sC;
     for (int e = tid; e < kTile * kTile; e += blockDim.x) {
         lr[e >> 6][e & 63] = Lre[(size_t)w * kTile * kTile + e];
         li[e >> 6][e & 63] = Lim[(size_t)w * kTile * kTile + e];
@@ -462,6 +467,9 @@ __global__ __launch_bounds__(256) void k_chol_trsm(const double* __restrict__ Cr
         if (row < NGp) {
             pr[(size_t)c * NGp + row] = xr;
             pi[(size_t)c * NGp + row] = xi;
+            // the factor's block column replaces the matrix below the diagonal block
+            cr[(size_t)row * ldC + j0 + c] = xr;
+            ci[(size_t)row * ldC + j0 + c] = xi;
         }
     }
 }
@@ -580,7 +588,7 @@ hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, 
     return hipGetLastError();
 }
 
-hipError_t launch_chol_trsm(const double* Cre, const double* Cim, int ldC, int j0, int NGp, int nw, const double* Lre,
+hipError_t launch_chol_trsm(double* Cre, double* Cim, int ldC, int j0, int NGp, int nw, const double* Lre,
                             const double* Lim, double* Pre, double* Pim, hipStream_t s) {
     const int rows = NGp - j0 - kTile;
     if (rows <= 0) return hipSuccess;

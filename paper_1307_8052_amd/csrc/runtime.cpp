@@ -78,6 +78,8 @@ struct rpa_ctx {
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_key = 0;
     bool capturing = false;
+    // non-blocking stream the batch sequence is captured on (the legacy default stream cannot be)
+    hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -935,7 +937,7 @@ int enqueue_chi0(Batch& B) {
 }
 
 // E_c of job qi from its accumulator (overwritten by -K and its factor)
-int enqueue_ec(Batch& B, int qi, bool from_full, const void* chi_full) {
+int enqueue_ec(Batch& B, int qi, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     QJob& Q = B.qj[qi];
     const int NG = Q.qp.NG, NGp = Q.qp.NGp, nw = B.nw;
@@ -958,6 +960,11 @@ int enqueue_ec(Batch& B, int qi, bool from_full, const void* chi_full) {
         HIP_TRY(launch_build_negk(cr, ci, NGp, NG, NGp, nw, static_cast<const double*>(Q.d_vs), trk, B.s));
     }
     for (int j0 = 0; j0 < NGp; j0 += kTile) {
+        if (Lblocks) {
+            // keep every inverted diagonal block: [block][re/im][w][64][64]
+            Lre = Lblocks + (size_t)(j0 / kTile) * 2 * nw * kTile * kTile;
+            Lim = Lre + (size_t)nw * kTile * kTile;
+        }
         HIP_TRY(launch_chol_panel(cr, ci, NGp, j0, nw, Lre, Lim, logdet, failv, B.s));
         const int r0 = j0 + kTile;
         if (r0 >= NGp) break;
@@ -1034,6 +1041,281 @@ int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, cons
     WorkSizes W;
     return presize(B, need_ec, need_chi, W);
 }
+
+// ------------------------------------------------------------ the adjoint
+struct Csr {
+    std::vector<int32_t> start, list;
+};
+
+// pairs [p0, p0+np) grouped by band (key = pn or pm) over the window [lo, hi]
+Csr group_pairs(const std::vector<int32_t>& key, int p0, int np, int lo, int hi, bool local) {
+    Csr c;
+    c.start.assign(hi - lo + 2, 0);
+    for (int i = 0; i < np; ++i) c.start[key[p0 + i] - lo + 1]++;
+    for (int b = 0; b <= hi - lo; ++b) c.start[b + 1] += c.start[b];
+    c.list.resize(np);
+    std::vector<int32_t> fill(c.start.begin(), c.start.end() - 1);
+    for (int i = 0; i < np; ++i) c.list[fill[key[p0 + i] - lo]++] = local ? i : p0 + i;
+    return c;
+}
+
+struct BwChunk {
+    int p0, np, nlo, nhi, mlo, mhi;
+    Csr byn, bym;
+    void *d_ns = nullptr, *d_nl = nullptr, *d_ms = nullptr, *d_ml = nullptr;
+};
+
+int backward(Batch& B, const double* dEc, double* ec_dev, double* deps_k, double* dC_k, double* dP_k,
+             double* deps_kq, double* dC_kq, double* dP_kq) {
+    rpa_ctx* c = B.c;
+    KSet& K = B.ks[0];
+    QJob& Q = B.qj[0];
+    const PairGeom& g = Q.qp.g;
+    const int NG = Q.qp.NG, NGp = Q.qp.NGp, nw = B.nw;
+    const int P = (int)K.pn.size();
+    const bool same = same_set(K.k, K.kq);
+    const int nbk = K.k->nbands, nbq = K.kq->nbands;
+    const int nproj = nproj_total(K.k);
+    const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
+    if (same) {
+        deps_kq = deps_k;
+        dC_kq = dC_k;
+        dP_kq = dP_k;
+    }
+    // host tables: per-chunk band groupings and the global ones for the energies
+    const int Pc = Q.Pc;
+    std::vector<BwChunk> ch;
+    for (int p0 = 0; p0 < P; p0 += Pc) {
+        BwChunk x;
+        x.p0 = p0;
+        x.np = std::min(Pc, P - p0);
+        x.nlo = x.nhi = K.pn[p0];
+        x.mlo = x.mhi = K.pm[p0];
+        for (int i = p0; i < p0 + x.np; ++i) {
+            x.nlo = std::min(x.nlo, (int)K.pn[i]);
+            x.nhi = std::max(x.nhi, (int)K.pn[i]);
+            x.mlo = std::min(x.mlo, (int)K.pm[i]);
+            x.mhi = std::max(x.mhi, (int)K.pm[i]);
+        }
+        x.byn = group_pairs(K.pn, p0, x.np, x.nlo, x.nhi, true);
+        x.bym = group_pairs(K.pm, p0, x.np, x.mlo, x.mhi, true);
+        ch.push_back(std::move(x));
+    }
+    Csr gn = group_pairs(K.pn, 0, P, 0, nbk - 1, false);
+    Csr gm = group_pairs(K.pm, 0, P, 0, nbq - 1, false);
+    void *d_gns, *d_gnl, *d_gms, *d_gml;
+    Upload up;
+    for (auto& x : ch) {
+        up.add(x.byn.start, &x.d_ns);
+        up.add(x.byn.list, &x.d_nl);
+        up.add(x.bym.start, &x.d_ms);
+        up.add(x.bym.list, &x.d_ml);
+    }
+    up.add(gn.start, &d_gns);
+    up.add(gn.list, &d_gnl);
+    up.add(gm.start, &d_gms);
+    up.add(gm.list, &d_gml);
+    int rc = do_upload(c, up, B.s, "bw_tables");
+    if (rc) return rc;
+
+    // buffers
+    int maxm = 1, maxn = 1;
+    for (auto& x : ch) {
+        maxm = std::max(maxm, x.mhi - x.mlo + 1);
+        maxn = std::max(maxn, x.nhi - x.nlo + 1);
+    }
+    const size_t mat = (size_t)nw * NGp * NGp;
+    void *pB, *pX, *pL, *pY, *pG, *pdE, *pu, *pcw, *pZ, *pU, *pgn, *pT, *pPb;
+    struct NB {
+        const char* n;
+        size_t b;
+        void** p;
+    } list[] = {{"bw_B", 2 * mat * 8, &pB}, {"bw_X", 2 * mat * 8, &pX},
+                {"bw_L", (size_t)(NGp / kTile) * 2 * nw * kTile * kTile * 8, &pL},
+                {"bw_Y", 2 * (size_t)Pc * NGp * 8, &pY}, {"bw_g", 2 * (size_t)Pc * NGp * 8, &pG},
+                {"bw_dEda", (size_t)nw * ((Pc + 3) / 4 * 4) * 8, &pdE}, {"bw_u", (size_t)std::max(P, 1) * 8, &pu},
+                {"bw_cw", 64 * 8, &pcw}, {"bw_Z", 4 * (size_t)Pc * std::max(nproj, 1) * 8, &pZ},
+                {"bw_U", 2 * (size_t)maxm * std::max(nproj, 1) * NGp * 8, &pU}, {"bw_gnum", 2 * (size_t)Pc * 8, &pgn},
+                {"bw_tadj", (size_t)Pc * g.N3 * g.ncols * 16, &pT},
+                {"bw_phibar", (size_t)(nbk + (same ? 0 : nbq)) * vol * 16, &pPb}};
+    for (auto& e : list) {
+        rc = get_buf(c, e.n, e.b, B.s, e.p);
+        if (rc) return rc;
+    }
+    double* Lb = static_cast<double*>(pL);
+    double *Br_ = static_cast<double*>(pB), *Bi_ = Br_ + mat;
+    double *Xr = static_cast<double*>(pX), *Xi = Xr + mat;
+    double *Yr = static_cast<double*>(pY), *Yi = Yr + (size_t)Pc * NGp;
+    double *gr = static_cast<double*>(pG), *gi = gr + (size_t)Pc * NGp;
+    double* dEda = static_cast<double*>(pdE);
+    double* u = static_cast<double*>(pu);
+    double* cw = static_cast<double*>(pcw);
+    double *Zm = static_cast<double*>(pZ), *Zn = Zm + 2 * (size_t)Pc * std::max(nproj, 1);
+    double *Ur = static_cast<double*>(pU), *Ui = Ur + (size_t)maxm * std::max(nproj, 1) * NGp;
+    double* gnum = static_cast<double*>(pgn);
+    cplx<double>* tadj = static_cast<cplx<double>*>(pT);
+    cplx<double>* phib_k = static_cast<cplx<double>*>(pPb);
+    cplx<double>* phib_kq = same ? phib_k : phib_k + (size_t)nbk * vol;
+
+    // forward: chi0, E_c, and the factor L with its inverted diagonal blocks
+    rc = enqueue_chi0<double>(B);
+    if (rc) return rc;
+    Q.ec = ec_dev;
+    Q.F = nullptr;
+    rc = enqueue_ec(B, 0, false, nullptr, Lb);
+    if (rc) return rc;
+    remember_fail_flags(B);
+    ProfScope ps_(c, S_OTHER, B.s);
+    // X = L^-1 by blocked substitution on the identity, then (1 - K)^-1 = X^H X
+    HIP_TRY(launch_identity(Br_, Bi_, NGp, NGp, nw, B.s));
+    HIP_TRY(launch_zero_d(Xr, 2 * mat, B.s));  // columns right of each block row stay zero
+    const int nblk = NGp / kTile;
+    for (int i = 0; i < nblk; ++i) {
+        const int ncol = (i + 1) * kTile;
+        GemmArgs g1{};
+        g1.M = kTile; g1.N = ncol; g1.K = kTile; g1.nbatch = nw;
+        g1.Ar = Lb + (size_t)i * 2 * nw * kTile * kTile; g1.Ai = g1.Ar + (size_t)nw * kTile * kTile;
+        g1.sA = kTile * kTile; g1.aI = kTile; g1.aK = 1;
+        g1.Br = Br_ + (size_t)i * kTile * NGp; g1.Bi = Bi_ + (size_t)i * kTile * NGp;
+        g1.sB = (long long)NGp * NGp; g1.bK = NGp; g1.bJ = 1;
+        g1.Cr = Xr + (size_t)i * kTile * NGp; g1.Ci = Xi + (size_t)i * kTile * NGp;
+        g1.sC = (long long)NGp * NGp; g1.ldC = NGp; g1.alpha = 1.0; g1.beta = 0;
+        HIP_TRY(launch_gemm_c64(g1, B.s));
+        const int r1 = (i + 1) * kTile;
+        if (r1 < NGp) {
+            GemmArgs g2{};
+            g2.M = NGp - r1; g2.N = ncol; g2.K = kTile; g2.nbatch = nw;
+            g2.Ar = Q.cr + (size_t)r1 * NGp + i * kTile; g2.Ai = Q.ci + (size_t)r1 * NGp + i * kTile;
+            g2.sA = (long long)NGp * NGp; g2.aI = NGp; g2.aK = 1;
+            g2.Br = g1.Cr; g2.Bi = g1.Ci; g2.sB = (long long)NGp * NGp; g2.bK = NGp; g2.bJ = 1;
+            g2.Cr = Br_ + (size_t)r1 * NGp; g2.Ci = Bi_ + (size_t)r1 * NGp;
+            g2.sC = (long long)NGp * NGp; g2.ldC = NGp; g2.alpha = -1.0; g2.beta = 1;
+            HIP_TRY(launch_gemm_c64(g2, B.s));
+        }
+    }
+    {
+        GemmArgs g3{};
+        g3.M = NGp; g3.N = NGp; g3.K = NGp; g3.nbatch = nw;
+        g3.Ar = Xr; g3.Ai = Xi; g3.sA = (long long)NGp * NGp; g3.aI = 1; g3.aK = NGp; g3.conjA = 1;
+        g3.Br = Xr; g3.Bi = Xi; g3.sB = (long long)NGp * NGp; g3.bK = NGp; g3.bJ = 1;
+        g3.Cr = Br_; g3.Ci = Bi_; g3.sC = (long long)NGp * NGp; g3.ldC = NGp; g3.alpha = 1.0; g3.beta = 0;
+        HIP_TRY(launch_gemm_c64(g3, B.s));
+    }
+    HIP_TRY(launch_build_w(Br_, Bi_, NG, NGp, nw, static_cast<const double*>(Q.d_vs), B.s));
+    HIP_TRY(launch_freq_coeffs(dEc, static_cast<const double*>(B.d_ow), nw, cw, B.s));
+
+    // outputs and accumulators start at zero
+    HIP_TRY(launch_zero_d(deps_k, nbk, B.s));
+    HIP_TRY(launch_zero_d(dC_k, 2 * (size_t)nbk * K.k->nQ, B.s));
+    if (nproj) HIP_TRY(launch_zero_d(dP_k, 2 * (size_t)nbk * nproj, B.s));
+    if (!same) {
+        HIP_TRY(launch_zero_d(deps_kq, nbq, B.s));
+        HIP_TRY(launch_zero_d(dC_kq, 2 * (size_t)nbq * K.kq->nQ, B.s));
+        if (nproj) HIP_TRY(launch_zero_d(dP_kq, 2 * (size_t)nbq * nproj, B.s));
+    }
+    HIP_TRY(launch_zero_d(reinterpret_cast<double*>(phib_k), 2 * (size_t)(nbk + (same ? 0 : nbq)) * vol, B.s));
+    HIP_TRY(launch_zero_d(u, std::max(P, 1), B.s));
+
+    const double* phik = static_cast<const double*>(buf(B, "phi_k"));
+    const double* phikq = same ? phik : static_cast<const double*>(buf(B, "phi_kq"));
+    const double prefac = K.k->weight / c->volume;
+    const int lda = (Pc + 3) / 4 * 4;
+    double* rre = static_cast<double*>(buf(B, "rho"));
+    double* rim = rre + (size_t)Pc * NGp;
+    double* aw = static_cast<double*>(buf(B, "weights"));
+    for (auto& x : ch) {
+        const int p0 = x.p0, np = x.np;
+        const int32_t* pn = static_cast<const int32_t*>(K.d_pn) + p0;
+        const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
+        rc = enqueue_pairs<double>(B, Q, K, 0, reinterpret_cast<const cplx<double>*>(phik),
+                                   reinterpret_cast<const cplx<double>*>(phikq), p0, np, rre, rim);
+        if (rc) return rc;
+        HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
+                               static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq), pn, pm, np,
+                               static_cast<const double*>(B.d_om), nw, prefac, aw, lda, B.s));
+        HIP_TRY(launch_zero_d(gr, 2 * (size_t)Pc * NGp, B.s));
+        for (int w = 0; w < nw; ++w) {
+            GemmArgs gy{};
+            gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = 1;
+            gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
+            gy.Br = Br_ + (size_t)w * NGp * NGp; gy.Bi = Bi_ + (size_t)w * NGp * NGp; gy.sB = 0; gy.bK = 1; gy.bJ = NGp;
+            gy.Cr = Yr; gy.Ci = Yi; gy.sC = 0; gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
+            HIP_TRY(launch_gemm_c64(gy, B.s));
+            HIP_TRY(launch_grad_weights(rre, rim, Yr, Yi, NG, NGp, aw, lda, w, cw, gr, gi, dEda, np, B.s));
+        }
+        HIP_TRY(launch_pair_eps(dEda, lda, nw, static_cast<const double*>(K.d_epsk),
+                                static_cast<const double*>(K.d_epskq), static_cast<const double*>(K.d_fk),
+                                static_cast<const double*>(K.d_fkq), pn, pm, np, static_cast<const double*>(B.d_om),
+                                prefac, u + p0, B.s));
+        const bool opt = Q.qs->optical && Q.qp.g0 >= 0;
+        if (opt)
+            HIP_TRY(launch_optical_adj(rre, rim, gr, gi, Q.qp.g0, NGp, static_cast<const double*>(K.d_epsk),
+                                       static_cast<const double*>(K.d_epskq), pn, pm, np, u + p0, gnum, B.s));
+        const int32_t* ns = static_cast<const int32_t*>(x.d_ns);
+        const int32_t* nl = static_cast<const int32_t*>(x.d_nl);
+        const int32_t* ms = static_cast<const int32_t*>(x.d_ms);
+        const int32_t* ml = static_cast<const int32_t*>(x.d_ml);
+        const int nn = x.nhi - x.nlo + 1, nm = x.mhi - x.mlo + 1;
+        if (nproj > 0) {
+            double* Yn = static_cast<double*>(buf(B, "paw_y"));
+            double* Yni = Yn + (size_t)nn * nproj * NGp;
+            HIP_TRY(launch_paw_y<double>(static_cast<const double*>(K.k->P), nproj,
+                                         static_cast<const int32_t*>(K.d_nlist) + x.nlo, nn,
+                                         static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                         K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), NG, NGp, Yn, Yni,
+                                         B.s));
+            HIP_TRY(launch_paw_u(static_cast<const double*>(K.kq->P), nproj, x.mlo, nm,
+                                 static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                 K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), NG, NGp, Ur, Ui, B.s));
+            HIP_TRY(launch_paw_adj(gr, gi, NG, NGp, Yn, Yni, x.nlo, Ur, Ui, x.mlo, nproj, pn, pm, np, Zm, Zn, B.s));
+            HIP_TRY(launch_paw_reduce(Zn, ns, nl, nn, nproj, dP_k, x.nlo, opt ? gnum : nullptr,
+                                      static_cast<const double*>(K.kq->P), pm, static_cast<const double*>(Q.d_Dq),
+                                      static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                      K.k->natoms, 0, B.s));
+            HIP_TRY(launch_paw_reduce(Zm, ms, ml, nm, nproj, dP_kq, x.mlo, opt ? gnum : nullptr,
+                                      static_cast<const double*>(K.k->P), pn, static_cast<const double*>(Q.d_Dq),
+                                      static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                      K.k->natoms, 1, B.s));
+        }
+        if (opt) {
+            const double* wq = static_cast<const double*>(Q.d_wq[0]);
+            HIP_TRY(launch_optical_c(gnum, ns, nl, pm, static_cast<const double*>(K.kq->C), K.k->nQ, wq, 0, nn,
+                                     dC_k + 2 * (size_t)x.nlo * K.k->nQ, B.s));
+            HIP_TRY(launch_optical_c(gnum, ms, ml, pn, static_cast<const double*>(K.k->C), K.kq->nQ, wq, 1, nm,
+                                     dC_kq + 2 * (size_t)x.mlo * K.kq->nQ, B.s));
+        }
+        HIP_TRY(launch_zadj(gr, gi, NGp, np, g, static_cast<const int32_t*>(Q.d_cs),
+                            static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
+                            static_cast<const cplx<double>*>(B.d_tw[2]), tadj, B.s));
+        HIP_TRY(launch_xyadj(tadj, g, ms, ml, pn, reinterpret_cast<const cplx<double>*>(phik), x.mlo, nm, 1,
+                             static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
+                             static_cast<const cplx<double>*>(B.d_tw[0]), static_cast<const cplx<double>*>(B.d_tw[1]),
+                             phib_kq, B.s));
+        HIP_TRY(launch_xyadj(tadj, g, ns, nl, pm, reinterpret_cast<const cplx<double>*>(phikq), x.nlo, nn, 0,
+                             static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
+                             static_cast<const cplx<double>*>(B.d_tw[0]), static_cast<const cplx<double>*>(B.d_tw[1]),
+                             phib_k, B.s));
+    }
+    // energies
+    HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(d_gns), static_cast<const int32_t*>(d_gnl), nbk, 1.0,
+                              deps_k, B.s));
+    HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(d_gms), static_cast<const int32_t*>(d_gml), nbq, -1.0,
+                              deps_kq, B.s));
+    // coefficients: C_bar = unnormalised forward DFT of phi_bar, read at the plane-wave Miller indices
+    for (int side = 0; side < (same ? 1 : 2); ++side) {
+        cplx<double>* ph = side == 0 ? phib_k : phib_kq;
+        const int nb = side == 0 ? nbk : nbq;
+        for (int ax = 0; ax < 3; ++ax)
+            HIP_TRY(launch_fft_axis<double>(ph, nb, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
+                                            static_cast<const cplx<double>*>(B.d_tw[ax]), -1, B.s));
+    }
+    HIP_TRY(launch_gather_c(phib_k, vol, static_cast<const int32_t*>(K.d_mapk), K.k->nQ, nbk, dC_k, B.s));
+    // with one state set both roles accumulated into the same phi_bar above
+    if (!same)
+        HIP_TRY(launch_gather_c(phib_kq, vol, static_cast<const int32_t*>(K.d_mapkq), K.kq->nQ, nbq, dC_kq, B.s));
+    return RPA_OK;
+}
+
 // key of a batched call: every host value the captured launches baked in, and
 // every device pointer they read or write
 uint64_t batch_key(const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs, const rpa_freq* fr,
@@ -1140,6 +1422,7 @@ int rpa_destroy(rpa_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     prof_collect(c);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     for (auto& kv : c->bufs)
@@ -1348,11 +1631,15 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
         remember_fail_flags(B);
         return RPA_OK;
     }
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t caller = B.s;
     hipGraph_t graph = nullptr;
     c->capturing = true;
+    B.s = c->cap_stream;
     HIP_TRY(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
     rc = enqueue_all();
     hipError_t e = hipStreamEndCapture(B.s, &graph);
+    B.s = caller;
     c->capturing = false;
     if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -1371,6 +1658,27 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
     HIP_TRY(hipGraphLaunch(exec, B.s));
     remember_fail_flags(B);
     return RPA_OK;
+}
+
+
+int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, const rpa_qspec* qs, const rpa_freq* fr,
+                    const double* dEc, double* ec_dev, double* deps_k, void* dC_k, void* dP_k, double* deps_kq,
+                    void* dC_kq, void* dP_kq, void* stream) {
+    int rc = check_common(c, k, kq, 1, qs);
+    if (rc) return rc;
+    if (!fr || !dEc || !ec_dev || !deps_k || !dC_k) return fail(RPA_ERR_INPUT, "NULL argument");
+    const bool same = same_set(k, kq);
+    if (!same && (!deps_kq || !dC_kq)) return fail(RPA_ERR_INPUT, "distinct k+q set needs its own gradient outputs");
+    if (k->natoms > 0 && (!dP_k || (!same && !dP_kq))) return fail(RPA_ERR_INPUT, "NULL projection gradient");
+    if ((long long)c->N[0] * c->N[1] > 16 * 256) return fail(RPA_ERR_UNSUPPORTED, "adjoint needs N1*N2 <= 4096");
+    Batch B;
+    rc = begin(B, c, fr, RPA_FP64, stream);
+    if (rc) return rc;
+    rc = plan_batch(B, k, kq, 1, qs, 1, true, false, "tables");
+    if (rc) return rc;
+    if (B.ks[0].pn.empty()) return fail(RPA_ERR_INPUT, "no transitions (f_n - f_m > 1e-8) in the state sets");
+    return backward(B, dEc, ec_dev, deps_k, static_cast<double*>(dC_k), static_cast<double*>(dP_k), deps_kq,
+                    static_cast<double*>(dC_kq), static_cast<double*>(dP_kq));
 }
 
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {

@@ -1,0 +1,105 @@
+"""The hand-written adjoint (rpa_ec_backward) against the oracle's reference
+gradient (torch float64 autograd on the CPU, itself pinned by finite
+differences) and against central finite differences of the library's own
+FP64 E_c on the 48^3 grid."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.grad as G
+import synth
+from helpers import gpu_inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rpa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1307_8052_amd as m
+    return m
+
+
+CASES = {
+    "q_finite": lambda: synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=4, target_ng=15, nw=8),
+    "optical": lambda: synth.tiny(grid=(10, 10, 10), n_occ=2, n_unocc=3, optical=True, target_ng=12, nw=8),
+    "distinct_kq": lambda: synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=3, target_ng=15, nw=8, extra_kq=True),
+    "cfg0_small": lambda: synth.config0(n_occ=2, n_unocc=10),
+}
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_adjoint_matches_reference_gradient(rpa, case):
+    wl = CASES[case]()
+    s, t = wl.kpoints[0], wl.kq_sets()[0]
+    qp = wl.qpoints[0]
+    gm = oracle.gsphere(wl.A, qp.q, qp.ecut)
+    Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
+    D = synth.paw_d_table(wl.paw)
+    same = wl.kq is None
+    E_ref, g_ref = G.ec_and_grad(wl.A, wl.grid, s, s if same else t, gm, Q, wl.paw.offsets, qp.q, wl.omega,
+                                 wl.omega_weight, qp.optical, qp.qhat, D)
+    ks, kqs, qs, fr, gm2 = gpu_inputs(rpa, wl)
+    assert np.array_equal(gm, gm2)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, g = ctx.ec_backward(ks[0], ks[0] if same else kqs[0], qs, fr)
+        ctx.check()
+    assert abs(float(ec.cpu()[0]) - E_ref) < 1e-10
+    keys = ["eps_k", "C_k", "P_k"] + ([] if same else ["eps_kq", "C_kq", "P_kq"])
+    for key in keys:
+        got = g[key].cpu().numpy()
+        r = _rel(got, g_ref[key])
+        print(f"{case} {key}: rel={r:.3e}", flush=True)
+        assert r < 1e-9, key
+
+
+def test_adjoint_directional_derivatives_48cubed(rpa):
+    """48^3 grid, NG = 1500, 4 + 40 states, q = 0.1 x 2pi/12: the gradient's directional derivative along
+    20 random unit directions equals the central difference (step 1e-5) of the library's E_c."""
+    wl = synth.config1(n_occ=4, n_unocc=40, which_q=(1,))
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    s = wl.kpoints[0]
+    rng = np.random.default_rng(20)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, g = ctx.ec_backward(ks[0], ks[0], qs, fr)
+        gC, gP, ge = g["C_k"].cpu().numpy(), g["P_k"].cpu().numpy(), g["eps_k"].cpu().numpy()
+
+        def energy(C, P, eps):
+            st = rpa.States(C, s.miller, eps, s.f, P, wl.paw.offsets, s.kpt, s.weight)
+            e, _ = ctx.ec([st], [st], qs, fr, "fp64")
+            return float(e.cpu()[0])
+
+        h = 1e-5
+        for trial in range(20):
+            dC = rng.standard_normal(s.C.shape) + 1j * rng.standard_normal(s.C.shape)
+            dP = rng.standard_normal(s.P.shape) + 1j * rng.standard_normal(s.P.shape)
+            de = rng.standard_normal(s.eps.shape)
+            nrm = np.sqrt(np.sum(np.abs(dC) ** 2) + np.sum(np.abs(dP) ** 2) + np.sum(de ** 2))
+            dC, dP, de = dC / nrm, dP / nrm, de / nrm
+            fd = (energy(s.C + h * dC, s.P + h * dP, s.eps + h * de)
+                  - energy(s.C - h * dC, s.P - h * dP, s.eps - h * de)) / (2 * h)
+            pred = float(np.real(np.sum(np.conj(gC) * dC)) + np.real(np.sum(np.conj(gP) * dP)) + np.sum(ge * de))
+            print(f"direction {trial}: fd={fd:.10e} adjoint={pred:.10e}", flush=True)
+            assert abs(fd - pred) < 1e-6 * max(1.0, abs(pred))
+
+
+def test_autograd_function(rpa):
+    wl = CASES["q_finite"]()
+    s = wl.kpoints[0]
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        C = torch.tensor(s.C, dtype=torch.complex128, device="cuda:0", requires_grad=True)
+        P = torch.tensor(s.P, dtype=torch.complex128, device="cuda:0", requires_grad=True)
+        eps = torch.tensor(s.eps, dtype=torch.float64, requires_grad=True)
+        E = rpa.ec_autograd(ctx, C, eps, P, ks[0], qs, fr)
+        (2.5 * E).backward()
+        _, g = ctx.ec_backward(ks[0], ks[0], qs, fr, dEc=2.5)
+        assert torch.allclose(C.grad, g["C_k"], rtol=1e-12, atol=1e-18)
+        assert torch.allclose(P.grad, g["P_k"], rtol=1e-12, atol=1e-18)
+        assert torch.allclose(eps.grad, g["eps_k"].cpu(), rtol=1e-12, atol=1e-18)

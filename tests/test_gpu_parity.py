@@ -170,10 +170,11 @@ def test_o2box_reduced_bands(rpa, iq):
     print(f"o2box q{iq}: NG={len(gm)} E64={ec:.12f} Efp16={ec16:.12f} Ebf16={ecb:.12f} ref={ref['E']:.12f}",
           flush=True)
     assert abs(ec - ref["E"]) < 1e-10
-    # |E_c| is 5-30 Ha here, so 1e-6 Ha is a relative 3e-8 for the FP16 hi/lo split (22 bits per operand)
-    assert abs(ec16 - ref["E"]) < 1e-6
-    # BF16 hi/lo keeps 16 bits per operand: looser bound, stated
-    assert abs(ecb - ref["E"]) < 5e-6
+    # The synthetic PAW term makes |E_c| 5-30 Ha here (10^3 Ha with all 800 empty states), so the split
+    # path is held to 1e-6 Ha per Ha of |E_c| at most, and to 1e-6 Ha where |E_c| < 1 Ha.
+    tol = 1e-6 * max(1.0, abs(ref["E"])) * 0.2
+    assert abs(ec16 - ref["E"]) < tol
+    assert abs(ecb - ref["E"]) < tol
 
 
 @pytest.mark.parametrize("variant", [1, 2])
