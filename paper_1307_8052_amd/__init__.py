@@ -310,6 +310,10 @@ class Context:
         _check(self._L.rpa_autotune(self._h, _prec(precision), int(NG), int(npairs), int(nw), _stream()), self._h)
         return self.tune_get(NG, precision)
 
+    def set_pair_path(self, path: int):
+        """0: register-resident pair transforms where the grid allows, 1: LDS radix passes."""
+        _check(self._L.rpa_set_pair_path(self._h, int(path)), self._h)
+
     def tune_set(self, NG: int, variant: int, precision="split_bf16"):
         _check(self._L.rpa_tune_set(self._h, _prec(precision), int(NG), int(variant)), self._h)
 

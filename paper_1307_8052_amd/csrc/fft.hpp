@@ -182,6 +182,70 @@ template <int DIR, typename T> struct Dft<12, DIR, T> { static RPA_HD void run(c
 template <int DIR, typename T> struct Dft<16, DIR, T> { static RPA_HD void run(cplx<T>* v) { dft_split<4, 4, DIR, T>(v); } };
 
 // ---------------------------------------------------------------------------
+// whole lines in registers: an N-point DFT (N = 2^a 3^b 5^c, known at compile
+// time) by recursive Cooley-Tukey splits N = A * (N / A), A the first of 4, 3,
+// 2, 5 dividing N. Every index and twiddle is a compile-time constant, so a
+// thread holds its line in registers and no LDS or twiddle table is touched.
+// ---------------------------------------------------------------------------
+template <int N>
+struct RegRadix {
+    static constexpr int value = (N % 4 == 0 && N > 5) ? 4 : (N % 3 == 0) ? 3 : (N % 2 == 0) ? 2 : 5;
+};
+
+template <int N, int DIR, typename T> struct RegFft;
+
+template <int A, int B, int DIR, typename T>
+RPA_HD void reg_split(cplx<T>* x) {
+    constexpr int R = A * B;
+    constexpr Roots<R> W{};
+    cplx<T> y[R];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+        cplx<T> t[A];
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) t[n1] = x[B * n1 + n2];
+        Dft<A, DIR, T>::run(t);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            const int e = (n2 * k1) % R;
+            if (e == 0) {
+                y[n2 * A + k1] = t[k1];
+            } else {
+                cplx<T> w = mk(T(W.c[e]), T(DIR * W.s[e]));
+                y[n2 * A + k1] = t[k1] * w;
+            }
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        cplx<T> t[B];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) t[n2] = y[n2 * A + k1];
+        RegFft<B, DIR, T>::run(t);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) x[k1 + A * k2] = t[k2];
+    }
+}
+
+template <int N, int DIR, typename T>
+struct RegFft {
+    static RPA_HD void run(cplx<T>* x) {
+        if constexpr (N == 1) {
+            (void)x;
+        } else if constexpr (N == 2 || N == 3 || N == 4 || N == 5) {
+            Dft<N, DIR, T>::run(x);
+        } else {
+            constexpr int A = RegRadix<N>::value;
+            static_assert(N % A == 0, "register DFT length must be 2^a 3^b 5^c");
+            reg_split<A, N / A, DIR, T>(x);
+        }
+    }
+};
+
+// Line lengths with register-resident kernels (other lengths use the LDS passes).
+#define RPA_REG_SIZES(X) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
+
+// ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
 constexpr int kMaxStages = 8;

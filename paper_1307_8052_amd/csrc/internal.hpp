@@ -22,6 +22,7 @@ struct PairGeom {
     int ncols;            // K1*K2 columns (m1, m2) of the sphere's bounding box
     int NG, NGp;          // sphere size and its padded size
     FftPlan p1, p2, p3;
+    int x0, y0;           // grid index of the first kept x / y frequency (the kept sets wrap modulo N)
 };
 
 // ----------------------------------------------------------------- FFT stages
@@ -42,6 +43,16 @@ hipError_t launch_pair_xy(const cplx<T>* phik, const cplx<T>* phikq, const int32
                           int npairs, const PairGeom& g, const int32_t* kx_grid, const int32_t* ky_grid,
                           const cplx<T>* tw1, const cplx<T>* tw2, cplx<T>* tbuf, hipStream_t s);
 
+// Register-resident variants of the two pair kernels (same tbuf layout and
+// output); supported when N1 == N2 and N1, N3 have compiled line lengths.
+template <typename T>
+bool pair_reg_supported(const PairGeom& g);
+template <typename T>
+hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const int32_t* pn, const int32_t* pm,
+                              int npairs, const PairGeom& g, cplx<T>* tbuf, hipStream_t s);
+template <typename T>
+hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
+                             const int32_t* col_g, const int32_t* col_kz, T* rho_re, T* rho_im, hipStream_t s);
 template <typename T>
 hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
                                 const int32_t* col_g, const int32_t* col_kz, const cplx<T>* tw3, T* rho_re,

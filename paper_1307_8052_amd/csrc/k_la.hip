@@ -345,82 +345,98 @@ __global__ void k_zero_i(int* p, int n) {
 //
 // Panel: factor the 64x64 diagonal block at j0 in LDS, accumulate its log-det,
 // and store the inverse of its lower-triangular factor for the row solve.
+//
+// Both the factorisation and the inversion are right-looking and keep their
+// columns unscaled (the pivot of column c is s_c = sqrt(1 + A_cc), so
+// L_rc L_jc^* = A_rc A_jc^* / (1 + A_cc)); the scaling is applied once when the
+// results are written. Lane j owns column j, wave v walks rows r = v (mod 4):
+// A[r][c] is a broadcast read and A[r][j] a contiguous one, and every thread
+// computes the pivot itself, so each column costs one barrier.
+constexpr int kPanelLd = kTile + 1;
 __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, double* __restrict__ Cim,
                                                     int ldC, long long sC, int j0, double* __restrict__ Lre,
                                                     double* __restrict__ Lim, double* __restrict__ logdet,
                                                     int* __restrict__ fail) {
-    __shared__ double sr[kTile][kTile + 1], si[kTile][kTile + 1];
-    __shared__ double vr[kTile][kTile + 1], vi[kTile][kTile + 1];
-    __shared__ double pinv, ldacc;
-    __shared__ int bad;
+    __shared__ double2 a[kTile][kPanelLd];
+    __shared__ double2 v[kTile][kPanelLd];
+    __shared__ double piv[kTile];
     const int w = blockIdx.x, tid = threadIdx.x;
+    const int j = tid & (kTile - 1), wv = tid >> 6;
     double* cr = Cre + (size_t)w * sC;
     double* ci = Cim + (size_t)w * sC;
     for (int e = tid; e < kTile * kTile; e += blockDim.x) {
         const int r = e >> 6, c = e & 63;
         const bool low = c <= r;
-        sr[r][c] = low ? cr[(size_t)(j0 + r) * ldC + j0 + c] : 0.0;
-        si[r][c] = low ? ci[(size_t)(j0 + r) * ldC + j0 + c] : 0.0;
-        vr[r][c] = 0.0;
-        vi[r][c] = 0.0;
+        a[r][c] = low ? make_double2(cr[(size_t)(j0 + r) * ldC + j0 + c], ci[(size_t)(j0 + r) * ldC + j0 + c])
+                      : make_double2(0.0, 0.0);
+        v[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
-    if (tid == 0) { ldacc = 0.0; bad = 0; }
+    double ldacc = 0.0;
+    int bad = 0;
     __syncthreads();
+    // factorisation: A[r][j] -= A[r][c] conj(A[j][c]) / (1 + A[c][c]) for c < j <= r
     for (int c = 0; c < kTile; ++c) {
+        const double d = a[c][c].x;
         if (tid == 0) {
-            const double d = sr[c][c];
             if (!(1.0 + d > 0.0) && !bad) bad = j0 + c + 1;
             ldacc += log1p(d);
-            const double s = sqrt(1.0 + d);
-            sr[c][c] = s;
-            si[c][c] = 0.0;
-            pinv = 1.0 / s;
+            piv[c] = sqrt(1.0 + d);
         }
-        __syncthreads();
-        for (int r = c + 1 + tid; r < kTile; r += blockDim.x) {
-            sr[r][c] *= pinv;
-            si[r][c] *= pinv;
-        }
-        __syncthreads();
-        const int m = kTile - 1 - c;
-        for (int e = tid; e < m * m; e += blockDim.x) {
-            const int r = c + 1 + e / m, cc = c + 1 + e % m;
-            if (cc <= r) {
-                // A[r][cc] -= L[r][c] conj(L[cc][c])
-                const double ar = sr[r][c], ai = si[r][c], br = sr[cc][c], bi = si[cc][c];
-                sr[r][cc] -= ar * br + ai * bi;
-                si[r][cc] -= ai * br - ar * bi;
+        if (j > c) {
+            const double inv = 1.0 / (1.0 + d);
+            const double2 ajc = a[j][c];
+            const double br = ajc.x * inv, bi = -ajc.y * inv;
+            for (int r = c + 1 + ((wv - c - 1) & 3); r < kTile; r += 4) {
+                if (r < j) continue;
+                const double2 arc = a[r][c];
+                double2 x = a[r][j];
+                x.x -= arc.x * br - arc.y * bi;
+                x.y -= arc.x * bi + arc.y * br;
+                a[r][j] = x;
             }
         }
         __syncthreads();
     }
-    // inverse of the lower-triangular factor, one column per thread
-    if (tid < kTile) {
-        const int c = tid;
-        vr[c][c] = 1.0 / sr[c][c];
-        vi[c][c] = 0.0;
-        for (int r = c + 1; r < kTile; ++r) {
-            double xr = 0, xi = 0;
-            for (int k = c; k < r; ++k) {
-                xr += sr[r][k] * vr[k][c] - si[r][k] * vi[k][c];
-                xi += sr[r][k] * vi[k][c] + si[r][k] * vr[k][c];
+    // inverse: W[r][j] -= A[r][k] W[k][j] / (1 + A[k][k]) for j <= k < r; V = W / s_r
+    for (int k = 0; k < kTile - 1; ++k) {
+        if (j <= k) {
+            const double s = piv[k];
+            const double inv = 1.0 / (s * s);
+            const double2 wkj = v[k][j];
+            const double br = wkj.x * inv, bi = wkj.y * inv;
+            for (int r = k + 1 + ((wv - k - 1) & 3); r < kTile; r += 4) {
+                const double2 ark = a[r][k];
+                double2 x = v[r][j];
+                x.x -= ark.x * br - ark.y * bi;
+                x.y -= ark.x * bi + ark.y * br;
+                v[r][j] = x;
             }
-            const double inv = 1.0 / sr[r][r];
-            vr[r][c] = -xr * inv;
-            vi[r][c] = -xi * inv;
         }
+        __syncthreads();
     }
-    __syncthreads();
     double* lr = Lre + (size_t)w * kTile * kTile;
     double* li = Lim + (size_t)w * kTile * kTile;
     for (int e = tid; e < kTile * kTile; e += blockDim.x) {
         const int r = e >> 6, c = e & 63;
-        lr[e] = vr[r][c];
-        li[e] = vi[r][c];
-        // the factor itself replaces the lower triangle of the block
         if (c <= r) {
-            cr[(size_t)(j0 + r) * ldC + j0 + c] = sr[r][c];
-            ci[(size_t)(j0 + r) * ldC + j0 + c] = si[r][c];
+            const double sr = 1.0 / piv[r];
+            lr[e] = v[r][c].x * sr;
+            li[e] = v[r][c].y * sr;
+            // the factor itself replaces the lower triangle of the block
+            double xr, xi;
+            if (c == r) {
+                xr = piv[c];
+                xi = 0.0;
+            } else {
+                const double sc = 1.0 / piv[c];
+                xr = a[r][c].x * sc;
+                xi = a[r][c].y * sc;
+            }
+            cr[(size_t)(j0 + r) * ldC + j0 + c] = xr;
+            ci[(size_t)(j0 + r) * ldC + j0 + c] = xi;
+        } else {
+            lr[e] = 0.0;
+            li[e] = 0.0;
         }
     }
     if (tid == 0) {

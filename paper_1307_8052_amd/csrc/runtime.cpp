@@ -78,6 +78,7 @@ struct rpa_ctx {
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_key = 0;
     bool capturing = false;
+    bool pair_reg = true;   // register-resident pair transforms where supported
     // non-blocking stream the batch sequence is captured on (the legacy default stream cannot be)
     hipStream_t cap_stream = nullptr;
 };
@@ -350,6 +351,8 @@ int plan_q(rpa_ctx* c, const rpa_qspec* qs, QPlan& P, bool need_coulomb) {
     P.ky.resize(g.K2);
     for (int i = 0; i < g.K1; ++i) P.kx[i] = ((lo[0] + i) % g.N1 + g.N1) % g.N1;
     for (int i = 0; i < g.K2; ++i) P.ky[i] = ((lo[1] + i) % g.N2 + g.N2) % g.N2;
+    g.x0 = P.kx[0];
+    g.y0 = P.ky[0];
     // entries sorted by column (m1, m2); value = G index, (kz << 16) | column
     std::vector<int> order(NG);
     std::vector<int> col(NG);
@@ -762,17 +765,26 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     cplx<T>* tb = static_cast<cplx<T>*>(buf(B, "tbuf"));
     const int32_t* pn = static_cast<const int32_t*>(K.d_pn) + p0;
     const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
+    const bool reg = c->pair_reg && pair_reg_supported<T>(g);
     {
         ProfScope ps_(c, S_PAIR_XY, B.s);
-        HIP_TRY(launch_pair_xy<T>(phik, phikq, pn, pm, np, g, static_cast<const int32_t*>(Q.d_kx),
-                                  static_cast<const int32_t*>(Q.d_ky), static_cast<const cplx<T>*>(B.d_tw[0]),
-                                  static_cast<const cplx<T>*>(B.d_tw[1]), tb, B.s));
+        if (reg)
+            HIP_TRY(launch_pair_xy_reg<T>(phik, phikq, pn, pm, np, g, tb, B.s));
+        else
+            HIP_TRY(launch_pair_xy<T>(phik, phikq, pn, pm, np, g, static_cast<const int32_t*>(Q.d_kx),
+                                      static_cast<const int32_t*>(Q.d_ky), static_cast<const cplx<T>*>(B.d_tw[0]),
+                                      static_cast<const cplx<T>*>(B.d_tw[1]), tb, B.s));
     }
     {
         ProfScope ps_(c, S_PAIR_Z, B.s);
-        HIP_TRY(launch_pair_z_gather<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
-                                        static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
-                                        static_cast<const cplx<T>*>(B.d_tw[2]), rre, rim, B.s));
+        if (reg)
+            HIP_TRY(launch_pair_z_reg<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
+                                         static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz), rre,
+                                         rim, B.s));
+        else
+            HIP_TRY(launch_pair_z_gather<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
+                                            static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
+                                            static_cast<const cplx<T>*>(B.d_tw[2]), rre, rim, B.s));
     }
     const int nproj = nproj_total(K.k);
     if (nproj > 0) {
@@ -1679,6 +1691,14 @@ int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, const
     if (B.ks[0].pn.empty()) return fail(RPA_ERR_INPUT, "no transitions (f_n - f_m > 1e-8) in the state sets");
     return backward(B, dEc, ec_dev, deps_k, static_cast<double*>(dC_k), static_cast<double*>(dP_k), deps_kq,
                     static_cast<double*>(dC_kq), static_cast<double*>(dP_kq));
+}
+
+int rpa_set_pair_path(rpa_ctx* ctx, int path) {
+    if (!ctx) return fail(RPA_ERR_INPUT, "NULL context");
+    if (path != 0 && path != 1) return fail(RPA_ERR_INPUT, "pair path must be 0 or 1");
+    if (ctx->pair_reg != (path == 0)) drop_graph(ctx);
+    ctx->pair_reg = path == 0;
+    return RPA_OK;
 }
 
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {

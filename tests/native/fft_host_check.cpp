@@ -29,3 +29,30 @@ extern "C" int fft_lines_host(int N, int dir, int nlines, const double* in, doub
     for (int i = 0; i < nlines * N; ++i) { out[2 * i] = src[i].x; out[2 * i + 1] = src[i].y; }
     return 0;
 }
+
+// One line through the register-resident transform of the same header.
+template <int N>
+static void reg_line(int dir, const double* in, double* out) {
+    cplx<double> v[N];
+    for (int i = 0; i < N; ++i) v[i] = rpa::mk(in[2 * i], in[2 * i + 1]);
+    if (dir < 0) rpa::RegFft<N, -1, double>::run(v);
+    else rpa::RegFft<N, +1, double>::run(v);
+    for (int i = 0; i < N; ++i) { out[2 * i] = v[i].x; out[2 * i + 1] = v[i].y; }
+}
+
+extern "C" int fft_reg_sizes(int* out, int cap) {
+    int n = 0;
+#define RPA_LIST(N) if (n < cap) out[n] = N; ++n;
+    RPA_REG_SIZES(RPA_LIST)
+#undef RPA_LIST
+    return n;
+}
+
+extern "C" int fft_reg_host(int N, int dir, const double* in, double* out) {
+    switch (N) {
+#define RPA_CASE(L) case L: reg_line<L>(dir, in, out); return 0;
+        RPA_REG_SIZES(RPA_CASE)
+#undef RPA_CASE
+        default: return -1;
+    }
+}

@@ -38,3 +38,32 @@ def test_stockham_matches_numpy(lib, N, direction):
 def test_unsupported_length_is_rejected(lib):
     x = np.zeros(7, dtype=np.complex128)
     assert lib.fft_lines_host(7, -1, 1, x.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p)) == -1
+
+
+def _reg_sizes(L):
+    buf = (ctypes.c_int * 64)()
+    n = L.fft_reg_sizes(buf, 64)
+    return [buf[i] for i in range(min(n, 64))]
+
+
+def test_register_lengths_match_numpy(lib):
+    """Every length with a register-resident kernel, both directions, on random lines
+    (the transform is linear, so three random lines per length cover every output)."""
+    sizes = _reg_sizes(lib)
+    assert sizes and 48 in sizes and 16 in sizes
+    for N in sizes:
+        rng = np.random.default_rng(1000 + N)
+        for direction in (-1, 1):
+            for _ in range(3):
+                x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+                out = np.empty_like(x)
+                rc = lib.fft_reg_host(N, direction, x.ctypes.data_as(ctypes.c_void_p),
+                                      out.ctypes.data_as(ctypes.c_void_p))
+                assert rc == 0
+                ref = np.fft.fft(x) if direction < 0 else np.fft.ifft(x) * N
+                assert np.max(np.abs(out - ref)) < 1e-13 * N, (N, direction)
+
+
+def test_register_unsupported_length_is_rejected(lib):
+    x = np.zeros(7, dtype=np.complex128)
+    assert lib.fft_reg_host(7, -1, x.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p)) == -1

@@ -42,9 +42,12 @@ WORKLOADS = {
 }
 
 
+@pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("name", list(WORKLOADS))
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
-def test_pair_density(rpa, name, prec):
+def test_pair_density(rpa, name, prec, path):
+    """Path 0 runs the register-resident transforms where the grid has them (8^3, 10^3, 12^3, 16^3; the
+    6x8x10 grid falls back to the LDS passes), path 1 always the LDS passes."""
     wl = WORKLOADS[name]()
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
     s, t = wl.kpoints[0], wl.kq_sets()[0]
@@ -55,9 +58,11 @@ def test_pair_density(rpa, name, prec):
     _, rho_ref = oracle.pair_densities(wl.A, wl.grid, s, t, ref_g, Q, wl.paw.offsets, wl.qpoints[0].optical,
                                        wl.qpoints[0].qhat, synth.paw_d_table(wl.paw))
     with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_pair_path(path)
         rho = ctx.pair_density(ks[0], kqs[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
     tol = 1e-12 if prec == "fp64" else 2e-6
-    print(f"{name} {prec}: pairs={pairs[0].size} NG={len(gm)} rel={_rel(rho, rho_ref):.3e}", flush=True)
+    print(f"{name} {prec} path {path}: pairs={pairs[0].size} NG={len(gm)} rel={_rel(rho, rho_ref):.3e}",
+          flush=True)
     assert _rel(rho, rho_ref) < tol
 
 
@@ -79,12 +84,14 @@ def test_pair_density_unsorted_pairs_and_diagonal(rpa):
     assert np.allclose(rho[:, g0], (pn == pm).astype(float), atol=1e-13)
 
 
+@pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("name", ["tiny8", "tiny12_distinct_kq", "tiny10_optical", "cfg0"])
-def test_chi0_and_ec_fp64(rpa, name):
+def test_chi0_and_ec_fp64(rpa, name, path):
     wl = WORKLOADS[name]()
     ref = oracle_q(wl)
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
     with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_pair_path(path)
         chi = ctx.chi0(ks, kqs, qs, fr, "fp64").cpu().numpy()
         ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
         ctx.check()
@@ -153,6 +160,29 @@ def test_alias_and_shape_errors_before_launch(rpa):
         with pytest.raises(rpa.RpaError) as ei:
             ctx.ec([bad], [bad], qs, fr)
         assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_o2box_pair_density_register_path(rpa, prec):
+    """48^3 grid, NG = 1503 (optical q): 2 occupied x 12 unoccupied pairs through the register-resident
+    transforms, element by element against the oracle, and equal (to rounding) to the LDS passes."""
+    wl = synth.config1(n_occ=2, n_unocc=12, which_q=(0,))
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    s = wl.kpoints[0]
+    pairs = oracle.pair_list(s.f, s.f)
+    Q = synth.paw_q_table(wl.paw, wl.A, wl.qpoints[0].q, gm)
+    _, ref = oracle.pair_densities(wl.A, wl.grid, s, s, gm, Q, wl.paw.offsets, wl.qpoints[0].optical,
+                                   wl.qpoints[0].qhat, synth.paw_d_table(wl.paw))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        reg = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+        ctx.set_pair_path(1)
+        lds = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    print(f"o2box pairs {prec}: reg rel={_rel(reg, ref):.3e} lds rel={_rel(lds, ref):.3e} "
+          f"reg-lds={_rel(reg, lds):.3e}", flush=True)
+    assert _rel(reg, ref) < tol
+    assert _rel(lds, ref) < tol
+    assert _rel(reg, lds) < tol
 
 
 @pytest.mark.parametrize("iq", [0, 1])
