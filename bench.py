@@ -71,6 +71,28 @@ def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False, use_graph=
     return (t1 - t0), ecs, prof
 
 
+HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 2: ("k_herk_split2", "k_herk_split2.hip"),
+                3: ("k_herk_split3", "k_herk_split2.hip")}
+
+
+def measured_traffic(kernel, src):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if that summary was
+    taken on the current source of the kernel (sha256 recorded in it); None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_o2box_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1307_8052_amd", "csrc", src), "rb").read()).hexdigest()
+    if fields.get("source_sha256") != sha or "bytes_per_launch" not in fields:
+        return None
+    return float(fields["bytes_per_launch"])
+
+
 def cpu_baseline(wl, iq=1, n_sample_occ=4):
     """The FP64 oracle on a bounded sample of the same workload: the chi0 build of
     q-point iq (orbitals, pair densities, PAW, weights, grouped update) for the
@@ -146,6 +168,7 @@ def main():
     herk_flops_step = flops_step
 
     ctx = rpa.Context(wl.A, wl.grid, device=0)
+    ctx_variant = ctx.tune_get(NGs[0], args.precision)
     # split path
     run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.warmup)
     dt, ec_split, prof = run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.steps, profile=True)
@@ -174,19 +197,22 @@ def main():
     stage_ms = {k: v[0] / args.steps for k, v in prof.items()}
     dominant = max(stage_ms, key=stage_ms.get)
     herk_ms, herk_n = prof["herk"]
-    # MFMA flops the split kernel issues: lower 64x64 tiles incl. the diagonal, K padded to 32,
+    # MFMA flops the split kernel issues: lower tiles (64 or 128 wide) incl. the diagonal, K padded to 32,
     # 12 real 16-bit products per complex multiply-add (4 real products x 3 split terms)
     executed = 0.0
     for ng in NGs:
-        nT = (ng + 63) // 64
-        executed += nT * (nT + 1) / 2 * nw * 64 * 64 * ((P + 31) // 32 * 32) * 12 * 2
+        tm = 64 if ctx_variant == 1 else 128
+        nT = (ng + tm - 1) // tm
+        executed += nT * (nT + 1) / 2 * nw * tm * tm * ((P + 31) // 32 * 32) * 12 * 2
     executed *= args.steps
     herk_avg_ms = herk_ms / max(herk_n, 1)
     achieved = herk_flops_step * args.steps / (herk_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    roofline = {"kernel": "k_herk_split (grouped complex rank-k update of chi0)", "bound": "mfma",
+    variant = ctx_variant
+    kname, ksrc = HERK_KERNELS[variant]
+    roofline = {"kernel": f"{kname} (grouped complex rank-k update of chi0, variant {variant})", "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "avg_launch_ms": herk_avg_ms, "launches": herk_n,
+                "traffic": measured_traffic(kname, ksrc), "avg_launch_ms": herk_avg_ms, "launches": herk_n,
                 "algorithmic_flops_per_launch": herk_flops_step / len(NGs),
                 "executed_mfma_tflops": executed / (herk_ms * 1e-3) / 1e12,
                 "executed_mfma_frac": executed / (herk_ms * 1e-3) / 1e12 / peak,

@@ -198,10 +198,12 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
 
 /* Rank-k kernel choice of the split precisions per padded sphere size
  * (NG rounded up to 64): variant 1 = 64x64 tiles staged from FP32 rho,
- * variant 2 = 128x128 tiles from the K-blocked pre-split rho. Without an
- * entry, NG >= 385 uses variant 2.
- *  rpa_autotune     times both variants on synthetic operands of the given
- *                   shape on `stream` (synchronizes) and records the faster.
+ * variant 2 = 128x128 tiles from the K-blocked pre-split rho, variant 3 = the
+ * same tiles and operands with a double-buffered, software-pipelined K loop
+ * (bit-identical to variant 2). Without an entry,
+ * NG >= 385 uses variant 3.
+ *  rpa_autotune     times the three variants on synthetic operands of the given
+ *                   shape on `stream` (synchronizes) and records the fastest.
  *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only).
  *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */
 int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, void* stream);

@@ -50,6 +50,11 @@ bool pair_reg_supported(const PairGeom& g);
 template <typename T>
 hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const int32_t* pn, const int32_t* pm,
                               int npairs, const PairGeom& g, cplx<T>* tbuf, hipStream_t s);
+// In-place 3-D transform of nb grids [nb][N3][N2][N1] (dir = +1 inverse without
+// 1/N, -1 forward) with register-resident lines; hipErrorNotSupported where the
+// register kernels do not cover the grid.
+template <typename T>
+hipError_t launch_grid_fft_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
 template <typename T>
 hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
                              const int32_t* col_g, const int32_t* col_kz, T* rho_re, T* rho_im, hipStream_t s);
@@ -116,7 +121,8 @@ struct HerkSplit2Args {
 };
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
                              int fp16, float* Xre, float* Xim, unsigned short* const B[4], hipStream_t s);
-hipError_t launch_herk_split2(const HerkSplit2Args& h, hipStream_t s);
+// pipelined = 1: double-buffered, branch-free K loop (same operands and result)
+hipError_t launch_herk_split2(const HerkSplit2Args& h, int pipelined, hipStream_t s);
 
 // -K = -v_i v_j chi_ij on the lower triangle (in place, planar), zero padding,
 // and Tr K per frequency.

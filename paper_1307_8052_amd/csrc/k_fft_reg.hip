@@ -1,5 +1,11 @@
-// Pair-density transforms (Eq. fft, Table 1 steps 5-6) with whole lines in
-// registers, for grid axes whose length has a compiled register transform.
+// Grid transforms with whole lines in registers, for grid axes whose length
+// has a compiled register transform: the orbitals of Eq. get_wfs (Table 1
+// step 3) and the pair densities of Eq. fft (Table 1 steps 5-6).
+//
+// Orbitals: k_fft_z_reg transforms every z-line in place (lanes take
+// consecutive x, so each load and store is coalesced without LDS);
+// k_fft_xy_reg takes one z-plane per workgroup through LDS, one thread per
+// x-row and then one per y-column.
 //
 // Same data flow and outputs as the LDS-pass kernels: k_pair_xy_reg leaves the
 // K2 x K1 kept (x, y) outputs of every z-plane of a pair in tbuf
@@ -9,10 +15,10 @@
 //     into LDS rows padded to N1 + 1 elements (so one thread per row reads
 //     without bank conflicts);
 //   * one thread transforms one x-line in registers (compile-time radix-4/3/2/5
-//     splits, constant twiddles) and writes its K1 kept outputs back into the
-//     start of its own row;
-//   * one thread transforms one kept y-column in registers and writes its K2
-//     kept outputs straight to tbuf;
+//     splits, constant twiddles) and writes it back into its own row;
+//   * one thread transforms one kept x-frequency column along y in place;
+//   * the kept K2 x K1 block of every plane goes to tbuf with coalesced stores
+//     (unconditional register stores keep the transforms branch-free);
 //   * along z one thread owns one column, LDS only holds the spectra for the
 //     sphere gather.
 #include "internal.hpp"
@@ -32,61 +38,88 @@ template <typename T, int N1, int N2>
 __global__ __launch_bounds__((xy_threads<T, N1>())) void k_pair_xy_reg(const cplx<T>* __restrict__ phik,
                                                      const cplx<T>* __restrict__ phikq,
                                                      const int32_t* __restrict__ pn,
-                                                     const int32_t* __restrict__ pm, PairGeom g, int S,
-                                                     cplx<T>* __restrict__ tbuf) {
+                                                     const int32_t* __restrict__ pm, int npairs, PairGeom g,
+                                                     int S, cplx<T>* __restrict__ tbuf) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<T>* X = reinterpret_cast<cplx<T>*>(smem);
     constexpr int LD = N1 + 1;
     constexpr int plane = N1 * N2;
-    const int K1 = g.K1, K2 = g.K2;
-    const int p = blockIdx.x;
-    const int z0 = blockIdx.y * S;
+    // Tasks t = slab * npairs + pair. Workgroup w runs on XCD w % 8; each XCD
+    // takes a contiguous range of t, so the pairs that share an orbital (the
+    // pair list runs over n fastest) meet in the same L2.
+    const unsigned ntask = gridDim.x, w = blockIdx.x;
+    const unsigned xcd = w & 7u, q = ntask >> 3, r = ntask & 7u;
+    const unsigned t = xcd * q + min(xcd, r) + (w >> 3);
+    const int slab = (int)(t / (unsigned)npairs);
+    const int p = (int)(t - (unsigned)slab * npairs);
+    const int z0 = slab * S;
     const int ns = min(S, g.N3 - z0);
     const size_t vol = (size_t)plane * g.N3;
     const cplx<T>* a0 = phik + (size_t)pn[p] * vol + (size_t)z0 * plane;
     const cplx<T>* b0 = phikq + (size_t)pm[p] * vol + (size_t)z0 * plane;
 
-    // conj(phi_n) phi_m on the slab, row (zs, y) at X[(zs N2 + y) LD]
+    // conj(phi_n) phi_m on the slab, row (zs, y) at X[(zs N2 + y) LD]; the loads of U elements are
+    // issued before any is used
     const int tot = ns * plane;
-    for (int f = threadIdx.x; f < tot; f += blockDim.x) {
-        const int row = f / N1, col = f - row * N1;
-        X[row * LD + col] = cmulc(a0[f], b0[f]);
+    constexpr int U = sizeof(T) == 4 ? 16 : 8;
+    for (int f0 = threadIdx.x; f0 < tot; f0 += U * blockDim.x) {
+        cplx<T> va[U], vb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int f = min(f0 + u * (int)blockDim.x, tot - 1);
+            va[u] = a0[f];
+            vb[u] = b0[f];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int f = f0 + u * (int)blockDim.x;
+            if (f < tot) {
+                const int row = f / N1, col = f - row * N1;
+                X[row * LD + col] = cmulc(va[u], vb[u]);
+            }
+        }
     }
     __syncthreads();
 
-    // x: one line per thread, K1 kept outputs back into the row
-    for (int l = threadIdx.x; l < ns * N2; l += blockDim.x) {
+    // x: one line per thread, transformed in place
+    const int l = threadIdx.x;
+    if (l < ns * N2) {
         cplx<T>* row = X + l * LD;
         cplx<T> v[N1];
 #pragma unroll
         for (int i = 0; i < N1; ++i) v[i] = row[i];
         RegFft<N1, -1, T>::run(v);
 #pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            int ix = k - g.x0;
-            if (ix < 0) ix += N1;
-            if (ix < K1) row[ix] = v[k];
-        }
+        for (int i = 0; i < N1; ++i) row[i] = v[i];
     }
     __syncthreads();
 
-    // y: one kept column per thread, K2 kept outputs to tbuf
-    const int kk = K1 * K2;
-    cplx<T>* to = tbuf + ((size_t)p * g.N3 + z0) * kk;
-    for (int l = threadIdx.x; l < ns * K1; l += blockDim.x) {
+    // y: one kept x-frequency column per thread, transformed in place
+    const int K1 = g.K1, K2 = g.K2;
+    if (l < ns * K1) {
         const int zs = l / K1, ix = l - zs * K1;
-        const cplx<T>* col = X + zs * N2 * LD + ix;
+        int kx = g.x0 + ix;
+        if (kx >= N1) kx -= N1;
+        cplx<T>* col = X + zs * N2 * LD + kx;
         cplx<T> v[N2];
 #pragma unroll
         for (int y = 0; y < N2; ++y) v[y] = col[y * LD];
         RegFft<N2, -1, T>::run(v);
-        cplx<T>* o = to + (size_t)zs * kk + ix;
 #pragma unroll
-        for (int k = 0; k < N2; ++k) {
-            int iy = k - g.y0;
-            if (iy < 0) iy += N2;
-            if (iy < K2) o[iy * K1] = v[k];
-        }
+        for (int y = 0; y < N2; ++y) col[y * LD] = v[y];
+    }
+    __syncthreads();
+
+    // kept (ky, kx) block of every plane to tbuf [pair][z][K2][K1], coalesced
+    const int kk = K1 * K2;
+    cplx<T>* to = tbuf + ((size_t)p * g.N3 + z0) * kk;
+    for (int f = threadIdx.x; f < ns * kk; f += blockDim.x) {
+        const int zs = f / kk, r = f - zs * kk;
+        const int iy = r / K1, ix = r - iy * K1;
+        int kx = g.x0 + ix, ky = g.y0 + iy;
+        if (kx >= N1) kx -= N1;
+        if (ky >= N2) ky -= N2;
+        to[f] = X[(zs * N2 + ky) * LD + kx];
     }
 }
 
@@ -133,6 +166,58 @@ __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ 
             oim[gi] = T(0);
         }
     }
+}
+
+template <typename T, int N3, int DIR>
+__global__ __launch_bounds__(256) void k_fft_z_reg(cplx<T>* __restrict__ data, long long nlines, int plane) {
+    const long long L = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= nlines) return;
+    const long long b = L / plane;
+    cplx<T>* base = data + b * (long long)plane * N3 + (L - b * plane);
+    cplx<T> v[N3];
+#pragma unroll
+    for (int z = 0; z < N3; ++z) v[z] = base[(long long)z * plane];
+    RegFft<N3, DIR, T>::run(v);
+#pragma unroll
+    for (int z = 0; z < N3; ++z) base[(long long)z * plane] = v[z];
+}
+
+template <typename T, int N, int DIR>
+__global__ __launch_bounds__(64) void k_fft_xy_reg(cplx<T>* __restrict__ data) {
+    __shared__ cplx<T> X[N][N + 1];
+    cplx<T>* base = data + (size_t)blockIdx.x * N * N;
+    constexpr int U = sizeof(T) == 4 ? 16 : 8;
+    for (int f0 = threadIdx.x; f0 < N * N; f0 += U * blockDim.x) {
+        cplx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = base[min(f0 + u * (int)blockDim.x, N * N - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int f = f0 + u * (int)blockDim.x;
+            if (f < N * N) X[f / N][f % N] = v[u];
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < N) {
+        cplx<T> v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = X[t][i];
+        RegFft<N, DIR, T>::run(v);
+#pragma unroll
+        for (int i = 0; i < N; ++i) X[t][i] = v[i];
+    }
+    __syncthreads();
+    if (t < N) {
+        cplx<T> v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = X[i][t];
+        RegFft<N, DIR, T>::run(v);
+#pragma unroll
+        for (int i = 0; i < N; ++i) X[i][t] = v[i];
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < N * N; f += blockDim.x) base[f] = X[f / N][f % N];
 }
 
 constexpr size_t kRegLdsBudget = 80 * 1024;
@@ -186,6 +271,47 @@ bool pair_reg_supported(const PairGeom& g) {
 }
 
 template <typename T>
+hipError_t launch_grid_fft_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s) {
+    if (!nb) return hipSuccess;
+    PairGeom g{};
+    g.N1 = N1;
+    g.N2 = N2;
+    g.N3 = N3;
+    g.K1 = 1;
+    g.K2 = 1;
+    if (!pair_reg_supported<T>(g)) return hipErrorNotSupported;
+    const int plane = N1 * N2;
+    const long long nlines = (long long)nb * plane;
+    const unsigned zb = (unsigned)((nlines + 255) / 256);
+    switch (N3) {
+#define RPA_CASE(L)                                                                                             \
+    case L:                                                                                                     \
+        if (dir > 0)                                                                                            \
+            hipLaunchKernelGGL((k_fft_z_reg<T, L, 1>), dim3(zb), dim3(256), 0, s, data, nlines, plane);          \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_fft_z_reg<T, L, -1>), dim3(zb), dim3(256), 0, s, data, nlines, plane);         \
+        break;
+        RPA_REG_SIZES(RPA_CASE)
+#undef RPA_CASE
+        default: return hipErrorNotSupported;
+    }
+    const unsigned planes = (unsigned)((long long)nb * N3);
+    switch (N1) {
+#define RPA_CASE(L)                                                                                   \
+    case L:                                                                                           \
+        if (dir > 0)                                                                                  \
+            hipLaunchKernelGGL((k_fft_xy_reg<T, L, 1>), dim3(planes), dim3(64), 0, s, data);           \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_fft_xy_reg<T, L, -1>), dim3(planes), dim3(64), 0, s, data);          \
+        break;
+        RPA_REG_SIZES(RPA_CASE)
+#undef RPA_CASE
+        default: return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const int32_t* pn, const int32_t* pm,
                               int npairs, const PairGeom& g, cplx<T>* tbuf, hipStream_t s) {
     if (!npairs) return hipSuccess;
@@ -193,13 +319,16 @@ hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const i
     const int S = xy_slab<T>(g);
     const int rows = S * g.N2;
     const int threads = std::min(xy_threads_rt<T>(g.N1), (rows + 63) / 64 * 64);
+    if (rows > threads || S * g.K1 > threads) return hipErrorInvalidValue;  // one line per thread
     const size_t lds = (size_t)S * g.N2 * (g.N1 + 1) * sizeof(cplx<T>);
-    dim3 grid((unsigned)npairs, (unsigned)((g.N3 + S - 1) / S));
+    const long long tasks = (long long)npairs * ((g.N3 + S - 1) / S);
+    if (tasks > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)tasks);
     switch (g.N1) {
 #define RPA_CASE(L)                                                                                              \
     case L:                                                                                                      \
-        hipLaunchKernelGGL((k_pair_xy_reg<T, L, L>), grid, dim3(threads), lds, s, phik, phikq, pn, pm, g, S,     \
-                           tbuf);                                                                                \
+        hipLaunchKernelGGL((k_pair_xy_reg<T, L, L>), grid, dim3(threads), lds, s, phik, phikq, pn, pm, npairs,   \
+                           g, S, tbuf);                                                                          \
         break;
         RPA_REG_SIZES(RPA_CASE)
 #undef RPA_CASE
@@ -231,6 +360,7 @@ hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g,
 
 #define RPA_INST(T)                                                                                              \
     template bool pair_reg_supported<T>(const PairGeom&);                                                        \
+    template hipError_t launch_grid_fft_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                   \
     template hipError_t launch_pair_xy_reg<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*, int, \
                                               const PairGeom&, cplx<T>*, hipStream_t);                           \
     template hipError_t launch_pair_z_reg<T>(const cplx<T>*, int, const PairGeom&, const int32_t*, const int32_t*, \

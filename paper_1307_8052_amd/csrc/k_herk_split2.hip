@@ -260,6 +260,168 @@ __global__ __launch_bounds__(256, 1) void k_herk_split2(HerkSplit2Args h) {
             }
 }
 
+// Variant 3: the same operands and products as k_herk_split2, software
+// pipelined. LDS holds two K-steps (double buffer, 128 KB with an XOR swizzle
+// of the 16-byte chunks of a row instead of padding), so one barrier per
+// K-step separates writing step k+1 from reading step k. The loop body has no
+// branches: the split of step k+1 (VALU and LDS writes) and the global loads of
+// step k+2 sit in the same block as the MFMAs of step k, and the weights a(w)
+// are prefetched with the operands.
+__device__ __forceinline__ int swz(int row, int chunk) { return 8 * (chunk ^ ((row >> 1) & 3)); }
+
+template <bool F16>
+__global__ __launch_bounds__(256, 1) void k_herk_split3(HerkSplit2Args h) {
+    typedef typename H<F16>::v8 hv;
+    __shared__ __align__(16) u16 sA[2][4][TM][KS];
+    __shared__ __align__(16) u16 sB[2][4][TM][KS];
+
+    const int b = blockIdx.x;
+    const int xcd = b % kXcds, local = b / kXcds;
+    const int tile = (local / h.nw) * kXcds + xcd;
+    const int w = local % h.nw;
+    if (tile >= h.ntiles) return;
+    int I, J;
+    tile_of(tile, I, J);
+    const int ci = I * TM, cj = J * TM;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const double* aw = h.w + (size_t)w * h.lda;
+    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
+    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
+    const int K = h.K;
+
+    // staging: thread -> (row sr, pairs sk .. sk+15)
+    const int sr = tid >> 1, sk = (tid & 1) * 16;
+    float pxr[16], pxi[16];
+    double pw[16];
+    v8u16 pb[4][2];
+    const int nkb = (K + KS - 1) / KS;
+    auto fetch = [&](int kb) {
+        const size_t oa = ((size_t)kb * h.NGq + ci + sr) * KS + sk;
+        const size_t ob = ((size_t)kb * h.NGq + cj + sr) * KS + sk;
+#pragma unroll
+        for (int e = 0; e < 16; e += 4) {
+            const v4f a = *reinterpret_cast<const v4f*>(h.Xre + oa + e);
+            const v4f c = *reinterpret_cast<const v4f*>(h.Xim + oa + e);
+            pxr[e] = a[0]; pxr[e + 1] = a[1]; pxr[e + 2] = a[2]; pxr[e + 3] = a[3];
+            pxi[e] = c[0]; pxi[e + 1] = c[1]; pxi[e + 2] = c[2]; pxi[e + 3] = c[3];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pb[q][0] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
+            pb[q][1] = *reinterpret_cast<const v8u16*>(h.B[q] + ob + 8);
+        }
+        const int k0 = kb * KS + sk;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) pw[e] = aw[min(k0 + e, K - 1)];
+    };
+    // X_w = rho a(w) sa split into hi/lo, and the pre-split rho, into buffer `buf`
+    auto store = [&](int kb, int buf) {
+        const int k0 = kb * KS + sk;
+        v8u16 xrh[2], xrl[2], xih[2], xil[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float wk = (k0 + e < K) ? (float)pw[e] * sa : 0.f;
+            u16 a, c;
+            split<F16>(pxr[e] * wk, a, c);
+            xrh[e >> 3][e & 7] = a;
+            xrl[e >> 3][e & 7] = c;
+            split<F16>(pxi[e] * wk, a, c);
+            xih[e >> 3][e & 7] = a;
+            xil[e >> 3][e & 7] = c;
+        }
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            const int o = swz(sr, (sk >> 3) + hf);
+            *reinterpret_cast<v8u16*>(&sA[buf][0][sr][o]) = xrh[hf];
+            *reinterpret_cast<v8u16*>(&sA[buf][1][sr][o]) = xrl[hf];
+            *reinterpret_cast<v8u16*>(&sA[buf][2][sr][o]) = xih[hf];
+            *reinterpret_cast<v8u16*>(&sA[buf][3][sr][o]) = xil[hf];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[buf][q][sr][o]) = pb[q][hf];
+        }
+    };
+
+    v4f accR[4][4], accI[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            accR[x][y] = v4f{0, 0, 0, 0};
+            accI[x][y] = v4f{0, 0, 0, 0};
+        }
+
+    fetch(0);
+    store(0, 0);
+    fetch(min(1, nkb - 1));
+    const int rr = lane & 15, kc = lane >> 4;
+    for (int kb = 0; kb < nkb; ++kb) {
+        __syncthreads();
+        const int cur = kb & 1;
+        hv bf[4][4], bn[4][2];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int row = wc + 16 * y + rr;
+            const int o = swz(row, kc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bf[y][q] = *reinterpret_cast<const hv*>(&sB[cur][q][row][o]);
+            bn[y][0] = -bf[y][2];
+            bn[y][1] = -bf[y][3];
+        }
+        hv af[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int row = wr + 16 * x + rr;
+            const int o = swz(row, kc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) af[x][q] = *reinterpret_cast<const hv*>(&sA[cur][q][row][o]);
+        }
+        // next K-step into the other buffer (the last iteration writes an unused buffer), then the
+        // global loads of the one after (clamped to the last block)
+        store(kb + 1, cur ^ 1);
+        fetch(min(kb + 2, nkb - 1));
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                v4f r = accR[x][y], im = accI[x][y];
+                r = H<F16>::mfma(af[x][1], bf[y][0], r);
+                r = H<F16>::mfma(af[x][0], bf[y][1], r);
+                r = H<F16>::mfma(af[x][3], bf[y][2], r);
+                r = H<F16>::mfma(af[x][2], bf[y][3], r);
+                r = H<F16>::mfma(af[x][0], bf[y][0], r);
+                r = H<F16>::mfma(af[x][2], bf[y][2], r);
+                im = H<F16>::mfma(af[x][3], bf[y][0], im);
+                im = H<F16>::mfma(af[x][2], bf[y][1], im);
+                im = H<F16>::mfma(af[x][1], bn[y][0], im);
+                im = H<F16>::mfma(af[x][0], bn[y][1], im);
+                im = H<F16>::mfma(af[x][2], bf[y][0], im);
+                im = H<F16>::mfma(af[x][0], bn[y][0], im);
+                accR[x][y] = r;
+                accI[x][y] = im;
+            }
+    }
+
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    double* Cre = h.Cre + (size_t)w * h.sC;
+    double* Cim = h.Cim + (size_t)w * h.sC;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                if (row < h.ldC && col < h.ldC) {
+                    const size_t o = (size_t)row * h.ldC + col;
+                    Cre[o] += (double)accR[x][y][r] * inv;
+                    Cim[o] += (double)accI[x][y][r] * inv;
+                }
+            }
+}
+
 }  // namespace
 
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
@@ -275,14 +437,21 @@ hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr,
     return hipGetLastError();
 }
 
-hipError_t launch_herk_split2(const HerkSplit2Args& h, hipStream_t s) {
+hipError_t launch_herk_split2(const HerkSplit2Args& h, int pipelined, hipStream_t s) {
     if (h.ntiles <= 0 || h.nw <= 0 || h.K <= 0) return hipSuccess;
     const int per_xcd = (h.ntiles + kXcds - 1) / kXcds;
     const unsigned blocks = (unsigned)(per_xcd * h.nw * kXcds);
-    if (h.fp16)
-        hipLaunchKernelGGL(k_herk_split2<true>, dim3(blocks), dim3(256), 0, s, h);
-    else
-        hipLaunchKernelGGL(k_herk_split2<false>, dim3(blocks), dim3(256), 0, s, h);
+    if (pipelined) {
+        if (h.fp16)
+            hipLaunchKernelGGL(k_herk_split3<true>, dim3(blocks), dim3(256), 0, s, h);
+        else
+            hipLaunchKernelGGL(k_herk_split3<false>, dim3(blocks), dim3(256), 0, s, h);
+    } else {
+        if (h.fp16)
+            hipLaunchKernelGGL(k_herk_split2<true>, dim3(blocks), dim3(256), 0, s, h);
+        else
+            hipLaunchKernelGGL(k_herk_split2<false>, dim3(blocks), dim3(256), 0, s, h);
+    }
     return hipGetLastError();
 }
 

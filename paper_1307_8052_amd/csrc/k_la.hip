@@ -169,8 +169,11 @@ __device__ __forceinline__ void tile_of(int t, int& I, int& J) {
     J = t - i * (i + 1) / 2;
 }
 
+// The next K-stage is loaded into registers while the current one runs on the
+// MFMA units, and LDS is double-buffered, so one barrier separates the stages.
 __global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
-    __shared__ double sAr[kHerkBK][kTile], sAi[kHerkBK][kTile], sBr[kHerkBK][kTile], sBi[kHerkBK][kTile];
+    __shared__ double sAr[2][kHerkBK][kTile], sAi[2][kHerkBK][kTile], sBr[2][kHerkBK][kTile],
+        sBi[2][kHerkBK][kTile];
     int I, J;
     tile_of(blockIdx.x, I, J);
     const int b = blockIdx.y;
@@ -186,8 +189,12 @@ __global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
             accR[x][y] = v4d{0, 0, 0, 0};
             accI[x][y] = v4d{0, 0, 0, 0};
         }
-    for (int k0 = 0; k0 < h.K; k0 += kHerkBK) {
-        for (int e = tid; e < kHerkBK * kTile; e += 256) {
+    constexpr int kPer = kHerkBK * kTile / 256;
+    double pr[kPer], pi[kPer], qr[kPer], qi[kPer];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
             const int kk = e >> 6, c = e & 63, k = k0 + kk;
             double ar = 0, ai = 0, br = 0, bi = 0;
             if (k < h.K) {
@@ -198,23 +205,41 @@ __global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
                 br = Are[row + cj + c];
                 bi = Aim[row + cj + c];
             }
-            sAr[kk][c] = ar;
-            sAi[kk][c] = ai;
-            sBr[kk][c] = br;
-            sBi[kk][c] = bi;
+            pr[i] = ar;
+            pi[i] = ai;
+            qr[i] = br;
+            qi[i] = bi;
         }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int kk = e >> 6, c = e & 63;
+            sAr[buf][kk][c] = pr[i];
+            sAi[buf][kk][c] = pi[i];
+            sBr[buf][kk][c] = qr[i];
+            sBi[buf][kk][c] = qi[i];
+        }
+    };
+    fetch(0);
+    stash(0);
+    int cur = 0;
+    for (int k0 = 0; k0 < h.K; k0 += kHerkBK) {
         __syncthreads();
+        const bool more = k0 + kHerkBK < h.K;
+        if (more) fetch(k0 + kHerkBK);
 #pragma unroll
         for (int kk = 0; kk < kHerkBK; kk += 4) {
             const int kr = kk + (lane >> 4), cc = lane & 15;
             double a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                a_r[x] = sAr[kr][wr + x * 16 + cc];
-                a_i[x] = sAi[kr][wr + x * 16 + cc];
+                a_r[x] = sAr[cur][kr][wr + x * 16 + cc];
+                a_i[x] = sAi[cur][kr][wr + x * 16 + cc];
                 a_n[x] = -a_r[x];
-                b_r[x] = sBr[kr][wc + x * 16 + cc];
-                b_i[x] = sBi[kr][wc + x * 16 + cc];
+                b_r[x] = sBr[cur][kr][wc + x * 16 + cc];
+                b_i[x] = sBi[cur][kr][wc + x * 16 + cc];
             }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -226,7 +251,8 @@ __global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
                     accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[x], b_i[y], accI[x][y], 0, 0, 0);
                 }
         }
-        __syncthreads();
+        if (more) stash(cur ^ 1);
+        cur ^= 1;
     }
     double* Cre = h.Cre + (size_t)b * h.sC;
     double* Cim = h.Cim + (size_t)b * h.sC;
@@ -359,7 +385,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
                                                     int* __restrict__ fail) {
     __shared__ double2 a[kTile][kPanelLd];
     __shared__ double2 v[kTile][kPanelLd];
-    __shared__ double piv[kTile];
+    __shared__ double piv[kTile], lgp[kTile];
     const int w = blockIdx.x, tid = threadIdx.x;
     const int j = tid & (kTile - 1), wv = tid >> 6;
     double* cr = Cre + (size_t)w * sC;
@@ -371,45 +397,67 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
                       : make_double2(0.0, 0.0);
         v[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
-    double ldacc = 0.0;
-    int bad = 0;
     __syncthreads();
-    // factorisation: A[r][j] -= A[r][c] conj(A[j][c]) / (1 + A[c][c]) for c < j <= r
+    // factorisation: A[r][j] -= A[r][c] conj(A[j][c]) / (1 + A[c][c]) for c < j <= r. A[c][c] is final
+    // once column c - 1 is done, so the pivots' square roots and logarithms wait until the end.
     for (int c = 0; c < kTile; ++c) {
         const double d = a[c][c].x;
-        if (tid == 0) {
-            if (!(1.0 + d > 0.0) && !bad) bad = j0 + c + 1;
-            ldacc += log1p(d);
-            piv[c] = sqrt(1.0 + d);
-        }
         if (j > c) {
             const double inv = 1.0 / (1.0 + d);
             const double2 ajc = a[j][c];
             const double br = ajc.x * inv, bi = -ajc.y * inv;
-            for (int r = c + 1 + ((wv - c - 1) & 3); r < kTile; r += 4) {
-                if (r < j) continue;
-                const double2 arc = a[r][c];
-                double2 x = a[r][j];
-                x.x -= arc.x * br - arc.y * bi;
-                x.y -= arc.x * bi + arc.y * br;
-                a[r][j] = x;
+            const int r0 = c + 1 + ((wv - c - 1) & 3);
+            // all loads of the step first, so their latencies overlap
+            double2 arc[kTile / 4], x[kTile / 4];
+#pragma unroll
+            for (int i = 0; i < kTile / 4; ++i) {
+                const int r = r0 + 4 * i;
+                if (r < kTile && r >= j) {
+                    arc[i] = a[r][c];
+                    x[i] = a[r][j];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kTile / 4; ++i) {
+                const int r = r0 + 4 * i;
+                if (r < kTile && r >= j) {
+                    x[i].x -= arc[i].x * br - arc[i].y * bi;
+                    x[i].y -= arc[i].x * bi + arc[i].y * br;
+                    a[r][j] = x[i];
+                }
             }
         }
         __syncthreads();
     }
+    if (tid < kTile) {
+        const double d = a[tid][tid].x;
+        piv[tid] = sqrt(1.0 + d);
+        lgp[tid] = (1.0 + d > 0.0) ? log1p(d) : __builtin_nan("");
+    }
     // inverse: W[r][j] -= A[r][k] W[k][j] / (1 + A[k][k]) for j <= k < r; V = W / s_r
     for (int k = 0; k < kTile - 1; ++k) {
         if (j <= k) {
-            const double s = piv[k];
-            const double inv = 1.0 / (s * s);
+            const double inv = 1.0 / (1.0 + a[k][k].x);
             const double2 wkj = v[k][j];
             const double br = wkj.x * inv, bi = wkj.y * inv;
-            for (int r = k + 1 + ((wv - k - 1) & 3); r < kTile; r += 4) {
-                const double2 ark = a[r][k];
-                double2 x = v[r][j];
-                x.x -= ark.x * br - ark.y * bi;
-                x.y -= ark.x * bi + ark.y * br;
-                v[r][j] = x;
+            const int r0 = k + 1 + ((wv - k - 1) & 3);
+            double2 ark[kTile / 4], x[kTile / 4];
+#pragma unroll
+            for (int i = 0; i < kTile / 4; ++i) {
+                const int r = r0 + 4 * i;
+                if (r < kTile) {
+                    ark[i] = a[r][k];
+                    x[i] = v[r][j];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kTile / 4; ++i) {
+                const int r = r0 + 4 * i;
+                if (r < kTile) {
+                    x[i].x -= ark[i].x * br - ark[i].y * bi;
+                    x[i].y -= ark[i].x * bi + ark[i].y * br;
+                    v[r][j] = x[i];
+                }
             }
         }
         __syncthreads();
@@ -440,6 +488,13 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
         }
     }
     if (tid == 0) {
+        // pivots in column order; the first one that is not positive marks the failure
+        double ldacc = 0.0;
+        int bad = 0;
+        for (int c = 0; c < kTile; ++c) {
+            if (!(1.0 + a[c][c].x > 0.0) && !bad) bad = j0 + c + 1;
+            ldacc += lgp[c];
+        }
         logdet[w] += ldacc;
         if (bad && !fail[w]) fail[w] = bad;
     }

@@ -70,7 +70,8 @@ struct rpa_ctx {
     double prof_ms[16] = {0};
     long long prof_n[16] = {0};
     int last_nq = 0;
-    // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 2 = 128x128 tiles
+    // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 2 = 128x128 tiles,
+    // 3 = 128x128 tiles software pipelined
     std::map<uint64_t, int> tune;
     std::map<uint64_t, double> tune_ms;
     // the captured batch graph
@@ -429,15 +430,20 @@ int check_freq(const rpa_freq* fr) {
     return RPA_OK;
 }
 
-void pair_list(const rpa_states* k, const rpa_states* kq, std::vector<int32_t>& pn, std::vector<int32_t>& pm) {
+// transitions n -> m with f_n - f_m > 0 (n outer, or m outer when m_major)
+void pair_list(const rpa_states* k, const rpa_states* kq, std::vector<int32_t>& pn, std::vector<int32_t>& pm,
+               bool m_major) {
     pn.clear();
     pm.clear();
-    for (int n = 0; n < k->nbands; ++n)
-        for (int m = 0; m < kq->nbands; ++m)
+    const int no = m_major ? kq->nbands : k->nbands, ni = m_major ? k->nbands : kq->nbands;
+    for (int o = 0; o < no; ++o)
+        for (int i = 0; i < ni; ++i) {
+            const int n = m_major ? i : o, m = m_major ? o : i;
             if (k->f[n] - kq->f[m] > kDeltaF) {
                 pn.push_back(n);
                 pm.push_back(m);
             }
+        }
 }
 
 std::vector<int32_t> scatter_map(const rpa_ctx* c, const rpa_states* s) {
@@ -491,9 +497,8 @@ struct QJob {
     std::vector<void*> d_wq;
     std::vector<double> Dq;
     void* d_Dq = nullptr;
-    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64 tiles, 2 split 128x128 tiles
+    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64 tiles, 2 / 3 split 128x128 tiles (3 pipelined)
     int Pc = 0;        // pair chunk
-    size_t chi_off = 0;
     double* cr = nullptr;
     double* ci = nullptr;
     double* ec = nullptr;
@@ -515,6 +520,8 @@ struct Batch {
     std::string prefix;              // buffer-name prefix (graph-owned and tuning buffers)
     std::vector<KSet> ks;
     std::vector<QJob> qj;
+    bool m_major = false;            // forward chi0: pairs ordered by m, then n (orbital reuse in cache)
+    int ld = 0;                      // leading dimension of every chi0 / -K matrix of the batch (max NGp)
     bool fp64() const { return prec == RPA_FP64; }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
 };
@@ -523,7 +530,7 @@ int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
     if (prec == RPA_FP64) return 0;
     auto it = c->tune.find(tune_key(prec, NGp));
     if (it != c->tune.end()) return it->second;
-    return ((NGp + 127) / 128 >= 4) ? 2 : 1;
+    return ((NGp + 127) / 128 >= 4) ? 3 : 1;
 }
 
 int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
@@ -588,7 +595,7 @@ int prepare_kset(Batch& B, KSet& K, Upload& up, const int32_t* pn_in = nullptr, 
     const rpa_states* k = K.k;
     const rpa_states* kq = K.kq;
     if (np_in < 0) {
-        pair_list(k, kq, K.pn, K.pm);
+        pair_list(k, kq, K.pn, K.pm, B.m_major);
     } else {
         K.pn.assign(pn_in, pn_in + np_in);
         K.pm.assign(pm_in, pm_in + np_in);
@@ -664,7 +671,6 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     rpa_ctx* c = B.c;
     const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
     const size_t el = B.elem();
-    size_t chi_off = 0;
     for (auto& K : B.ks) {
         W.phi_k = std::max(W.phi_k, (size_t)K.k->nbands * vol * 2 * el);
         if (!same_set(K.k, K.kq)) W.phi_kq = std::max(W.phi_kq, (size_t)K.kq->nbands * vol * 2 * el);
@@ -705,18 +711,18 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
             W.pack = std::max(W.pack, blk * (2 * sizeof(float) + 4 * sizeof(unsigned short)));
             W.scales = std::max(W.scales, (size_t)(B.nw + 1 + 256) * sizeof(float));
         }
-        if (need_ec || need_chi) {
-            Q.chi_off = chi_off;
-            chi_off += 2 * (size_t)B.nw * g.NGp * g.NGp * sizeof(double);
-        }
-        if (need_ec) {
-            W.cholL = std::max(W.cholL, 2 * (size_t)B.nw * kTile * kTile * sizeof(double));
-            W.cholP = std::max(W.cholP, 2 * (size_t)B.nw * kTile * g.NGp * sizeof(double));
-        }
+        B.ld = std::max(B.ld, g.NGp);
         Q.variant = default_variant(c, B.prec, g.NGp);
     }
-    W.chi = chi_off;
-    if (need_ec) W.small = B.qj.size() * (size_t)B.nw * (2 * sizeof(double) + sizeof(int)) + 64;
+    // every (q, w) matrix at one leading dimension: all real parts, then all imaginary parts, so that
+    // matrix b = q nw + w sits at b * ld^2 and the E_c stage treats the batch as one set of matrices
+    const size_t nmat = B.qj.size() * (size_t)B.nw, ld2 = (size_t)B.ld * B.ld;
+    if (need_ec || need_chi) W.chi = 2 * nmat * ld2 * sizeof(double);
+    if (need_ec) {
+        W.cholL = 2 * nmat * kTile * kTile * sizeof(double);
+        W.cholP = 2 * nmat * kTile * (size_t)B.ld * sizeof(double);
+        W.small = nmat * (2 * sizeof(double) + sizeof(int)) + 64;
+    }
     struct NB {
         const char* n;
         size_t b;
@@ -730,11 +736,10 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         if (rc) return rc;
     }
     if (W.chi) {
-        char* base = static_cast<char*>(buf(B, "chi"));
-        for (auto& Q : B.qj) {
-            const size_t mat = (size_t)B.nw * Q.qp.NGp * Q.qp.NGp;
-            Q.cr = reinterpret_cast<double*>(base + Q.chi_off);
-            Q.ci = Q.cr + mat;
+        double* base = static_cast<double*>(buf(B, "chi"));
+        for (size_t qi = 0; qi < B.qj.size(); ++qi) {
+            B.qj[qi].cr = base + qi * B.nw * ld2;
+            B.qj[qi].ci = base + (nmat + qi * B.nw) * ld2;
         }
     }
     return RPA_OK;
@@ -749,9 +754,15 @@ int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const char* nam
     HIP_TRY(launch_fill_zero<T>(phi, (size_t)s->nbands * vol, B.s));
     HIP_TRY(launch_orb_scatter<T>(static_cast<const double*>(s->C), s->nbands, s->nQ,
                                   static_cast<const int32_t*>(d_map), vol, phi, B.s));
-    for (int ax = 0; ax < 3; ++ax)
-        HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
-                                   static_cast<const cplx<T>*>(B.d_tw[ax]), +1, B.s));
+    hipError_t e = hipErrorNotSupported;
+    if (c->pair_reg) e = launch_grid_fft_reg<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], +1, B.s);
+    if (e == hipErrorNotSupported) {
+        for (int ax = 0; ax < 3; ++ax)
+            HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
+                                       static_cast<const cplx<T>*>(B.d_tw[ax]), +1, B.s));
+    } else {
+        HIP_TRY(e);
+    }
     *out = phi;
     return RPA_OK;
 }
@@ -836,8 +847,8 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
         h.alpha = 0;
         h.Cre = Q.cr;
         h.Cim = Q.ci;
-        h.sC = (long long)NGp * NGp;
-        h.ldC = NGp;
+        h.sC = (long long)B.ld * B.ld;
+        h.ldC = B.ld;
         h.r0 = 0;
         h.nT = NGp / kTile;
         h.nbatch = B.nw;
@@ -850,7 +861,7 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             HIP_TRY(launch_split_scales(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim),
                                         (size_t)np * NGp, aw, lda, np, B.nw, scales, scales + B.nw + 1, B.s));
         }
-        if (Q.variant == 2) {
+        if (Q.variant == 2 || Q.variant == 3) {
             const int NGq = (NGp + 127) / 128 * 128;
             const size_t blk = (size_t)((np + 31) / 32) * NGq * 32;
             float* Xre = static_cast<float*>(buf(B, "split_pack"));
@@ -869,14 +880,14 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.lda = lda;
             h.Cre = Q.cr;
             h.Cim = Q.ci;
-            h.sC = (long long)NGp * NGp;
-            h.ldC = NGp;
+            h.sC = (long long)B.ld * B.ld;
+            h.ldC = B.ld;
             const int nT = NGq / 128;
             h.ntiles = nT * (nT + 1) / 2;
             h.nw = B.nw;
             h.fp16 = fp16;
             h.scales = scales;
-            HIP_TRY(launch_herk_split2(h, B.s));
+            HIP_TRY(launch_herk_split2(h, Q.variant == 3, B.s));
         } else {
             HerkSplitArgs h{};
             h.Are = reinterpret_cast<const float*>(rre);
@@ -887,8 +898,8 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.lda = lda;
             h.Cre = Q.cr;
             h.Cim = Q.ci;
-            h.sC = (long long)NGp * NGp;
-            h.ldC = NGp;
+            h.sC = (long long)B.ld * B.ld;
+            h.ldC = B.ld;
             h.nT = NGp / kTile;
             h.nw = B.nw;
             h.fp16 = fp16;
@@ -903,10 +914,9 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
 template <typename T>
 int enqueue_chi0(Batch& B) {
     rpa_ctx* c = B.c;
-    for (auto& Q : B.qj) {
-        const size_t mat = (size_t)B.nw * Q.qp.NGp * Q.qp.NGp;
-        HIP_TRY(launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(Q.cr), mat, B.s));
-    }
+    // every accumulator of the batch (real and imaginary blocks, padding included)
+    HIP_TRY(launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(B.qj[0].cr),
+                                     B.qj.size() * (size_t)B.nw * B.ld * B.ld, B.s));
     for (size_t ik = 0; ik < B.ks.size(); ++ik) {
         KSet& K = B.ks[ik];
         const int P = (int)K.pn.size();
@@ -948,44 +958,82 @@ int enqueue_chi0(Batch& B) {
     return RPA_OK;
 }
 
-// E_c of job qi from its accumulator (overwritten by -K and its factor)
-int enqueue_ec(Batch& B, int qi, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
+// E_c of every job of the batch from its accumulator (overwritten by -K and its
+// factor). The nq * nw matrices share one leading dimension and are factorised
+// together, so each 64-column panel step is one launch for the whole batch.
+// from_full (one job): -K from a caller chi0 [nw][NG][NG] instead.
+// Lblocks (one job): keep every inverted diagonal block and the factor itself.
+int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
-    QJob& Q = B.qj[qi];
-    const int NG = Q.qp.NG, NGp = Q.qp.NGp, nw = B.nw;
-    double* cr = Q.cr;
-    double* ci = Q.ci;
-    char* sm = static_cast<char*>(buf(B, "ec_small"));
-    double* logdet = reinterpret_cast<double*>(sm) + (size_t)qi * 2 * nw;
-    double* trk = logdet + nw;
-    int* failv = reinterpret_cast<int*>(reinterpret_cast<double*>(sm) + B.qj.size() * 2 * nw) + (size_t)qi * nw;
+    const int nw = B.nw, ld = B.ld;
+    const int nq = (int)B.qj.size();
+    const int nb = nq * nw;
+    double* logdet = static_cast<double*>(buf(B, "ec_small"));
+    double* trk = logdet + nb;
+    int* failv = reinterpret_cast<int*>(trk + nb);
     double* Lre = static_cast<double*>(buf(B, "chol_L"));
-    double* Lim = Lre + (size_t)nw * kTile * kTile;
+    double* Lim = Lre + (size_t)nb * kTile * kTile;
     double* Pre = static_cast<double*>(buf(B, "chol_panel"));
-    double* Pim = Pre + (size_t)nw * kTile * NGp;
+    double* Pim = Pre + (size_t)nb * kTile * ld;
+    double* cr = B.qj[0].cr;
+    double* ci = B.qj[0].ci;
+    const long long ld2 = (long long)ld * ld;
     ProfScope ps_(c, S_CHOL, B.s);
-    HIP_TRY(launch_zero(logdet, 2 * nw, failv, nw, B.s));
-    if (from_full) {
-        HIP_TRY(launch_build_negk_from_full(static_cast<const double*>(chi_full), NG, cr, ci, NGp, nw,
-                                            static_cast<const double*>(Q.d_vs), trk, B.s));
-    } else {
-        HIP_TRY(launch_build_negk(cr, ci, NGp, NG, NGp, nw, static_cast<const double*>(Q.d_vs), trk, B.s));
+    HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, B.s));
+    for (int qi = 0; qi < nq; ++qi) {
+        QJob& Q = B.qj[qi];
+        if (from_full) {
+            HIP_TRY(launch_build_negk_from_full(static_cast<const double*>(chi_full), Q.qp.NG, Q.cr, Q.ci, ld, nw,
+                                                static_cast<const double*>(Q.d_vs), trk + qi * nw, B.s));
+        } else {
+            HIP_TRY(launch_build_negk(Q.cr, Q.ci, ld, Q.qp.NG, ld, nw, static_cast<const double*>(Q.d_vs),
+                                      trk + qi * nw, B.s));
+        }
     }
-    for (int j0 = 0; j0 < NGp; j0 += kTile) {
+    for (int j0 = 0; j0 < ld; j0 += kTile) {
         if (Lblocks) {
             // keep every inverted diagonal block: [block][re/im][w][64][64]
-            Lre = Lblocks + (size_t)(j0 / kTile) * 2 * nw * kTile * kTile;
-            Lim = Lre + (size_t)nw * kTile * kTile;
+            Lre = Lblocks + (size_t)(j0 / kTile) * 2 * nb * kTile * kTile;
+            Lim = Lre + (size_t)nb * kTile * kTile;
         }
-        HIP_TRY(launch_chol_panel(cr, ci, NGp, j0, nw, Lre, Lim, logdet, failv, B.s));
+        HIP_TRY(launch_chol_panel(cr, ci, ld, j0, nb, Lre, Lim, logdet, failv, B.s));
         const int r0 = j0 + kTile;
-        if (r0 >= NGp) break;
-        HIP_TRY(launch_chol_trsm(cr, ci, NGp, j0, NGp, nw, Lre, Lim, Pre, Pim, B.s));
+        if (r0 >= ld) break;
+        if (Lblocks) {
+            // the adjoint needs the factor itself: L21 also replaces the block column
+            HIP_TRY(launch_chol_trsm(cr, ci, ld, j0, ld, nb, Lre, Lim, Pre, Pim, B.s));
+        } else {
+            // panel operand of the trailing update only: P[c][r] = sum_k conj(L11^-1[c][k]) A21[r][k]
+            GemmArgs gm{};
+            gm.M = kTile;
+            gm.N = ld - r0;
+            gm.K = kTile;
+            gm.nbatch = nb;
+            gm.Ar = Lre;
+            gm.Ai = Lim;
+            gm.sA = (long long)kTile * kTile;
+            gm.aI = kTile;
+            gm.aK = 1;
+            gm.conjA = 1;
+            gm.Br = cr + (size_t)r0 * ld + j0;
+            gm.Bi = ci + (size_t)r0 * ld + j0;
+            gm.sB = ld2;
+            gm.bK = 1;
+            gm.bJ = ld;
+            gm.conjB = 0;
+            gm.Cr = Pre + r0;
+            gm.Ci = Pim + r0;
+            gm.sC = (long long)kTile * ld;
+            gm.ldC = ld;
+            gm.alpha = 1.0;
+            gm.beta = 0;
+            HIP_TRY(launch_gemm_c64(gm, B.s));
+        }
         HerkArgs h{};
         h.Are = Pre;
         h.Aim = Pim;
-        h.sA = (long long)kTile * NGp;
-        h.ldA = NGp;
+        h.sA = (long long)kTile * ld;
+        h.ldA = ld;
         h.colA = r0;
         h.K = kTile;
         h.w = nullptr;
@@ -993,14 +1041,18 @@ int enqueue_ec(Batch& B, int qi, bool from_full, const void* chi_full, double* L
         h.alpha = -1.0;
         h.Cre = cr;
         h.Cim = ci;
-        h.sC = (long long)NGp * NGp;
-        h.ldC = NGp;
+        h.sC = ld2;
+        h.ldC = ld;
         h.r0 = r0;
-        h.nT = (NGp - r0) / kTile;
-        h.nbatch = nw;
+        h.nT = (ld - r0) / kTile;
+        h.nbatch = nb;
         HIP_TRY(launch_herk_f64(h, B.s));
     }
-    HIP_TRY(launch_finalize(logdet, trk, failv, static_cast<const double*>(B.d_ow), nw, Q.F, Q.ec, B.s));
+    for (int qi = 0; qi < nq; ++qi) {
+        QJob& Q = B.qj[qi];
+        HIP_TRY(launch_finalize(logdet + qi * nw, trk + qi * nw, failv + qi * nw,
+                                static_cast<const double*>(B.d_ow), nw, Q.F, Q.ec, B.s));
+    }
     return RPA_OK;
 }
 
@@ -1174,7 +1226,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, double* deps_k, double
     if (rc) return rc;
     Q.ec = ec_dev;
     Q.F = nullptr;
-    rc = enqueue_ec(B, 0, false, nullptr, Lb);
+    rc = enqueue_ec_all(B, false, nullptr, Lb);
     if (rc) return rc;
     remember_fail_flags(B);
     ProfScope ps_(c, S_OTHER, B.s);
@@ -1535,12 +1587,13 @@ int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, cons
     Batch B;
     rc = begin(B, c, fr, prec, stream);
     if (rc) return rc;
+    B.m_major = true;
     rc = plan_batch(B, k, kq, nk, qs, 1, false, true, "tables");
     if (rc) return rc;
     rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
     if (rc) return rc;
     QJob& Q = B.qj[0];
-    HIP_TRY(launch_chi_out(Q.cr, Q.ci, Q.qp.NGp, Q.qp.NG, B.nw, static_cast<double*>(chi0_out), B.s));
+    HIP_TRY(launch_chi_out(Q.cr, Q.ci, B.ld, Q.qp.NG, B.nw, static_cast<double*>(chi0_out), B.s));
     return RPA_OK;
 }
 
@@ -1553,13 +1606,14 @@ int rpa_ec(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const 
     Batch B;
     rc = begin(B, c, fr, prec, stream);
     if (rc) return rc;
+    B.m_major = true;
     rc = plan_batch(B, k, kq, nk, qs, 1, true, false, "tables");
     if (rc) return rc;
     rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
     if (rc) return rc;
     B.qj[0].ec = ec_dev;
     B.qj[0].F = F_dev;
-    rc = enqueue_ec(B, 0, false, nullptr);
+    rc = enqueue_ec_all(B, false, nullptr);
     if (rc) return rc;
     remember_fail_flags(B);
     return RPA_OK;
@@ -1588,7 +1642,7 @@ int rpa_ec_from_chi0(rpa_ctx* c, const rpa_qspec* qs, const rpa_freq* fr, const 
     if (rc) return rc;
     Q.ec = ec_dev;
     Q.F = F_dev;
-    rc = enqueue_ec(B, 0, true, chi0);
+    rc = enqueue_ec_all(B, true, chi0);
     if (rc) return rc;
     remember_fail_flags(B);
     return RPA_OK;
@@ -1605,6 +1659,7 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
     Batch B;
     rc = begin(B, c, fr, prec, stream);
     if (rc) return rc;
+    B.m_major = true;
     const uint64_t key = use_graph ? batch_key(k, kq, nk, nq, qs, fr, prec, ec_dev, F_dev, stream) : 0;
     if (use_graph && c->graph_exec && c->graph_key == key) {
         HIP_TRY(hipGraphLaunch(c->graph_exec, B.s));
@@ -1625,9 +1680,9 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
         for (int j = 0; j < nq; ++j) {
             B.qj[j].ec = ec_dev + j;
             B.qj[j].F = F_dev ? F_dev + (size_t)j * B.nw : nullptr;
-            r = enqueue_ec(B, j, false, nullptr);
-            if (r) return r;
         }
+        r = enqueue_ec_all(B, false, nullptr);
+        if (r) return r;
         HIP_TRY(launch_weighted_sum(ec_dev, static_cast<const double*>(B.d_wq), nq, ec_dev + nq, B.s));
         return RPA_OK;
     };
@@ -1704,7 +1759,8 @@ int rpa_set_pair_path(rpa_ctx* ctx, int path) {
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
     if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
-    if (variant != 1 && variant != 2) return fail(RPA_ERR_INPUT, "split variants are 1 (64x64) and 2 (128x128)");
+    if (variant < 1 || variant > 3)
+        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 2 (128x128) and 3 (128x128 pipelined)");
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     c->tune[tune_key(prec, NGp)] = variant;
     return RPA_OK;
@@ -1729,6 +1785,7 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     B.prec = prec;
     B.nw = nw;
     B.prefix = "tune:";
+    B.ld = NGp;
     B.qj.resize(1);
     QJob& Q = B.qj[0];
     Q.qp.NG = NG;
@@ -1754,7 +1811,7 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e300;
     int bestv = 1;
-    for (int v = 1; v <= 2; ++v) {
+    for (int v = 1; v <= 3; ++v) {
         Q.variant = v;
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1786,7 +1843,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (save) {
         FILE* f = std::fopen(path, "w");
         if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
-        std::fprintf(f, "# precision padded_NG variant (1 = 64x64 tiles, 2 = 128x128 tiles)\n");
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64 tiles, 2 = 128x128 tiles, 3 = pipelined 128x128)\n");
         for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
         std::fclose(f);
         return RPA_OK;
@@ -1797,7 +1854,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int p, ng, v;
-        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || v == 2) && ng > 0)
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && v >= 1 && v <= 3 && ng > 0)
             c->tune[tune_key((rpa_precision)p, ng)] = v;
     }
     std::fclose(f);

@@ -207,11 +207,11 @@ def test_o2box_reduced_bands(rpa, iq):
     assert abs(ecb - ref["E"]) < tol
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_split_kernel_variants(rpa, variant, prec):
-    """Both split rank-k kernels (64x64 and 128x128 tiles) against the oracle on the 16^3 workload
-    (NG = 126) and a tiny grid (NG = 15: one 128-tile, half of it padding)."""
+    """The split rank-k kernels (64x64 tiles, 128x128 tiles, 128x128 pipelined) against the oracle on the
+    16^3 workload (NG = 126) and a tiny grid (NG = 15: one 128-tile, half of it padding)."""
     for wl in (synth.config0(), synth.tiny(grid=(8, 8, 8))):
         ref = oracle_q(wl)
         ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
@@ -273,8 +273,25 @@ def test_batched_graph_replays_match_per_q_calls(rpa, prec):
             assert abs(e - ref["E"]) < (1e-10 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_pipelined_split_kernel_is_bit_identical(rpa, prec):
+    """Variant 3 issues the same products in the same order as variant 2: chi0 is bit-identical, here on
+    the 48^3 grid (NG = 1500, twelve 128-row tiles) with 2 x 40 pairs (three K-steps, a ragged last one)."""
+    wl = synth.config1(n_occ=2, n_unocc=40, which_q=(1,))
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    out = {}
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        for v in (2, 3):
+            ctx.tune_set(len(gm), v, prec)
+            out[v] = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
+        ctx.check()
+    print(f"{prec}: max|chi| = {np.abs(out[2]).max():.3e}", flush=True)
+    assert np.abs(out[2]).max() > 0
+    assert np.array_equal(out[2], out[3])
+
+
 def test_autotune_records_a_variant(rpa):
     with rpa.Context(np.eye(3) * 10.0, (16, 16, 16)) as ctx:
         v = ctx.autotune(NG=700, npairs=512, nw=4, precision="split_bf16")
-        assert v in (1, 2)
+        assert v in (1, 2, 3)
         assert ctx.tune_get(700, "split_bf16") == v
