@@ -72,7 +72,7 @@ def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False, use_graph=
 
 
 HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 2: ("k_herk_split2", "k_herk_split2.hip"),
-                3: ("k_herk_split3", "k_herk_split2.hip")}
+                3: ("k_herk_split3", "k_herk_split2.hip"), 4: ("k_herk_split4", "k_herk_split2.hip")}
 
 
 def measured_traffic(kernel, src):
@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--n-unocc", type=int, default=800)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="force the split rank-k kernel variant (1, 2, 3); 0 keeps the library's choice")
     ap.add_argument("--cpu-sample-occ", type=int, default=4,
                     help="occupied states in the oracle's sample (all unoccupied states paired with each)")
     args = ap.parse_args()
@@ -168,6 +170,9 @@ def main():
     herk_flops_step = flops_step
 
     ctx = rpa.Context(wl.A, wl.grid, device=0)
+    if args.variant:
+        for ng in NGs:
+            ctx.tune_set(ng, args.variant, args.precision)
     ctx_variant = ctx.tune_get(NGs[0], args.precision)
     # split path
     run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.warmup)
@@ -197,13 +202,18 @@ def main():
     stage_ms = {k: v[0] / args.steps for k, v in prof.items()}
     dominant = max(stage_ms, key=stage_ms.get)
     herk_ms, herk_n = prof["herk"]
-    # MFMA flops the split kernel issues: lower tiles (64 or 128 wide) incl. the diagonal, K padded to 32,
+    # MFMA flops the split kernel issues: its lower-triangle tiles incl. the diagonal, K padded to 32,
     # 12 real 16-bit products per complex multiply-add (4 real products x 3 split terms)
     executed = 0.0
     for ng in NGs:
-        tm = 64 if ctx_variant == 1 else 128
-        nT = (ng + tm - 1) // tm
-        executed += nT * (nT + 1) / 2 * nw * tm * tm * ((P + 31) // 32 * 32) * 12 * 2
+        if ctx_variant == 4:
+            nr = (ng + 63) // 64
+            elems = sum(i // 2 + 1 for i in range(nr)) * 64 * 128
+        else:
+            tm = 64 if ctx_variant == 1 else 128
+            nT = (ng + tm - 1) // tm
+            elems = nT * (nT + 1) / 2 * tm * tm
+        executed += elems * nw * ((P + 31) // 32 * 32) * 12 * 2
     executed *= args.steps
     herk_avg_ms = herk_ms / max(herk_n, 1)
     achieved = herk_flops_step * args.steps / (herk_ms * 1e-3) / 1e12

@@ -197,13 +197,21 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
                     double* deps_kq, void* dC_kq, void* dP_kq, void* stream);
 
 /* Rank-k kernel choice of the split precisions per padded sphere size
- * (NG rounded up to 64): variant 1 = 64x64 tiles staged from FP32 rho,
- * variant 2 = 128x128 tiles from the K-blocked pre-split rho, variant 3 = the
- * same tiles and operands with a double-buffered, software-pipelined K loop
- * (bit-identical to variant 2). Without an entry,
- * NG >= 385 uses variant 3.
- *  rpa_autotune     times the three variants on synthetic operands of the given
- *                   shape on `stream` (synchronizes) and records the fastest.
+ * (NG rounded up to 64):
+ *   1 = 64x64 tiles staged from FP32 rho, FP32 partial sums added into FP64
+ *       every 8 K-steps;
+ *   2 = 128x128 tiles from the K-blocked pre-split rho, FP32 accumulation over
+ *       the whole pair chunk;
+ *   3 = variant 2 with a double-buffered, software-pipelined K loop
+ *       (bit-identical to 2);
+ *   4 = pipelined 64x128 tiles from the pre-split rho, FP32 partial sums added
+ *       into FP64 every 8 K-steps.
+ * Variants 2 and 3 keep the whole sum over a chunk (up to all pairs of a
+ * q-point) in FP32, whose rounding reaches ~1e-6 of E_c at 12,800 pairs; 1 and
+ * 4 stay near 1e-8. Without an entry, NG >= 385 uses variant 4, smaller
+ * spheres variant 1.
+ *  rpa_autotune     times variants 1 and 4 on synthetic operands of the given
+ *                   shape on `stream` (synchronizes) and records the faster.
  *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only).
  *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */
 int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, void* stream);

@@ -422,6 +422,193 @@ __global__ __launch_bounds__(256, 1) void k_herk_split3(HerkSplit2Args h) {
             }
 }
 
+// Variant 4: the pipeline of variant 3 with FP64 accumulation. A workgroup
+// computes a 64-row x 128-column tile (each wave all 64 rows x 32 columns); the
+// MFMAs accumulate in FP32 for 8 K-steps (256 pairs), then the partial sums are
+// added into FP64 registers, which bounds the FP32 rounding of the long sum
+// over pairs. The 64-row side is the one scaled by a(w) and split in the kernel,
+// so the split work per MFMA is the same as in variant 3. Row block I of the
+// lower triangle holds column blocks 0 .. I/2.
+constexpr int kFlush4 = 8;
+
+template <bool F16>
+__global__ __launch_bounds__(256, 1) void k_herk_split4(HerkSplit2Args h) {
+    typedef typename H<F16>::v8 hv;
+    constexpr int TR = 64, TC = 128;
+    __shared__ __align__(16) u16 sA[2][4][TR][KS];
+    __shared__ __align__(16) u16 sB[2][4][TC][KS];
+
+    const int b = blockIdx.x;
+    const int xcd = b % kXcds, local = b / kXcds;
+    const int tile = (local / h.nw) * kXcds + xcd;
+    const int w = local % h.nw;
+    if (tile >= h.ntiles) return;
+    int I = 0, t = tile;
+    while (t >= I / 2 + 1) {
+        t -= I / 2 + 1;
+        ++I;
+    }
+    const int ci = I * TR, cj = t * TC;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wc = wave * 32;
+    const double* aw = h.w + (size_t)w * h.lda;
+    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
+    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
+    const int K = h.K;
+
+    // staging: A row ar, pairs ak .. ak+7; B row br, pairs bk .. bk+15
+    const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int br = tid >> 1, bk = (tid & 1) * 16;
+    float pxr[8], pxi[8];
+    double pw[8];
+    v8u16 pb[4][2];
+    const int nkb = (K + KS - 1) / KS;
+    auto fetch = [&](int kb) {
+        const size_t oa = ((size_t)kb * h.NGq + ci + ar) * KS + ak;
+        const size_t ob = ((size_t)kb * h.NGq + cj + br) * KS + bk;
+#pragma unroll
+        for (int e = 0; e < 8; e += 4) {
+            const v4f a = *reinterpret_cast<const v4f*>(h.Xre + oa + e);
+            const v4f c = *reinterpret_cast<const v4f*>(h.Xim + oa + e);
+            pxr[e] = a[0]; pxr[e + 1] = a[1]; pxr[e + 2] = a[2]; pxr[e + 3] = a[3];
+            pxi[e] = c[0]; pxi[e + 1] = c[1]; pxi[e + 2] = c[2]; pxi[e + 3] = c[3];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pb[q][0] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
+            pb[q][1] = *reinterpret_cast<const v8u16*>(h.B[q] + ob + 8);
+        }
+        const int k0 = kb * KS + ak;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pw[e] = aw[min(k0 + e, K - 1)];
+    };
+    auto store = [&](int kb, int buf) {
+        const int k0 = kb * KS + ak;
+        v8u16 xrh, xrl, xih, xil;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float wk = (k0 + e < K) ? (float)pw[e] * sa : 0.f;
+            u16 a, c;
+            split<F16>(pxr[e] * wk, a, c);
+            xrh[e] = a;
+            xrl[e] = c;
+            split<F16>(pxi[e] * wk, a, c);
+            xih[e] = a;
+            xil[e] = c;
+        }
+        const int oa = swz(ar, ak >> 3);
+        *reinterpret_cast<v8u16*>(&sA[buf][0][ar][oa]) = xrh;
+        *reinterpret_cast<v8u16*>(&sA[buf][1][ar][oa]) = xrl;
+        *reinterpret_cast<v8u16*>(&sA[buf][2][ar][oa]) = xih;
+        *reinterpret_cast<v8u16*>(&sA[buf][3][ar][oa]) = xil;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            const int ob = swz(br, (bk >> 3) + hf);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[buf][q][br][ob]) = pb[q][hf];
+        }
+    };
+
+    v4f accR[4][2], accI[4][2];
+    double dR[4][2][4], dI[4][2][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            accR[x][y] = v4f{0, 0, 0, 0};
+            accI[x][y] = v4f{0, 0, 0, 0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                dR[x][y][r] = 0.0;
+                dI[x][y][r] = 0.0;
+            }
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    dR[x][y][r] += (double)accR[x][y][r];
+                    dI[x][y][r] += (double)accI[x][y][r];
+                }
+                accR[x][y] = v4f{0, 0, 0, 0};
+                accI[x][y] = v4f{0, 0, 0, 0};
+            }
+    };
+
+    fetch(0);
+    store(0, 0);
+    fetch(min(1, nkb - 1));
+    const int rr = lane & 15, kc = lane >> 4;
+    for (int kb = 0; kb < nkb; ++kb) {
+        __syncthreads();
+        const int cur = kb & 1;
+        hv bf[2][4], bn[2][2];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int row = wc + 16 * y + rr;
+            const int o = swz(row, kc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bf[y][q] = *reinterpret_cast<const hv*>(&sB[cur][q][row][o]);
+            bn[y][0] = -bf[y][2];
+            bn[y][1] = -bf[y][3];
+        }
+        hv af[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int row = 16 * x + rr;
+            const int o = swz(row, kc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) af[x][q] = *reinterpret_cast<const hv*>(&sA[cur][q][row][o]);
+        }
+        store(kb + 1, cur ^ 1);
+        fetch(min(kb + 2, nkb - 1));
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                v4f r = accR[x][y], im = accI[x][y];
+                r = H<F16>::mfma(af[x][1], bf[y][0], r);
+                r = H<F16>::mfma(af[x][0], bf[y][1], r);
+                r = H<F16>::mfma(af[x][3], bf[y][2], r);
+                r = H<F16>::mfma(af[x][2], bf[y][3], r);
+                r = H<F16>::mfma(af[x][0], bf[y][0], r);
+                r = H<F16>::mfma(af[x][2], bf[y][2], r);
+                im = H<F16>::mfma(af[x][3], bf[y][0], im);
+                im = H<F16>::mfma(af[x][2], bf[y][1], im);
+                im = H<F16>::mfma(af[x][1], bn[y][0], im);
+                im = H<F16>::mfma(af[x][0], bn[y][1], im);
+                im = H<F16>::mfma(af[x][2], bf[y][0], im);
+                im = H<F16>::mfma(af[x][0], bn[y][0], im);
+                accR[x][y] = r;
+                accI[x][y] = im;
+            }
+        if ((kb & (kFlush4 - 1)) == kFlush4 - 1) flush();
+    }
+    flush();
+
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    double* Cre = h.Cre + (size_t)w * h.sC;
+    double* Cim = h.Cim + (size_t)w * h.sC;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                if (row < h.ldC && col < h.ldC) {
+                    const size_t o = (size_t)row * h.ldC + col;
+                    Cre[o] += dR[x][y][r] * inv;
+                    Cim[o] += dI[x][y][r] * inv;
+                }
+            }
+}
+
 }  // namespace
 
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
@@ -434,6 +621,17 @@ hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr,
     else
         hipLaunchKernelGGL(k_pack_split<false>, grid, dim3(256), 0, s, rre, rim, K, ldr, NGq, scales, nw, Xre, Xim,
                            B[0], B[1], B[2], B[3]);
+    return hipGetLastError();
+}
+
+hipError_t launch_herk_split4(const HerkSplit2Args& h, hipStream_t s) {
+    if (h.ntiles <= 0 || h.nw <= 0 || h.K <= 0) return hipSuccess;
+    const int per_xcd = (h.ntiles + kXcds - 1) / kXcds;
+    const unsigned blocks = (unsigned)(per_xcd * h.nw * kXcds);
+    if (h.fp16)
+        hipLaunchKernelGGL(k_herk_split4<true>, dim3(blocks), dim3(256), 0, s, h);
+    else
+        hipLaunchKernelGGL(k_herk_split4<false>, dim3(blocks), dim3(256), 0, s, h);
     return hipGetLastError();
 }
 

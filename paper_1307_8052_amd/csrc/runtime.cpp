@@ -71,7 +71,7 @@ struct rpa_ctx {
     long long prof_n[16] = {0};
     int last_nq = 0;
     // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 2 = 128x128 tiles,
-    // 3 = 128x128 tiles software pipelined
+    // 3 = 128x128 tiles software pipelined, 4 = pipelined 64x128 tiles with FP64 accumulation
     std::map<uint64_t, int> tune;
     std::map<uint64_t, double> tune_ms;
     // the captured batch graph
@@ -82,6 +82,10 @@ struct rpa_ctx {
     bool pair_reg = true;   // register-resident pair transforms where supported
     // non-blocking stream the batch sequence is captured on (the legacy default stream cannot be)
     hipStream_t cap_stream = nullptr;
+    // look-ahead of the blocked Cholesky: the next panel runs on la_stream while the
+    // main stream finishes the trailing update (default priority, non-blocking)
+    hipStream_t la_stream = nullptr;
+    hipEvent_t la_ev[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -497,7 +501,7 @@ struct QJob {
     std::vector<void*> d_wq;
     std::vector<double> Dq;
     void* d_Dq = nullptr;
-    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64 tiles, 2 / 3 split 128x128 tiles (3 pipelined)
+    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64, 2 / 3 split 128x128 (3 pipelined), 4 split 64x128 pipelined
     int Pc = 0;        // pair chunk
     double* cr = nullptr;
     double* ci = nullptr;
@@ -530,7 +534,7 @@ int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
     if (prec == RPA_FP64) return 0;
     auto it = c->tune.find(tune_key(prec, NGp));
     if (it != c->tune.end()) return it->second;
-    return ((NGp + 127) / 128 >= 4) ? 3 : 1;
+    return ((NGp + 127) / 128 >= 4) ? 4 : 1;
 }
 
 int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
@@ -720,7 +724,7 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     if (need_ec || need_chi) W.chi = 2 * nmat * ld2 * sizeof(double);
     if (need_ec) {
         W.cholL = 2 * nmat * kTile * kTile * sizeof(double);
-        W.cholP = 2 * nmat * kTile * (size_t)B.ld * sizeof(double);
+        W.cholP = 2 * 2 * nmat * kTile * (size_t)B.ld * sizeof(double);   // two panels in flight
         W.small = nmat * (2 * sizeof(double) + sizeof(int)) + 64;
     }
     struct NB {
@@ -861,7 +865,7 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             HIP_TRY(launch_split_scales(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim),
                                         (size_t)np * NGp, aw, lda, np, B.nw, scales, scales + B.nw + 1, B.s));
         }
-        if (Q.variant == 2 || Q.variant == 3) {
+        if (Q.variant >= 2) {
             const int NGq = (NGp + 127) / 128 * 128;
             const size_t blk = (size_t)((np + 31) / 32) * NGq * 32;
             float* Xre = static_cast<float*>(buf(B, "split_pack"));
@@ -882,12 +886,20 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.Cim = Q.ci;
             h.sC = (long long)B.ld * B.ld;
             h.ldC = B.ld;
-            const int nT = NGq / 128;
-            h.ntiles = nT * (nT + 1) / 2;
             h.nw = B.nw;
             h.fp16 = fp16;
             h.scales = scales;
-            HIP_TRY(launch_herk_split2(h, Q.variant == 3, B.s));
+            if (Q.variant == 4) {
+                // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
+                const int nR = NGp / kTile;
+                h.ntiles = 0;
+                for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
+                HIP_TRY(launch_herk_split4(h, B.s));
+            } else {
+                const int nT = NGq / 128;
+                h.ntiles = nT * (nT + 1) / 2;
+                HIP_TRY(launch_herk_split2(h, Q.variant == 3, B.s));
+            }
         } else {
             HerkSplitArgs h{};
             h.Are = reinterpret_cast<const float*>(rre);
@@ -958,11 +970,26 @@ int enqueue_chi0(Batch& B) {
     return RPA_OK;
 }
 
+// side stream and events of the Cholesky look-ahead (created outside any graph capture)
+int ensure_lookahead(rpa_ctx* c) {
+    if (!c->la_stream) HIP_TRY(hipStreamCreateWithFlags(&c->la_stream, hipStreamNonBlocking));
+    for (auto& e : c->la_ev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return RPA_OK;
+}
+
 // E_c of every job of the batch from its accumulator (overwritten by -K and its
 // factor). The nq * nw matrices share one leading dimension and are factorised
 // together, so each 64-column panel step is one launch for the whole batch.
 // from_full (one job): -K from a caller chi0 [nw][NG][NG] instead.
 // Lblocks (one job): keep every inverted diagonal block and the factor itself.
+//
+// Look-ahead: the trailing update of step j is split into the next block column
+// (a_j, a GEMM) and the rest (b_j). The main stream runs panel, solve and a_j in
+// turn; b_j runs on la_stream once a_j is done, overlapping panel j+1 and its
+// solve (which come first on the main stream and so reach the CUs first). b_j
+// touches only columns right of block column j+1; a_{j+1} waits for b_j, since
+// both update block column j+2; the solved panels alternate between two buffers.
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     const int nw = B.nw, ld = B.ld;
@@ -973,35 +1000,44 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     int* failv = reinterpret_cast<int*>(trk + nb);
     double* Lre = static_cast<double*>(buf(B, "chol_L"));
     double* Lim = Lre + (size_t)nb * kTile * kTile;
-    double* Pre = static_cast<double*>(buf(B, "chol_panel"));
-    double* Pim = Pre + (size_t)nb * kTile * ld;
+    double* Pbase = static_cast<double*>(buf(B, "chol_panel"));
+    const size_t pstride = 2 * (size_t)nb * kTile * ld;   // one panel buffer (re and im)
     double* cr = B.qj[0].cr;
     double* ci = B.qj[0].ci;
     const long long ld2 = (long long)ld * ld;
-    ProfScope ps_(c, S_CHOL, B.s);
-    HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, B.s));
+    int rc = ensure_lookahead(c);
+    if (rc) return rc;
+    hipStream_t M = B.s, S = c->la_stream;
+    hipEvent_t evA = c->la_ev[0], evL = c->la_ev[1];
+    ProfScope ps_(c, S_CHOL, M);
+    HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, M));
     for (int qi = 0; qi < nq; ++qi) {
         QJob& Q = B.qj[qi];
         if (from_full) {
             HIP_TRY(launch_build_negk_from_full(static_cast<const double*>(chi_full), Q.qp.NG, Q.cr, Q.ci, ld, nw,
-                                                static_cast<const double*>(Q.d_vs), trk + qi * nw, B.s));
+                                                static_cast<const double*>(Q.d_vs), trk + qi * nw, M));
         } else {
             HIP_TRY(launch_build_negk(Q.cr, Q.ci, ld, Q.qp.NG, ld, nw, static_cast<const double*>(Q.d_vs),
-                                      trk + qi * nw, B.s));
+                                      trk + qi * nw, M));
         }
     }
+    bool pending_b = false;   // a trailing update b_j is in flight on S
     for (int j0 = 0; j0 < ld; j0 += kTile) {
+        const int step = j0 / kTile;
+        double* Pre = Pbase + (size_t)(step & 1) * pstride;
+        double* Pim = Pre + (size_t)nb * kTile * ld;
         if (Lblocks) {
             // keep every inverted diagonal block: [block][re/im][w][64][64]
-            Lre = Lblocks + (size_t)(j0 / kTile) * 2 * nb * kTile * kTile;
+            Lre = Lblocks + (size_t)step * 2 * nb * kTile * kTile;
             Lim = Lre + (size_t)nb * kTile * kTile;
         }
-        HIP_TRY(launch_chol_panel(cr, ci, ld, j0, nb, Lre, Lim, logdet, failv, B.s));
+        // panel j: block column j is complete (a_{j-1} before it here, b_{j-2} before a_{j-1})
+        HIP_TRY(launch_chol_panel(cr, ci, ld, j0, nb, Lre, Lim, logdet, failv, M));
         const int r0 = j0 + kTile;
         if (r0 >= ld) break;
         if (Lblocks) {
             // the adjoint needs the factor itself: L21 also replaces the block column
-            HIP_TRY(launch_chol_trsm(cr, ci, ld, j0, ld, nb, Lre, Lim, Pre, Pim, B.s));
+            HIP_TRY(launch_chol_trsm(cr, ci, ld, j0, ld, nb, Lre, Lim, Pre, Pim, M));
         } else {
             // panel operand of the trailing update only: P[c][r] = sum_k conj(L11^-1[c][k]) A21[r][k]
             GemmArgs gm{};
@@ -1027,31 +1063,68 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             gm.ldC = ld;
             gm.alpha = 1.0;
             gm.beta = 0;
-            HIP_TRY(launch_gemm_c64(gm, B.s));
+            HIP_TRY(launch_gemm_c64(gm, M));
         }
-        HerkArgs h{};
-        h.Are = Pre;
-        h.Aim = Pim;
-        h.sA = (long long)kTile * ld;
-        h.ldA = ld;
-        h.colA = r0;
-        h.K = kTile;
-        h.w = nullptr;
-        h.sw = 0;
-        h.alpha = -1.0;
-        h.Cre = cr;
-        h.Cim = ci;
-        h.sC = ld2;
-        h.ldC = ld;
-        h.r0 = r0;
-        h.nT = (ld - r0) / kTile;
-        h.nbatch = nb;
-        HIP_TRY(launch_herk_f64(h, B.s));
+        // a_j: the next block column C[r0:, r0:r0+64] -= P^H P (full 64-wide GEMM; the strict upper part
+        // of its diagonal tile is never read), after b_{j-1}, which also updates that column
+        if (pending_b) HIP_TRY(hipStreamWaitEvent(M, evL, 0));
+        GemmArgs ga{};
+        ga.M = ld - r0;
+        ga.N = kTile;
+        ga.K = kTile;
+        ga.nbatch = nb;
+        ga.Ar = Pre + r0;
+        ga.Ai = Pim + r0;
+        ga.sA = (long long)kTile * ld;
+        ga.aI = 1;
+        ga.aK = ld;
+        ga.conjA = 0;
+        ga.Br = Pre + r0;
+        ga.Bi = Pim + r0;
+        ga.sB = (long long)kTile * ld;
+        ga.bK = ld;
+        ga.bJ = 1;
+        ga.conjB = 1;
+        ga.Cr = cr + (size_t)r0 * ld + r0;
+        ga.Ci = ci + (size_t)r0 * ld + r0;
+        ga.sC = ld2;
+        ga.ldC = ld;
+        ga.alpha = -1.0;
+        ga.beta = 1;
+        HIP_TRY(launch_gemm_c64(ga, M));
+        // b_j on the side stream: the lower tiles right of that column
+        const int r1 = r0 + kTile;
+        pending_b = false;
+        if (r1 < ld) {
+            HIP_TRY(hipEventRecord(evA, M));
+            HIP_TRY(hipStreamWaitEvent(S, evA, 0));
+            HerkArgs h{};
+            h.Are = Pre;
+            h.Aim = Pim;
+            h.sA = (long long)kTile * ld;
+            h.ldA = ld;
+            h.colA = r1;
+            h.K = kTile;
+            h.w = nullptr;
+            h.sw = 0;
+            h.alpha = -1.0;
+            h.Cre = cr;
+            h.Cim = ci;
+            h.sC = ld2;
+            h.ldC = ld;
+            h.r0 = r1;
+            h.nT = (ld - r1) / kTile;
+            h.nbatch = nb;
+            HIP_TRY(launch_herk_f64(h, S));
+            HIP_TRY(hipEventRecord(evL, S));
+            pending_b = true;
+        }
     }
+    if (pending_b) HIP_TRY(hipStreamWaitEvent(M, evL, 0));
     for (int qi = 0; qi < nq; ++qi) {
         QJob& Q = B.qj[qi];
         HIP_TRY(launch_finalize(logdet + qi * nw, trk + qi * nw, failv + qi * nw,
-                                static_cast<const double*>(B.d_ow), nw, Q.F, Q.ec, B.s));
+                                static_cast<const double*>(B.d_ow), nw, Q.F, Q.ec, M));
     }
     return RPA_OK;
 }
@@ -1487,6 +1560,9 @@ int rpa_destroy(rpa_ctx* c) {
     (void)hipDeviceSynchronize();
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->la_stream) (void)hipStreamDestroy(c->la_stream);
+    for (hipEvent_t e : c->la_ev)
+        if (e) (void)hipEventDestroy(e);
     prof_collect(c);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     for (auto& kv : c->bufs)
@@ -1699,6 +1775,8 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
         return RPA_OK;
     }
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    rc = ensure_lookahead(c);
+    if (rc) return rc;
     hipStream_t caller = B.s;
     hipGraph_t graph = nullptr;
     c->capturing = true;
@@ -1759,8 +1837,9 @@ int rpa_set_pair_path(rpa_ctx* ctx, int path) {
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
     if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
-    if (variant < 1 || variant > 3)
-        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 2 (128x128) and 3 (128x128 pipelined)");
+    if (variant < 1 || variant > 4)
+        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 2 (128x128), 3 (128x128 pipelined) and 4 "
+                                   "(64x128 pipelined, FP64 accumulation)");
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     c->tune[tune_key(prec, NGp)] = variant;
     return RPA_OK;
@@ -1811,7 +1890,8 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e300;
     int bestv = 1;
-    for (int v = 1; v <= 3; ++v) {
+    // only the variants that accumulate the pair sum in FP64 are candidates
+    for (int v : {1, 4}) {
         Q.variant = v;
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1843,7 +1923,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (save) {
         FILE* f = std::fopen(path, "w");
         if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
-        std::fprintf(f, "# precision padded_NG variant (1 = 64x64 tiles, 2 = 128x128 tiles, 3 = pipelined 128x128)\n");
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 2 = 128x128, 3 = pipelined 128x128, 4 = pipelined 64x128)\n");
         for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
         std::fclose(f);
         return RPA_OK;
@@ -1854,7 +1934,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int p, ng, v;
-        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && v >= 1 && v <= 3 && ng > 0)
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && v >= 1 && v <= 4 && ng > 0)
             c->tune[tune_key((rpa_precision)p, ng)] = v;
     }
     std::fclose(f);
