@@ -72,7 +72,8 @@ def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False, use_graph=
 
 
 HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 2: ("k_herk_split2", "k_herk_split2.hip"),
-                3: ("k_herk_split3", "k_herk_split2.hip"), 4: ("k_herk_split4", "k_herk_split2.hip")}
+                3: ("k_herk_split3", "k_herk_split2.hip"), 4: ("k_herk_split4", "k_herk_split2.hip"),
+                5: ("k_herk_split5", "k_herk_split2.hip")}
 
 
 def measured_traffic(kernel, src):
@@ -206,7 +207,7 @@ def main():
     # 12 real 16-bit products per complex multiply-add (4 real products x 3 split terms)
     executed = 0.0
     for ng in NGs:
-        if ctx_variant == 4:
+        if ctx_variant >= 4:
             nr = (ng + 63) // 64
             elems = sum(i // 2 + 1 for i in range(nr)) * 64 * 128
         else:

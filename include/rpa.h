@@ -205,12 +205,14 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
  *   3 = variant 2 with a double-buffered, software-pipelined K loop
  *       (bit-identical to 2);
  *   4 = pipelined 64x128 tiles from the pre-split rho, FP32 partial sums added
- *       into FP64 every 8 K-steps.
+ *       into FP64 every 8 K-steps;
+ *   5 = variant 4 with eight waves per workgroup, two per SIMD (bit-identical
+ *       to 4).
  * Variants 2 and 3 keep the whole sum over a chunk (up to all pairs of a
- * q-point) in FP32, whose rounding reaches ~1e-6 of E_c at 12,800 pairs; 1 and
- * 4 stay near 1e-8. Without an entry, NG >= 385 uses variant 4, smaller
+ * q-point) in FP32, whose rounding reaches ~1e-6 of E_c at 12,800 pairs; 1, 4
+ * and 5 stay near 1e-8. Without an entry, NG >= 385 uses variant 5, smaller
  * spheres variant 1.
- *  rpa_autotune     times variants 1 and 4 on synthetic operands of the given
+ *  rpa_autotune     times variants 1, 4 and 5 on synthetic operands of the given
  *                   shape on `stream` (synchronizes) and records the faster.
  *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only).
  *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */

@@ -609,6 +609,179 @@ __global__ __launch_bounds__(256, 1) void k_herk_split4(HerkSplit2Args h) {
             }
 }
 
+// Variant 5: the tiles, operands and FP64 accumulation of variant 4 with eight
+// waves per workgroup (two per SIMD), each a 32 x 32 sub-tile, so that one wave's
+// MFMAs overlap the other's split, LDS and global traffic. Each thread stages
+// 4 pairs of one row of the 64-row side and 8 pairs of one row of the other.
+typedef u16 v4u16 __attribute__((ext_vector_type(4)));
+
+template <bool F16>
+__global__ __launch_bounds__(512, 1) void k_herk_split5(HerkSplit2Args h) {
+    typedef typename H<F16>::v8 hv;
+    constexpr int TR = 64, TC = 128;
+    __shared__ __align__(16) u16 sA[2][4][TR][KS];
+    __shared__ __align__(16) u16 sB[2][4][TC][KS];
+
+    const int b = blockIdx.x;
+    const int xcd = b % kXcds, local = b / kXcds;
+    const int tile = (local / h.nw) * kXcds + xcd;
+    const int w = local % h.nw;
+    if (tile >= h.ntiles) return;
+    int I = 0, t = tile;
+    while (t >= I / 2 + 1) {
+        t -= I / 2 + 1;
+        ++I;
+    }
+    const int ci = I * TR, cj = t * TC;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
+    const double* aw = h.w + (size_t)w * h.lda;
+    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
+    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
+    const int K = h.K;
+
+    // staging: A row ar, pairs ak .. ak+3; B row br, pairs bk .. bk+7
+    const int ar = tid >> 3, ak = (tid & 7) * 4;
+    const int br = tid >> 2, bk = (tid & 3) * 8;
+    v4f pxr, pxi;
+    double pw[4];
+    v8u16 pb[4];
+    const int nkb = (K + KS - 1) / KS;
+    auto fetch = [&](int kb) {
+        const size_t oa = ((size_t)kb * h.NGq + ci + ar) * KS + ak;
+        const size_t ob = ((size_t)kb * h.NGq + cj + br) * KS + bk;
+        pxr = *reinterpret_cast<const v4f*>(h.Xre + oa);
+        pxi = *reinterpret_cast<const v4f*>(h.Xim + oa);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pb[q] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
+        const int k0 = kb * KS + ak;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pw[e] = aw[min(k0 + e, K - 1)];
+    };
+    auto store = [&](int kb, int buf) {
+        const int k0 = kb * KS + ak;
+        v4u16 xrh, xrl, xih, xil;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float wk = (k0 + e < K) ? (float)pw[e] * sa : 0.f;
+            u16 a, c;
+            split<F16>(pxr[e] * wk, a, c);
+            xrh[e] = a;
+            xrl[e] = c;
+            split<F16>(pxi[e] * wk, a, c);
+            xih[e] = a;
+            xil[e] = c;
+        }
+        const int oa = swz(ar, ak >> 3) + (ak & 7);
+        *reinterpret_cast<v4u16*>(&sA[buf][0][ar][oa]) = xrh;
+        *reinterpret_cast<v4u16*>(&sA[buf][1][ar][oa]) = xrl;
+        *reinterpret_cast<v4u16*>(&sA[buf][2][ar][oa]) = xih;
+        *reinterpret_cast<v4u16*>(&sA[buf][3][ar][oa]) = xil;
+        const int ob = swz(br, bk >> 3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[buf][q][br][ob]) = pb[q];
+    };
+
+    v4f accR[2][2], accI[2][2];
+    double dR[2][2][4], dI[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            accR[x][y] = v4f{0, 0, 0, 0};
+            accI[x][y] = v4f{0, 0, 0, 0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                dR[x][y][r] = 0.0;
+                dI[x][y][r] = 0.0;
+            }
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    dR[x][y][r] += (double)accR[x][y][r];
+                    dI[x][y][r] += (double)accI[x][y][r];
+                }
+                accR[x][y] = v4f{0, 0, 0, 0};
+                accI[x][y] = v4f{0, 0, 0, 0};
+            }
+    };
+
+    fetch(0);
+    store(0, 0);
+    fetch(min(1, nkb - 1));
+    const int rr = lane & 15, kc = lane >> 4;
+    for (int kb = 0; kb < nkb; ++kb) {
+        __syncthreads();
+        const int cur = kb & 1;
+        hv bf[2][4], bn[2][2];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int row = wc + 16 * y + rr;
+            const int o = swz(row, kc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bf[y][q] = *reinterpret_cast<const hv*>(&sB[cur][q][row][o]);
+            bn[y][0] = -bf[y][2];
+            bn[y][1] = -bf[y][3];
+        }
+        hv af[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int row = wr + 16 * x + rr;
+            const int o = swz(row, kc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) af[x][q] = *reinterpret_cast<const hv*>(&sA[cur][q][row][o]);
+        }
+        store(kb + 1, cur ^ 1);
+        fetch(min(kb + 2, nkb - 1));
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                v4f r = accR[x][y], im = accI[x][y];
+                r = H<F16>::mfma(af[x][1], bf[y][0], r);
+                r = H<F16>::mfma(af[x][0], bf[y][1], r);
+                r = H<F16>::mfma(af[x][3], bf[y][2], r);
+                r = H<F16>::mfma(af[x][2], bf[y][3], r);
+                r = H<F16>::mfma(af[x][0], bf[y][0], r);
+                r = H<F16>::mfma(af[x][2], bf[y][2], r);
+                im = H<F16>::mfma(af[x][3], bf[y][0], im);
+                im = H<F16>::mfma(af[x][2], bf[y][1], im);
+                im = H<F16>::mfma(af[x][1], bn[y][0], im);
+                im = H<F16>::mfma(af[x][0], bn[y][1], im);
+                im = H<F16>::mfma(af[x][2], bf[y][0], im);
+                im = H<F16>::mfma(af[x][0], bn[y][0], im);
+                accR[x][y] = r;
+                accI[x][y] = im;
+            }
+        if ((kb & (kFlush4 - 1)) == kFlush4 - 1) flush();
+    }
+    flush();
+
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    double* Cre = h.Cre + (size_t)w * h.sC;
+    double* Cim = h.Cim + (size_t)w * h.sC;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                if (row < h.ldC && col < h.ldC) {
+                    const size_t o = (size_t)row * h.ldC + col;
+                    Cre[o] += dR[x][y][r] * inv;
+                    Cim[o] += dI[x][y][r] * inv;
+                }
+            }
+}
+
 }  // namespace
 
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
@@ -624,14 +797,21 @@ hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr,
     return hipGetLastError();
 }
 
-hipError_t launch_herk_split4(const HerkSplit2Args& h, hipStream_t s) {
+hipError_t launch_herk_split4(const HerkSplit2Args& h, int eight_waves, hipStream_t s) {
     if (h.ntiles <= 0 || h.nw <= 0 || h.K <= 0) return hipSuccess;
     const int per_xcd = (h.ntiles + kXcds - 1) / kXcds;
     const unsigned blocks = (unsigned)(per_xcd * h.nw * kXcds);
-    if (h.fp16)
-        hipLaunchKernelGGL(k_herk_split4<true>, dim3(blocks), dim3(256), 0, s, h);
-    else
-        hipLaunchKernelGGL(k_herk_split4<false>, dim3(blocks), dim3(256), 0, s, h);
+    if (eight_waves) {
+        if (h.fp16)
+            hipLaunchKernelGGL(k_herk_split5<true>, dim3(blocks), dim3(512), 0, s, h);
+        else
+            hipLaunchKernelGGL(k_herk_split5<false>, dim3(blocks), dim3(512), 0, s, h);
+    } else {
+        if (h.fp16)
+            hipLaunchKernelGGL(k_herk_split4<true>, dim3(blocks), dim3(256), 0, s, h);
+        else
+            hipLaunchKernelGGL(k_herk_split4<false>, dim3(blocks), dim3(256), 0, s, h);
+    }
     return hipGetLastError();
 }
 

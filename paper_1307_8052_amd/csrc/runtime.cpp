@@ -71,7 +71,8 @@ struct rpa_ctx {
     long long prof_n[16] = {0};
     int last_nq = 0;
     // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 2 = 128x128 tiles,
-    // 3 = 128x128 tiles software pipelined, 4 = pipelined 64x128 tiles with FP64 accumulation
+    // 3 = 128x128 tiles software pipelined, 4 / 5 = pipelined 64x128 tiles with FP64 accumulation
+    // (4: four waves, 5: eight waves per workgroup)
     std::map<uint64_t, int> tune;
     std::map<uint64_t, double> tune_ms;
     // the captured batch graph
@@ -534,7 +535,7 @@ int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
     if (prec == RPA_FP64) return 0;
     auto it = c->tune.find(tune_key(prec, NGp));
     if (it != c->tune.end()) return it->second;
-    return ((NGp + 127) / 128 >= 4) ? 4 : 1;
+    return ((NGp + 127) / 128 >= 4) ? 5 : 1;
 }
 
 int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
@@ -889,12 +890,12 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.nw = B.nw;
             h.fp16 = fp16;
             h.scales = scales;
-            if (Q.variant == 4) {
+            if (Q.variant >= 4) {
                 // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
                 const int nR = NGp / kTile;
                 h.ntiles = 0;
                 for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
-                HIP_TRY(launch_herk_split4(h, B.s));
+                HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
             } else {
                 const int nT = NGq / 128;
                 h.ntiles = nT * (nT + 1) / 2;
@@ -1837,9 +1838,9 @@ int rpa_set_pair_path(rpa_ctx* ctx, int path) {
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
     if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
-    if (variant < 1 || variant > 4)
-        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 2 (128x128), 3 (128x128 pipelined) and 4 "
-                                   "(64x128 pipelined, FP64 accumulation)");
+    if (variant < 1 || variant > 5)
+        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 2 (128x128), 3 (128x128 pipelined), 4 "
+                                   "(64x128 pipelined, FP64 accumulation) and 5 (as 4, eight waves)");
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     c->tune[tune_key(prec, NGp)] = variant;
     return RPA_OK;
@@ -1891,7 +1892,7 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     double best = 1e300;
     int bestv = 1;
     // only the variants that accumulate the pair sum in FP64 are candidates
-    for (int v : {1, 4}) {
+    for (int v : {1, 4, 5}) {
         Q.variant = v;
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1923,7 +1924,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (save) {
         FILE* f = std::fopen(path, "w");
         if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
-        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 2 = 128x128, 3 = pipelined 128x128, 4 = pipelined 64x128)\n");
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 2 = 128x128, 3 = pipelined 128x128, 4 / 5 = pipelined 64x128)\n");
         for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
         std::fclose(f);
         return RPA_OK;
@@ -1934,7 +1935,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int p, ng, v;
-        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && v >= 1 && v <= 4 && ng > 0)
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && v >= 1 && v <= 5 && ng > 0)
             c->tune[tune_key((rpa_precision)p, ng)] = v;
     }
     std::fclose(f);

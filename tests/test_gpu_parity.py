@@ -207,7 +207,7 @@ def test_o2box_reduced_bands(rpa, iq):
     assert abs(ecb - ref["E"]) < tol
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_split_kernel_variants(rpa, variant, prec):
     """The split rank-k kernels (64x64 tiles, 128x128 tiles, 128x128 pipelined, 64x128 pipelined with FP64
@@ -274,21 +274,24 @@ def test_batched_graph_replays_match_per_q_calls(rpa, prec):
             assert abs(e - ref["E"]) < (1e-10 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("pair", [(2, 3), (4, 5)])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
-def test_pipelined_split_kernel_is_bit_identical(rpa, prec):
-    """Variant 3 issues the same products in the same order as variant 2: chi0 is bit-identical, here on
-    the 48^3 grid (NG = 1500, twelve 128-row tiles) with 2 x 40 pairs (three K-steps, a ragged last one)."""
-    wl = synth.config1(n_occ=2, n_unocc=40, which_q=(1,))
+def test_split_kernel_twins_are_bit_identical(rpa, prec, pair):
+    """Variant 3 issues the same products in the same order as variant 2, and variant 5 as variant 4 (the
+    same tiles split over eight waves instead of four): chi0 is bit-identical, here on the 48^3 grid
+    (NG = 1500) with 2 x 300 pairs (19 K-steps: two FP64 flushes of v4/v5 and a ragged last step)."""
+    wl = synth.config1(n_occ=2, n_unocc=300, which_q=(1,))
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
     out = {}
     with rpa.Context(wl.A, wl.grid) as ctx:
-        for v in (2, 3):
+        for v in pair:
             ctx.tune_set(len(gm), v, prec)
             out[v] = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
         ctx.check()
-    print(f"{prec}: max|chi| = {np.abs(out[2]).max():.3e}", flush=True)
-    assert np.abs(out[2]).max() > 0
-    assert np.array_equal(out[2], out[3])
+    a, b = pair
+    print(f"{prec} {pair}: max|chi| = {np.abs(out[a]).max():.3e}", flush=True)
+    assert np.abs(out[a]).max() > 0
+    assert np.array_equal(out[a], out[b])
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
@@ -300,7 +303,7 @@ def test_split_full_size_matches_fp64(rpa, prec):
     wl = synth.config1(which_q=(1,))
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
     with rpa.Context(wl.A, wl.grid) as ctx:
-        assert ctx.tune_get(len(gm), prec) == 4
+        assert ctx.tune_get(len(gm), prec) == 5
         e64, _ = ctx.ec(ks, kqs, qs, fr, "fp64")
         es, _ = ctx.ec(ks, kqs, qs, fr, prec)
         ctx.check()
@@ -313,5 +316,5 @@ def test_split_full_size_matches_fp64(rpa, prec):
 def test_autotune_records_a_variant(rpa):
     with rpa.Context(np.eye(3) * 10.0, (16, 16, 16)) as ctx:
         v = ctx.autotune(NG=700, npairs=512, nw=4, precision="split_bf16")
-        assert v in (1, 4)
+        assert v in (1, 4, 5)
         assert ctx.tune_get(700, "split_bf16") == v
