@@ -218,10 +218,12 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
  *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */
 int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, void* stream);
 
-/* Pair-transform kernels of Eq. fft for this context: path 0 (default) runs the
- * register-resident transforms when N1 == N2 and N1, N3 are among the compiled
- * line lengths (8, 10, 12, 16, 20, 24, 32, 40, 48, and 64 in the split
- * precisions) and the LDS radix passes otherwise; path 1 always runs the LDS radix passes. Both give the same
+/* Grid-transform kernels (Eq. get_wfs, Eq. fft) for this context: path 0
+ * (default) runs register-resident lines along z when N3 is one of the
+ * compiled line lengths (8, 10, 12, 16, 20, 24, 32, 40, 48, and 64 in the split
+ * precisions), and along x and y when N1 == N2 is one of them, and LDS radix
+ * passes for the other axes (a 40 x 40 x 160 grid runs x and y in registers and
+ * z through LDS); path 1 always runs the LDS radix passes. Both give the same
  * result up to rounding order. RPA_ERR_INPUT for another value. */
 int rpa_set_pair_path(rpa_ctx* ctx, int path);
 int rpa_tune_set(rpa_ctx* ctx, rpa_precision prec, int NG, int variant);

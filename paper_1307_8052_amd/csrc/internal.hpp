@@ -44,17 +44,22 @@ hipError_t launch_pair_xy(const cplx<T>* phik, const cplx<T>* phikq, const int32
                           const cplx<T>* tw1, const cplx<T>* tw2, cplx<T>* tbuf, hipStream_t s);
 
 // Register-resident variants of the two pair kernels (same tbuf layout and
-// output); supported when N1 == N2 and N1, N3 have compiled line lengths.
+// output): the xy kernel when N1 == N2 has a compiled line length, the z kernel
+// when N3 has one; each can pair with the other's LDS-pass counterpart.
 template <typename T>
-bool pair_reg_supported(const PairGeom& g);
+bool pair_xy_reg_supported(const PairGeom& g);
+template <typename T>
+bool pair_z_reg_supported(const PairGeom& g);
 template <typename T>
 hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const int32_t* pn, const int32_t* pm,
                               int npairs, const PairGeom& g, cplx<T>* tbuf, hipStream_t s);
-// In-place 3-D transform of nb grids [nb][N3][N2][N1] (dir = +1 inverse without
-// 1/N, -1 forward) with register-resident lines; hipErrorNotSupported where the
-// register kernels do not cover the grid.
+// In-place transforms of nb grids [nb][N3][N2][N1] (dir = +1 inverse without
+// 1/N, -1 forward) with register-resident lines: along z, or along x and y;
+// hipErrorNotSupported where the register kernels do not cover the axis.
 template <typename T>
-hipError_t launch_grid_fft_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
+hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
+template <typename T>
+hipError_t launch_grid_fft_xy_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
 template <typename T>
 hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
                              const int32_t* col_g, const int32_t* col_kz, T* rho_re, T* rho_im, hipStream_t s);

@@ -5,7 +5,9 @@
 // Orbitals: k_fft_z_reg transforms every z-line in place (lanes take
 // consecutive x, so each load and store is coalesced without LDS);
 // k_fft_xy_reg takes one z-plane per workgroup through LDS, one thread per
-// x-row and then one per y-column.
+// x-row and then one per y-column. Each axis pair uses its register kernel when
+// its length has one, so a grid such as 40 x 40 x 160 runs x and y in registers
+// and z through the LDS passes.
 //
 // Same data flow and outputs as the LDS-pass kernels: k_pair_xy_reg leaves the
 // K2 x K1 kept (x, y) outputs of every z-plane of a pair in tbuf
@@ -261,25 +263,28 @@ int z_block() {
 }  // namespace
 
 template <typename T>
-bool pair_reg_supported(const PairGeom& g) {
-    if (g.N1 != g.N2 || !reg_size(g.N1) || !reg_size(g.N3)) return false;
+bool pair_xy_reg_supported(const PairGeom& g) {
+    if (g.N1 != g.N2 || !reg_size(g.N1)) return false;
     // a 64-point FP64 line does not fit the register file
-    if (sizeof(T) == 8 && (g.N1 > 48 || g.N3 > 48)) return false;
-    if (xy_slab<T>(g) < 1) return false;
-    if (g.ncols > 0xffff) return false;
-    return true;
+    if (sizeof(T) == 8 && g.N1 > 48) return false;
+    return xy_slab<T>(g) >= 1;
 }
 
 template <typename T>
-hipError_t launch_grid_fft_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s) {
+bool pair_z_reg_supported(const PairGeom& g) {
+    if (!reg_size(g.N3)) return false;
+    if (sizeof(T) == 8 && g.N3 > 48) return false;
+    return g.ncols <= 0xffff;
+}
+
+template <typename T>
+hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s) {
     if (!nb) return hipSuccess;
     PairGeom g{};
     g.N1 = N1;
     g.N2 = N2;
     g.N3 = N3;
-    g.K1 = 1;
-    g.K2 = 1;
-    if (!pair_reg_supported<T>(g)) return hipErrorNotSupported;
+    if (!pair_z_reg_supported<T>(g)) return hipErrorNotSupported;
     const int plane = N1 * N2;
     const long long nlines = (long long)nb * plane;
     const unsigned zb = (unsigned)((nlines + 255) / 256);
@@ -295,6 +300,18 @@ hipError_t launch_grid_fft_reg(cplx<T>* data, int nb, int N1, int N2, int N3, in
 #undef RPA_CASE
         default: return hipErrorNotSupported;
     }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grid_fft_xy_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s) {
+    if (!nb) return hipSuccess;
+    PairGeom g{};
+    g.N1 = N1;
+    g.N2 = N2;
+    g.N3 = N3;
+    g.K1 = 1;
+    if (!pair_xy_reg_supported<T>(g)) return hipErrorNotSupported;
     const unsigned planes = (unsigned)((long long)nb * N3);
     switch (N1) {
 #define RPA_CASE(L)                                                                                   \
@@ -315,7 +332,7 @@ template <typename T>
 hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const int32_t* pn, const int32_t* pm,
                               int npairs, const PairGeom& g, cplx<T>* tbuf, hipStream_t s) {
     if (!npairs) return hipSuccess;
-    if (!pair_reg_supported<T>(g)) return hipErrorNotSupported;
+    if (!pair_xy_reg_supported<T>(g)) return hipErrorNotSupported;
     const int S = xy_slab<T>(g);
     const int rows = S * g.N2;
     const int threads = std::min(xy_threads_rt<T>(g.N1), (rows + 63) / 64 * 64);
@@ -341,7 +358,7 @@ template <typename T>
 hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
                              const int32_t* col_g, const int32_t* col_kz, T* rho_re, T* rho_im, hipStream_t s) {
     if (!npairs) return hipSuccess;
-    if (!pair_reg_supported<T>(g)) return hipErrorNotSupported;
+    if (!pair_z_reg_supported<T>(g)) return hipErrorNotSupported;
     const int CB = z_block<T>();
     const size_t lds = (size_t)CB * (g.N3 + 1) * sizeof(cplx<T>);
     dim3 grid((unsigned)npairs, (unsigned)((g.ncols + CB - 1) / CB));
@@ -359,8 +376,10 @@ hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g,
 }
 
 #define RPA_INST(T)                                                                                              \
-    template bool pair_reg_supported<T>(const PairGeom&);                                                        \
-    template hipError_t launch_grid_fft_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                   \
+    template bool pair_xy_reg_supported<T>(const PairGeom&);                                                     \
+    template bool pair_z_reg_supported<T>(const PairGeom&);                                                      \
+    template hipError_t launch_grid_fft_z_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                 \
+    template hipError_t launch_grid_fft_xy_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                \
     template hipError_t launch_pair_xy_reg<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*, int, \
                                               const PairGeom&, cplx<T>*, hipStream_t);                           \
     template hipError_t launch_pair_z_reg<T>(const cplx<T>*, int, const PairGeom&, const int32_t*, const int32_t*, \

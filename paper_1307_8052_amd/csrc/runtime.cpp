@@ -759,10 +759,18 @@ int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const char* nam
     HIP_TRY(launch_fill_zero<T>(phi, (size_t)s->nbands * vol, B.s));
     HIP_TRY(launch_orb_scatter<T>(static_cast<const double*>(s->C), s->nbands, s->nQ,
                                   static_cast<const int32_t*>(d_map), vol, phi, B.s));
-    hipError_t e = hipErrorNotSupported;
-    if (c->pair_reg) e = launch_grid_fft_reg<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], +1, B.s);
+    // z, then x and y: register-resident lines where the axis length has them, LDS passes otherwise
+    hipError_t e = c->pair_reg ? launch_grid_fft_z_reg<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], +1, B.s)
+                               : hipErrorNotSupported;
+    if (e == hipErrorNotSupported)
+        HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], 2, c->plan[2],
+                                   static_cast<const cplx<T>*>(B.d_tw[2]), +1, B.s));
+    else
+        HIP_TRY(e);
+    e = c->pair_reg ? launch_grid_fft_xy_reg<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], +1, B.s)
+                    : hipErrorNotSupported;
     if (e == hipErrorNotSupported) {
-        for (int ax = 0; ax < 3; ++ax)
+        for (int ax = 0; ax < 2; ++ax)
             HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
                                        static_cast<const cplx<T>*>(B.d_tw[ax]), +1, B.s));
     } else {
@@ -781,10 +789,11 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     cplx<T>* tb = static_cast<cplx<T>*>(buf(B, "tbuf"));
     const int32_t* pn = static_cast<const int32_t*>(K.d_pn) + p0;
     const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
-    const bool reg = c->pair_reg && pair_reg_supported<T>(g);
+    const bool reg_xy = c->pair_reg && pair_xy_reg_supported<T>(g);
+    const bool reg_z = c->pair_reg && pair_z_reg_supported<T>(g);
     {
         ProfScope ps_(c, S_PAIR_XY, B.s);
-        if (reg)
+        if (reg_xy)
             HIP_TRY(launch_pair_xy_reg<T>(phik, phikq, pn, pm, np, g, tb, B.s));
         else
             HIP_TRY(launch_pair_xy<T>(phik, phikq, pn, pm, np, g, static_cast<const int32_t*>(Q.d_kx),
@@ -793,7 +802,7 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     }
     {
         ProfScope ps_(c, S_PAIR_Z, B.s);
-        if (reg)
+        if (reg_z)
             HIP_TRY(launch_pair_z_reg<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
                                          static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz), rre,
                                          rim, B.s));

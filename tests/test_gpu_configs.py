@@ -1,0 +1,103 @@
+"""The metal-slab and uneven-batch workload shapes at reduced band counts, through the C ABI.
+
+Same cells, grids, occupations and PAW sizes as the full workloads (9 x 9 x 36 bohr, 40 x 40 x 160 grid,
+20 atoms x 18 projectors), with fewer states so that the FP64 oracle finishes in seconds:
+  metal slab  - two k-points off Gamma, Fermi-smeared occupations (T = 0.01 Ha), 6 + 24 states,
+                NG = 303;
+  uneven batch - eight q-points of the 4 x 4 x 4 mesh with spheres of 252 to 1752 vectors, 4 + 24 states.
+The 40 x 40 x 160 grid runs x and y through the register kernels and z through the LDS passes.
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import gpu_inputs, oracle_q
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rpa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1307_8052_amd as m
+    return m
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _split_tol(E):
+    return 1e-6 * max(1.0, abs(E)) * 0.2
+
+
+@pytest.fixture(scope="module")
+def slab():
+    wl = synth.config2(n_below=6, n_above=24, nk=2, target_ng=300)
+    return wl, oracle_q(wl)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_metal_slab_reduced(rpa, slab, path):
+    wl, ref = slab
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    assert np.array_equal(gm, ref["gm"])
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_pair_path(path)
+        chi = ctx.chi0(ks, kqs, qs, fr, "fp64").cpu().numpy()
+        ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
+        ecs, _ = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        ctx.check()
+    ec, ecs, F = float(ec.cpu()[0]), float(ecs.cpu()[0]), F.cpu().numpy()
+    r = _rel(chi, ref["chi"])
+    print(f"slab path {path}: NG={len(gm)} chi rel={r:.3e} E={ec:.12f} ref={ref['E']:.12f} "
+          f"dE={ec - ref['E']:.3e} split dE={ecs - ref['E']:.3e}", flush=True)
+    assert r < 1e-12
+    assert np.max(np.abs(F - ref["F"])) < 1e-10
+    assert abs(ec - ref["E"]) < 1e-10
+    assert abs(ecs - ref["E"]) < _split_tol(ref["E"])
+
+
+def test_uneven_batch_reduced(rpa):
+    """Eight q-points in one call (one leading dimension, padded to the largest sphere): equal to the per-q
+    calls, a captured graph replay bit-identical to the eager call, the small spheres against the oracle,
+    and the split precision within its bound of the FP64 batch."""
+    wl = synth.config3(n_occ=4, n_unocc=24, nq=8)
+    ks = [rpa.States.from_synth(wl.kpoints[0], wl.paw, "cuda:0")]
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    qspecs, ngs = [], []
+    for qp in wl.qpoints:
+        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+        ngs.append(len(gm))
+        qspecs.append(rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight))
+    assert min(ngs) < 300 and max(ngs) > 1700
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        per_q = []
+        for qs in qspecs:
+            e, _ = ctx.ec(ks, ks, qs, fr, "fp64")
+            per_q.append(float(e.cpu()[0]))
+        ec0, _ = ctx.ec_batched(ks, ks, qspecs, fr, "fp64")
+        eager = ec0.cpu().numpy().copy()
+        out = ctx.ec_batched(ks, ks, qspecs, fr, "fp64", use_graph=True)
+        out = ctx.ec_batched(ks, ks, qspecs, fr, "fp64", use_graph=True, out=out)
+        graph = out[0].cpu().numpy().copy()
+        ecs, _ = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
+        ctx.check()
+        split = ecs.cpu().numpy()
+    print(f"NG={ngs} E={eager[:len(ngs)]}", flush=True)
+    assert np.allclose(eager[:len(ngs)], per_q, rtol=1e-12, atol=0)
+    assert np.array_equal(graph, eager)
+    assert abs(eager[len(ngs)] - sum(q.weight * e for q, e in zip(qspecs, per_q))) < 1e-12 * max(1.0, abs(eager[len(ngs)]))
+    for i, e in enumerate(eager[:len(ngs)]):
+        assert abs(split[i] - e) < _split_tol(e), (i, split[i], e)
+    small = [i for i, n in enumerate(ngs) if n < 400]
+    assert len(small) >= 3
+    for i in small:
+        wl1 = synth.Workload(name="t", A=wl.A, grid=wl.grid, kpoints=wl.kpoints, paw=wl.paw,
+                             qpoints=[wl.qpoints[i]], omega=wl.omega, omega_weight=wl.omega_weight, seed=0)
+        ref = oracle_q(wl1)
+        print(f"q{i} NG={ngs[i]}: E={eager[i]:.12f} ref={ref['E']:.12f}", flush=True)
+        assert abs(eager[i] - ref["E"]) < 1e-10
