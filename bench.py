@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--variant", type=int, default=0,
                     help="force the split rank-k kernel variant (1, 2, 3); 0 keeps the library's choice")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-q loop and adjoint timings")
     ap.add_argument("--cpu-sample-occ", type=int, default=4,
                     help="occupied states in the oracle's sample (all unoccupied states paired with each)")
     args = ap.parse_args()
@@ -189,6 +191,29 @@ def main():
         dtg, ec_graph, _ = run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.steps, use_graph=True)
         ms_step_graph = dtg / args.steps * 1e3
         log(f"split (graph replay): {ms_step_graph:.2f} ms/step")
+
+    # the same q-points as a loop of single-q calls, and the adjoint of one q-point
+    extras = {}
+    if not args.no_extras:
+        def loop_step():
+            for qs in qspecs:
+                ctx.ec(ks, ks, qs, fr, args.precision)
+        loop_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            loop_step()
+        torch.cuda.synchronize()
+        extras["per_q_loop_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
+        log(f"per-q loop: {extras['per_q_loop_ms_per_step']:.2f} ms/step")
+        ctx.ec_backward(ks[0], ks[0], qspecs[1], fr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ecb, _ = ctx.ec_backward(ks[0], ks[0], qspecs[1], fr)
+        torch.cuda.synchronize()
+        extras["adjoint_fp64_ms_q1"] = (time.perf_counter() - t0) * 1e3
+        ctx.check()
+        log(f"adjoint (FP64, q-point 1, E_c and dE_c/d(eps, C, P)): {extras['adjoint_fp64_ms_q1']:.1f} ms")
 
     # FP64 path on the same inputs
     k64 = args.fp64_steps if args.fp64_steps is not None else args.steps
@@ -253,6 +278,7 @@ def main():
         "ms_per_step_graph": ms_step_graph,
         "ec_graph_equals_eager": None if ec_graph is None else ec_graph == ec_split,
         "speedup_vs_fp64": fp64 and fp64["ms_per_step"] / ms_step,
+        **extras,
         "stage_ms": stage_ms,
         "fp64": fp64,
         "roofline": roofline,
