@@ -22,7 +22,9 @@
  *    rpa_status; nothing aborts or throws across the ABI. A failed kernel
  *    launch or an earlier asynchronous fault is reported as RPA_ERR_HIP.
  *    rpa_last_error() gives a per-thread detail string for the last failure.
- *  - Calls on one context are not re-entrant: one host thread at a time.
+ *  - Calls on one context are not re-entrant: one host thread at a time. All
+ *    calls on a context share its device workspaces, so calls issued on
+ *    different streams must be ordered by the caller (e.g. with events).
  */
 #ifndef RPA_MI355X_H
 #define RPA_MI355X_H
@@ -90,6 +92,8 @@ typedef struct {
  *  q        Cartesian q (bohr^-1).
  *  optical  1: q -> 0 limit along qhat (q must be 0). Row G = 0 of every pair
  *           density is replaced by Eq. n_q0 and v^1/2 at G = 0 is sqrt(4 pi).
+ *           Eq. n_q0 divides by eps_m - eps_n: a transition with equal
+ *           eigenvalues is RPA_ERR_INPUT.
  *  NG, gmiller  HOST int32 [NG][3]: the G-sphere (any order; chi0 comes out in
  *           this order). rpa_gsphere() produces the canonical one.
  *  Qpaw     DEVICE complex128 [sum_a Np_a^2][NG]: Q^a_ij(q+G), row
@@ -213,7 +217,7 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
  * and 5 stay near 1e-8. Without an entry, NG >= 385 uses variant 5, smaller
  * spheres variant 1.
  *  rpa_autotune     times variants 1, 4 and 5 on synthetic operands of the given
- *                   shape on `stream` (synchronizes) and records the faster.
+ *                   shape on `stream` (synchronizes) and records the fastest.
  *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only).
  *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */
 int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, void* stream);

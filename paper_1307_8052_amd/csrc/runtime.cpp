@@ -1173,6 +1173,14 @@ int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, cons
         }
         rc = prepare_kset(B, B.ks[i], up, pn, pm, npairs);
         if (rc) return rc;
+        // the optical head divides by eps_m - eps_n (Eq. n_q0): no degenerate transition
+        bool optical = false;
+        for (int j = 0; j < nq; ++j) optical = optical || qs[j].optical;
+        const KSet& K = B.ks[i];
+        for (size_t p = 0; optical && p < K.pn.size(); ++p)
+            if (K.k->eps[K.pn[p]] == K.kq->eps[K.pm[p]])
+                return fail(RPA_ERR_INPUT, "optical limit with a degenerate transition (n = " + std::to_string(K.pn[p]) +
+                                               ", m = " + std::to_string(K.pm[p]) + ": eps_m == eps_n)");
     }
     B.qj.resize(nq);
     for (int j = 0; j < nq; ++j) {

@@ -147,6 +147,33 @@ def test_not_positive_definite_is_reported(rpa):
     assert ei.value.status == -5 and "frequency index 2" in str(ei.value)
 
 
+def test_no_transitions_give_zero(rpa):
+    """All states fully occupied: no pair has f_n - f_m > 0, chi0 vanishes and E_c is exactly 0."""
+    wl = synth.tiny(grid=(8, 8, 8), n_occ=4, n_unocc=3)
+    s = wl.kpoints[0]
+    s.f = np.full_like(s.f, 2.0)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        for prec in ("fp64", "split_bf16"):
+            chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
+            ec, F = ctx.ec(ks, kqs, qs, fr, prec)
+            ctx.check()
+            assert not np.any(chi)
+            assert float(ec.cpu()[0]) == 0.0 and not np.any(F.cpu().numpy())
+
+
+def test_degenerate_optical_transition_is_rejected(rpa):
+    wl = synth.tiny(grid=(10, 10, 10), n_occ=2, n_unocc=4, optical=True, target_ng=12)
+    s = wl.kpoints[0]
+    s.eps = s.eps.copy()
+    s.eps[2] = s.eps[1]    # an occupied and an empty state at the same energy
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        with pytest.raises(rpa.RpaError) as ei:
+            ctx.ec(ks, kqs, qs, fr)
+    assert ei.value.status == -1 and "degenerate" in str(ei.value)
+
+
 def test_alias_and_shape_errors_before_launch(rpa):
     wl = synth.config0(n_occ=1, n_unocc=3)
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
