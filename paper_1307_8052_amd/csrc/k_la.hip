@@ -190,40 +190,36 @@ __global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
             accI[x][y] = v4d{0, 0, 0, 0};
         }
     constexpr int kPer = kHerkBK * kTile / 256;
-    double pr[kPer], pi[kPer], qr[kPer], qi[kPer];
+    // fetch only issues loads (rows past K are clamped to a valid one and masked in stash), so the loads
+    // of the next stage stay in flight while the MFMAs of this one run
+    double pr[kPer], pi[kPer], qr[kPer], qi[kPer], pw[kPer];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int e = threadIdx.x + 256 * i;
-            const int kk = e >> 6, c = e & 63, k = k0 + kk;
-            double ar = 0, ai = 0, br = 0, bi = 0;
-            if (k < h.K) {
-                const size_t row = (size_t)k * h.ldA;
-                const double wk = w ? w[k] : h.alpha;
-                ar = Are[row + ci + c] * wk;
-                ai = Aim[row + ci + c] * wk;
-                br = Are[row + cj + c];
-                bi = Aim[row + cj + c];
-            }
-            pr[i] = ar;
-            pi[i] = ai;
-            qr[i] = br;
-            qi[i] = bi;
+            const int kk = e >> 6, c = e & 63, k = min(k0 + kk, h.K - 1);
+            const size_t row = (size_t)k * h.ldA;
+            pw[i] = w ? w[k] : h.alpha;
+            pr[i] = Are[row + ci + c];
+            pi[i] = Aim[row + ci + c];
+            qr[i] = Are[row + cj + c];
+            qi[i] = Aim[row + cj + c];
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, int k0) {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int e = threadIdx.x + 256 * i;
             const int kk = e >> 6, c = e & 63;
-            sAr[buf][kk][c] = pr[i];
-            sAi[buf][kk][c] = pi[i];
-            sBr[buf][kk][c] = qr[i];
-            sBi[buf][kk][c] = qi[i];
+            const bool ok = k0 + kk < h.K;
+            sAr[buf][kk][c] = ok ? pr[i] * pw[i] : 0.0;
+            sAi[buf][kk][c] = ok ? pi[i] * pw[i] : 0.0;
+            sBr[buf][kk][c] = ok ? qr[i] : 0.0;
+            sBi[buf][kk][c] = ok ? qi[i] : 0.0;
         }
     };
     fetch(0);
-    stash(0);
+    stash(0, 0);
     int cur = 0;
     for (int k0 = 0; k0 < h.K; k0 += kHerkBK) {
         __syncthreads();
@@ -251,22 +247,34 @@ __global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
                     accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[x], b_i[y], accI[x][y], 0, 0, 0);
                 }
         }
-        if (more) stash(cur ^ 1);
+        if (more) stash(cur ^ 1, k0 + kHerkBK);
         cur ^= 1;
     }
-    double* Cre = h.Cre + (size_t)b * h.sC;
-    double* Cim = h.Cim + (size_t)b * h.sC;
+    // C += acc: every load of the tile is issued before the first store (the stores could alias the loads
+    // as far as the compiler knows, so interleaving them would serialise 32 round trips to memory)
+    double* Cre = h.Cre + (size_t)b * h.sC + (size_t)(h.r0 + I * kTile + wr + (lane >> 4)) * h.ldC +
+                  h.r0 + J * kTile + wc + (lane & 15);
+    double* Cim = h.Cim + (Cre - h.Cre);
+    double cr[2][2][4], cim[2][2][4];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = h.r0 + I * kTile + wr + x * 16 + (lane >> 4) + 4 * r;
-                const int col = h.r0 + J * kTile + wc + y * 16 + (lane & 15);
-                const size_t o = (size_t)row * h.ldC + col;
-                Cre[o] += accR[x][y][r];
-                Cim[o] += accI[x][y][r];
+                const size_t o = (size_t)(x * 16 + 4 * r) * h.ldC + y * 16;
+                cr[x][y][r] = Cre[o];
+                cim[x][y][r] = Cim[o];
+            }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const size_t o = (size_t)(x * 16 + 4 * r) * h.ldC + y * 16;
+                Cre[o] = cr[x][y][r] + accR[x][y][r];
+                Cim[o] = cim[x][y][r] + accI[x][y][r];
             }
 }
 
@@ -383,93 +391,74 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
                                                     int ldC, long long sC, int j0, double* __restrict__ Lre,
                                                     double* __restrict__ Lim, double* __restrict__ logdet,
                                                     int* __restrict__ fail) {
-    __shared__ double2 a[kTile][kPanelLd];
-    __shared__ double2 v[kTile][kPanelLd];
+    // A (lower triangle, diagonal included) and the strict lower triangle of W share one array:
+    // W[r][j] (j < r) sits at t[j][r + 1], in the upper part that A leaves free. W's diagonal is 1.
+    __shared__ double2 t[kTile][kPanelLd];
     __shared__ double piv[kTile], lgp[kTile];
     const int w = blockIdx.x, tid = threadIdx.x;
     const int j = tid & (kTile - 1), wv = tid >> 6;
     double* cr = Cre + (size_t)w * sC;
     double* ci = Cim + (size_t)w * sC;
-    for (int e = tid; e < kTile * kTile; e += blockDim.x) {
-        const int r = e >> 6, c = e & 63;
-        const bool low = c <= r;
-        a[r][c] = low ? make_double2(cr[(size_t)(j0 + r) * ldC + j0 + c], ci[(size_t)(j0 + r) * ldC + j0 + c])
-                      : make_double2(0.0, 0.0);
-        v[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    for (int e = tid; e < kTile * kPanelLd; e += blockDim.x) {
+        const int r = e / kPanelLd, c = e - r * kPanelLd;
+        t[r][c] = c <= r ? make_double2(cr[(size_t)(j0 + r) * ldC + j0 + c], ci[(size_t)(j0 + r) * ldC + j0 + c])
+                         : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    // factorisation: A[r][j] -= A[r][c] conj(A[j][c]) / (1 + A[c][c]) for c < j <= r. A[c][c] is final
-    // once column c - 1 is done, so the pivots' square roots and logarithms wait until the end.
-    for (int c = 0; c < kTile; ++c) {
-        const double d = a[c][c].x;
-        if (j > c) {
-            const double inv = 1.0 / (1.0 + d);
-            const double2 ajc = a[j][c];
-            const double br = ajc.x * inv, bi = -ajc.y * inv;
-            const int r0 = c + 1 + ((wv - c - 1) & 3);
-            // all loads of the step first, so their latencies overlap
-            double2 arc[kTile / 4], x[kTile / 4];
+    // Factor and inverse advance together, one barrier per column c. Column c of A is final once step
+    // c - 1 is done, and step c reads nothing else of A, so the two updates of step c touch disjoint
+    // entries and can share the interval:
+    //   factor  (lanes j > c):  A[r][j] -= A[r][c] conj(A[j][c]) / (1 + A[c][c]),  j <= r;
+    //   inverse (lanes j <= c): W[r][j] -= A[r][c] W[c][j] / (1 + A[c][c]),        c < r,
+    // with W = I at the start and V = W / s_r at the end. Both read x[r] -= A[r][c] g_j. The pivots' square
+    // roots and logarithms wait until the end.
+    for (int c = 0; c < kTile - 1; ++c) {
+        const double inv = 1.0 / (1.0 + t[c][c].x);
+        const bool fac = j > c;
+        // g_j: conj(A[j][c]) for the factor; W[c][j] (1 on the diagonal) for the inverse
+        double2 g = fac ? t[j][c] : (j == c ? make_double2(1.0, 0.0) : t[j][c + 1]);
+        const double br = g.x * inv, bi = (fac ? -g.y : g.y) * inv;
+        const int rlo = fac ? j : 0;
+        const int r0 = c + 1 + ((wv - c - 1) & 3);
+        // lane j walks A's column j (t[r][j]) or W's column j (t[j][r + 1])
+        double2* xp = fac ? &t[0][j] : &t[j][1];
+        const int xs = fac ? kPanelLd : 1;
+        // all loads of the step first, so their latencies overlap
+        double2 arc[kTile / 4], x[kTile / 4];
 #pragma unroll
-            for (int i = 0; i < kTile / 4; ++i) {
-                const int r = r0 + 4 * i;
-                if (r < kTile && r >= j) {
-                    arc[i] = a[r][c];
-                    x[i] = a[r][j];
-                }
+        for (int i = 0; i < kTile / 4; ++i) {
+            const int r = r0 + 4 * i;
+            if (r < kTile && r >= rlo) {
+                arc[i] = t[r][c];
+                x[i] = xp[r * xs];
             }
+        }
 #pragma unroll
-            for (int i = 0; i < kTile / 4; ++i) {
-                const int r = r0 + 4 * i;
-                if (r < kTile && r >= j) {
-                    x[i].x -= arc[i].x * br - arc[i].y * bi;
-                    x[i].y -= arc[i].x * bi + arc[i].y * br;
-                    a[r][j] = x[i];
-                }
+        for (int i = 0; i < kTile / 4; ++i) {
+            const int r = r0 + 4 * i;
+            if (r < kTile && r >= rlo) {
+                x[i].x -= arc[i].x * br - arc[i].y * bi;
+                x[i].y -= arc[i].x * bi + arc[i].y * br;
+                xp[r * xs] = x[i];
             }
         }
         __syncthreads();
     }
     if (tid < kTile) {
-        const double d = a[tid][tid].x;
+        const double d = t[tid][tid].x;
         piv[tid] = sqrt(1.0 + d);
         lgp[tid] = (1.0 + d > 0.0) ? log1p(d) : __builtin_nan("");
     }
-    // inverse: W[r][j] -= A[r][k] W[k][j] / (1 + A[k][k]) for j <= k < r; V = W / s_r
-    for (int k = 0; k < kTile - 1; ++k) {
-        if (j <= k) {
-            const double inv = 1.0 / (1.0 + a[k][k].x);
-            const double2 wkj = v[k][j];
-            const double br = wkj.x * inv, bi = wkj.y * inv;
-            const int r0 = k + 1 + ((wv - k - 1) & 3);
-            double2 ark[kTile / 4], x[kTile / 4];
-#pragma unroll
-            for (int i = 0; i < kTile / 4; ++i) {
-                const int r = r0 + 4 * i;
-                if (r < kTile) {
-                    ark[i] = a[r][k];
-                    x[i] = v[r][j];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < kTile / 4; ++i) {
-                const int r = r0 + 4 * i;
-                if (r < kTile) {
-                    x[i].x -= ark[i].x * br - ark[i].y * bi;
-                    x[i].y -= ark[i].x * bi + ark[i].y * br;
-                    v[r][j] = x[i];
-                }
-            }
-        }
-        __syncthreads();
-    }
+    __syncthreads();
     double* lr = Lre + (size_t)w * kTile * kTile;
     double* li = Lim + (size_t)w * kTile * kTile;
     for (int e = tid; e < kTile * kTile; e += blockDim.x) {
         const int r = e >> 6, c = e & 63;
         if (c <= r) {
             const double sr = 1.0 / piv[r];
-            lr[e] = v[r][c].x * sr;
-            li[e] = v[r][c].y * sr;
+            const double2 wv2 = c == r ? make_double2(1.0, 0.0) : t[c][r + 1];
+            lr[e] = wv2.x * sr;
+            li[e] = wv2.y * sr;
             // the factor itself replaces the lower triangle of the block
             double xr, xi;
             if (c == r) {
@@ -477,8 +466,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
                 xi = 0.0;
             } else {
                 const double sc = 1.0 / piv[c];
-                xr = a[r][c].x * sc;
-                xi = a[r][c].y * sc;
+                xr = t[r][c].x * sc;
+                xi = t[r][c].y * sc;
             }
             cr[(size_t)(j0 + r) * ldC + j0 + c] = xr;
             ci[(size_t)(j0 + r) * ldC + j0 + c] = xi;
@@ -492,7 +481,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
         double ldacc = 0.0;
         int bad = 0;
         for (int c = 0; c < kTile; ++c) {
-            if (!(1.0 + a[c][c].x > 0.0) && !bad) bad = j0 + c + 1;
+            if (!(1.0 + t[c][c].x > 0.0) && !bad) bad = j0 + c + 1;
             ldacc += lgp[c];
         }
         logdet[w] += ldacc;

@@ -996,10 +996,13 @@ int ensure_lookahead(rpa_ctx* c) {
 //
 // Look-ahead: the trailing update of step j is split into the next block column
 // (a_j, a GEMM) and the rest (b_j). The main stream runs panel, solve and a_j in
-// turn; b_j runs on la_stream once a_j is done, overlapping panel j+1 and its
-// solve (which come first on the main stream and so reach the CUs first). b_j
-// touches only columns right of block column j+1; a_{j+1} waits for b_j, since
-// both update block column j+2; the solved panels alternate between two buffers.
+// turn; b_j runs on la_stream as soon as the solve of step j is done, beside a_j,
+// panel j+1 and its solve. b_j touches only columns right of block column j+1;
+// a_{j+1} waits for b_j, since both update block column j+2, and so the b's run
+// back to back when they are the longer chain. The solved panels alternate between
+// two buffers (the solve of step j+2 comes after a_{j+1}, hence after b_j), and the
+// completion of b_j is marked by one of two events in turn, so that the main
+// stream's wait for b_{j-1} is issued before that event is recorded again.
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     const int nw = B.nw, ld = B.ld;
@@ -1018,7 +1021,7 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     int rc = ensure_lookahead(c);
     if (rc) return rc;
     hipStream_t M = B.s, S = c->la_stream;
-    hipEvent_t evA = c->la_ev[0], evL = c->la_ev[1];
+    hipEvent_t evA = c->la_ev[0];
     ProfScope ps_(c, S_CHOL, M);
     HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, M));
     for (int qi = 0; qi < nq; ++qi) {
@@ -1032,6 +1035,7 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
         }
     }
     bool pending_b = false;   // a trailing update b_j is in flight on S
+    int last_b = 0;           // step of the last b_j
     for (int j0 = 0; j0 < ld; j0 += kTile) {
         const int step = j0 / kTile;
         double* Pre = Pbase + (size_t)(step & 1) * pstride;
@@ -1075,9 +1079,38 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             gm.beta = 0;
             HIP_TRY(launch_gemm_c64(gm, M));
         }
+        // b_j on the side stream: the lower tiles right of the next block column
+        const int r1 = r0 + kTile;
+        const bool prev_b = pending_b;
+        pending_b = false;
+        if (r1 < ld) {
+            HIP_TRY(hipEventRecord(evA, M));
+            HIP_TRY(hipStreamWaitEvent(S, evA, 0));
+            HerkArgs h{};
+            h.Are = Pre;
+            h.Aim = Pim;
+            h.sA = (long long)kTile * ld;
+            h.ldA = ld;
+            h.colA = r1;
+            h.K = kTile;
+            h.w = nullptr;
+            h.sw = 0;
+            h.alpha = -1.0;
+            h.Cre = cr;
+            h.Cim = ci;
+            h.sC = ld2;
+            h.ldC = ld;
+            h.r0 = r1;
+            h.nT = (ld - r1) / kTile;
+            h.nbatch = nb;
+            HIP_TRY(launch_herk_f64(h, S));
+            HIP_TRY(hipEventRecord(c->la_ev[1 + (step & 1)], S));
+            pending_b = true;
+            last_b = step;
+        }
         // a_j: the next block column C[r0:, r0:r0+64] -= P^H P (full 64-wide GEMM; the strict upper part
         // of its diagonal tile is never read), after b_{j-1}, which also updates that column
-        if (pending_b) HIP_TRY(hipStreamWaitEvent(M, evL, 0));
+        if (prev_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + ((step - 1) & 1)], 0));
         GemmArgs ga{};
         ga.M = ld - r0;
         ga.N = kTile;
@@ -1102,35 +1135,8 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
         ga.alpha = -1.0;
         ga.beta = 1;
         HIP_TRY(launch_gemm_c64(ga, M));
-        // b_j on the side stream: the lower tiles right of that column
-        const int r1 = r0 + kTile;
-        pending_b = false;
-        if (r1 < ld) {
-            HIP_TRY(hipEventRecord(evA, M));
-            HIP_TRY(hipStreamWaitEvent(S, evA, 0));
-            HerkArgs h{};
-            h.Are = Pre;
-            h.Aim = Pim;
-            h.sA = (long long)kTile * ld;
-            h.ldA = ld;
-            h.colA = r1;
-            h.K = kTile;
-            h.w = nullptr;
-            h.sw = 0;
-            h.alpha = -1.0;
-            h.Cre = cr;
-            h.Cim = ci;
-            h.sC = ld2;
-            h.ldC = ld;
-            h.r0 = r1;
-            h.nT = (ld - r1) / kTile;
-            h.nbatch = nb;
-            HIP_TRY(launch_herk_f64(h, S));
-            HIP_TRY(hipEventRecord(evL, S));
-            pending_b = true;
-        }
     }
-    if (pending_b) HIP_TRY(hipStreamWaitEvent(M, evL, 0));
+    if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + (last_b & 1)], 0));
     for (int qi = 0; qi < nq; ++qi) {
         QJob& Q = B.qj[qi];
         HIP_TRY(launch_finalize(logdet + qi * nw, trk + qi * nw, failv + qi * nw,
