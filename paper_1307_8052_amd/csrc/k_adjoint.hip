@@ -25,8 +25,14 @@ __device__ __forceinline__ cplx<double> ldc(const double* p, size_t i) { return 
 // v_mfma_f64_16x16x4f64 (D lane l element r holds row l/16 + 4r, column l%16).
 constexpr int kGB = 16;
 
+// The next K-stage is loaded into registers while the current one runs on the MFMA units (the loads carry
+// no arithmetic, so they stay in flight), LDS is double-buffered, and with beta the whole C block of a
+// row of sub-tiles is read before any of it is written.
 __global__ __launch_bounds__(256) void k_gemm_c64(GemmArgs g) {
-    __shared__ double sAr[kGB][kTile], sAi[kGB][kTile], sBr[kGB][kTile], sBi[kGB][kTile];
+    // rows padded by two doubles: operands contiguous along k are staged down a column, 16 rows apart,
+    // and the padding spreads those 16 writes over distinct banks
+    constexpr int kLd = kTile + 2;
+    __shared__ double sAr[2][kGB][kLd], sAi[2][kGB][kLd], sBr[2][kGB][kLd], sBi[2][kGB][kLd];
     const int I = blockIdx.x, J = blockIdx.y, b = blockIdx.z;
     const double* Ar = g.Ar + (size_t)b * g.sA;
     const double* Ai = g.Ai + (size_t)b * g.sA;
@@ -41,43 +47,66 @@ __global__ __launch_bounds__(256) void k_gemm_c64(GemmArgs g) {
             accR[x][y] = v4d{0, 0, 0, 0};
             accI[x][y] = v4d{0, 0, 0, 0};
         }
-    for (int k0 = 0; k0 < g.K; k0 += kGB) {
-        for (int e = tid; e < kGB * kTile; e += 256) {
-            // index order follows the contiguous direction of each operand
+    // element e of a stage: the index order follows the contiguous direction of each operand
+    auto a_at = [&](int e, int& kk, int& c) {
+        if (g.aI == 1) { kk = e >> 6; c = e & 63; } else { c = e >> 4; kk = e & 15; }
+    };
+    auto b_at = [&](int e, int& kk, int& c) {
+        if (g.bJ == 1) { kk = e >> 6; c = e & 63; } else { c = e >> 4; kk = e & 15; }
+    };
+    constexpr int kPer = kGB * kTile / 256;
+    double pr[kPer], pi[kPer], qr[kPer], qi[kPer];
+    // indices past M, N or K are clamped to valid elements here and masked in stash
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
             int kk, c;
-            if (g.aI == 1) { kk = e >> 6; c = e & 63; } else { c = e >> 4; kk = e & 15; }
-            const int i = I * kTile + c, k = k0 + kk;
-            double xr = 0, xi = 0;
-            if (i < g.M && k < g.K) {
-                const size_t o = (size_t)i * g.aI + (size_t)k * g.aK;
-                xr = Ar[o];
-                xi = sa * Ai[o];
-            }
-            sAr[kk][c] = xr;
-            sAi[kk][c] = xi;
-            if (g.bJ == 1) { kk = e >> 6; c = e & 63; } else { c = e >> 4; kk = e & 15; }
-            const int j = J * kTile + c, k2 = k0 + kk;
-            double yr = 0, yi = 0;
-            if (j < g.N && k2 < g.K) {
-                const size_t o = (size_t)k2 * g.bK + (size_t)j * g.bJ;
-                yr = Br[o];
-                yi = sb * Bi[o];
-            }
-            sBr[kk][c] = yr;
-            sBi[kk][c] = yi;
+            a_at(e, kk, c);
+            size_t o = (size_t)min(I * kTile + c, g.M - 1) * g.aI + (size_t)min(k0 + kk, g.K - 1) * g.aK;
+            pr[u] = Ar[o];
+            pi[u] = Ai[o];
+            b_at(e, kk, c);
+            o = (size_t)min(k0 + kk, g.K - 1) * g.bK + (size_t)min(J * kTile + c, g.N - 1) * g.bJ;
+            qr[u] = Br[o];
+            qi[u] = Bi[o];
         }
+    };
+    auto stash = [&](int buf, int k0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            int kk, c;
+            a_at(e, kk, c);
+            bool ok = I * kTile + c < g.M && k0 + kk < g.K;
+            sAr[buf][kk][c] = ok ? pr[u] : 0.0;
+            sAi[buf][kk][c] = ok ? sa * pi[u] : 0.0;
+            b_at(e, kk, c);
+            ok = J * kTile + c < g.N && k0 + kk < g.K;
+            sBr[buf][kk][c] = ok ? qr[u] : 0.0;
+            sBi[buf][kk][c] = ok ? sb * qi[u] : 0.0;
+        }
+    };
+    if (g.K > 0) {
+        fetch(0);
+        stash(0, 0);
+    }
+    int cur = 0;
+    for (int k0 = 0; k0 < g.K; k0 += kGB) {
         __syncthreads();
+        const bool more = k0 + kGB < g.K;
+        if (more) fetch(k0 + kGB);
 #pragma unroll
         for (int kk = 0; kk < kGB; kk += 4) {
             const int kr = kk + (lane >> 4), cc = lane & 15;
             double a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                a_r[x] = sAr[kr][wr + x * 16 + cc];
-                a_i[x] = sAi[kr][wr + x * 16 + cc];
+                a_r[x] = sAr[cur][kr][wr + x * 16 + cc];
+                a_i[x] = sAi[cur][kr][wr + x * 16 + cc];
                 a_n[x] = -a_i[x];
-                b_r[x] = sBr[kr][wc + x * 16 + cc];
-                b_i[x] = sBi[kr][wc + x * 16 + cc];
+                b_r[x] = sBr[cur][kr][wc + x * 16 + cc];
+                b_i[x] = sBi[cur][kr][wc + x * 16 + cc];
             }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -90,12 +119,26 @@ __global__ __launch_bounds__(256) void k_gemm_c64(GemmArgs g) {
                     accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_r[y], accI[x][y], 0, 0, 0);
                 }
         }
-        __syncthreads();
+        if (more) stash(cur ^ 1, k0 + kGB);
+        cur ^= 1;
     }
     double* Cr = g.Cr + (size_t)b * g.sC;
     double* Ci = g.Ci + (size_t)b * g.sC;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x) {
+        double cr[2][4], ci[2][4];
+        if (g.beta) {
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = I * kTile + wr + x * 16 + (lane >> 4) + 4 * r;
+                    const int j = J * kTile + wc + y * 16 + (lane & 15);
+                    const size_t o = (i < g.M && j < g.N) ? (size_t)i * g.ldC + j : 0;
+                    cr[y][r] = Cr[o];
+                    ci[y][r] = Ci[o];
+                }
+        }
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -106,14 +149,15 @@ __global__ __launch_bounds__(256) void k_gemm_c64(GemmArgs g) {
                     const size_t o = (size_t)i * g.ldC + j;
                     const double vr = g.alpha * accR[x][y][r], vi = g.alpha * accI[x][y][r];
                     if (g.beta) {
-                        Cr[o] += vr;
-                        Ci[o] += vi;
+                        Cr[o] = cr[y][r] + vr;
+                        Ci[o] = ci[y][r] + vi;
                     } else {
                         Cr[o] = vr;
                         Ci[o] = vi;
                     }
                 }
             }
+    }
 }
 
 // identity in rows [0, n) of a [nb][ld][ld] planar batch (zero elsewhere)

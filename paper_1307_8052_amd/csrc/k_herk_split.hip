@@ -171,8 +171,11 @@ __global__ __launch_bounds__(256) void k_herk_split(HerkSplitArgs h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
+    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
+    // could alias them as far as the compiler knows)
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x) {
+        double cre[2][4], cim[2][4];
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -180,9 +183,20 @@ __global__ __launch_bounds__(256) void k_herk_split(HerkSplitArgs h) {
                 const int row = ci + wr + x * 16 + 4 * (lane >> 4) + r;
                 const int col = cj + wc + y * 16 + (lane & 15);
                 const size_t o = (size_t)row * h.ldC + col;
-                Cre[o] += totR[x][y][r] * inv;
-                Cim[o] += totI[x][y][r] * inv;
+                cre[y][r] = Cre[o];
+                cim[y][r] = Cim[o];
             }
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + x * 16 + 4 * (lane >> 4) + r;
+                const int col = cj + wc + y * 16 + (lane & 15);
+                const size_t o = (size_t)row * h.ldC + col;
+                Cre[o] = cre[y][r] + totR[x][y][r] * inv;
+                Cim[o] = cim[y][r] + totI[x][y][r] * inv;
+            }
+    }
 }
 
 // Power-of-two operand scales for the FP16 split: scales[w] for X_w = rho a(w)

@@ -244,8 +244,21 @@ __global__ __launch_bounds__(256, 1) void k_herk_split2(HerkSplit2Args h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
+    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
+    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 4; ++x) {
+        double cre[4][4], cim[4][4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
+                cre[y][r] = Cre[o];
+                cim[y][r] = Cim[o];
+            }
 #pragma unroll
         for (int y = 0; y < 4; ++y)
 #pragma unroll
@@ -254,10 +267,11 @@ __global__ __launch_bounds__(256, 1) void k_herk_split2(HerkSplit2Args h) {
                 const int col = cj + wc + 16 * y + (lane & 15);
                 if (row < h.ldC && col < h.ldC) {
                     const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] += (double)accR[x][y][r] * inv;
-                    Cim[o] += (double)accI[x][y][r] * inv;
+                    Cre[o] = cre[y][r] + (double)accR[x][y][r] * inv;
+                    Cim[o] = cim[y][r] + (double)accI[x][y][r] * inv;
                 }
             }
+    }
 }
 
 // Variant 3: the same operands and products as k_herk_split2, software
@@ -406,8 +420,21 @@ __global__ __launch_bounds__(256, 1) void k_herk_split3(HerkSplit2Args h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
+    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
+    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 4; ++x) {
+        double cre[4][4], cim[4][4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
+                cre[y][r] = Cre[o];
+                cim[y][r] = Cim[o];
+            }
 #pragma unroll
         for (int y = 0; y < 4; ++y)
 #pragma unroll
@@ -416,10 +443,11 @@ __global__ __launch_bounds__(256, 1) void k_herk_split3(HerkSplit2Args h) {
                 const int col = cj + wc + 16 * y + (lane & 15);
                 if (row < h.ldC && col < h.ldC) {
                     const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] += (double)accR[x][y][r] * inv;
-                    Cim[o] += (double)accI[x][y][r] * inv;
+                    Cre[o] = cre[y][r] + (double)accR[x][y][r] * inv;
+                    Cim[o] = cim[y][r] + (double)accI[x][y][r] * inv;
                 }
             }
+    }
 }
 
 // Variant 4: the pipeline of variant 3 with FP64 accumulation. A workgroup
@@ -593,8 +621,21 @@ __global__ __launch_bounds__(256, 1) void k_herk_split4(HerkSplit2Args h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
+    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
+    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 4; ++x) {
+        double cre[2][4], cim[2][4];
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
+                cre[y][r] = Cre[o];
+                cim[y][r] = Cim[o];
+            }
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -603,10 +644,11 @@ __global__ __launch_bounds__(256, 1) void k_herk_split4(HerkSplit2Args h) {
                 const int col = cj + wc + 16 * y + (lane & 15);
                 if (row < h.ldC && col < h.ldC) {
                     const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] += dR[x][y][r] * inv;
-                    Cim[o] += dI[x][y][r] * inv;
+                    Cre[o] = cre[y][r] + dR[x][y][r] * inv;
+                    Cim[o] = cim[y][r] + dI[x][y][r] * inv;
                 }
             }
+    }
 }
 
 // Variant 5: the tiles, operands and FP64 accumulation of variant 4 with eight
@@ -766,8 +808,21 @@ __global__ __launch_bounds__(512, 1) void k_herk_split5(HerkSplit2Args h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
+    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
+    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x) {
+        double cre[2][4], cim[2][4];
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                const int col = cj + wc + 16 * y + (lane & 15);
+                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
+                cre[y][r] = Cre[o];
+                cim[y][r] = Cim[o];
+            }
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -776,10 +831,11 @@ __global__ __launch_bounds__(512, 1) void k_herk_split5(HerkSplit2Args h) {
                 const int col = cj + wc + 16 * y + (lane & 15);
                 if (row < h.ldC && col < h.ldC) {
                     const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] += dR[x][y][r] * inv;
-                    Cim[o] += dI[x][y][r] * inv;
+                    Cre[o] = cre[y][r] + dR[x][y][r] * inv;
+                    Cim[o] = cim[y][r] + dI[x][y][r] * inv;
                 }
             }
+    }
 }
 
 }  // namespace
