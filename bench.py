@@ -94,7 +94,7 @@ def measured_traffic(kernel, src):
     return float(fields["bytes_per_launch"])
 
 
-def cpu_baseline(wl, iq=1, n_sample_occ=4):
+def cpu_baseline(wl, iq=1, n_sample_occ=8):
     """The FP64 oracle on a bounded sample of the same workload: the chi0 build of
     q-point iq (orbitals, pair densities, PAW, weights, grouped update) for the
     pairs of the first n_sample_occ occupied states with every unoccupied state."""
@@ -125,7 +125,7 @@ def cpu_baseline(wl, iq=1, n_sample_occ=4):
     return {"value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": int(max(ncpu, blas)),
             "kind": "oracle",
             "sample": f"chi0 build of q-point {iq} (NG={len(gm)}) for {P} pairs (first {n_sample_occ} occupied "
-                      f"state x all unoccupied), orbitals included; {t1 - t0:.1f} s",
+                      f"states x all unoccupied), orbitals included; {t1 - t0:.1f} s",
             "seconds": t1 - t0, "chi0_norm": float(np.abs(chi).max())}
 
 
@@ -143,7 +143,7 @@ def main():
                     help="force the split rank-k kernel variant (1, 2, 3); 0 keeps the library's choice")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-q loop and adjoint timings")
-    ap.add_argument("--cpu-sample-occ", type=int, default=4,
+    ap.add_argument("--cpu-sample-occ", type=int, default=8,
                     help="occupied states in the oracle's sample (all unoccupied states paired with each)")
     args = ap.parse_args()
 
