@@ -243,8 +243,10 @@ int rpa_check(rpa_ctx* ctx, void* stream);
  * calls that follow (0 stops). rpa_profile_get() synchronizes on the recorded
  * events and returns the summed elapsed milliseconds and the number of timed
  * groups of one stage: "orbitals", "pair_xy", "pair_z_gather", "paw",
- * "optical", "weights", "herk" (the rank-k update of chi0, one launch per pair
- * chunk and frequency set) or "cholesky" (the whole E_c stage).
+ * "optical", "weights", "split_pack" (the split precisions' hi/lo packing and
+ * FP16 scales ahead of each rank-k update), "herk" (the rank-k update kernel of
+ * chi0 alone, one launch per pair chunk and frequency set) or "cholesky" (the
+ * whole E_c stage).
  * RPA_ERR_INPUT for an unknown stage name. */
 int rpa_profile(rpa_ctx* ctx, int enable);
 int rpa_profile_get(rpa_ctx* ctx, const char* stage, double* ms, long long* launches);

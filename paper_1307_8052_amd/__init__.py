@@ -336,7 +336,7 @@ class Context:
                self._h)
         return ec, F
 
-    STAGES = ("orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights", "herk", "cholesky")
+    STAGES = ("orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights", "split_pack", "herk", "cholesky")
 
     def profile(self, enable: bool = True):
         """Start (or stop) per-stage HIP-event timing; totals are cleared."""

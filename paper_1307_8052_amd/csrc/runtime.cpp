@@ -92,9 +92,9 @@ struct rpa_ctx {
 namespace {
 
 // ---------------------------------------------------------------- profiler
-enum Stage { S_ORB = 0, S_PAIR_XY, S_PAIR_Z, S_PAW, S_OPTICAL, S_WEIGHTS, S_HERK, S_CHOL, S_OTHER, S_COUNT };
+enum Stage { S_ORB = 0, S_PAIR_XY, S_PAIR_Z, S_PAW, S_OPTICAL, S_WEIGHTS, S_PACK, S_HERK, S_CHOL, S_OTHER, S_COUNT };
 const char* kStageNames[S_COUNT] = {"orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights",
-                                    "herk", "cholesky", "other"};
+                                    "split_pack", "herk", "cholesky", "other"};
 
 hipEvent_t prof_event(rpa_ctx* c) {
     if (!c->pool.empty()) {
@@ -847,8 +847,8 @@ template <typename T>
 int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const double* aw, int lda) {
     rpa_ctx* c = B.c;
     const int NGp = Q.qp.NGp;
-    ProfScope ps_(c, S_HERK, B.s);
     if constexpr (sizeof(T) == 8) {
+        ProfScope ps_(c, S_HERK, B.s);
         HerkArgs h{};
         h.Are = reinterpret_cast<const double*>(rre);
         h.Aim = reinterpret_cast<const double*>(rim);
@@ -870,20 +870,30 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
     } else {
         const bool fp16 = B.prec == RPA_SPLIT_FP16;
         float* scales = nullptr;
-        if (fp16) {
-            scales = static_cast<float*>(buf(B, "split_scales"));
-            HIP_TRY(launch_split_scales(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim),
-                                        (size_t)np * NGp, aw, lda, np, B.nw, scales, scales + B.nw + 1, B.s));
+        // operands of the pipelined kernels: the FP32 pair densities in K-steps of 32 pairs and the
+        // pre-split 16-bit hi/lo of each
+        const int NGq = (NGp + 127) / 128 * 128;
+        const size_t blk = (size_t)((np + 31) / 32) * NGq * 32;
+        float* Xre = nullptr;
+        float* Xim = nullptr;
+        unsigned short* Bp[4] = {nullptr, nullptr, nullptr, nullptr};
+        {
+            ProfScope pp_(c, S_PACK, B.s);
+            if (fp16) {
+                scales = static_cast<float*>(buf(B, "split_scales"));
+                HIP_TRY(launch_split_scales(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim),
+                                            (size_t)np * NGp, aw, lda, np, B.nw, scales, scales + B.nw + 1, B.s));
+            }
+            if (Q.variant >= 2) {
+                Xre = static_cast<float*>(buf(B, "split_pack"));
+                Xim = Xre + blk;
+                for (int q = 0; q < 4; ++q) Bp[q] = reinterpret_cast<unsigned short*>(Xim + blk) + q * blk;
+                HIP_TRY(launch_pack_split(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim),
+                                          np, NGp, NGq, scales, B.nw, fp16, Xre, Xim, Bp, B.s));
+            }
         }
+        ProfScope ps_(c, S_HERK, B.s);
         if (Q.variant >= 2) {
-            const int NGq = (NGp + 127) / 128 * 128;
-            const size_t blk = (size_t)((np + 31) / 32) * NGq * 32;
-            float* Xre = static_cast<float*>(buf(B, "split_pack"));
-            float* Xim = Xre + blk;
-            unsigned short* Bp[4];
-            for (int q = 0; q < 4; ++q) Bp[q] = reinterpret_cast<unsigned short*>(Xim + blk) + q * blk;
-            HIP_TRY(launch_pack_split(reinterpret_cast<const float*>(rre), reinterpret_cast<const float*>(rim), np,
-                                      NGp, NGq, scales, B.nw, fp16, Xre, Xim, Bp, B.s));
             HerkSplit2Args h{};
             h.Xre = Xre;
             h.Xim = Xim;

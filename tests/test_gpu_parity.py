@@ -8,6 +8,8 @@ of the 48^3 configuration. Tolerances:
   split path  - pair densities (FP32 FFT) within 2e-6 relative, chi0 within
                 2e-4 of the largest element, E_c within 1e-6 Ha.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -145,6 +147,38 @@ def test_not_positive_definite_is_reported(rpa):
         with pytest.raises(rpa.RpaError) as ei:
             ctx.check()
     assert ei.value.status == -5 and "frequency index 2" in str(ei.value)
+
+
+def test_stage_profiler(rpa):
+    """The stage profiler the benchmark reads: every stage name is accepted, an unknown one is an input error;
+    one batched split-precision call over two q-points times two packing groups and two rank-k launches (one
+    chunk per q), each with positive elapsed time, and one Cholesky stage; nothing is recorded after
+    profiling stops."""
+    wl = synth.config1(n_occ=2, n_unocc=20, which_q=(0, 1))
+    qspecs = []
+    for iq in range(2):
+        ks, _, qs, fr, _ = gpu_inputs(rpa, wl, iq)
+        qspecs.append(qs)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")   # plans and workspaces outside the timed call
+        ctx.profile(True)
+        ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
+        prof = ctx.profile_get()
+        ctx.profile(False)
+        ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
+        after = ctx.profile_get()
+        with pytest.raises(rpa.RpaError):
+            ms = ctypes.c_double(0)
+            n = ctypes.c_longlong(0)
+            rpa._check(ctx._L.rpa_profile_get(ctx._h, b"no_such_stage", ctypes.byref(ms), ctypes.byref(n)), ctx._h)
+    print({k: (round(v[0], 3), v[1]) for k, v in prof.items()}, flush=True)
+    assert set(prof) == set(rpa.Context.STAGES)
+    assert prof["herk"][1] == 2 and prof["herk"][0] > 0
+    assert prof["split_pack"][1] == 2 and prof["split_pack"][0] > 0
+    assert prof["cholesky"][1] == 1 and prof["cholesky"][0] > 0
+    assert prof["pair_xy"][1] >= 2
+    assert all(v[0] >= 0 for v in prof.values())
+    assert all(v[1] == 0 for v in after.values())
 
 
 def test_no_transitions_give_zero(rpa):
