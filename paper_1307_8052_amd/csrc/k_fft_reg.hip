@@ -222,7 +222,11 @@ __global__ __launch_bounds__(64) void k_fft_xy_reg(cplx<T>* __restrict__ data) {
     for (int f = threadIdx.x; f < N * N; f += blockDim.x) base[f] = X[f / N][f % N];
 }
 
-constexpr size_t kRegLdsBudget = 80 * 1024;
+// LDS of one pair-transform slab: two FP32 planes of 48^2 (one FP64 plane). Small slabs leave room for
+// four workgroups per CU, each running its loads, x pass and y pass on its own, which overlaps the phases
+// better than fewer, larger slabs (measured at 48^3: 3.43 ms per launch for 2 planes, 3.57 for 4, 4.44
+// for 3)
+constexpr size_t kRegLdsBudget = 40 * 1024;
 
 bool reg_size(int n) {
     switch (n) {
