@@ -36,6 +36,30 @@ constexpr int xy_threads() {
     return (sizeof(T) == 8 && N >= 32) || N >= 64 ? 256 : 512;
 }
 
+// LDS of one pair-transform slab: two FP32 planes of 48^2 (one FP64 plane). Small slabs leave room for
+// four workgroups per CU, each running its loads, x pass and y pass on its own, which overlaps the phases
+// better than fewer, larger slabs (measured at 48^3: 3.43 ms per launch for 2 planes, 3.57 for 4, 4.44
+// for 3)
+constexpr size_t kRegLdsBudget = 40 * 1024;
+
+// planes per slab and threads per workgroup of the pair kernel, known at compile time (the launcher computes
+// the same from the geometry), and the load batch: each thread issues the loads of all its elements of the
+// slab (at most 48 FP32 or 16 FP64 pairs of loads) before the first is used
+template <typename T, int N1, int N2>
+constexpr int xy_planes() {
+    const int s = (int)(kRegLdsBudget / ((size_t)N2 * (N1 + 1) * sizeof(cplx<T>)));
+    const int t = xy_threads<T, N1>() / N2;
+    return s < t ? (s < 1 ? 1 : s) : t;
+}
+template <typename T, int N1, int N2>
+constexpr int xy_batch() {
+    const int rows = xy_planes<T, N1, N2>() * N2;
+    const int thr = (rows + 63) / 64 * 64 < xy_threads<T, N1>() ? (rows + 63) / 64 * 64 : xy_threads<T, N1>();
+    const int u = (xy_planes<T, N1, N2>() * N1 * N2 + thr - 1) / thr;
+    const int cap = sizeof(T) == 4 ? 48 : 16;
+    return u < cap ? u : cap;
+}
+
 template <typename T, int N1, int N2>
 __global__ __launch_bounds__((xy_threads<T, N1>())) void k_pair_xy_reg(const cplx<T>* __restrict__ phik,
                                                      const cplx<T>* __restrict__ phikq,
@@ -63,7 +87,7 @@ __global__ __launch_bounds__((xy_threads<T, N1>())) void k_pair_xy_reg(const cpl
     // conj(phi_n) phi_m on the slab, row (zs, y) at X[(zs N2 + y) LD]; the loads of U elements are
     // issued before any is used
     const int tot = ns * plane;
-    constexpr int U = sizeof(T) == 4 ? 16 : 8;
+    constexpr int U = xy_batch<T, N1, N2>();
     for (int f0 = threadIdx.x; f0 < tot; f0 += U * blockDim.x) {
         cplx<T> va[U], vb[U];
 #pragma unroll
@@ -222,11 +246,6 @@ __global__ __launch_bounds__(64) void k_fft_xy_reg(cplx<T>* __restrict__ data) {
     for (int f = threadIdx.x; f < N * N; f += blockDim.x) base[f] = X[f / N][f % N];
 }
 
-// LDS of one pair-transform slab: two FP32 planes of 48^2 (one FP64 plane). Small slabs leave room for
-// four workgroups per CU, each running its loads, x pass and y pass on its own, which overlaps the phases
-// better than fewer, larger slabs (measured at 48^3: 3.43 ms per launch for 2 planes, 3.57 for 4, 4.44
-// for 3)
-constexpr size_t kRegLdsBudget = 40 * 1024;
 
 bool reg_size(int n) {
     switch (n) {
