@@ -36,18 +36,21 @@ constexpr int xy_threads() {
     return (sizeof(T) == 8 && N >= 32) || N >= 64 ? 256 : 512;
 }
 
-// LDS of one pair-transform slab: two FP32 planes of 48^2 (one FP64 plane). Small slabs leave room for
-// four workgroups per CU, each running its loads, x pass and y pass on its own, which overlaps the phases
-// better than fewer, larger slabs (measured at 48^3: 3.43 ms per launch for 2 planes, 3.57 for 4, 4.44
-// for 3)
-constexpr size_t kRegLdsBudget = 40 * 1024;
+// LDS of one pair-transform slab: one plane of 48^2, FP32 or FP64. Small slabs leave room for several
+// workgroups per CU, each running its loads, x pass and y pass on its own, which overlaps the phases
+// better than fewer, larger slabs (measured on the FP32 48^3 grid: 3.0 ms per launch for 1 plane,
+// 3.04 for 2, 3.57 for 4 (before the load batch below covered a whole slab: 3.43 for 2), 4.44 for 3)
+template <typename T>
+constexpr size_t reg_lds_budget() {
+    return sizeof(T) == 4 ? 20 * 1024 : 40 * 1024;
+}
 
 // planes per slab and threads per workgroup of the pair kernel, known at compile time (the launcher computes
 // the same from the geometry), and the load batch: each thread issues the loads of all its elements of the
 // slab (at most 48 FP32 or 16 FP64 pairs of loads) before the first is used
 template <typename T, int N1, int N2>
 constexpr int xy_planes() {
-    const int s = (int)(kRegLdsBudget / ((size_t)N2 * (N1 + 1) * sizeof(cplx<T>)));
+    const int s = (int)(reg_lds_budget<T>() / ((size_t)N2 * (N1 + 1) * sizeof(cplx<T>)));
     const int t = xy_threads<T, N1>() / N2;
     return s < t ? (s < 1 ? 1 : s) : t;
 }
@@ -272,7 +275,7 @@ int xy_threads_rt(int N) {
 template <typename T>
 int xy_slab(const PairGeom& g) {
     const size_t per_plane = (size_t)g.N2 * (g.N1 + 1) * sizeof(cplx<T>);
-    int S = (int)(kRegLdsBudget / per_plane);
+    int S = (int)(reg_lds_budget<T>() / per_plane);
     S = std::min(S, std::max(1, xy_threads_rt<T>(g.N1) / g.N2));
     S = std::min(S, g.N3);
     return S;
