@@ -48,6 +48,56 @@ constexpr size_t reg_lds_budget() {
 // planes per slab and threads per workgroup of the pair kernel, known at compile time (the launcher computes
 // the same from the geometry), and the load batch: each thread issues the loads of all its elements of the
 // slab (at most 48 FP32 or 16 FP64 pairs of loads) before the first is used
+// Lane exchange inside quads of lanes (DPP quad permutation): 0x4E reads lane r ^ 2, 0xB1 lane r ^ 1.
+template <int CTRL>
+__device__ __forceinline__ float quad_xchg(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_xchg(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cplx<T> quad_xchg(cplx<T> v) {
+    return mk(quad_xchg<CTRL>(v.x), quad_xchg<CTRL>(v.y));
+}
+
+// Forward transform of one column of N (stride LD) by the four lanes of a quad: lane r takes the samples
+// 4 i + r and transforms them (length N/4), multiplies output k by w^(r k) (w = exp(-2 pi i / N)), and a
+// four-point transform across the quad (two lane exchanges) leaves outputs k + (N/4) s in lane r with
+// s = (r >> 1) + 2 (r & 1). A kept column thus costs a quarter of a whole-line transform per lane.
+template <typename T, int N, int LD>
+__device__ __forceinline__ void fft_column_quad(cplx<T>* col, int r) {
+    constexpr int M = N / 4;
+    constexpr Roots<N> W{};
+    cplx<T> v[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) v[i] = col[(4 * i + r) * LD];
+    RegFft<M, -1, T>::run(v);
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+        const int e1 = k % N, e2 = (2 * k) % N, e3 = (3 * k) % N;
+        const T c = r == 1 ? T(W.c[e1]) : r == 2 ? T(W.c[e2]) : T(W.c[e3]);
+        const T sn = r == 1 ? T(-W.s[e1]) : r == 2 ? T(-W.s[e2]) : T(-W.s[e3]);
+        if (r != 0) v[k] = v[k] * mk(c, sn);
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        // r = r0 + 2 r1: sum over r1, twiddle exp(-i pi/2) for r0 = 1 at output bit 1, then sum over r0
+        cplx<T> p = quad_xchg<0x4E>(v[k]);
+        cplx<T> u = (r & 2) ? p - v[k] : v[k] + p;
+        if (r == 3) u = imul<-1>(u);
+        p = quad_xchg<0xB1>(u);
+        v[k] = (r & 1) ? p - u : u + p;
+    }
+    const int s = (r >> 1) + 2 * (r & 1);
+#pragma unroll
+    for (int k = 0; k < M; ++k) col[(k + M * s) * LD] = v[k];
+}
+
 template <typename T, int N1, int N2>
 constexpr int xy_planes() {
     const int s = (int)(reg_lds_budget<T>() / ((size_t)N2 * (N1 + 1) * sizeof(cplx<T>)));
@@ -123,9 +173,22 @@ __global__ __launch_bounds__((xy_threads<T, N1>())) void k_pair_xy_reg(const cpl
     }
     __syncthreads();
 
-    // y: one kept x-frequency column per thread, transformed in place
+    // y: each kept x-frequency column transformed in place by a quad of lanes where the workgroup has
+    // enough of them, else by one thread
     const int K1 = g.K1, K2 = g.K2;
-    if (l < ns * K1) {
+    bool quad = false;
+    if constexpr (N2 % 4 == 0) quad = 4 * ns * K1 <= (int)blockDim.x;
+    if (quad) {
+        if constexpr (N2 % 4 == 0) {
+            if (l < 4 * ns * K1) {
+                const int cq = l >> 2;
+                const int zs = cq / K1, ix = cq - zs * K1;
+                int kx = g.x0 + ix;
+                if (kx >= N1) kx -= N1;
+                fft_column_quad<T, N2, LD>(X + zs * N2 * LD + kx, l & 3);
+            }
+        }
+    } else if (l < ns * K1) {
         const int zs = l / K1, ix = l - zs * K1;
         int kx = g.x0 + ix;
         if (kx >= N1) kx -= N1;
