@@ -159,7 +159,14 @@ __global__ void k_weights(const double* __restrict__ epsk, const double* __restr
 // Fragment layouts (16x16x4 f64): A lane l holds A[l%16][l/16], B lane l holds
 // B[l/16][l%16], D lane l element r holds D[l/16 + 4*r][l%16] (rows interleave
 // across the four lane groups, unlike the 16-bit-input MFMAs).
-constexpr int kHerkBK = 16;
+// K-stage of the FP64 rank-k kernel. Stages of 8 (32 KB of LDS, double-buffered) with registers bounded
+// for three workgroups per CU hide more latency (48 x 1408^2 at K = 256: 57.7 against 51.9 TFLOP/s for
+// stages of 16 at two per CU) and serve the chi0 update. The Cholesky trailing updates (K = 64) keep stages
+// of 16: three such workgroups fill a CU's registers and LDS, and the panel and solve of the next block
+// column, which run beside them, would wait for their tail (the step as a whole is faster this way).
+template <int BK> struct HerkF64Cfg;
+template <> struct HerkF64Cfg<8> { static constexpr int waves_per_simd = 3; };
+template <> struct HerkF64Cfg<16> { static constexpr int waves_per_simd = 2; };
 
 __device__ __forceinline__ void tile_of(int t, int& I, int& J) {
     int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -171,7 +178,8 @@ __device__ __forceinline__ void tile_of(int t, int& I, int& J) {
 
 // The next K-stage is loaded into registers while the current one runs on the
 // MFMA units, and LDS is double-buffered, so one barrier separates the stages.
-__global__ __launch_bounds__(256) void k_herk_f64(HerkArgs h) {
+template <int kHerkBK>
+__global__ __launch_bounds__(256, HerkF64Cfg<kHerkBK>::waves_per_simd) void k_herk_f64(HerkArgs h) {
     __shared__ double sAr[2][kHerkBK][kTile], sAi[2][kHerkBK][kTile], sBr[2][kHerkBK][kTile],
         sBi[2][kHerkBK][kTile];
     int I, J;
@@ -620,7 +628,10 @@ hipError_t launch_weights(const double* epsk, const double* epskq, const double*
 hipError_t launch_herk_f64(const HerkArgs& h, hipStream_t s) {
     if (h.nT <= 0 || h.nbatch <= 0 || h.K <= 0) return hipSuccess;
     const unsigned ntiles = (unsigned)(h.nT * (h.nT + 1) / 2);
-    hipLaunchKernelGGL(k_herk_f64, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
+    if (h.K > kTile)
+        hipLaunchKernelGGL(k_herk_f64<8>, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
+    else
+        hipLaunchKernelGGL(k_herk_f64<16>, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
     return hipGetLastError();
 }
 
