@@ -191,12 +191,22 @@ __global__ __launch_bounds__(256, HerkF64Cfg<kHerkBK>::waves_per_simd) void k_he
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int ci = h.colA + I * kTile, cj = h.colA + J * kTile;
+    // the accumulators start from C itself: its loads are in flight with those of the first stage, and
+    // the epilogue only stores (with a short K, a load of C after the loop would be an exposed round trip)
+    double* Cre = h.Cre + (size_t)b * h.sC + (size_t)(h.r0 + I * kTile + wr + (lane >> 4)) * h.ldC +
+                  h.r0 + J * kTile + wc + (lane & 15);
+    double* Cim = h.Cim + (Cre - h.Cre);
     v4d accR[2][2], accI[2][2];
+#pragma unroll
     for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) {
-            accR[x][y] = v4d{0, 0, 0, 0};
-            accI[x][y] = v4d{0, 0, 0, 0};
-        }
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const size_t o = (size_t)(x * 16 + 4 * r) * h.ldC + y * 16;
+                accR[x][y][r] = Cre[o];
+                accI[x][y][r] = Cim[o];
+            }
     constexpr int kPer = kHerkBK * kTile / 256;
     // fetch only issues loads (rows past K are clamped to a valid one and masked in stash), so the loads
     // of the next stage stay in flight while the MFMAs of this one run
@@ -258,12 +268,6 @@ __global__ __launch_bounds__(256, HerkF64Cfg<kHerkBK>::waves_per_simd) void k_he
         if (more) stash(cur ^ 1, k0 + kHerkBK);
         cur ^= 1;
     }
-    // C += acc: every load of the tile is issued before the first store (the stores could alias the loads
-    // as far as the compiler knows, so interleaving them would serialise 32 round trips to memory)
-    double* Cre = h.Cre + (size_t)b * h.sC + (size_t)(h.r0 + I * kTile + wr + (lane >> 4)) * h.ldC +
-                  h.r0 + J * kTile + wc + (lane & 15);
-    double* Cim = h.Cim + (Cre - h.Cre);
-    double cr[2][2][4], cim[2][2][4];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -271,18 +275,8 @@ __global__ __launch_bounds__(256, HerkF64Cfg<kHerkBK>::waves_per_simd) void k_he
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const size_t o = (size_t)(x * 16 + 4 * r) * h.ldC + y * 16;
-                cr[x][y][r] = Cre[o];
-                cim[x][y][r] = Cim[o];
-            }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const size_t o = (size_t)(x * 16 + 4 * r) * h.ldC + y * 16;
-                Cre[o] = cr[x][y][r] + accR[x][y][r];
-                Cim[o] = cim[x][y][r] + accI[x][y][r];
+                Cre[o] = accR[x][y][r];
+                Cim[o] = accI[x][y][r];
             }
 }
 

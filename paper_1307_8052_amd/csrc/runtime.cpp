@@ -83,10 +83,13 @@ struct rpa_ctx {
     bool pair_reg = true;   // register-resident pair transforms where supported
     // non-blocking stream the batch sequence is captured on (the legacy default stream cannot be)
     hipStream_t cap_stream = nullptr;
-    // look-ahead of the blocked Cholesky: the next panel runs on la_stream while the
-    // main stream finishes the trailing update (default priority, non-blocking)
+    // look-ahead of the blocked Cholesky: the trailing update of each step runs on
+    // la_stream and the rows below the next diagonal block on la2_stream, beside the
+    // main stream's panel and solve (default priority, non-blocking)
     hipStream_t la_stream = nullptr;
+    hipStream_t la2_stream = nullptr;
     hipEvent_t la_ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t la2_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -993,7 +996,10 @@ int enqueue_chi0(Batch& B) {
 // side stream and events of the Cholesky look-ahead (created outside any graph capture)
 int ensure_lookahead(rpa_ctx* c) {
     if (!c->la_stream) HIP_TRY(hipStreamCreateWithFlags(&c->la_stream, hipStreamNonBlocking));
+    if (!c->la2_stream) HIP_TRY(hipStreamCreateWithFlags(&c->la2_stream, hipStreamNonBlocking));
     for (auto& e : c->la_ev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : c->la2_ev)
         if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return RPA_OK;
 }
@@ -1013,6 +1019,10 @@ int ensure_lookahead(rpa_ctx* c) {
 // two buffers (the solve of step j+2 comes after a_{j+1}, hence after b_j), and the
 // completion of b_j is marked by one of two events in turn, so that the main
 // stream's wait for b_{j-1} is issued before that event is recorded again.
+// a_j itself is split once more: panel j+1 reads only its diagonal tile, so the
+// main stream runs that tile and la2_stream the rows below it, beside panel j+1;
+// solve j+1 waits for them. la2_stream runs these in step order, so the solve of
+// step j+2, which overwrites the panel buffer of step j, comes after them too.
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     const int nw = B.nw, ld = B.ld;
@@ -1030,8 +1040,8 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     const long long ld2 = (long long)ld * ld;
     int rc = ensure_lookahead(c);
     if (rc) return rc;
-    hipStream_t M = B.s, S = c->la_stream;
-    hipEvent_t evA = c->la_ev[0];
+    hipStream_t M = B.s, S = c->la_stream, S2 = c->la2_stream;
+    hipEvent_t evA = c->la_ev[0], evD = c->la2_ev[0], evR = c->la2_ev[1];
     ProfScope ps_(c, S_CHOL, M);
     HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, M));
     for (int qi = 0; qi < nq; ++qi) {
@@ -1046,6 +1056,7 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     }
     bool pending_b = false;   // a trailing update b_j is in flight on S
     int last_b = 0;           // step of the last b_j
+    bool pending_r = false;   // the rows of a_j below its diagonal tile are in flight on S2
     for (int j0 = 0; j0 < ld; j0 += kTile) {
         const int step = j0 / kTile;
         double* Pre = Pbase + (size_t)(step & 1) * pstride;
@@ -1055,10 +1066,14 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             Lre = Lblocks + (size_t)step * 2 * nb * kTile * kTile;
             Lim = Lre + (size_t)nb * kTile * kTile;
         }
-        // panel j: block column j is complete (a_{j-1} before it here, b_{j-2} before a_{j-1})
+        // panel j: the diagonal tile of block column j is complete (a_{j-1} before it here,
+        // b_{j-2} before a_{j-1}); the rows below it are once the main stream has waited for
+        // the rest of a_{j-1}
         HIP_TRY(launch_chol_panel(cr, ci, ld, j0, nb, Lre, Lim, logdet, failv, M));
         const int r0 = j0 + kTile;
         if (r0 >= ld) break;
+        if (pending_r) HIP_TRY(hipStreamWaitEvent(M, evR, 0));
+        pending_r = false;
         if (Lblocks) {
             // the adjoint needs the factor itself: L21 also replaces the block column
             HIP_TRY(launch_chol_trsm(cr, ci, ld, j0, ld, nb, Lre, Lim, Pre, Pim, M));
@@ -1119,10 +1134,12 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             last_b = step;
         }
         // a_j: the next block column C[r0:, r0:r0+64] -= P^H P (full 64-wide GEMM; the strict upper part
-        // of its diagonal tile is never read), after b_{j-1}, which also updates that column
+        // of its diagonal tile is never read), after b_{j-1}, which also updates that column.
+        // Its diagonal tile is all that panel j+1 reads, so only that tile runs here; the rows below
+        // it run on la2_stream beside panel j+1, and the main stream waits for them before solve j+1.
         if (prev_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + ((step - 1) & 1)], 0));
         GemmArgs ga{};
-        ga.M = ld - r0;
+        ga.M = kTile;
         ga.N = kTile;
         ga.K = kTile;
         ga.nbatch = nb;
@@ -1145,7 +1162,20 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
         ga.alpha = -1.0;
         ga.beta = 1;
         HIP_TRY(launch_gemm_c64(ga, M));
+        if (r1 < ld) {
+            HIP_TRY(hipEventRecord(evD, M));
+            HIP_TRY(hipStreamWaitEvent(S2, evD, 0));
+            ga.M = ld - r1;
+            ga.Ar = Pre + r1;
+            ga.Ai = Pim + r1;
+            ga.Cr = cr + (size_t)r1 * ld + r0;
+            ga.Ci = ci + (size_t)r1 * ld + r0;
+            HIP_TRY(launch_gemm_c64(ga, S2));
+            HIP_TRY(hipEventRecord(evR, S2));
+            pending_r = true;
+        }
     }
+    if (pending_r) HIP_TRY(hipStreamWaitEvent(M, evR, 0));
     if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + (last_b & 1)], 0));
     for (int qi = 0; qi < nq; ++qi) {
         QJob& Q = B.qj[qi];
@@ -1595,6 +1625,9 @@ int rpa_destroy(rpa_ctx* c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->la_stream) (void)hipStreamDestroy(c->la_stream);
+    if (c->la2_stream) (void)hipStreamDestroy(c->la2_stream);
+    for (hipEvent_t e : c->la2_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->la_ev)
         if (e) (void)hipEventDestroy(e);
     prof_collect(c);
