@@ -161,9 +161,10 @@ __global__ void k_weights(const double* __restrict__ epsk, const double* __restr
 // across the four lane groups, unlike the 16-bit-input MFMAs).
 // K-stage of the FP64 rank-k kernel. Stages of 8 (32 KB of LDS, double-buffered) with registers bounded
 // for three workgroups per CU hide more latency (48 x 1408^2 at K = 256: 57.7 against 51.9 TFLOP/s for
-// stages of 16 at two per CU) and serve the chi0 update. The Cholesky trailing updates (K = 64) keep stages
-// of 16: three such workgroups fill a CU's registers and LDS, and the panel and solve of the next block
-// column, which run beside them, would wait for their tail (the step as a whole is faster this way).
+// stages of 16 at two per CU) and serve the chi0 update and the long Cholesky trailing updates (K = 64).
+// The short trailing updates of the late Cholesky steps take stages of 16: three stage-8 workgroups fill
+// a CU's registers and LDS, and the panel and solve of the next block column, which then bound the step
+// and run beside them, would wait for their tail.
 template <int BK> struct HerkF64Cfg;
 template <> struct HerkF64Cfg<8> { static constexpr int waves_per_simd = 3; };
 template <> struct HerkF64Cfg<16> { static constexpr int waves_per_simd = 2; };
@@ -385,20 +386,26 @@ __global__ void k_zero_i(int* p, int n) {
 // Both the factorisation and the inversion are right-looking and keep their
 // columns unscaled (the pivot of column c is s_c = sqrt(1 + A_cc), so
 // L_rc L_jc^* = A_rc A_jc^* / (1 + A_cc)); the scaling is applied once when the
-// results are written. Lane j owns column j, wave v walks rows r = v (mod 4):
-// A[r][c] is a broadcast read and A[r][j] a contiguous one, and every thread
-// computes the pivot itself, so each column costs one barrier.
+// results are written. Lane j owns column j and wave v of eight walks the rows
+// r = v (mod 8): A[r][c] is a broadcast read and A[r][j] a contiguous one. Each
+// column costs one barrier: the reciprocal of the next pivot is formed during
+// the step by the lane that updates it, the rows of a wave are counted
+// wave-uniformly, and lanes whose entry of a row is not updated write it to a
+// slot of their own instead of branching.
 constexpr int kPanelLd = kTile + 1;
-__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, double* __restrict__ Cim,
-                                                    int ldC, long long sC, int j0, double* __restrict__ Lre,
-                                                    double* __restrict__ Lim, double* __restrict__ logdet,
-                                                    int* __restrict__ fail) {
+constexpr int kPanelWaves = 8;
+__global__ __launch_bounds__(64 * kPanelWaves) void k_chol_panel(double* __restrict__ Cre, double* __restrict__ Cim,
+                                                                 int ldC, long long sC, int j0,
+                                                                 double* __restrict__ Lre, double* __restrict__ Lim,
+                                                                 double* __restrict__ logdet, int* __restrict__ fail) {
+    constexpr int NW = kPanelWaves;
     // A (lower triangle, diagonal included) and the strict lower triangle of W share one array:
     // W[r][j] (j < r) sits at t[j][r + 1], in the upper part that A leaves free. W's diagonal is 1.
     __shared__ double2 t[kTile][kPanelLd];
-    __shared__ double piv[kTile], lgp[kTile];
+    __shared__ double2 sink[kTile];
+    __shared__ double pinv[kTile], piv[kTile], lgp[kTile];
     const int w = blockIdx.x, tid = threadIdx.x;
-    const int j = tid & (kTile - 1), wv = tid >> 6;
+    const int j = tid & (kTile - 1), wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     double* cr = Cre + (size_t)w * sC;
     double* ci = Cim + (size_t)w * sC;
     for (int e = tid; e < kTile * kPanelLd; e += blockDim.x) {
@@ -406,6 +413,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
         t[r][c] = c <= r ? make_double2(cr[(size_t)(j0 + r) * ldC + j0 + c], ci[(size_t)(j0 + r) * ldC + j0 + c])
                          : make_double2(0.0, 0.0);
     }
+    __syncthreads();
+    if (tid == 0) pinv[0] = 1.0 / (1.0 + t[0][0].x);
     __syncthreads();
     // Factor and inverse advance together, one barrier per column c. Column c of A is final once step
     // c - 1 is done, and step c reads nothing else of A, so the two updates of step c touch disjoint
@@ -415,33 +424,38 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Cre, do
     // with W = I at the start and V = W / s_r at the end. Both read x[r] -= A[r][c] g_j. The pivots' square
     // roots and logarithms wait until the end.
     for (int c = 0; c < kTile - 1; ++c) {
-        const double inv = 1.0 / (1.0 + t[c][c].x);
+        const double inv = pinv[c];
         const bool fac = j > c;
         // g_j: conj(A[j][c]) for the factor; W[c][j] (1 on the diagonal) for the inverse
-        double2 g = fac ? t[j][c] : (j == c ? make_double2(1.0, 0.0) : t[j][c + 1]);
+        const double2 g = fac ? t[j][c] : (j == c ? make_double2(1.0, 0.0) : t[j][c + 1]);
         const double br = g.x * inv, bi = (fac ? -g.y : g.y) * inv;
         const int rlo = fac ? j : 0;
-        const int r0 = c + 1 + ((wv - c - 1) & 3);
+        // this wave's rows above c: the first, r0, and their number (both wave-uniform)
+        const int r0 = c + 1 + ((wv - c - 1) & (NW - 1));
+        const int ns = (kTile - r0 + NW - 1) / NW;
         // lane j walks A's column j (t[r][j]) or W's column j (t[j][r + 1])
-        double2* xp = fac ? &t[0][j] : &t[j][1];
         const int xs = fac ? kPanelLd : 1;
+        const int rb = min(r0, kTile - 1);
+        double2* xq = fac ? &t[rb][j] : &t[j][rb + 1];
+        const double2* aq = &t[rb][c];
         // all loads of the step first, so their latencies overlap
-        double2 arc[kTile / 4], x[kTile / 4];
+        double2 arc[kTile / NW], x[kTile / NW];
 #pragma unroll
-        for (int i = 0; i < kTile / 4; ++i) {
-            const int r = r0 + 4 * i;
-            if (r < kTile && r >= rlo) {
-                arc[i] = t[r][c];
-                x[i] = xp[r * xs];
+        for (int i = 0; i < kTile / NW; ++i) {
+            if (i < ns) {
+                arc[i] = aq[i * NW * kPanelLd];
+                x[i] = xq[i * NW * xs];
             }
         }
 #pragma unroll
-        for (int i = 0; i < kTile / 4; ++i) {
-            const int r = r0 + 4 * i;
-            if (r < kTile && r >= rlo) {
+        for (int i = 0; i < kTile / NW; ++i) {
+            if (i < ns) {
                 x[i].x -= arc[i].x * br - arc[i].y * bi;
                 x[i].y -= arc[i].x * bi + arc[i].y * br;
-                xp[r * xs] = x[i];
+                double2* d = r0 + NW * i >= rlo ? &xq[i * NW * xs] : &sink[j];
+                *d = x[i];
+                // the wave that owns row c + 1: its lane c + 1 now holds the final A[c+1][c+1]
+                if (i == 0 && r0 == c + 1 && j == c + 1) pinv[c + 1] = 1.0 / (1.0 + x[0].x);
             }
         }
         __syncthreads();
@@ -622,7 +636,7 @@ hipError_t launch_weights(const double* epsk, const double* epskq, const double*
 hipError_t launch_herk_f64(const HerkArgs& h, hipStream_t s) {
     if (h.nT <= 0 || h.nbatch <= 0 || h.K <= 0) return hipSuccess;
     const unsigned ntiles = (unsigned)(h.nT * (h.nT + 1) / 2);
-    if (h.K > kTile)
+    if (h.stages == 8 || (h.stages == 0 && h.K > kTile))
         hipLaunchKernelGGL(k_herk_f64<8>, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
     else
         hipLaunchKernelGGL(k_herk_f64<16>, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
@@ -648,8 +662,8 @@ hipError_t launch_build_negk_from_full(const double* chi, int NG, double* Cre, d
 
 hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, double* Lre, double* Lim,
                              double* logdet, int* fail, hipStream_t s) {
-    hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)nw), dim3(256), 0, s, Cre, Cim, ldC, (long long)ldC * ldC, j0, Lre,
-                       Lim, logdet, fail);
+    hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)nw), dim3(64 * kPanelWaves), 0, s, Cre, Cim, ldC,
+                       (long long)ldC * ldC, j0, Lre, Lim, logdet, fail);
     return hipGetLastError();
 }
 

@@ -1023,6 +1023,7 @@ int ensure_lookahead(rpa_ctx* c) {
 // main stream runs that tile and la2_stream the rows below it, beside panel j+1;
 // solve j+1 waits for them. la2_stream runs these in step order, so the solve of
 // step j+2, which overwrites the panel buffer of step j, comes after them too.
+constexpr long long kDeepUpdateWgs = 14 * 256;   // workgroups of a trailing update: 14 per CU
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     const int nw = B.nw, ld = B.ld;
@@ -1128,6 +1129,10 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             h.r0 = r1;
             h.nT = (ld - r1) / kTile;
             h.nbatch = nb;
+            // while b_j is long against the main stream's panel, solve and a_j, it is the critical path
+            // and takes the deeper kernel (three workgroups per CU); once it is short, the panel that
+            // runs beside it needs room on the CUs, which stages of 16 at two per CU leave
+            h.stages = (long long)h.nT * (h.nT + 1) / 2 * nb >= kDeepUpdateWgs ? 8 : 16;
             HIP_TRY(launch_herk_f64(h, S));
             HIP_TRY(hipEventRecord(c->la_ev[1 + (step & 1)], S));
             pending_b = true;
