@@ -169,8 +169,12 @@ struct GemmArgs {
     const double* Ar; const double* Ai; long long sA; long long aI, aK; int conjA;
     const double* Br; const double* Bi; long long sB; long long bK, bJ; int conjB;
     double* Cr; double* Ci; long long sC; long long ldC; double alpha; int beta;
+    int lower;           // only entries i >= j of C are needed (a hint: tiles wholly above may be skipped)
 };
 hipError_t launch_gemm_c64(const GemmArgs& g, hipStream_t s);
+// The same product for 1 <= K <= 64 in one round trip to memory (latency-bound shapes of the Cholesky
+// chain); other K go to launch_gemm_c64.
+hipError_t launch_gemm_c64_shortk(const GemmArgs& g, hipStream_t s);
 hipError_t launch_identity(double* Xr, double* Xi, int n, int ld, int nb, hipStream_t s);
 hipError_t launch_build_w(double* Mr, double* Mi, int NG, int NGp, int nw, const double* vs, hipStream_t s);
 hipError_t launch_freq_coeffs(const double* dE, const double* ow, int nw, double* cw, hipStream_t s);

@@ -163,6 +163,71 @@ __global__ __launch_bounds__(256, 3) void k_gemm_c64(GemmArgs g) {
     }
 }
 
+// Short-K form (K <= 64) for the latency-bound GEMMs of the Cholesky chain (the panel solve and the
+// look-ahead column): 32x32 tiles, each wave one 16x16 block, and every operand value of the whole K
+// loaded from memory straight into the MFMA operand registers at once (no LDS, no barrier), so that
+// a workgroup waits for memory once instead of once per K-stage.
+constexpr int kShortK = 64;
+__global__ __launch_bounds__(256) void k_gemm_c64_k64(GemmArgs g) {
+    if (g.lower && blockIdx.y > blockIdx.x) return;   // the tile lies wholly above the diagonal
+    const int b = blockIdx.z, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 32 + (wave >> 1) * 16, j0 = blockIdx.y * 32 + (wave & 1) * 16;
+    const double* Ar = g.Ar + (size_t)b * g.sA;
+    const double* Ai = g.Ai + (size_t)b * g.sA;
+    const double* Br = g.Br + (size_t)b * g.sB;
+    const double* Bi = g.Bi + (size_t)b * g.sB;
+    double* Cr = g.Cr + (size_t)b * g.sC;
+    double* Ci = g.Ci + (size_t)b * g.sC;
+    const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+    // operand layouts of v_mfma_f64_16x16x4f64: A lane l holds A[l%16][l/16], B lane l holds B[l/16][l%16];
+    // indices past M, N or K are clamped to valid elements and their values masked below
+    const int cc = lane & 15, kq = lane >> 4;
+    const size_t ia = (size_t)min(i0 + cc, g.M - 1) * g.aI, jb = (size_t)min(j0 + cc, g.N - 1) * g.bJ;
+    double ar[kShortK / 4], ai[kShortK / 4], br[kShortK / 4], bi[kShortK / 4];
+#pragma unroll
+    for (int s = 0; s < kShortK / 4; ++s) {
+        const size_t k = (size_t)min(4 * s + kq, g.K - 1);
+        ar[s] = Ar[ia + k * g.aK];
+        ai[s] = Ai[ia + k * g.aK];
+        br[s] = Br[k * g.bK + jb];
+        bi[s] = Bi[k * g.bK + jb];
+    }
+    // D lane l element r holds row l/16 + 4r, column l%16; with beta C is read along with the operands
+    const int jc = j0 + cc;
+    double cr[4] = {0, 0, 0, 0}, ci[4] = {0, 0, 0, 0};
+    if (g.beta) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + kq + 4 * r;
+            const size_t o = (i < g.M && jc < g.N) ? (size_t)i * g.ldC + jc : 0;
+            cr[r] = Cr[o];
+            ci[r] = Ci[o];
+        }
+    }
+    v4d accR = {0, 0, 0, 0}, accI = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < kShortK / 4; ++s) {
+        if (4 * s >= g.K) break;
+        const bool ok = 4 * s + kq < g.K;
+        const double a_r = ok ? ar[s] : 0.0, a_i = ok ? sa * ai[s] : 0.0;
+        const double b_r = ok ? br[s] : 0.0, b_i = ok ? sb * bi[s] : 0.0;
+        // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
+        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, b_r, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i, b_i, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, b_i, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, b_r, accI, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + kq + 4 * r;
+        if (i < g.M && jc < g.N) {
+            const size_t o = (size_t)i * g.ldC + jc;
+            Cr[o] = cr[r] + g.alpha * accR[r];
+            Ci[o] = ci[r] + g.alpha * accI[r];
+        }
+    }
+}
+
 // identity in rows [0, n) of a [nb][ld][ld] planar batch (zero elsewhere)
 __global__ void k_identity(double* __restrict__ Xr, double* __restrict__ Xi, int n, int ld) {
     const int i = blockIdx.x, b = blockIdx.y;
@@ -550,6 +615,14 @@ hipError_t launch_gemm_c64(const GemmArgs& g, hipStream_t s) {
     if (g.K <= 0 && g.beta) return hipSuccess;
     dim3 grid((unsigned)((g.M + kTile - 1) / kTile), (unsigned)((g.N + kTile - 1) / kTile), (unsigned)g.nbatch);
     hipLaunchKernelGGL(k_gemm_c64, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_c64_shortk(const GemmArgs& g, hipStream_t s) {
+    if (g.K < 1 || g.K > kShortK) return launch_gemm_c64(g, s);
+    if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
+    dim3 grid((unsigned)((g.M + 31) / 32), (unsigned)((g.N + 31) / 32), (unsigned)g.nbatch);
+    hipLaunchKernelGGL(k_gemm_c64_k64, grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 

@@ -1166,10 +1166,12 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
         ga.ldC = ld;
         ga.alpha = -1.0;
         ga.beta = 1;
-        HIP_TRY(launch_gemm_c64(ga, M));
+        ga.lower = 1;
+        HIP_TRY(launch_gemm_c64_shortk(ga, M));
         if (r1 < ld) {
             HIP_TRY(hipEventRecord(evD, M));
             HIP_TRY(hipStreamWaitEvent(S2, evD, 0));
+            ga.lower = 0;
             ga.M = ld - r1;
             ga.Ar = Pre + r1;
             ga.Ai = Pim + r1;
