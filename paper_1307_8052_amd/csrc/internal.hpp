@@ -143,8 +143,10 @@ hipError_t launch_build_negk_from_full(const double* chi, int NG, double* Cre, d
 hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, double* Lre, double* Lim,
                              double* logdet, int* fail, hipStream_t s);
 // Both also write the factor L (lower triangle, diagonal real) back into C.
+// Pre/Pim: the solved panel of each matrix, P[c][r] at c * NGp + r; one matrix every sP doubles.
 hipError_t launch_chol_trsm(double* Cre, double* Cim, int ldC, int j0, int NGp, int nw,
-                            const double* Lre, const double* Lim, double* Pre, double* Pim, hipStream_t s);
+                            const double* Lre, const double* Lim, double* Pre, double* Pim, long long sP,
+                            hipStream_t s);
 hipError_t launch_finalize(const double* logdet, const double* trk, const int* fail, const double* wgt, int nw,
                            double* F, double* ec, hipStream_t s);
 

@@ -511,7 +511,7 @@ constexpr int kTrsmRows = 32;
 __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ Cre, double* __restrict__ Cim,
                                                    int ldC, long long sC, int j0, int NGp,
                                                    const double* __restrict__ Lre, const double* __restrict__ Lim,
-                                                   double* __restrict__ Pre, double* __restrict__ Pim) {
+                                                   double* __restrict__ Pre, double* __restrict__ Pim, long long sP) {
     __shared__ double lr[kTile][kTile + 1], li[kTile][kTile + 1];
     __shared__ double ar[kTrsmRows][kTile + 1], ai[kTrsmRows][kTile + 1];
     const int w = blockIdx.y, tid = threadIdx.x;
@@ -529,8 +529,8 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ Cre, dou
         ai[r][c] = row < NGp ? ci[(size_t)row * ldC + j0 + c] : 0.0;
     }
     __syncthreads();
-    double* pr = Pre + (size_t)w * kTile * NGp;
-    double* pi = Pim + (size_t)w * kTile * NGp;
+    double* pr = Pre + (size_t)w * sP;
+    double* pi = Pim + (size_t)w * sP;
     for (int e = tid; e < kTrsmRows * kTile; e += blockDim.x) {
         const int r = e % kTrsmRows, c = e / kTrsmRows;
         const int row = r0 + r;
@@ -668,12 +668,12 @@ hipError_t launch_chol_panel(double* Cre, double* Cim, int ldC, int j0, int nw, 
 }
 
 hipError_t launch_chol_trsm(double* Cre, double* Cim, int ldC, int j0, int NGp, int nw, const double* Lre,
-                            const double* Lim, double* Pre, double* Pim, hipStream_t s) {
+                            const double* Lim, double* Pre, double* Pim, long long sP, hipStream_t s) {
     const int rows = NGp - j0 - kTile;
     if (rows <= 0) return hipSuccess;
     dim3 grid((unsigned)((rows + kTrsmRows - 1) / kTrsmRows), (unsigned)nw);
     hipLaunchKernelGGL(k_chol_trsm, grid, dim3(256), 0, s, Cre, Cim, ldC, (long long)ldC * ldC, j0, NGp, Lre, Lim, Pre,
-                       Pim);
+                       Pim, sP);
     return hipGetLastError();
 }
 

@@ -728,7 +728,7 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     if (need_ec || need_chi) W.chi = 2 * nmat * ld2 * sizeof(double);
     if (need_ec) {
         W.cholL = 2 * nmat * kTile * kTile * sizeof(double);
-        W.cholP = 2 * 2 * nmat * kTile * (size_t)B.ld * sizeof(double);   // two panels in flight
+        W.cholP = 2 * 2 * nmat * 2 * kTile * (size_t)B.ld * sizeof(double);   // two pairs of panels in flight
         W.small = nmat * (2 * sizeof(double) + sizeof(int)) + 64;
     }
     struct NB {
@@ -1010,19 +1010,22 @@ int ensure_lookahead(rpa_ctx* c) {
 // from_full (one job): -K from a caller chi0 [nw][NG][NG] instead.
 // Lblocks (one job): keep every inverted diagonal block and the factor itself.
 //
-// Look-ahead: the trailing update of step j is split into the next block column
-// (a_j, a GEMM) and the rest (b_j). The main stream runs panel, solve and a_j in
-// turn; b_j runs on la_stream as soon as the solve of step j is done, beside a_j,
-// panel j+1 and its solve. b_j touches only columns right of block column j+1;
-// a_{j+1} waits for b_j, since both update block column j+2, and so the b's run
-// back to back when they are the longer chain. The solved panels alternate between
-// two buffers (the solve of step j+2 comes after a_{j+1}, hence after b_j), and the
-// completion of b_j is marked by one of two events in turn, so that the main
-// stream's wait for b_{j-1} is issued before that event is recorded again.
-// a_j itself is split once more: panel j+1 reads only its diagonal tile, so the
-// main stream runs that tile and la2_stream the rows below it, beside panel j+1;
-// solve j+1 waits for them. la2_stream runs these in step order, so the solve of
-// step j+2, which overwrites the panel buffer of step j, comes after them too.
+// Blocking and look-ahead. The panel steps go in pairs (j = 2p, 2p+1) and the trailing matrix is
+// updated once per pair, with K = 128 (both solved panels of the pair): half the passes over the
+// trailing matrix of an update per step. The solved panels of pair p share one buffer of two
+// 64-row slots, and the pairs alternate between two such buffers.
+//   even step j: panel, solve into slot 0, then a_j: block column j+1 with P_j (K = 64);
+//   odd step j:  panel, solve into slot 1, then b_p on la_stream: every block column from j+3 on
+//                with K = 128, and a'_p: block columns j+1 and j+2 with K = 128, after b_{p-1}
+//                (which covers them), on the main stream.
+// b_p covers none of the block columns the next pair's panels need before a'_p has run, so the b's
+// run back to back on la_stream while the main stream factors the next pair. Every look-ahead update
+// (a_j, a'_p) runs the diagonal tile of its first block column on the main stream, where the next
+// panel reads it, and the rest on la2_stream beside that panel; the next solve waits for the rest.
+// Ordering of the pairs of updates that touch the same tiles: b_{p-1} before a'_p (main stream wait);
+// a'_p's rest before a_{j+1} (la2_stream order and the main stream's wait before solve j+1); a_j's and
+// a'_p's rests before the solve that follows them. A pair buffer is overwritten by the solves of pair
+// p+2, after the main stream has waited for b_p (at a'_{p+1}) and for the rests on la2_stream.
 constexpr long long kDeepUpdateWgs = 14 * 256;   // workgroups of a trailing update: 14 per CU
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
@@ -1035,7 +1038,10 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     double* Lre = static_cast<double*>(buf(B, "chol_L"));
     double* Lim = Lre + (size_t)nb * kTile * kTile;
     double* Pbase = static_cast<double*>(buf(B, "chol_panel"));
-    const size_t pstride = 2 * (size_t)nb * kTile * ld;   // one panel buffer (re and im)
+    // pair buffers: [2][re, im][nb][2 * kTile][ld]
+    const size_t pslot = (size_t)kTile * ld;   // one slot of one matrix
+    const size_t pmat = 2 * pslot;             // both slots of one matrix (the matrix stride)
+    const size_t ppart = (size_t)nb * pmat;    // the real (or imaginary) part of a pair buffer
     double* cr = B.qj[0].cr;
     double* ci = B.qj[0].ci;
     const long long ld2 = (long long)ld * ld;
@@ -1055,31 +1061,62 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
                                       trk + qi * nw, M));
         }
     }
-    bool pending_b = false;   // a trailing update b_j is in flight on S
-    int last_b = 0;           // step of the last b_j
-    bool pending_r = false;   // the rows of a_j below its diagonal tile are in flight on S2
+    // C[rows r, columns c] -= sum_k P[k][r] conj(P[k][c]) for k < K from the panel buffer at P
+    auto lookahead = [&](double* Pr, double* Pi, int K, int r, int col, int rows, int cols, int lower,
+                         hipStream_t st) -> hipError_t {
+        GemmArgs g{};
+        g.M = rows;
+        g.N = cols;
+        g.K = K;
+        g.nbatch = nb;
+        g.Ar = Pr + r;
+        g.Ai = Pi + r;
+        g.sA = (long long)pmat;
+        g.aI = 1;
+        g.aK = ld;
+        g.conjA = 0;
+        g.Br = Pr + col;
+        g.Bi = Pi + col;
+        g.sB = (long long)pmat;
+        g.bK = ld;
+        g.bJ = 1;
+        g.conjB = 1;
+        g.Cr = cr + (size_t)r * ld + col;
+        g.Ci = ci + (size_t)r * ld + col;
+        g.sC = ld2;
+        g.ldC = ld;
+        g.alpha = -1.0;
+        g.beta = 1;
+        g.lower = lower;
+        return lower ? launch_gemm_c64_shortk(g, st) : launch_gemm_c64(g, st);
+    };
+    bool pending_b = false;   // a pair's trailing update is in flight on S
+    int last_p = 0;           // pair of the last one
+    bool pending_r = false;   // the rest of a look-ahead update is in flight on S2
     for (int j0 = 0; j0 < ld; j0 += kTile) {
-        const int step = j0 / kTile;
-        double* Pre = Pbase + (size_t)(step & 1) * pstride;
-        double* Pim = Pre + (size_t)nb * kTile * ld;
+        const int step = j0 / kTile, pair = step >> 1, slot = step & 1;
+        double* PPre = Pbase + (size_t)(pair & 1) * 2 * ppart;   // this pair's buffer
+        double* PPim = PPre + ppart;
+        double* Pre = PPre + slot * pslot;                       // this step's slot
+        double* Pim = PPim + slot * pslot;
         if (Lblocks) {
             // keep every inverted diagonal block: [block][re/im][w][64][64]
             Lre = Lblocks + (size_t)step * 2 * nb * kTile * kTile;
             Lim = Lre + (size_t)nb * kTile * kTile;
         }
-        // panel j: the diagonal tile of block column j is complete (a_{j-1} before it here,
-        // b_{j-2} before a_{j-1}); the rows below it are once the main stream has waited for
-        // the rest of a_{j-1}
+        // panel j: the diagonal tile of block column j is complete (its look-ahead tile ran before it
+        // here, and every trailing update that covers it was waited for before that)
         HIP_TRY(launch_chol_panel(cr, ci, ld, j0, nb, Lre, Lim, logdet, failv, M));
         const int r0 = j0 + kTile;
         if (r0 >= ld) break;
+        // the rows below the diagonal tile are complete once the rest of the last look-ahead is
         if (pending_r) HIP_TRY(hipStreamWaitEvent(M, evR, 0));
         pending_r = false;
         if (Lblocks) {
             // the adjoint needs the factor itself: L21 also replaces the block column
-            HIP_TRY(launch_chol_trsm(cr, ci, ld, j0, ld, nb, Lre, Lim, Pre, Pim, M));
+            HIP_TRY(launch_chol_trsm(cr, ci, ld, j0, ld, nb, Lre, Lim, Pre, Pim, (long long)pmat, M));
         } else {
-            // panel operand of the trailing update only: P[c][r] = sum_k conj(L11^-1[c][k]) A21[r][k]
+            // panel operand of the updates only: P[c][r] = sum_k conj(L11^-1[c][k]) A21[r][k]
             GemmArgs gm{};
             gm.M = kTile;
             gm.N = ld - r0;
@@ -1099,26 +1136,39 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             gm.conjB = 0;
             gm.Cr = Pre + r0;
             gm.Ci = Pim + r0;
-            gm.sC = (long long)kTile * ld;
+            gm.sC = (long long)pmat;
             gm.ldC = ld;
             gm.alpha = 1.0;
             gm.beta = 0;
             HIP_TRY(launch_gemm_c64(gm, M));
         }
-        // b_j on the side stream: the lower tiles right of the next block column
-        const int r1 = r0 + kTile;
-        const bool prev_b = pending_b;
-        pending_b = false;
-        if (r1 < ld) {
+        int la_cols = kTile, la_K = kTile;   // the look-ahead update of this step: block columns from r0
+        double *Lr = Pre, *Li = Pim;           // and its operand: this step's slot, or both slots of the pair
+        if (slot == 1) {
+            // a'_p: block columns j+1 and j+2 with K = 128, after b_{p-1}, which covers them too
+            if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + ((pair - 1) & 1)], 0));
+            pending_b = false;
+            la_cols = std::min(2 * kTile, ld - r0);
+            la_K = 2 * kTile;
+            Lr = PPre;
+            Li = PPim;
+        }
+        // the look-ahead's diagonal tile, which the next panel reads (K = 64 at a time on the short-K kernel)
+        for (int k0 = 0; k0 < la_K; k0 += kTile)
+            HIP_TRY(lookahead(Lr + (size_t)k0 * ld, Li + (size_t)k0 * ld, kTile, r0, r0, kTile, kTile, 1, M));
+        // b_p on the side stream: every block column from j+3 on, K = 128. It starts after the diagonal tile
+        // above, so that the tile the next panel waits for is not queued behind the whole update.
+        const int rb = r0 + 2 * kTile;
+        if (slot == 1 && rb < ld) {
             HIP_TRY(hipEventRecord(evA, M));
             HIP_TRY(hipStreamWaitEvent(S, evA, 0));
             HerkArgs h{};
-            h.Are = Pre;
-            h.Aim = Pim;
-            h.sA = (long long)kTile * ld;
+            h.Are = PPre;
+            h.Aim = PPim;
+            h.sA = (long long)pmat;
             h.ldA = ld;
-            h.colA = r1;
-            h.K = kTile;
+            h.colA = rb;
+            h.K = 2 * kTile;
             h.w = nullptr;
             h.sw = 0;
             h.alpha = -1.0;
@@ -1126,64 +1176,31 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             h.Cim = ci;
             h.sC = ld2;
             h.ldC = ld;
-            h.r0 = r1;
-            h.nT = (ld - r1) / kTile;
+            h.r0 = rb;
+            h.nT = (ld - rb) / kTile;
             h.nbatch = nb;
-            // while b_j is long against the main stream's panel, solve and a_j, it is the critical path
-            // and takes the deeper kernel (three workgroups per CU); once it is short, the panel that
-            // runs beside it needs room on the CUs, which stages of 16 at two per CU leave
+            // while b_p is long against the main stream's chain it is the critical path and takes the
+            // deeper kernel (three workgroups per CU); once it is short, the panel that runs beside it
+            // needs room on the CUs, which stages of 16 at two per CU leave
             h.stages = (long long)h.nT * (h.nT + 1) / 2 * nb >= kDeepUpdateWgs ? 8 : 16;
             HIP_TRY(launch_herk_f64(h, S));
-            HIP_TRY(hipEventRecord(c->la_ev[1 + (step & 1)], S));
+            HIP_TRY(hipEventRecord(c->la_ev[1 + (pair & 1)], S));
             pending_b = true;
-            last_b = step;
+            last_p = pair;
         }
-        // a_j: the next block column C[r0:, r0:r0+64] -= P^H P (full 64-wide GEMM; the strict upper part
-        // of its diagonal tile is never read), after b_{j-1}, which also updates that column.
-        // Its diagonal tile is all that panel j+1 reads, so only that tile runs here; the rows below
-        // it run on la2_stream beside panel j+1, and the main stream waits for them before solve j+1.
-        if (prev_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + ((step - 1) & 1)], 0));
-        GemmArgs ga{};
-        ga.M = kTile;
-        ga.N = kTile;
-        ga.K = kTile;
-        ga.nbatch = nb;
-        ga.Ar = Pre + r0;
-        ga.Ai = Pim + r0;
-        ga.sA = (long long)kTile * ld;
-        ga.aI = 1;
-        ga.aK = ld;
-        ga.conjA = 0;
-        ga.Br = Pre + r0;
-        ga.Bi = Pim + r0;
-        ga.sB = (long long)kTile * ld;
-        ga.bK = ld;
-        ga.bJ = 1;
-        ga.conjB = 1;
-        ga.Cr = cr + (size_t)r0 * ld + r0;
-        ga.Ci = ci + (size_t)r0 * ld + r0;
-        ga.sC = ld2;
-        ga.ldC = ld;
-        ga.alpha = -1.0;
-        ga.beta = 1;
-        ga.lower = 1;
-        HIP_TRY(launch_gemm_c64_shortk(ga, M));
-        if (r1 < ld) {
+        // the rest of the look-ahead on S2, beside the next panel
+        if (r0 + kTile < ld) {
             HIP_TRY(hipEventRecord(evD, M));
             HIP_TRY(hipStreamWaitEvent(S2, evD, 0));
-            ga.lower = 0;
-            ga.M = ld - r1;
-            ga.Ar = Pre + r1;
-            ga.Ai = Pim + r1;
-            ga.Cr = cr + (size_t)r1 * ld + r0;
-            ga.Ci = ci + (size_t)r1 * ld + r0;
-            HIP_TRY(launch_gemm_c64(ga, S2));
+            // rows below the diagonal tile of the first block column, and (K = 128) the second block
+            // column from its own diagonal tile down; the strict upper part of a diagonal tile is never read
+            HIP_TRY(lookahead(Lr, Li, la_K, r0 + kTile, r0, ld - r0 - kTile, la_cols, 0, S2));
             HIP_TRY(hipEventRecord(evR, S2));
             pending_r = true;
         }
     }
     if (pending_r) HIP_TRY(hipStreamWaitEvent(M, evR, 0));
-    if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + (last_b & 1)], 0));
+    if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + (last_p & 1)], 0));
     for (int qi = 0; qi < nq; ++qi) {
         QJob& Q = B.qj[qi];
         HIP_TRY(launch_finalize(logdet + qi * nw, trk + qi * nw, failv + qi * nw,
