@@ -27,6 +27,9 @@ CASES = {
     "optical": lambda: synth.tiny(grid=(10, 10, 10), n_occ=2, n_unocc=3, optical=True, target_ng=12, nw=8),
     "distinct_kq": lambda: synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=3, target_ng=15, nw=8, extra_kq=True),
     "cfg0_small": lambda: synth.config0(n_occ=2, n_unocc=10),
+    # NG = 300: five 64-wide block columns, so the factorisation ends on an unpaired panel step
+    "five_blocks": lambda: synth.tiny(grid=(24, 24, 24), L=(8.0, 8.5, 9.0), n_occ=2, n_unocc=6, target_ng=300,
+                                      nw=8),
 }
 
 

@@ -106,6 +106,32 @@ def test_chi0_and_ec_fp64(rpa, name, path):
     assert abs(ec - ref["E"]) < 1e-10
 
 
+@pytest.mark.parametrize("target_ng,grid", [(150, (16, 16, 16)), (250, (24, 24, 24)), (300, (24, 24, 24)),
+                                             (421, (24, 24, 24))])
+def test_ec_block_column_counts(rpa, target_ng, grid):
+    """The blocked factorisation pairs its 64-wide panel steps and looks two block columns ahead: NG padded
+    to 192, 256, 320 and 448 gives 3, 4, 5 and 7 block columns (an unpaired last step, a look-ahead clipped
+    at the last block column). FP64 E_c and F(w) against the oracle, and the split path's E_c."""
+    wl = synth.tiny(grid=grid, L=(8.0, 8.5, 9.0), n_occ=2, n_unocc=10, target_ng=target_ng)
+    ref = oracle_q(wl)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    assert np.array_equal(gm, ref["gm"])
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
+        ecb, _ = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        ecf, Ff = ctx.ec_from_chi0(qs, fr, torch.from_numpy(ref["chi"]))
+        ctx.check()
+        ec, ecb, ecf = float(ec.cpu()[0]), float(ecb.cpu()[0]), float(ecf.cpu()[0])
+        F, Ff = F.cpu().numpy(), Ff.cpu().numpy()
+    print(f"NG={len(gm)} blocks={(len(gm) + 63) // 64}: E={ec:.14f} from oracle chi0 {ecf:.14f} "
+          f"split {ecb:.12f} ref={ref['E']:.14f}", flush=True)
+    assert abs(ec - ref["E"]) < 1e-10
+    assert np.max(np.abs(F - ref["F"])) < 1e-10
+    assert abs(ecf - ref["E"]) < 1e-12
+    assert np.max(np.abs(Ff - ref["F"])) < 1e-12
+    assert abs(ecb - ref["E"]) < 1e-6
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_chi0_and_ec_split(rpa, prec):
     wl = synth.config0()
