@@ -89,7 +89,7 @@ struct rpa_ctx {
     hipStream_t la_stream = nullptr;
     hipStream_t la2_stream = nullptr;
     hipEvent_t la_ev[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t la2_ev[2] = {nullptr, nullptr};
+    hipEvent_t la2_ev[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -1048,7 +1048,7 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     int rc = ensure_lookahead(c);
     if (rc) return rc;
     hipStream_t M = B.s, S = c->la_stream, S2 = c->la2_stream;
-    hipEvent_t evA = c->la_ev[0], evD = c->la2_ev[0], evR = c->la2_ev[1];
+    hipEvent_t evA = c->la_ev[0], evD = c->la2_ev[0], evR = c->la2_ev[1], evR2 = c->la2_ev[2];
     ProfScope ps_(c, S_CHOL, M);
     HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, M));
     for (int qi = 0; qi < nq; ++qi) {
@@ -1092,7 +1092,8 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     };
     bool pending_b = false;   // a pair's trailing update is in flight on S
     int last_p = 0;           // pair of the last one
-    bool pending_r = false;   // the rest of a look-ahead update is in flight on S2
+    bool pending_r = false;   // the rest of a look-ahead update's first block column is in flight on S2
+    bool pending_r2 = false;  // and that of its second block column (K = 128 look-aheads)
     for (int j0 = 0; j0 < ld; j0 += kTile) {
         const int step = j0 / kTile, pair = step >> 1, slot = step & 1;
         double* PPre = Pbase + (size_t)(pair & 1) * 2 * ppart;   // this pair's buffer
@@ -1153,7 +1154,10 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             Lr = PPre;
             Li = PPim;
         }
-        // the look-ahead's diagonal tile, which the next panel reads (K = 64 at a time on the short-K kernel)
+        // the look-ahead's diagonal tile, which the next panel reads (K = 64 at a time on the short-K kernel),
+        // after the previous look-ahead's second block column, which covers this tile too
+        if (pending_r2) HIP_TRY(hipStreamWaitEvent(M, evR2, 0));
+        pending_r2 = false;
         for (int k0 = 0; k0 < la_K; k0 += kTile)
             HIP_TRY(lookahead(Lr + (size_t)k0 * ld, Li + (size_t)k0 * ld, kTile, r0, r0, kTile, kTile, 1, M));
         // b_p on the side stream: every block column from j+3 on, K = 128. It starts after the diagonal tile
@@ -1192,14 +1196,21 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
         if (r0 + kTile < ld) {
             HIP_TRY(hipEventRecord(evD, M));
             HIP_TRY(hipStreamWaitEvent(S2, evD, 0));
-            // rows below the diagonal tile of the first block column, and (K = 128) the second block
-            // column from its own diagonal tile down; the strict upper part of a diagonal tile is never read
-            HIP_TRY(lookahead(Lr, Li, la_K, r0 + kTile, r0, ld - r0 - kTile, la_cols, 0, S2));
+            // rows below the diagonal tile of the first block column (the next solve waits for these), then
+            // (K = 128) the second block column from its own diagonal tile down (the next look-ahead's
+            // diagonal tile waits for that); the strict upper part of a diagonal tile is never read
+            HIP_TRY(lookahead(Lr, Li, la_K, r0 + kTile, r0, ld - r0 - kTile, kTile, 0, S2));
             HIP_TRY(hipEventRecord(evR, S2));
             pending_r = true;
+            if (la_cols > kTile) {
+                HIP_TRY(lookahead(Lr, Li, la_K, r0 + kTile, r0 + kTile, ld - r0 - kTile, la_cols - kTile, 0, S2));
+                HIP_TRY(hipEventRecord(evR2, S2));
+                pending_r2 = true;
+            }
         }
     }
     if (pending_r) HIP_TRY(hipStreamWaitEvent(M, evR, 0));
+    if (pending_r2) HIP_TRY(hipStreamWaitEvent(M, evR2, 0));
     if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + (last_p & 1)], 0));
     for (int qi = 0; qi < nq; ++qi) {
         QJob& Q = B.qj[qi];
