@@ -97,7 +97,6 @@ struct HerkArgs {
     const double* w; long long sw; double alpha;
     double* Cre; double* Cim; long long sC; int ldC; int r0;
     int nT; int nbatch;
-    int stages;          // K-stage depth: 8 (three workgroups per CU) or 16 (two); 0 = by K
 };
 hipError_t launch_herk_f64(const HerkArgs& h, hipStream_t s);
 

@@ -161,10 +161,8 @@ __global__ void k_weights(const double* __restrict__ epsk, const double* __restr
 // across the four lane groups, unlike the 16-bit-input MFMAs).
 // K-stage of the FP64 rank-k kernel. Stages of 8 (32 KB of LDS, double-buffered) with registers bounded
 // for three workgroups per CU hide more latency (48 x 1408^2 at K = 256: 57.7 against 51.9 TFLOP/s for
-// stages of 16 at two per CU) and serve the chi0 update and the long Cholesky trailing updates (K = 64).
-// The short trailing updates of the late Cholesky steps take stages of 16: three stage-8 workgroups fill
-// a CU's registers and LDS, and the panel and solve of the next block column, which then bound the step
-// and run beside them, would wait for their tail.
+// stages of 16 at two per CU) and serve the chi0 update and the Cholesky trailing updates (K = 128, once
+// per pair of panels). Stages of 16 at two per CU serve K <= 64.
 template <int BK> struct HerkF64Cfg;
 template <> struct HerkF64Cfg<8> { static constexpr int waves_per_simd = 3; };
 template <> struct HerkF64Cfg<16> { static constexpr int waves_per_simd = 2; };
@@ -636,7 +634,7 @@ hipError_t launch_weights(const double* epsk, const double* epskq, const double*
 hipError_t launch_herk_f64(const HerkArgs& h, hipStream_t s) {
     if (h.nT <= 0 || h.nbatch <= 0 || h.K <= 0) return hipSuccess;
     const unsigned ntiles = (unsigned)(h.nT * (h.nT + 1) / 2);
-    if (h.stages == 8 || (h.stages == 0 && h.K > kTile))
+    if (h.K > kTile)
         hipLaunchKernelGGL(k_herk_f64<8>, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);
     else
         hipLaunchKernelGGL(k_herk_f64<16>, dim3(ntiles, (unsigned)h.nbatch), dim3(256), 0, s, h);

@@ -1026,7 +1026,6 @@ int ensure_lookahead(rpa_ctx* c) {
 // a'_p's rest before a_{j+1} (la2_stream order and the main stream's wait before solve j+1); a_j's and
 // a'_p's rests before the solve that follows them. A pair buffer is overwritten by the solves of pair
 // p+2, after the main stream has waited for b_p (at a'_{p+1}) and for the rests on la2_stream.
-constexpr long long kDeepUpdateWgs = 14 * 256;   // workgroups of a trailing update: 14 per CU
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     const int nw = B.nw, ld = B.ld;
@@ -1183,10 +1182,6 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
             h.r0 = rb;
             h.nT = (ld - rb) / kTile;
             h.nbatch = nb;
-            // while b_p is long against the main stream's chain it is the critical path and takes the
-            // deeper kernel (three workgroups per CU); once it is short, the panel that runs beside it
-            // needs room on the CUs, which stages of 16 at two per CU leave
-            h.stages = (long long)h.nT * (h.nT + 1) / 2 * nb >= kDeepUpdateWgs ? 8 : 16;
             HIP_TRY(launch_herk_f64(h, S));
             HIP_TRY(hipEventRecord(c->la_ev[1 + (pair & 1)], S));
             pending_b = true;
