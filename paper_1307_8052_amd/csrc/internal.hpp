@@ -55,9 +55,12 @@ hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const i
                               int npairs, const PairGeom& g, cplx<T>* tbuf, hipStream_t s);
 // In-place transforms of nb grids [nb][N3][N2][N1] (dir = +1 inverse without
 // 1/N, -1 forward) with register-resident lines: along z, or along x and y;
-// hipErrorNotSupported where the register kernels do not cover the axis.
+// hipErrorNotSupported where the register kernels do not cover the axis. Along z,
+// cols (DEVICE, ncols offsets y * N1 + x into a plane) restricts the transform to
+// those columns (the others must be zero); NULL transforms all of them.
 template <typename T>
-hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
+hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, const int32_t* cols,
+                                 int ncols, hipStream_t s);
 template <typename T>
 hipError_t launch_grid_fft_xy_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
 template <typename T>

@@ -2,8 +2,9 @@
 // has a compiled register transform: the orbitals of Eq. get_wfs (Table 1
 // step 3) and the pair densities of Eq. fft (Table 1 steps 5-6).
 //
-// Orbitals: k_fft_z_reg transforms every z-line in place (lanes take
-// consecutive x, so each load and store is coalesced without LDS);
+// Orbitals: k_fft_z_reg transforms the z-lines in place (lanes take
+// consecutive x, so each load and store is coalesced without LDS), only those
+// of the (x, y) columns that hold plane-wave coefficients (the others are zero);
 // k_fft_xy_reg takes one z-plane per workgroup through LDS, one thread per
 // x-row and then one per y-column. Each axis pair uses its register kernel when
 // its length has one, so a grid such as 40 x 40 x 160 runs x and y in registers
@@ -261,11 +262,13 @@ __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ 
 }
 
 template <typename T, int N3, int DIR>
-__global__ __launch_bounds__(256) void k_fft_z_reg(cplx<T>* __restrict__ data, long long nlines, int plane) {
+__global__ __launch_bounds__(256) void k_fft_z_reg(cplx<T>* __restrict__ data, long long nlines, int plane,
+                                                   const int32_t* __restrict__ cols, int ncols) {
     const long long L = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (L >= nlines) return;
-    const long long b = L / plane;
-    cplx<T>* base = data + b * (long long)plane * N3 + (L - b * plane);
+    const long long b = L / ncols;
+    const int i = (int)(L - b * ncols);
+    cplx<T>* base = data + b * (long long)plane * N3 + (cols ? cols[i] : i);
     cplx<T> v[N3];
 #pragma unroll
     for (int z = 0; z < N3; ++z) v[z] = base[(long long)z * plane];
@@ -367,7 +370,8 @@ bool pair_z_reg_supported(const PairGeom& g) {
 }
 
 template <typename T>
-hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s) {
+hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, const int32_t* cols,
+                                 int ncols, hipStream_t s) {
     if (!nb) return hipSuccess;
     PairGeom g{};
     g.N1 = N1;
@@ -375,15 +379,19 @@ hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, 
     g.N3 = N3;
     if (!pair_z_reg_supported<T>(g)) return hipErrorNotSupported;
     const int plane = N1 * N2;
-    const long long nlines = (long long)nb * plane;
+    if (!cols) ncols = plane;
+    if (ncols <= 0) return hipSuccess;
+    const long long nlines = (long long)nb * ncols;
     const unsigned zb = (unsigned)((nlines + 255) / 256);
     switch (N3) {
 #define RPA_CASE(L)                                                                                             \
     case L:                                                                                                     \
         if (dir > 0)                                                                                            \
-            hipLaunchKernelGGL((k_fft_z_reg<T, L, 1>), dim3(zb), dim3(256), 0, s, data, nlines, plane);          \
+            hipLaunchKernelGGL((k_fft_z_reg<T, L, 1>), dim3(zb), dim3(256), 0, s, data, nlines, plane, cols,     \
+                               ncols);                                                                          \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_fft_z_reg<T, L, -1>), dim3(zb), dim3(256), 0, s, data, nlines, plane);         \
+            hipLaunchKernelGGL((k_fft_z_reg<T, L, -1>), dim3(zb), dim3(256), 0, s, data, nlines, plane, cols,    \
+                               ncols);                                                                          \
         break;
         RPA_REG_SIZES(RPA_CASE)
 #undef RPA_CASE
@@ -467,7 +475,7 @@ hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g,
 #define RPA_INST(T)                                                                                              \
     template bool pair_xy_reg_supported<T>(const PairGeom&);                                                     \
     template bool pair_z_reg_supported<T>(const PairGeom&);                                                      \
-    template hipError_t launch_grid_fft_z_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                 \
+    template hipError_t launch_grid_fft_z_reg<T>(cplx<T>*, int, int, int, int, int, const int32_t*, int, hipStream_t);                 \
     template hipError_t launch_grid_fft_xy_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                \
     template hipError_t launch_pair_xy_reg<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*, int, \
                                               const PairGeom&, cplx<T>*, hipStream_t);                           \

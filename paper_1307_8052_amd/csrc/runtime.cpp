@@ -454,6 +454,17 @@ void pair_list(const rpa_states* k, const rpa_states* kq, std::vector<int32_t>& 
         }
 }
 
+// the distinct (x, y) columns of a scatter map, as offsets y * N1 + x into a z-plane, ascending
+std::vector<int32_t> grid_columns(const rpa_ctx* c, const std::vector<int32_t>& map) {
+    const int32_t plane = c->N[0] * c->N[1];
+    std::vector<char> used(plane, 0);
+    for (int32_t m : map) used[m % plane] = 1;
+    std::vector<int32_t> cols;
+    for (int32_t i = 0; i < plane; ++i)
+        if (used[i]) cols.push_back(i);
+    return cols;
+}
+
 std::vector<int32_t> scatter_map(const rpa_ctx* c, const rpa_states* s) {
     std::vector<int32_t> map(s->nQ);
     for (int i = 0; i < s->nQ; ++i) {
@@ -487,10 +498,12 @@ struct KSet {
     const rpa_states* kq;
     std::vector<int32_t> pn, pm;
     std::vector<int32_t> mapk, mapkq;
+    std::vector<int32_t> zcolk, zcolkq;   // (x, y) columns of the grid that hold coefficients, y * N1 + x
     std::vector<double> epsk, epskq, fk, fkq;
     std::vector<int32_t> nlist_all;  // n = 0 .. nbands-1
     void* d_pn = nullptr; void* d_pm = nullptr;
     void* d_mapk = nullptr; void* d_mapkq = nullptr;
+    void* d_zcolk = nullptr; void* d_zcolkq = nullptr;
     void* d_epsk = nullptr; void* d_epskq = nullptr; void* d_fk = nullptr; void* d_fkq = nullptr;
     void* d_nlist = nullptr;
 };
@@ -612,12 +625,16 @@ int prepare_kset(Batch& B, KSet& K, Upload& up, const int32_t* pn_in = nullptr, 
                 return fail(RPA_ERR_SHAPE, "pair index out of range");
     }
     K.mapk = scatter_map(B.c, k);
+    K.zcolk = grid_columns(B.c, K.mapk);
     up.add(K.pn, &K.d_pn);
     up.add(K.pm, &K.d_pm);
     up.add(K.mapk, &K.d_mapk);
+    up.add(K.zcolk, &K.d_zcolk);
     if (!same_set(k, kq)) {
         K.mapkq = scatter_map(B.c, kq);
+        K.zcolkq = grid_columns(B.c, K.mapkq);
         up.add(K.mapkq, &K.d_mapkq);
+        up.add(K.zcolkq, &K.d_zcolkq);
     }
     K.epsk.assign(k->eps, k->eps + k->nbands);
     K.fk.assign(k->f, k->f + k->nbands);
@@ -754,7 +771,8 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
 }
 
 template <typename T>
-int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const char* name, cplx<T>** out) {
+int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const std::vector<int32_t>& zcols, void* d_zcols,
+                     const char* name, cplx<T>** out) {
     rpa_ctx* c = B.c;
     const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
     cplx<T>* phi = static_cast<cplx<T>*>(buf(B, name));
@@ -763,7 +781,10 @@ int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const char* nam
     HIP_TRY(launch_orb_scatter<T>(static_cast<const double*>(s->C), s->nbands, s->nQ,
                                   static_cast<const int32_t*>(d_map), vol, phi, B.s));
     // z, then x and y: register-resident lines where the axis length has them, LDS passes otherwise
-    hipError_t e = c->pair_reg ? launch_grid_fft_z_reg<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], +1, B.s)
+    // (only the columns that hold coefficients: the rest of the grid is zero and stays so along z)
+    hipError_t e = c->pair_reg ? launch_grid_fft_z_reg<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], +1,
+                                                          static_cast<const int32_t*>(d_zcols), (int)zcols.size(),
+                                                          B.s)
                                : hipErrorNotSupported;
     if (e == hipErrorNotSupported)
         HIP_TRY(launch_fft_axis<T>(phi, s->nbands, c->N[0], c->N[1], c->N[2], 2, c->plan[2],
@@ -958,12 +979,12 @@ int enqueue_chi0(Batch& B) {
         if (P == 0) continue;
         cplx<T>* phik = nullptr;
         cplx<T>* phikq = nullptr;
-        int rc = enqueue_orbitals<T>(B, K.k, K.d_mapk, "phi_k", &phik);
+        int rc = enqueue_orbitals<T>(B, K.k, K.d_mapk, K.zcolk, K.d_zcolk, "phi_k", &phik);
         if (rc) return rc;
         if (same_set(K.k, K.kq)) {
             phikq = phik;
         } else {
-            rc = enqueue_orbitals<T>(B, K.kq, K.d_mapkq, "phi_kq", &phikq);
+            rc = enqueue_orbitals<T>(B, K.kq, K.d_mapkq, K.zcolkq, K.d_zcolkq, "phi_kq", &phikq);
             if (rc) return rc;
         }
         const double prefac = K.k->weight / c->volume;
@@ -1729,11 +1750,11 @@ int rpa_pair_density(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, cons
         QJob& Q = B.qj[0];
         cplx<T>* phik = nullptr;
         cplx<T>* phikq = nullptr;
-        int r = enqueue_orbitals<T>(B, k, K.d_mapk, "phi_k", &phik);
+        int r = enqueue_orbitals<T>(B, k, K.d_mapk, K.zcolk, K.d_zcolk, "phi_k", &phik);
         if (r) return r;
         if (same_set(k, kq)) phikq = phik;
         else {
-            r = enqueue_orbitals<T>(B, kq, K.d_mapkq, "phi_kq", &phikq);
+            r = enqueue_orbitals<T>(B, kq, K.d_mapkq, K.zcolkq, K.d_zcolkq, "phi_kq", &phikq);
             if (r) return r;
         }
         const int NGp = Q.qp.NGp, Pc = Q.Pc;
