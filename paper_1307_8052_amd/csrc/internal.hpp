@@ -126,6 +126,7 @@ struct HerkSplit2Args {
     const double* w; int lda;
     double* Cre; double* Cim; long long sC; int ldC;
     int ntiles; int nw; int fp16; const float* scales;
+    int overwrite;       // variants 4 and 5: C = the update instead of C += it (a fresh accumulator)
 };
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
                              int fp16, float* Xre, float* Xim, unsigned short* const B[4], hipStream_t s);

@@ -630,21 +630,24 @@ __global__ __launch_bounds__(256, 1) void k_herk_split4(HerkSplit2Args h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
-    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
-    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
+    // C += acc (C = acc for the first update of a fresh accumulator: nothing read), one row block x at a
+    // time: all loads of the block are issued before its stores (which could alias them as far as the
+    // compiler knows); rows and columns past ldC read a valid address
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-        double cre[2][4], cim[2][4];
+        double cre[2][4] = {}, cim[2][4] = {};
+        if (!h.overwrite) {
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
-                cre[y][r] = Cre[o];
-                cim[y][r] = Cim[o];
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = ci + 16 * x + 4 * (lane >> 4) + r;
+                    const int col = cj + wc + 16 * y + (lane & 15);
+                    const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
+                    cre[y][r] = Cre[o];
+                    cim[y][r] = Cim[o];
+                }
+        }
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -817,21 +820,24 @@ __global__ __launch_bounds__(512, 1) void k_herk_split5(HerkSplit2Args h) {
     const double inv = 1.0 / ((double)sa * (double)sb);
     double* Cre = h.Cre + (size_t)w * h.sC;
     double* Cim = h.Cim + (size_t)w * h.sC;
-    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
-    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
+    // C += acc (C = acc for the first update of a fresh accumulator: nothing read), one row block x at a
+    // time: all loads of the block are issued before its stores (which could alias them as far as the
+    // compiler knows); rows and columns past ldC read a valid address
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-        double cre[2][4], cim[2][4];
+        double cre[2][4] = {}, cim[2][4] = {};
+        if (!h.overwrite) {
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
-                cre[y][r] = Cre[o];
-                cim[y][r] = Cim[o];
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
+                    const int col = cj + wc + 16 * y + (lane & 15);
+                    const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
+                    cre[y][r] = Cre[o];
+                    cim[y][r] = Cim[o];
+                }
+        }
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll

@@ -524,6 +524,7 @@ struct QJob {
     double* ci = nullptr;
     double* ec = nullptr;
     double* F = nullptr;
+    bool fresh = false;   // the accumulator holds nothing yet (no update has run into it)
 };
 
 struct Batch {
@@ -867,10 +868,24 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
 }
 
 // chi0(w) += rho diag(a(w)) rho^H for one chunk, with the job's kernel variant
+// chi0 accumulator of one job: nw matrices of ld x ld, real and imaginary blocks
+hipError_t zero_accumulator(Batch& B, QJob& Q) {
+    const size_t n = (size_t)B.nw * B.ld * B.ld / 2;   // complex pairs of doubles per block
+    hipError_t e = launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(Q.cr), n, B.s);
+    if (e != hipSuccess) return e;
+    return launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(Q.ci), n, B.s);
+}
+
 template <typename T>
 int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const double* aw, int lda) {
     rpa_ctx* c = B.c;
     const int NGp = Q.qp.NGp;
+    // the first update of an accumulator: variants 4 and 5 store instead of adding (their tiles cover the
+    // whole lower triangle, padding included, which is all the E_c stage and the chi0 output read); the
+    // others add into a zero-filled accumulator
+    const bool store_first = Q.fresh && sizeof(T) == 4 && Q.variant >= 4;
+    if (Q.fresh && !store_first) HIP_TRY(zero_accumulator(B, Q));
+    Q.fresh = false;
     if constexpr (sizeof(T) == 8) {
         ProfScope ps_(c, S_HERK, B.s);
         HerkArgs h{};
@@ -938,6 +953,7 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
                 const int nR = NGp / kTile;
                 h.ntiles = 0;
                 for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
+                h.overwrite = store_first;
                 HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
             } else {
                 const int nT = NGq / 128;
@@ -970,9 +986,9 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
 template <typename T>
 int enqueue_chi0(Batch& B) {
     rpa_ctx* c = B.c;
-    // every accumulator of the batch (real and imaginary blocks, padding included)
-    HIP_TRY(launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(B.qj[0].cr),
-                                     B.qj.size() * (size_t)B.nw * B.ld * B.ld, B.s));
+    // every accumulator starts fresh: its first update stores or zero-fills it (one with no update at all
+    // is zero-filled at the end)
+    for (auto& Q : B.qj) Q.fresh = true;
     for (size_t ik = 0; ik < B.ks.size(); ++ik) {
         KSet& K = B.ks[ik];
         const int P = (int)K.pn.size();
@@ -1011,6 +1027,8 @@ int enqueue_chi0(Batch& B) {
             }
         }
     }
+    for (auto& Q : B.qj)
+        if (Q.fresh) HIP_TRY(zero_accumulator(B, Q));
     return RPA_OK;
 }
 
