@@ -1058,13 +1058,16 @@ int ensure_lookahead(rpa_ctx* c) {
 //                with K = 128, and a'_p: block columns j+1 and j+2 with K = 128, after b_{p-1}
 //                (which covers them), on the main stream.
 // b_p covers none of the block columns the next pair's panels need before a'_p has run, so the b's
-// run back to back on la_stream while the main stream factors the next pair. Every look-ahead update
+// run back to back on la_stream while the main stream factors the next pair; b_p starts after a'_p's
+// diagonal tile, so that this tile is not queued behind the whole update. Every look-ahead update
 // (a_j, a'_p) runs the diagonal tile of its first block column on the main stream, where the next
-// panel reads it, and the rest on la2_stream beside that panel; the next solve waits for the rest.
-// Ordering of the pairs of updates that touch the same tiles: b_{p-1} before a'_p (main stream wait);
-// a'_p's rest before a_{j+1} (la2_stream order and the main stream's wait before solve j+1); a_j's and
-// a'_p's rests before the solve that follows them. A pair buffer is overwritten by the solves of pair
-// p+2, after the main stream has waited for b_p (at a'_{p+1}) and for the rests on la2_stream.
+// panel reads it, and the rest on la2_stream beside that panel: first the rows below that tile, which
+// the next solve waits for, then (a'_p) the second block column, which the next look-ahead's diagonal
+// tile waits for. Ordering of the updates that touch the same tiles: b_{p-1} before a'_p (main stream
+// wait); a'_p's second block column before a_{j+1} (the main stream's wait before a_{j+1}'s diagonal
+// tile, and la2_stream order for its rest); every rest before the solve that reads its block column.
+// A pair buffer is overwritten by the solves of pair p+2, after the main stream has waited for b_p
+// (at a'_{p+1}) and for the rests on la2_stream.
 int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
     rpa_ctx* c = B.c;
     const int nw = B.nw, ld = B.ld;
