@@ -280,24 +280,20 @@ def integrand(chi, vsqrt):
 integrand_eigen = integrand
 
 
-def logdet_one_minus(K, block=64):
-    """ln det(1 - K) for Hermitian K with 1 - K positive definite, by a blocked Cholesky
-    factorisation of 1 + A, A = -K, that never forms the identity: each pivot is
-    1 + A_jj and contributes log1p(A_jj) to the log-determinant."""
+def logdet_one_minus(K):
+    """ln det(1 - K) for Hermitian K with 1 - K positive definite, by the textbook (unblocked,
+    right-looking) Cholesky factorisation of 1 + A, A = -K, that never forms the identity: each pivot
+    is 1 + A_jj and contributes log1p(A_jj) to the log-determinant."""
     A = -np.array(K, dtype=np.complex128, copy=True)
     n = A.shape[0]
     total = 0.0
-    for j0 in range(0, n, block):
-        j1 = min(n, j0 + block)
-        for j in range(j0, j1):
-            d = float(np.real(A[j, j]))
-            if not 1.0 + d > 0.0:
-                raise np.linalg.LinAlgError(f"pivot {j} not positive")
-            total += np.log1p(d)
-            A[j + 1:, j] /= np.sqrt(1.0 + d)
-            A[j + 1:, j + 1:j1] -= np.outer(A[j + 1:, j], np.conj(A[j + 1:j1, j]))
-        L = A[j1:, j0:j1]
-        A[j1:, j1:] -= L @ np.conj(L.T)
+    for j in range(n):
+        d = float(np.real(A[j, j]))
+        if not 1.0 + d > 0.0:
+            raise np.linalg.LinAlgError(f"pivot {j} not positive")
+        total += np.log1p(d)
+        col = A[j + 1:, j] / np.sqrt(1.0 + d)
+        A[j + 1:, j + 1:] -= np.outer(col, np.conj(col))
     return total
 
 

@@ -10,6 +10,7 @@ import scipy.fft as sfft
 
 import oracle
 import oracle.rpa as R
+import test_oracle_optical as optical_pins
 import test_oracle_pins as pins
 
 
@@ -95,6 +96,29 @@ def _chi0_missing_conj(rho, a, group=None):
     return np.stack([(rho.T * a[:, w][None, :]) @ rho for w in range(nw)])
 
 
+def _head_variant(paw_sign=-1.0, conj=False, flip_denominator=False, transpose_d=False):
+    def head(C_k, miller_k, kpt, A, P_k, Dtab, offsets, eps, pairs, qhat):
+        n_idx, m_idx = pairs
+        pseudo = R.momentum_pw(C_k, miller_k, kpt, A, pairs, qhat)
+        Dq = np.tensordot(np.asarray(qhat, dtype=np.float64), Dtab, axes=(0, 0))
+        paw = np.zeros(n_idx.size, dtype=np.complex128)
+        qoff = 0
+        for a in range(len(offsets) - 1):
+            lo, hi = offsets[a], offsets[a + 1]
+            npj = hi - lo
+            Da = Dq[qoff:qoff + npj * npj].reshape(npj, npj)
+            qoff += npj * npj
+            if transpose_d:
+                Da = Da.T
+            paw += np.einsum("pi,ij,pj->p", np.conj(P_k[n_idx][:, lo:hi]), Da, P_k[m_idx][:, lo:hi])
+        de = np.asarray(eps)[m_idx] - np.asarray(eps)[n_idx]
+        if flip_denominator:
+            de = -de
+        out = (pseudo + paw_sign * 1j * paw) / de
+        return np.conj(out) if conj else out
+    return head
+
+
 def _gsphere_strict(A, q, ecut):
     return ORIG_GSPHERE(A, q, ecut * 0.97)
 
@@ -112,10 +136,23 @@ CASES = [
     ("orbitals", _orbitals_conjugated, pins.test_orbitals_equal_direct_plane_wave_sum),
     ("chi0_grouped", _chi0_missing_conj, pins.test_chi0_hermitian_negative_semidefinite_and_gauge_invariant),
     ("gsphere", _gsphere_strict, pins.test_gsphere_matches_python_enumeration),
+    ("optical_head", _head_variant(conj=True), optical_pins.test_pseudo_head_is_the_kp_limit_of_the_pair_density),
+    ("optical_head", _head_variant(flip_denominator=True),
+     optical_pins.test_pseudo_head_is_the_kp_limit_of_the_pair_density),
+    ("optical_head", _head_variant(paw_sign=+1.0), optical_pins.test_paw_head_equals_the_all_electron_head),
+    ("optical_head", _head_variant(transpose_d=True), optical_pins.test_paw_head_equals_the_all_electron_head),
 ]
 
 
-@pytest.mark.parametrize("name,bad,pin", CASES, ids=[f"{c[0]}:{c[1].__name__}" for c in CASES])
+def test_unmutated_head_variant_passes_both_head_pins(monkeypatch):
+    """The reference form of the mutated head (every switch off) passes, so the cases above fail only
+    through their planted mistake."""
+    _patch(monkeypatch, "optical_head", _head_variant())
+    optical_pins.test_pseudo_head_is_the_kp_limit_of_the_pair_density()
+    optical_pins.test_paw_head_equals_the_all_electron_head()
+
+
+@pytest.mark.parametrize("name,bad,pin", CASES, ids=[f"{c[0]}:{i}" for i, c in enumerate(CASES)])
 def test_planted_mistake_is_caught(monkeypatch, name, bad, pin):
     _patch(monkeypatch, name, bad)
     with pytest.raises(AssertionError):
