@@ -71,8 +71,7 @@ def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False, use_graph=
     return (t1 - t0), ecs, prof
 
 
-HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 2: ("k_herk_split2", "k_herk_split2.hip"),
-                3: ("k_herk_split3", "k_herk_split2.hip"), 4: ("k_herk_split4", "k_herk_split2.hip"),
+HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 4: ("k_herk_split4", "k_herk_split2.hip"),
                 5: ("k_herk_split5", "k_herk_split2.hip")}
 
 
@@ -140,7 +139,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--variant", type=int, default=0,
-                    help="force the split rank-k kernel variant (1, 2, 3); 0 keeps the library's choice")
+                    help="force the split rank-k kernel variant (1, 4, 5); 0 keeps the library's choice")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-q loop and adjoint timings")
     ap.add_argument("--cpu-sample-occ", type=int, default=8,

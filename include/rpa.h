@@ -64,8 +64,10 @@ typedef struct {
 
 /* One state set at k (or at k+q) - Eq. get_wfs and Eq. n_G_2.
  *  C        DEVICE complex128 [nbands][nQ]: plane-wave coefficients C_n(Q) of the
- *           periodic part; psi~_n(r) = e^{ik.r} sum_Q C_n(Q) e^{i G_Q.r}. Rows are
- *           expected orthonormal (sum_Q C_n^* C_m = delta_nm); no 1/sqrt(Omega).
+ *           periodic part; psi~_n(r) = e^{ik.r} sum_Q C_n(Q) e^{i G_Q.r}, no
+ *           1/sqrt(Omega). The states are expected orthonormal in the PAW sense
+ *           (Sec. 2.2: sum_Q C_n^* C_m + sum_a sum_ij conj(P_ni) S^a_ij P_mj =
+ *           delta_nm with S^a_ij = Q^a_ij(0)); the library does not check it.
  *  miller   HOST int32 [nQ][3]: Miller index of each Q; every |m_i| < n[i]/2.
  *  eps      HOST [nbands]: Kohn-Sham eigenvalues (Ha), ascending.
  *  f        HOST [nbands]: occupations in [0, 2] (spin included), non-increasing.
@@ -204,21 +206,15 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
  * (NG rounded up to 64):
  *   1 = 64x64 tiles staged from FP32 rho, FP32 partial sums added into FP64
  *       every 8 K-steps;
- *   2 = 128x128 tiles from the K-blocked pre-split rho, FP32 accumulation over
- *       the whole pair chunk;
- *   3 = variant 2 with a double-buffered, software-pipelined K loop
- *       (bit-identical to 2);
- *   4 = pipelined 64x128 tiles from the pre-split rho, FP32 partial sums added
- *       into FP64 every 8 K-steps;
+ *   4 = pipelined 64x128 tiles from the K-blocked pre-split rho, FP32 partial
+ *       sums added into FP64 every 8 K-steps;
  *   5 = variant 4 with eight waves per workgroup, two per SIMD (bit-identical
  *       to 4).
- * Variants 2 and 3 keep the whole sum over a chunk (up to all pairs of a
- * q-point) in FP32, whose rounding reaches ~1e-6 of E_c at 12,800 pairs; 1, 4
- * and 5 stay near 1e-8. Without an entry, NG >= 385 uses variant 5, smaller
- * spheres variant 1.
- *  rpa_autotune     times variants 1, 4 and 5 on synthetic operands of the given
+ * Without an entry, NG >= 385 uses variant 5, smaller spheres variant 1.
+ *  rpa_autotune     times the variants on synthetic operands of the given
  *                   shape on `stream` (synchronizes) and records the fastest.
- *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only).
+ *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only;
+ *                   RPA_ERR_INPUT for another variant).
  *  rpa_tune_cache_io saves (save = 1) or loads a text table at `path`. */
 int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, void* stream);
 
@@ -230,6 +226,14 @@ int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, v
  * z through LDS); path 1 always runs the LDS radix passes. Both give the same
  * result up to rounding order. RPA_ERR_INPUT for another value. */
 int rpa_set_pair_path(rpa_ctx* ctx, int path);
+
+/* Upper bound on the pairs of one chunk (the K of one grouped rank-k update,
+ * Eq. zher_multi's group). 0 (default): the chunk is as large as the workspace
+ * budget allows (up to 6 GiB of per-chunk buffers, a quarter of the cap when
+ * one is set). A smaller bound lowers the per-chunk memory and splits a
+ * q-point's sum into more updates; chi0 is the same up to rounding order.
+ * RPA_ERR_INPUT if max_pairs < 0. */
+int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs);
 int rpa_tune_set(rpa_ctx* ctx, rpa_precision prec, int NG, int variant);
 int rpa_tune_get(rpa_ctx* ctx, rpa_precision prec, int NG, int* variant);
 int rpa_tune_cache_io(rpa_ctx* ctx, const char* path, int save);

@@ -388,5 +388,7 @@ def ec_q(A, grid, ksets, kqsets, gmiller, Qtab, offsets, q, omega, omega_weight,
 
 def two_level_ec(delta, b):
     """Closed form of int_0^inf dw/2pi [ln(1 + c) - c], c = b delta/(w^2 + delta^2):
-    (1/2)[sqrt(delta^2 + b delta) - delta - b/2]."""
-    return 0.5 * (np.sqrt(delta * delta + b * delta) - delta - 0.5 * b)
+    (1/2)[sqrt(delta^2 + b delta) - delta - b/2], written without the cancellation of its three terms
+    at small b/delta: with x = b/delta, sqrt(1+x) - 1 - x/2 = -(x^2/4)/(sqrt(1+x) + 1 + x/2)."""
+    x = b / delta
+    return -0.125 * delta * x * x / (np.sqrt(1.0 + x) + 1.0 + 0.5 * x)

@@ -314,6 +314,10 @@ class Context:
         """0: register-resident pair transforms where the grid allows, 1: LDS radix passes."""
         _check(self._L.rpa_set_pair_path(self._h, int(path)), self._h)
 
+    def set_chunk_pairs(self, max_pairs: int):
+        """Upper bound on the pairs of one grouped rank-k update (0: set by the workspace budget)."""
+        _check(self._L.rpa_set_chunk_pairs(self._h, int(max_pairs)), self._h)
+
     def tune_set(self, NG: int, variant: int, precision="split_bf16"):
         _check(self._L.rpa_tune_set(self._h, _prec(precision), int(NG), int(variant)), self._h)
 

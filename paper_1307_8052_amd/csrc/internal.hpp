@@ -131,7 +131,6 @@ struct HerkSplit2Args {
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
                              int fp16, float* Xre, float* Xim, unsigned short* const B[4], hipStream_t s);
 // pipelined = 1: double-buffered, branch-free K loop (same operands and result)
-hipError_t launch_herk_split2(const HerkSplit2Args& h, int pipelined, hipStream_t s);
 // 64 x 128 tiles (ntiles = sum over 64-row blocks I of I/2 + 1), FP32 partial sums
 // added into FP64 every 8 K-steps; four waves of 64 x 32, or eight of 32 x 32
 hipError_t launch_herk_split4(const HerkSplit2Args& h, int eight_waves, hipStream_t s);

@@ -5,12 +5,11 @@
 // [K/32][NGq][32] with the 32 pairs of a block contiguous per G:
 //   X  FP32 (re, im), the operand that each frequency scales by a(w);
 //   B  16-bit hi/lo (re_hi, re_lo, im_hi, im_lo) of rho, split once.
-// k_herk_split2 then computes one 128x128 lower tile of chi0(w) per
-// workgroup (four waves, 64x64 each as 4x4 blocks of 16x16): every K-step it
-// loads 32 pairs of X, multiplies by a(w), splits into hi/lo in registers and
-// stages both operands in LDS, and issues 12 v_mfma_f32_16x16x32 per block
-// (Re = Xr Br^T + Xi Bi^T, Im = Xi Br^T - Xr Bi^T, three split products each).
-// The next K-step's global loads are in flight while the MFMAs run.
+// k_herk_split4 / k_herk_split5 then compute one 64x128 lower tile of chi0(w)
+// per workgroup: every K-step they load 32 pairs of X, multiply by a(w), split
+// into hi/lo in registers and stage both operands in LDS, and issue 12
+// v_mfma_f32_16x16x32 per 16x16 block (Re = Xr Br^T + Xi Bi^T,
+// Im = Xi Br^T - Xr Bi^T, three split products each).
 //
 // Workgroups are numbered so that the nw frequencies of one tile go to the
 // same XCD (consecutive workgroup ids are dealt round-robin to the 8 XCDs),
@@ -121,352 +120,21 @@ __global__ __launch_bounds__(256) void k_pack_split(const float* __restrict__ rr
     *reinterpret_cast<v8u16*>(B3 + o) = li;
 }
 
-__device__ __forceinline__ void tile_of(int t, int& I, int& J) {
-    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = t - i * (i + 1) / 2;
-}
-
-template <bool F16>
-__global__ __launch_bounds__(256, 1) void k_herk_split2(HerkSplit2Args h) {
-    typedef typename H<F16>::v8 hv;
-    __shared__ __align__(16) u16 sA[4][TM][LDR];
-    __shared__ __align__(16) u16 sB[4][TM][LDR];
-
-    // XCD-aware numbering: ids b, b+8, b+16, ... run on one XCD
-    const int b = blockIdx.x;
-    const int xcd = b % kXcds, local = b / kXcds;
-    const int tile = (local / h.nw) * kXcds + xcd;
-    const int w = local % h.nw;
-    if (tile >= h.ntiles) return;
-    int I, J;
-    tile_of(tile, I, J);
-    const int ci = I * TM, cj = J * TM;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    const double* aw = h.w + (size_t)w * h.lda;
-    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
-    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
-
-    // staging assignment: thread -> (row r, 16 consecutive pairs)
-    const int sr = tid >> 1, sk = (tid & 1) * 16;
-    float pxr[16], pxi[16];
-    v8u16 pb[4][2];
-    auto fetch = [&](int kb) {
-        const size_t oa = ((size_t)kb * h.NGq + ci + sr) * KS + sk;
-        const size_t ob = ((size_t)kb * h.NGq + cj + sr) * KS + sk;
-#pragma unroll
-        for (int e = 0; e < 16; e += 4) {
-            const v4f a = *reinterpret_cast<const v4f*>(h.Xre + oa + e);
-            const v4f c = *reinterpret_cast<const v4f*>(h.Xim + oa + e);
-            pxr[e] = a[0]; pxr[e + 1] = a[1]; pxr[e + 2] = a[2]; pxr[e + 3] = a[3];
-            pxi[e] = c[0]; pxi[e + 1] = c[1]; pxi[e + 2] = c[2]; pxi[e + 3] = c[3];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            pb[q][0] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
-            pb[q][1] = *reinterpret_cast<const v8u16*>(h.B[q] + ob + 8);
-        }
-    };
-
-    v4f accR[4][4], accI[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            accR[x][y] = v4f{0, 0, 0, 0};
-            accI[x][y] = v4f{0, 0, 0, 0};
-        }
-
-    const int nkb = (h.K + KS - 1) / KS;
-    fetch(0);
-    for (int kb = 0; kb < nkb; ++kb) {
-        __syncthreads();
-        {
-            // X_w = rho a(w) sa, split into hi/lo
-            v8u16 xrh[2], xrl[2], xih[2], xil[2];
-            const int kbase = kb * KS + sk;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int k = kbase + e;
-                const float wk = k < h.K ? (float)aw[k] * sa : 0.f;
-                u16 a, c;
-                split<F16>(pxr[e] * wk, a, c);
-                xrh[e >> 3][e & 7] = a;
-                xrl[e >> 3][e & 7] = c;
-                split<F16>(pxi[e] * wk, a, c);
-                xih[e >> 3][e & 7] = a;
-                xil[e >> 3][e & 7] = c;
-            }
-#pragma unroll
-            for (int hf = 0; hf < 2; ++hf) {
-                *reinterpret_cast<v8u16*>(&sA[0][sr][sk + 8 * hf]) = xrh[hf];
-                *reinterpret_cast<v8u16*>(&sA[1][sr][sk + 8 * hf]) = xrl[hf];
-                *reinterpret_cast<v8u16*>(&sA[2][sr][sk + 8 * hf]) = xih[hf];
-                *reinterpret_cast<v8u16*>(&sA[3][sr][sk + 8 * hf]) = xil[hf];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[q][sr][sk + 8 * hf]) = pb[q][hf];
-            }
-        }
-        __syncthreads();
-        if (kb + 1 < nkb) fetch(kb + 1);
-
-        const int rr = lane & 15, kq = 8 * (lane >> 4);
-        hv bf[4][4], bn[4][2];  // [col block][re_hi, re_lo, im_hi, im_lo], -im
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bf[y][q] = *reinterpret_cast<const hv*>(&sB[q][wc + 16 * y + rr][kq]);
-            bn[y][0] = neg8(bf[y][2]);
-            bn[y][1] = neg8(bf[y][3]);
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            hv af[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) af[q] = *reinterpret_cast<const hv*>(&sA[q][wr + 16 * x + rr][kq]);
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                v4f r = accR[x][y], im = accI[x][y];
-                // small terms first, then the hi*hi products
-                r = H<F16>::mfma(af[1], bf[y][0], r);
-                r = H<F16>::mfma(af[0], bf[y][1], r);
-                r = H<F16>::mfma(af[3], bf[y][2], r);
-                r = H<F16>::mfma(af[2], bf[y][3], r);
-                r = H<F16>::mfma(af[0], bf[y][0], r);
-                r = H<F16>::mfma(af[2], bf[y][2], r);
-                im = H<F16>::mfma(af[3], bf[y][0], im);
-                im = H<F16>::mfma(af[2], bf[y][1], im);
-                im = H<F16>::mfma(af[1], bn[y][0], im);
-                im = H<F16>::mfma(af[0], bn[y][1], im);
-                im = H<F16>::mfma(af[2], bf[y][0], im);
-                im = H<F16>::mfma(af[0], bn[y][0], im);
-                accR[x][y] = r;
-                accI[x][y] = im;
-            }
-        }
-    }
-
-    const double inv = 1.0 / ((double)sa * (double)sb);
-    double* Cre = h.Cre + (size_t)w * h.sC;
-    double* Cim = h.Cim + (size_t)w * h.sC;
-    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
-    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        double cre[4][4], cim[4][4];
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
-                cre[y][r] = Cre[o];
-                cim[y][r] = Cim[o];
-            }
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                if (row < h.ldC && col < h.ldC) {
-                    const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] = cre[y][r] + (double)accR[x][y][r] * inv;
-                    Cim[o] = cim[y][r] + (double)accI[x][y][r] * inv;
-                }
-            }
-    }
-}
-
-// Variant 3: the same operands and products as k_herk_split2, software
-// pipelined. LDS holds two K-steps (double buffer, 128 KB with an XOR swizzle
-// of the 16-byte chunks of a row instead of padding), so one barrier per
-// K-step separates writing step k+1 from reading step k. The loop body has no
-// branches: the split of step k+1 (VALU and LDS writes) and the global loads of
-// step k+2 sit in the same block as the MFMAs of step k, and the weights a(w)
-// are prefetched with the operands.
-__device__ __forceinline__ int swz(int row, int chunk) { return 8 * (chunk ^ ((row >> 1) & 3)); }
-
-template <bool F16>
-__global__ __launch_bounds__(256, 1) void k_herk_split3(HerkSplit2Args h) {
-    typedef typename H<F16>::v8 hv;
-    __shared__ __align__(16) u16 sA[2][4][TM][KS];
-    __shared__ __align__(16) u16 sB[2][4][TM][KS];
-
-    const int b = blockIdx.x;
-    const int xcd = b % kXcds, local = b / kXcds;
-    const int tile = (local / h.nw) * kXcds + xcd;
-    const int w = local % h.nw;
-    if (tile >= h.ntiles) return;
-    int I, J;
-    tile_of(tile, I, J);
-    const int ci = I * TM, cj = J * TM;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    const double* aw = h.w + (size_t)w * h.lda;
-    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
-    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
-    const int K = h.K;
-
-    // staging: thread -> (row sr, pairs sk .. sk+15)
-    const int sr = tid >> 1, sk = (tid & 1) * 16;
-    float pxr[16], pxi[16];
-    double pw[16];
-    v8u16 pb[4][2];
-    const int nkb = (K + KS - 1) / KS;
-    auto fetch = [&](int kb) {
-        const size_t oa = ((size_t)kb * h.NGq + ci + sr) * KS + sk;
-        const size_t ob = ((size_t)kb * h.NGq + cj + sr) * KS + sk;
-#pragma unroll
-        for (int e = 0; e < 16; e += 4) {
-            const v4f a = *reinterpret_cast<const v4f*>(h.Xre + oa + e);
-            const v4f c = *reinterpret_cast<const v4f*>(h.Xim + oa + e);
-            pxr[e] = a[0]; pxr[e + 1] = a[1]; pxr[e + 2] = a[2]; pxr[e + 3] = a[3];
-            pxi[e] = c[0]; pxi[e + 1] = c[1]; pxi[e + 2] = c[2]; pxi[e + 3] = c[3];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            pb[q][0] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
-            pb[q][1] = *reinterpret_cast<const v8u16*>(h.B[q] + ob + 8);
-        }
-        const int k0 = kb * KS + sk;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) pw[e] = aw[min(k0 + e, K - 1)];
-    };
-    // X_w = rho a(w) sa split into hi/lo, and the pre-split rho, into buffer `buf`
-    auto store = [&](int kb, int buf) {
-        const int k0 = kb * KS + sk;
-        v8u16 xrh[2], xrl[2], xih[2], xil[2];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float wk = (k0 + e < K) ? (float)pw[e] * sa : 0.f;
-            u16 a, c;
-            split<F16>(pxr[e] * wk, a, c);
-            xrh[e >> 3][e & 7] = a;
-            xrl[e >> 3][e & 7] = c;
-            split<F16>(pxi[e] * wk, a, c);
-            xih[e >> 3][e & 7] = a;
-            xil[e >> 3][e & 7] = c;
-        }
-#pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
-            const int o = swz(sr, (sk >> 3) + hf);
-            *reinterpret_cast<v8u16*>(&sA[buf][0][sr][o]) = xrh[hf];
-            *reinterpret_cast<v8u16*>(&sA[buf][1][sr][o]) = xrl[hf];
-            *reinterpret_cast<v8u16*>(&sA[buf][2][sr][o]) = xih[hf];
-            *reinterpret_cast<v8u16*>(&sA[buf][3][sr][o]) = xil[hf];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[buf][q][sr][o]) = pb[q][hf];
-        }
-    };
-
-    v4f accR[4][4], accI[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            accR[x][y] = v4f{0, 0, 0, 0};
-            accI[x][y] = v4f{0, 0, 0, 0};
-        }
-
-    fetch(0);
-    store(0, 0);
-    fetch(min(1, nkb - 1));
-    const int rr = lane & 15, kc = lane >> 4;
-    for (int kb = 0; kb < nkb; ++kb) {
-        __syncthreads();
-        const int cur = kb & 1;
-        hv bf[4][4], bn[4][2];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int row = wc + 16 * y + rr;
-            const int o = swz(row, kc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bf[y][q] = *reinterpret_cast<const hv*>(&sB[cur][q][row][o]);
-            bn[y][0] = neg8(bf[y][2]);
-            bn[y][1] = neg8(bf[y][3]);
-        }
-        hv af[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int row = wr + 16 * x + rr;
-            const int o = swz(row, kc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) af[x][q] = *reinterpret_cast<const hv*>(&sA[cur][q][row][o]);
-        }
-        // next K-step into the other buffer (the last iteration writes an unused buffer), then the
-        // global loads of the one after (clamped to the last block)
-        store(kb + 1, cur ^ 1);
-        fetch(min(kb + 2, nkb - 1));
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                v4f r = accR[x][y], im = accI[x][y];
-                r = H<F16>::mfma(af[x][1], bf[y][0], r);
-                r = H<F16>::mfma(af[x][0], bf[y][1], r);
-                r = H<F16>::mfma(af[x][3], bf[y][2], r);
-                r = H<F16>::mfma(af[x][2], bf[y][3], r);
-                r = H<F16>::mfma(af[x][0], bf[y][0], r);
-                r = H<F16>::mfma(af[x][2], bf[y][2], r);
-                im = H<F16>::mfma(af[x][3], bf[y][0], im);
-                im = H<F16>::mfma(af[x][2], bf[y][1], im);
-                im = H<F16>::mfma(af[x][1], bn[y][0], im);
-                im = H<F16>::mfma(af[x][0], bn[y][1], im);
-                im = H<F16>::mfma(af[x][2], bf[y][0], im);
-                im = H<F16>::mfma(af[x][0], bn[y][0], im);
-                accR[x][y] = r;
-                accI[x][y] = im;
-            }
-    }
-
-    const double inv = 1.0 / ((double)sa * (double)sb);
-    double* Cre = h.Cre + (size_t)w * h.sC;
-    double* Cim = h.Cim + (size_t)w * h.sC;
-    // C += acc, one row block x at a time: all loads of the block are issued before its stores (which
-    // could alias them as far as the compiler knows); rows and columns past ldC read a valid address
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        double cre[4][4], cim[4][4];
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
-                cre[y][r] = Cre[o];
-                cim[y][r] = Cim[o];
-            }
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                if (row < h.ldC && col < h.ldC) {
-                    const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] = cre[y][r] + (double)accR[x][y][r] * inv;
-                    Cim[o] = cim[y][r] + (double)accI[x][y][r] * inv;
-                }
-            }
-    }
-}
-
-// Variant 4: the pipeline of variant 3 with FP64 accumulation. A workgroup
-// computes a 64-row x 128-column tile (each wave all 64 rows x 32 columns); the
-// MFMAs accumulate in FP32 for 8 K-steps (256 pairs), then the partial sums are
-// added into FP64 registers, which bounds the FP32 rounding of the long sum
-// over pairs. The 64-row side is the one scaled by a(w) and split in the kernel,
-// so the split work per MFMA is the same as in variant 3. Row block I of the
+// Variant 4: a software-pipelined K loop with FP64 accumulation. LDS holds two
+// K-steps (double buffer with an XOR swizzle of the 16-byte chunks of a row
+// instead of padding), so one barrier per K-step separates writing step k+1
+// from reading step k, and the global loads of step k+1 are in flight while
+// the MFMAs of step k run. A workgroup computes a 64-row x 128-column tile
+// (each wave all 64 rows x 32 columns); the MFMAs accumulate in FP32 for 8
+// K-steps (256 pairs), then the partial sums are added into FP64 registers,
+// which bounds the FP32 rounding of the long sum over pairs. The 64-row side
+// is the one scaled by a(w) and split in the kernel. Row block I of the
 // lower triangle holds column blocks 0 .. I/2.
 constexpr int kFlush4 = 8;
+
+// LDS offset (in 16-bit elements) of 16-byte chunk `chunk` of row `row`: an XOR swizzle of the chunks of
+// a row so that the fragment reads of a K-step spread over the banks without padding
+__device__ __forceinline__ int swz(int row, int chunk) { return 8 * (chunk ^ ((row >> 1) & 3)); }
 
 template <bool F16>
 __global__ __launch_bounds__(256, 1) void k_herk_split4(HerkSplit2Args h) {
@@ -882,24 +550,6 @@ hipError_t launch_herk_split4(const HerkSplit2Args& h, int eight_waves, hipStrea
             hipLaunchKernelGGL(k_herk_split4<true>, dim3(blocks), dim3(256), 0, s, h);
         else
             hipLaunchKernelGGL(k_herk_split4<false>, dim3(blocks), dim3(256), 0, s, h);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_herk_split2(const HerkSplit2Args& h, int pipelined, hipStream_t s) {
-    if (h.ntiles <= 0 || h.nw <= 0 || h.K <= 0) return hipSuccess;
-    const int per_xcd = (h.ntiles + kXcds - 1) / kXcds;
-    const unsigned blocks = (unsigned)(per_xcd * h.nw * kXcds);
-    if (pipelined) {
-        if (h.fp16)
-            hipLaunchKernelGGL(k_herk_split3<true>, dim3(blocks), dim3(256), 0, s, h);
-        else
-            hipLaunchKernelGGL(k_herk_split3<false>, dim3(blocks), dim3(256), 0, s, h);
-    } else {
-        if (h.fp16)
-            hipLaunchKernelGGL(k_herk_split2<true>, dim3(blocks), dim3(256), 0, s, h);
-        else
-            hipLaunchKernelGGL(k_herk_split2<false>, dim3(blocks), dim3(256), 0, s, h);
     }
     return hipGetLastError();
 }

@@ -318,10 +318,12 @@ __global__ void k_negk(double* __restrict__ Cre, double* __restrict__ Cim, int l
     double* rr = Cre + (size_t)w * sC + (size_t)i * ldC;
     double* ri = Cim + (size_t)w * sC + (size_t)i * ldC;
     const double vi = i < NG ? vsqrt[i] : 0.0;
+    // the padding is assigned, not scaled: whatever it held (NaN included) must not reach the factorisation
     for (int j = threadIdx.x; j <= i; j += blockDim.x) {
-        const double s = (i < NG && j < NG) ? -vi * vsqrt[j] : 0.0;
-        rr[j] = rr[j] * s;
-        ri[j] = ri[j] * s;
+        const bool in = i < NG && j < NG;
+        const double s = in ? -vi * vsqrt[j] : 0.0;
+        rr[j] = in ? rr[j] * s : 0.0;
+        ri[j] = in ? ri[j] * s : 0.0;
     }
 }
 

@@ -70,8 +70,8 @@ struct rpa_ctx {
     double prof_ms[16] = {0};
     long long prof_n[16] = {0};
     int last_nq = 0;
-    // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 2 = 128x128 tiles,
-    // 3 = 128x128 tiles software pipelined, 4 / 5 = pipelined 64x128 tiles with FP64 accumulation
+    // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 4 / 5 = pipelined 64x128 tiles
+    // with FP64 accumulation
     // (4: four waves, 5: eight waves per workgroup)
     std::map<uint64_t, int> tune;
     std::map<uint64_t, double> tune_ms;
@@ -81,6 +81,7 @@ struct rpa_ctx {
     uint64_t graph_key = 0;
     bool capturing = false;
     bool pair_reg = true;   // register-resident pair transforms where supported
+    int max_chunk = 0;      // upper bound on the pairs of one chunk (0: set by the workspace budget alone)
     // non-blocking stream the batch sequence is captured on (the legacy default stream cannot be)
     hipStream_t cap_stream = nullptr;
     // look-ahead of the blocked Cholesky: the trailing update of each step runs on
@@ -518,7 +519,7 @@ struct QJob {
     std::vector<void*> d_wq;
     std::vector<double> Dq;
     void* d_Dq = nullptr;
-    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64, 2 / 3 split 128x128 (3 pipelined), 4 split 64x128 pipelined
+    int variant = 0;   // 0 FP64 MFMA, 1 split 64x64, 4 / 5 split 64x128 pipelined (four / eight waves)
     int Pc = 0;        // pair chunk
     double* cr = nullptr;
     double* ci = nullptr;
@@ -564,6 +565,7 @@ int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
     size_t pc = budget / per;
     pc = std::max<size_t>(pc, 64);
     pc = std::min<size_t>(pc, 1 << 20);
+    if (c->max_chunk > 0) pc = std::min<size_t>(pc, (size_t)c->max_chunk);
     return (int)pc;
 }
 
@@ -948,18 +950,12 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.nw = B.nw;
             h.fp16 = fp16;
             h.scales = scales;
-            if (Q.variant >= 4) {
-                // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
-                const int nR = NGp / kTile;
-                h.ntiles = 0;
-                for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
-                h.overwrite = store_first;
-                HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
-            } else {
-                const int nT = NGq / 128;
-                h.ntiles = nT * (nT + 1) / 2;
-                HIP_TRY(launch_herk_split2(h, Q.variant == 3, B.s));
-            }
+            // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
+            const int nR = NGp / kTile;
+            h.ntiles = 0;
+            for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
+            h.overwrite = store_first;
+            HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
         } else {
             HerkSplitArgs h{};
             h.Are = reinterpret_cast<const float*>(rre);
@@ -1686,6 +1682,13 @@ int rpa_create(rpa_ctx** out, const rpa_cell* cell, int device, size_t cap) {
         delete c;
         return fail(RPA_ERR_HIP, "hipEventCreate failed");
     }
+    // the Cholesky look-ahead streams, created once here
+    rc = ensure_lookahead(c);
+    if (rc) {
+        const std::string msg = g_err;
+        rpa_destroy(c);
+        return fail(rc, msg);
+    }
     *out = c;
     return RPA_OK;
 }
@@ -1973,12 +1976,20 @@ int rpa_set_pair_path(rpa_ctx* ctx, int path) {
     return RPA_OK;
 }
 
+int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs) {
+    if (!ctx) return fail(RPA_ERR_INPUT, "NULL context");
+    if (max_pairs < 0) return fail(RPA_ERR_INPUT, "chunk bound must be >= 0");
+    if (ctx->max_chunk != max_pairs) drop_graph(ctx);
+    ctx->max_chunk = max_pairs;
+    return RPA_OK;
+}
+
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
     if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
-    if (variant < 1 || variant > 5)
-        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 2 (128x128), 3 (128x128 pipelined), 4 "
-                                   "(64x128 pipelined, FP64 accumulation) and 5 (as 4, eight waves)");
+    if (variant != 1 && variant != 4 && variant != 5)
+        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 4 (64x128 pipelined, FP64 accumulation) and 5 "
+                                   "(as 4, eight waves)");
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     c->tune[tune_key(prec, NGp)] = variant;
     return RPA_OK;
@@ -2062,7 +2073,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (save) {
         FILE* f = std::fopen(path, "w");
         if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
-        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 2 = 128x128, 3 = pipelined 128x128, 4 / 5 = pipelined 64x128)\n");
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 4 / 5 = pipelined 64x128)\n");
         for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
         std::fclose(f);
         return RPA_OK;
@@ -2073,7 +2084,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int p, ng, v;
-        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && v >= 1 && v <= 5 && ng > 0)
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || v == 4 || v == 5) && ng > 0)
             c->tune[tune_key((rpa_precision)p, ng)] = v;
     }
     std::fclose(f);

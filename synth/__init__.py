@@ -16,9 +16,22 @@ Conventions
 * Miller triples m give G = m1 b1 + m2 b2 + m3 b3; on an N-point axis an index
   m maps to grid position m mod N.
 * Plane-wave coefficients C_n(Q) multiply e^{i (k+G_Q).r} with no 1/sqrt(Omega);
-  rows of C are orthonormal (sum_Q C_n(Q)^* C_m(Q) = delta_nm).
+  the states are orthonormal (under the PAW overlap in the default model,
+  plainly in the "independent" model; see below).
 * PAW projections are stored per band as one row over all atoms,
   ``P[n, off[a] + i]`` = <p~_i^a | psi~_n>.
+* Two projection models:
+  - "overlap" (default): the projections are a linear map of the
+    coefficients, P = C Pi, with Pi[Q, off_a + i] an atom-centred projector in
+    plane-wave space (smooth envelope times e^{i (k+Q).R_a}), and the states
+    are orthonormal under the PAW overlap
+    1 + sum_a Pi_a s^a Pi_a^H, i.e.
+    sum_Q C_n^* C_m + sum_a sum_ij conj(P_ni) s^a_ij P_mj = delta_nm.
+    This is what the all-electron normalisation of Sec. 2.2 asks of the pair
+    density at q = 0, G = 0, given Q^a_ij(0) = s^a_ij.
+  - "independent" (stress workload): C orthonormal on its own and P drawn
+    independently, Re and Im ~ N(0, 0.1). The full pair density at G -> 0 then
+    carries sum_a P^* s P for n != m, which the Coulomb head amplifies.
 * Q^a_ij(K) (the augmentation form factor of the PAW pair density) needs
   partial waves that are not available, so a separable Gaussian model stands
   in: Q^a_ij(K) = s^a_ij exp(-|K|^2 sigma^2 / 2) e^{-i K.R_a}, s^a real
@@ -32,6 +45,7 @@ import hashlib
 from typing import List, Optional, Sequence
 
 import numpy as np
+import scipy.linalg as scipy_linalg
 
 TWO_PI = 2.0 * np.pi
 
@@ -114,7 +128,7 @@ class StateSet:
     kpt: np.ndarray          # (3,) Cartesian, bohr^-1
     weight: float            # w_k (1/N_k)
     miller: np.ndarray       # int32 [NQ, 3]
-    C: np.ndarray            # complex128 [nb, NQ], orthonormal rows
+    C: np.ndarray            # complex128 [nb, NQ]; states orthonormal (see the module docstring)
     eps: np.ndarray          # float64 [nb], ascending
     f: np.ndarray            # float64 [nb], in [0, 2], non-increasing
     P: np.ndarray            # complex128 [nb, sum Np]
@@ -215,6 +229,62 @@ def fermi_levels(rng, n_below, n_above, T=0.01, mu=0.0):
     return eps, f
 
 
+def raw_coefficients(rng, A, kpt, miller, nb):
+    """Re, Im ~ N(0,1) x exp(-|k+Q|^2/8), not yet orthonormal; [nb, NQ]."""
+    B = reciprocal_rows(A)
+    kq = cart(miller, B, kpt)
+    env = np.exp(-(kq[:, 0] ** 2 + kq[:, 1] ** 2 + kq[:, 2] ** 2) / 8.0)
+    NQ = miller.shape[0]
+    if nb > NQ:
+        raise ValueError(f"{nb} bands need at least as many plane waves (have {NQ})")
+    return (rng.standard_normal((nb, NQ)) + 1j * rng.standard_normal((nb, NQ))) * env[None, :]
+
+
+def projector_map(rng, A, kpt, miller, paw, overlap_spread=0.5):
+    """Pi[Q, off_a + i] = beta z_Qi exp(-|k+Q|^2/8) e^{i (k+Q).R_a}, z_Qi complex N(0,1), each column
+    scaled to unit norm, then all columns by one beta chosen so that the eigenvalues of the overlap
+    1 + sum_a Pi_a s^a Pi_a^H lie in [1 - overlap_spread, 1 + overlap_spread]; [NQ, sum Np]."""
+    B = reciprocal_rows(A)
+    kq = cart(miller, B, kpt)
+    env = np.exp(-(kq[:, 0] ** 2 + kq[:, 1] ** 2 + kq[:, 2] ** 2) / 8.0)
+    NQ = miller.shape[0]
+    off = paw.offsets
+    tot = int(off[-1])
+    Z = rng.standard_normal((NQ, tot)) + 1j * rng.standard_normal((NQ, tot))
+    Pi = Z * env[:, None]
+    for a in range(len(paw.nproj)):
+        Pi[:, off[a]:off[a + 1]] *= np.exp(1j * (kq @ paw.R[a]))[:, None]
+    Pi /= np.linalg.norm(Pi, axis=0)[None, :]
+    # the nonzero eigenvalues of Pi S Pi^H (S = blockdiag s^a) are those of G^1/2 S G^1/2, G = Pi^H Pi
+    S = np.zeros((tot, tot))
+    for a, n in enumerate(paw.nproj):
+        S[off[a]:off[a + 1], off[a]:off[a + 1]] = paw.s[a]
+    G = Pi.conj().T @ Pi
+    w, V = np.linalg.eigh(G)
+    Gh = (V * np.sqrt(np.maximum(w, 0.0))[None, :]) @ V.conj().T
+    lam = np.linalg.eigvalsh(Gh @ S @ Gh)
+    beta = np.sqrt(overlap_spread / max(np.max(np.abs(lam)), 1e-300))
+    return np.ascontiguousarray(beta * Pi)
+
+
+def paw_orthonormal_states(C0, Pi, paw):
+    """Gram-Schmidt of the rows of C0 under the PAW overlap: returns (C, P) with P = C Pi and
+    sum_Q C_n^* C_m + sum_a sum_ij conj(P_ni) s^a_ij P_mj = delta_nm (positive diagonal of the
+    triangular factor, the generalised form of QR with diag(R) > 0)."""
+    P0 = C0 @ Pi
+    off = paw.offsets
+    G = C0.conj() @ C0.T
+    for a in range(len(paw.nproj)):
+        Pa = P0[:, off[a]:off[a + 1]]
+        G += Pa.conj() @ paw.s[a] @ Pa.T
+    G = 0.5 * (G + G.conj().T)
+    M = np.linalg.cholesky(G)                       # G = M M^H
+    Mc = np.conj(M)
+    C = scipy_linalg.solve_triangular(Mc, C0, lower=True)
+    P = scipy_linalg.solve_triangular(Mc, P0, lower=True)
+    return np.ascontiguousarray(C), np.ascontiguousarray(P)
+
+
 def draw_projections(rng, nb, nproj_total):
     """P with Re, Im ~ N(0, 0.1) each."""
     return 0.1 * rng.standard_normal((nb, nproj_total)) + 0.1j * rng.standard_normal((nb, nproj_total))
@@ -271,35 +341,68 @@ def paw_d_table(paw: Paw) -> np.ndarray:
 # configurations
 # ----------------------------------------------------------------------------
 def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
-              extra_kq=False, w0=1.0):
-    """Draw in the fixed order: C, eps_occ, eps_unocc, P, s^a, R_a, D^a (per k for the first four)."""
+              extra_kq=False, w0=1.0, paw_model="overlap"):
+    """Draw a workload from one seeded generator.
+
+    paw_model "overlap" draws, in this order: per k the raw coefficients and the levels; s^a, R_a,
+    D^a; per k the projector map Pi, then orthonormalises (C, P = C Pi) under the PAW overlap; then,
+    with extra_kq, per set the raw coefficients and levels of a distinct k+q set (same Pi).
+    paw_model "independent" draws C (orthonormal on its own), eps_occ, eps_unocc per k; then P per k;
+    then s^a, R_a, D^a; then the distinct k+q sets (C, levels, P).
+    """
     rng = np.random.default_rng(seed)
     A = np.asarray(A, dtype=np.float64)
     ecut_max = max(qp.ecut for qp in qpoints)
     ecut_wf = 4.0 * ecut_max
     nproj_total = int(sum(nproj))
     sets = []
-    pend = []
-    for ik, k in enumerate(kpts):
-        miller = wavefunction_sphere(A, k, ecut_wf)
-        nb = levels(None, dry=True)
-        C = orthonormal_coefficients(rng, A, k, miller, nb)
-        eps, f = levels(rng)
-        pend.append((k, kweights[ik], miller, C, eps, f))
-    for (k, w, miller, C, eps, f) in pend:
-        P = draw_projections(rng, C.shape[0], nproj_total)
-        sets.append(StateSet(kpt=np.asarray(k, dtype=np.float64), weight=float(w), miller=miller,
-                             C=C, eps=eps, f=f, P=P))
-    paw = draw_paw(rng, A, nproj)
     kq = None
-    if extra_kq:
-        kq = []
-        for s in sets:
-            C2 = orthonormal_coefficients(rng, A, s.kpt, s.miller, s.nbands)
-            eps2, f2 = levels(rng)
-            P2 = draw_projections(rng, s.nbands, nproj_total)
-            kq.append(StateSet(kpt=s.kpt.copy(), weight=s.weight, miller=s.miller, C=C2,
-                               eps=eps2, f=f2, P=P2))
+    if paw_model == "overlap":
+        raw = []
+        for ik, k in enumerate(kpts):
+            miller = wavefunction_sphere(A, k, ecut_wf)
+            C0 = raw_coefficients(rng, A, k, miller, levels(None, dry=True))
+            eps, f = levels(rng)
+            raw.append((k, kweights[ik], miller, C0, eps, f))
+        paw = draw_paw(rng, A, nproj)
+        pis = []
+        for (k, w, miller, C0, eps, f) in raw:
+            Pi = projector_map(rng, A, k, miller, paw)
+            pis.append(Pi)
+            C, P = paw_orthonormal_states(C0, Pi, paw)
+            sets.append(StateSet(kpt=np.asarray(k, dtype=np.float64), weight=float(w), miller=miller,
+                                 C=C, eps=eps, f=f, P=P))
+        if extra_kq:
+            kq = []
+            for s, Pi in zip(sets, pis):
+                C0 = raw_coefficients(rng, A, s.kpt, s.miller, s.nbands)
+                eps2, f2 = levels(rng)
+                C2, P2 = paw_orthonormal_states(C0, Pi, paw)
+                kq.append(StateSet(kpt=s.kpt.copy(), weight=s.weight, miller=s.miller, C=C2,
+                                   eps=eps2, f=f2, P=P2))
+    elif paw_model == "independent":
+        pend = []
+        for ik, k in enumerate(kpts):
+            miller = wavefunction_sphere(A, k, ecut_wf)
+            nb = levels(None, dry=True)
+            C = orthonormal_coefficients(rng, A, k, miller, nb)
+            eps, f = levels(rng)
+            pend.append((k, kweights[ik], miller, C, eps, f))
+        for (k, w, miller, C, eps, f) in pend:
+            P = draw_projections(rng, C.shape[0], nproj_total)
+            sets.append(StateSet(kpt=np.asarray(k, dtype=np.float64), weight=float(w), miller=miller,
+                                 C=C, eps=eps, f=f, P=P))
+        paw = draw_paw(rng, A, nproj)
+        if extra_kq:
+            kq = []
+            for s in sets:
+                C2 = orthonormal_coefficients(rng, A, s.kpt, s.miller, s.nbands)
+                eps2, f2 = levels(rng)
+                P2 = draw_projections(rng, s.nbands, nproj_total)
+                kq.append(StateSet(kpt=s.kpt.copy(), weight=s.weight, miller=s.miller, C=C2,
+                                   eps=eps2, f=f2, P=P2))
+    else:
+        raise ValueError(f"unknown paw_model {paw_model!r}")
     omega, ow = frequency_grid(nw, w0)
     wl = Workload(name=name, A=A, grid=tuple(int(x) for x in grid), kpoints=sets, paw=paw,
                   qpoints=qpoints, omega=omega, omega_weight=ow, seed=seed, kq=kq)
@@ -343,7 +446,8 @@ def check_alias_free(wl: Workload):
                 raise ValueError("wavefunction sphere does not fit the grid")
 
 
-def config0(seed: int = 0, n_occ: int = 4, n_unocc: int = 60, nw: int = 8, extra_kq=False) -> Workload:
+def config0(seed: int = 0, n_occ: int = 4, n_unocc: int = 60, nw: int = 8, extra_kq=False,
+            paw_model: str = "overlap") -> Workload:
     """Tiny plain FP64 case: cubic L=10 bohr, 16^3 grid, Gamma, q=(0.1,0,0) 2pi/L,
     4 occupied + 60 unoccupied states, 2 atoms x 4 projectors, ~120 G, 8 frequencies."""
     L = 10.0
@@ -352,11 +456,12 @@ def config0(seed: int = 0, n_occ: int = 4, n_unocc: int = 60, nw: int = 8, extra
     ecut = ecut_for_count(A, q, 120)
     qps = [QPoint(q=q, ecut=ecut)]
     return _assemble("cfg0-tiny", A, (16, 16, 16), seed, [np.zeros(3)], [1.0],
-                     _gapped(n_occ, n_unocc), [4, 4], qps, nw, extra_kq=extra_kq)
+                     _gapped(n_occ, n_unocc), [4, 4], qps, nw, extra_kq=extra_kq, paw_model=paw_model)
 
 
 def config1(seed: int = 1, n_occ: int = 16, n_unocc: int = 800, nw: int = 16,
-            target_ng: int = 1500, grid=(48, 48, 48), which_q=(0, 1, 2)) -> Workload:
+            target_ng: int = 1500, grid=(48, 48, 48), which_q=(0, 1, 2),
+            paw_model: str = "overlap") -> Workload:
     """O2-in-box scale: 12x12x13 bohr, 48^3 grid, Gamma, 16 occupied + 800 unoccupied,
     2 atoms x 13 projectors, ~1500 G, 16 frequencies, q = 0 (optical), 0.1, 0.2 x 2pi/12 along x."""
     A = np.diag([12.0, 12.0, 13.0])
@@ -370,11 +475,11 @@ def config1(seed: int = 1, n_occ: int = 16, n_unocc: int = 800, nw: int = 16,
             q = np.array([0.1 * i * TWO_PI / 12.0, 0.0, 0.0])
             qs.append(QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), weight=1.0 / 3))
     return _assemble("cfg1-o2box", A, grid, seed, [np.zeros(3)], [1.0],
-                     _gapped(n_occ, n_unocc), [13, 13], qs, nw)
+                     _gapped(n_occ, n_unocc), [13, 13], qs, nw, paw_model=paw_model)
 
 
 def config2(seed: int = 2, n_below: int = 120, n_above: int = 3000, nk: int = 8, nw: int = 16,
-            target_ng: int = 4000, T: float = 0.01) -> Workload:
+            target_ng: int = 4000, T: float = 0.01, paw_model: str = "overlap") -> Workload:
     """Metal-slab scale: 9x9x36 bohr, 40x40x160 grid, 2x2x2 Gamma-centred k (independent sets,
     w_k = 1/8), 120 + 3000 Fermi-smeared states (T = 0.01 Ha), 20 atoms x 18 projectors,
     ~4000 G, 16 frequencies, q = (0.1 2pi/9, 0, 0)."""
@@ -385,7 +490,7 @@ def config2(seed: int = 2, n_below: int = 120, n_above: int = 3000, nk: int = 8,
     q = np.array([0.1 * TWO_PI / 9.0, 0.0, 0.0])
     qps = [QPoint(q=q, ecut=ecut_for_count(A, q, target_ng))]
     return _assemble("cfg2-slab", A, (40, 40, 160), seed, kpts, [1.0 / len(kpts)] * len(kpts),
-                     _fermi(n_below, n_above, T), [18] * 20, qps, nw)
+                     _fermi(n_below, n_above, T), [18] * 20, qps, nw, paw_model=paw_model)
 
 
 def config3_qpoints(seed: int = 3, nq: int = 64):
@@ -403,16 +508,18 @@ def config3_qpoints(seed: int = 3, nq: int = 64):
     return A, qps
 
 
-def config3(seed: int = 3, n_occ: int = 60, n_unocc: int = 1500, nq: int = 64, nw: int = 16) -> Workload:
+def config3(seed: int = 3, n_occ: int = 60, n_unocc: int = 1500, nq: int = 64, nw: int = 16,
+            paw_model: str = "overlap") -> Workload:
     """Batching form: 9x9x36 bohr, 40x40x160 grid, Gamma, 60 + 1500 states, 64 q-points of a
     4x4x4 Monkhorst-Pack mesh without Gamma, G-sphere sizes log-uneven in [200, 3000]."""
     A, qps = config3_qpoints(seed, nq)
     return _assemble("cfg3-batched", A, (40, 40, 160), seed, [np.zeros(3)], [1.0],
-                     _gapped(n_occ, n_unocc), [18] * 20, qps, nw)
+                     _gapped(n_occ, n_unocc), [18] * 20, qps, nw, paw_model=paw_model)
 
 
 def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), target_ng=15,
-         q_frac=(0.1, 0.0, 0.0), nw=8, seed=11, optical=False, extra_kq=False, ecut_wf_scale=None):
+         q_frac=(0.1, 0.0, 0.0), nw=8, seed=11, optical=False, extra_kq=False, ecut_wf_scale=None,
+         paw_model="overlap"):
     """Small cases on tiny grids for direct-sum checks and ragged shapes."""
     A = np.diag(np.asarray(L, dtype=np.float64))
     B = reciprocal_rows(A)
@@ -421,4 +528,4 @@ def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), ta
         q = np.zeros(3)
     qp = QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), optical=optical)
     return _assemble("tiny", A, grid, seed, [np.zeros(3)], [1.0], _gapped(n_occ, n_unocc),
-                     list(nproj), [qp], nw, extra_kq=extra_kq)
+                     list(nproj), [qp], nw, extra_kq=extra_kq, paw_model=paw_model)

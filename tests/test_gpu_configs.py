@@ -31,7 +31,7 @@ def _rel(a, b):
 
 
 def _split_tol(E):
-    return 1e-6 * max(1.0, abs(E)) * 0.2
+    return 1e-6
 
 
 @pytest.fixture(scope="module")

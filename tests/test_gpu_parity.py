@@ -41,6 +41,8 @@ WORKLOADS = {
                                              target_ng=40, extra_kq=True),
     "tiny10_optical": lambda: synth.tiny(grid=(10, 10, 10), n_occ=2, n_unocc=4, optical=True, target_ng=12),
     "cfg0": lambda: synth.config0(),
+    # the stress workload: projections drawn apart from the coefficients, a large PAW term
+    "cfg0_independent": lambda: synth.config0(paw_model="independent"),
 }
 
 
@@ -87,7 +89,7 @@ def test_pair_density_unsorted_pairs_and_diagonal(rpa):
 
 
 @pytest.mark.parametrize("path", [0, 1])
-@pytest.mark.parametrize("name", ["tiny8", "tiny12_distinct_kq", "tiny10_optical", "cfg0"])
+@pytest.mark.parametrize("name", ["tiny8", "tiny12_distinct_kq", "tiny10_optical", "cfg0", "cfg0_independent"])
 def test_chi0_and_ec_fp64(rpa, name, path):
     wl = WORKLOADS[name]()
     ref = oracle_q(wl)
@@ -287,19 +289,16 @@ def test_o2box_reduced_bands(rpa, iq):
     print(f"o2box q{iq}: NG={len(gm)} E64={ec:.12f} Efp16={ec16:.12f} Ebf16={ecb:.12f} ref={ref['E']:.12f}",
           flush=True)
     assert abs(ec - ref["E"]) < 1e-10
-    # The synthetic PAW term makes |E_c| 5-30 Ha here (10^3 Ha with all 800 empty states), so the split
-    # path is held to 1e-6 Ha per Ha of |E_c| at most, and to 1e-6 Ha where |E_c| < 1 Ha.
-    tol = 1e-6 * max(1.0, abs(ref["E"])) * 0.2
-    assert abs(ec16 - ref["E"]) < tol
-    assert abs(ecb - ref["E"]) < tol
+    assert abs(ec16 - ref["E"]) < 1e-6
+    assert abs(ecb - ref["E"]) < 1e-6
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [1, 4, 5])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_split_kernel_variants(rpa, variant, prec):
-    """The split rank-k kernels (64x64 tiles, 128x128 tiles, 128x128 pipelined, 64x128 pipelined with FP64
-    accumulation) against the oracle on the 16^3 workload (NG = 126) and a tiny grid (NG = 15: one tile,
-    mostly padding)."""
+    """The split rank-k kernels (64x64 tiles; 64x128 pipelined with FP64 accumulation, four or eight waves)
+    against the oracle on the 16^3 workload (NG = 126) and a tiny grid (NG = 15: one tile, mostly
+    padding)."""
     for wl in (synth.config0(), synth.tiny(grid=(8, 8, 8))):
         ref = oracle_q(wl)
         ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
@@ -361,12 +360,12 @@ def test_batched_graph_replays_match_per_q_calls(rpa, prec):
             assert abs(e - ref["E"]) < (1e-10 if prec == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("pair", [(2, 3), (4, 5)])
+@pytest.mark.parametrize("pair", [(4, 5)])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_split_kernel_twins_are_bit_identical(rpa, prec, pair):
-    """Variant 3 issues the same products in the same order as variant 2, and variant 5 as variant 4 (the
-    same tiles split over eight waves instead of four): chi0 is bit-identical, here on the 48^3 grid
-    (NG = 1500) with 2 x 300 pairs (19 K-steps: two FP64 flushes of v4/v5 and a ragged last step)."""
+    """Variant 5 issues the same products in the same order as variant 4 (the same tiles split over eight
+    waves instead of four): chi0 is bit-identical, here on the 48^3 grid (NG = 1500) with 2 x 300 pairs
+    (19 K-steps: two FP64 flushes and a ragged last step)."""
     wl = synth.config1(n_occ=2, n_unocc=300, which_q=(1,))
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
     out = {}
@@ -381,23 +380,144 @@ def test_split_kernel_twins_are_bit_identical(rpa, prec, pair):
     assert np.array_equal(out[a], out[b])
 
 
+def _golden_o2box():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "o2box_ec.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.fixture(scope="module")
+def o2box_full():
+    return synth.config1()
+
+
+@pytest.mark.parametrize("iq", [0, 1])
+def test_o2box_full_size_against_oracle(rpa, o2box_full, iq):
+    """All 16 x 800 pairs of the O2-in-box workload (NG ~ 1500, 16 frequencies) at the optical q-point and
+    at q = 0.1 x 2 pi/12: E_c(q) and F(w) of the FP64 path within 1e-10 Ha of the oracle, and of both split
+    precisions within 1e-6 Ha. The oracle's values were written by tests/golden/make_o2box_ec.py, which
+    calls the FP64 CPU oracle alone on the same seeded inputs."""
+    wl = o2box_full
+    gold = _golden_o2box()["qpoints"][iq]
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl, iq)
+    assert len(gm) == gold["NG"]
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        e64, F64 = ctx.ec(ks, kqs, qs, fr, "fp64")
+        eb, Fb = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        eh, Fh = ctx.ec(ks, kqs, qs, fr, "split_fp16")
+        ctx.check()
+    e64, eb, eh = (float(x.cpu()[0]) for x in (e64, eb, eh))
+    Fref = np.asarray(gold["F"])
+    print(f"o2box q{iq}: NG={len(gm)} ref={gold['E_c']:.12f} fp64 dE={e64 - gold['E_c']:.3e} "
+          f"bf16 dE={eb - gold['E_c']:.3e} fp16 dE={eh - gold['E_c']:.3e}", flush=True)
+    assert abs(e64 - gold["E_c"]) < 1e-10
+    assert np.max(np.abs(F64.cpu().numpy() - Fref)) < 1e-9
+    assert abs(eb - gold["E_c"]) < 1e-6
+    assert abs(eh - gold["E_c"]) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_o2box_full_size_chi0_band_subset(rpa, o2box_full, prec):
+    """chi0 of the O2-in-box q-point 1 (NG = 1500) element by element against the oracle on a band subset:
+    all 16 occupied states and every 37th unoccupied one (352 pairs)."""
+    wl = o2box_full
+    s = wl.kpoints[0]
+    keep = np.concatenate([np.arange(16), 16 + np.arange(0, 800, 37)])
+    sub = synth.StateSet(kpt=s.kpt, weight=s.weight, miller=s.miller, C=np.ascontiguousarray(s.C[keep]),
+                         eps=s.eps[keep].copy(), f=s.f[keep].copy(), P=np.ascontiguousarray(s.P[keep]))
+    wl1 = synth.Workload(name="sub", A=wl.A, grid=wl.grid, kpoints=[sub], paw=wl.paw, qpoints=[wl.qpoints[1]],
+                         omega=wl.omega, omega_weight=wl.omega_weight, seed=0)
+    ref = oracle_q(wl1)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl1)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
+        ec, _ = ctx.ec(ks, kqs, qs, fr, prec)
+        ctx.check()
+    r = _rel(chi, ref["chi"])
+    dE = float(ec.cpu()[0]) - ref["E"]
+    print(f"o2box subset {prec}: pairs={16 * len(keep[16:])} chi rel={r:.3e} dE={dE:.3e}", flush=True)
+    assert r < (1e-12 if prec == "fp64" else 2e-4)
+    assert abs(dE) < (1e-10 if prec == "fp64" else 1e-6)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
-def test_split_full_size_matches_fp64(rpa, prec):
-    """All 16 x 800 pairs of the O2-in-box q-point 1 (NG = 1500): with the default kernel (FP32 partial
-    sums added into FP64 every 256 pairs) the split E_c stays within 5e-8 of the FP64 path's E_c, relative;
-    a kernel that kept the 12,800-pair sum in FP32 lands near 1e-6. The FP64 path itself is held to the
-    oracle at 1e-10 Ha on this grid with fewer bands."""
-    wl = synth.config1(which_q=(1,))
+@pytest.mark.parametrize("case", ["o2box_chunks", "slab_two_k"])
+def test_split_accumulate_branch(rpa, prec, case):
+    """Updates after the first one into a q-point's accumulator (the branch that reads C and adds): the pair
+    sum split into chunks by a bound on the chunk size, over one k set at NG = 1500 (4 x 40 pairs in chunks
+    of 64) and over two k sets of the metal slab at NG ~ 500 (chunks of 48). chi0 element by element and
+    E_c against the oracle."""
+    if case == "o2box_chunks":
+        wl = synth.config1(n_occ=4, n_unocc=40, which_q=(1,))
+        chunk = 64
+    else:
+        wl = synth.config2(n_below=6, n_above=24, nk=2, target_ng=500)
+        chunk = 48
+    ref = oracle_q(wl)
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    npairs = [int(np.sum(s.f[:, None] - t.f[None, :] > 1e-8)) for s, t in zip(wl.kpoints, wl.kq_sets())]
+    nchunks = sum((p + chunk - 1) // chunk for p in npairs)
+    assert nchunks >= 3
     with rpa.Context(wl.A, wl.grid) as ctx:
         assert ctx.tune_get(len(gm), prec) == 5
-        e64, _ = ctx.ec(ks, kqs, qs, fr, "fp64")
-        es, _ = ctx.ec(ks, kqs, qs, fr, prec)
+        ctx.set_chunk_pairs(chunk)
+        chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
+        ec, _ = ctx.ec(ks, kqs, qs, fr, prec)
+        ctx.set_chunk_pairs(0)
+        chi1 = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
         ctx.check()
-    e64, es = float(e64.cpu()[0]), float(es.cpu()[0])
-    rel = abs(es - e64) / abs(e64)
-    print(f"{prec}: E64={e64:.10f} Esplit={es:.10f} rel={rel:.3e}", flush=True)
-    assert rel < 5e-8
+    r = _rel(chi, ref["chi"])
+    dE = float(ec.cpu()[0]) - ref["E"]
+    print(f"{case} {prec}: NG={len(gm)} pairs={npairs} chunks={nchunks} chi rel={r:.3e} dE={dE:.3e} "
+          f"vs one chunk {_rel(chi, chi1):.3e}", flush=True)
+    assert r < 2e-4
+    assert abs(dE) < 1e-6
+    assert _rel(chi, chi1) < 1e-6
+
+
+def test_nan_workspace_does_not_reach_an_uneven_batch(rpa):
+    """A failed factorisation (a chi0 with 1 - K not positive definite) leaves NaN in the context's chi0
+    workspace; an uneven split batch on the same context afterwards must not see it: its E_c values are
+    finite and bit-identical to the same batch on a fresh context."""
+    wl = synth.config3(n_occ=2, n_unocc=10, nq=4)
+    ks = [rpa.States.from_synth(wl.kpoints[0], wl.paw, "cuda:0")]
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    qspecs, ngs = [], []
+    for qp in wl.qpoints:
+        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+        ngs.append(len(gm))
+        qspecs.append(rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight))
+    # smallest sphere first: its accumulator (padded to the largest sphere) is where the NaN lands
+    order = np.argsort(ngs)
+    qspecs = [qspecs[i] for i in order]
+    ngs = [ngs[i] for i in order]
+    assert (ngs[0] + 63) // 64 < (ngs[-1] + 63) // 64
+    nbig = ngs[-1]
+    # +1e3 on the diagonal of chi0: 1 - K has large negative eigenvalues at every frequency
+    bad = torch.zeros((len(wl.omega), nbig, nbig), dtype=torch.complex128, device="cuda:0")
+    bad.diagonal(dim1=1, dim2=2).fill_(1e3)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        # the batch first, so that its workspace is allocated and the failed call below writes into it
+        e0, _ = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
+        ctx.check()
+        first = e0.cpu().numpy().copy()
+        ctx.ec_from_chi0(qspecs[-1], fr, bad)
+        with pytest.raises(rpa.RpaError) as ei:
+            ctx.check()
+        assert ei.value.status == -5
+        e1, _ = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
+        ctx.check()
+        got = e1.cpu().numpy().copy()
+    assert np.array_equal(first, got)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        e2, _ = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
+        ctx.check()
+        fresh = e2.cpu().numpy().copy()
+    print(f"NG={ngs} after NOT_PD: {got} fresh: {fresh}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.array_equal(got, fresh)
 
 
 def test_autotune_records_a_variant(rpa):
