@@ -71,8 +71,10 @@ def test_pair_density(rpa, name, prec, path):
 
 
 def test_pair_density_unsorted_pairs_and_diagonal(rpa):
-    """Arbitrary pair order (including n = m) and the G = 0 normalisation of the pseudo part."""
-    wl = synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=5, q_frac=(0.0, 0.0, 0.0), nproj=(1,), target_ng=7)
+    """Arbitrary pair order (including n = m) and the G = 0 normalisation of the pseudo part (the stress
+    workload, whose coefficients are orthonormal on their own)."""
+    wl = synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=5, q_frac=(0.0, 0.0, 0.0), nproj=(1,), target_ng=7,
+                    paw_model="independent")
     wl.qpoints[0].q = np.zeros(3)
     s = wl.kpoints[0]
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
