@@ -170,6 +170,29 @@ int rpa_ec_from_chi0(rpa_ctx* ctx, const rpa_qspec* qs, const rpa_freq* fr, cons
 int rpa_ec(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
            const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, void* stream);
 
+/* rpa_ec for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, kernels and results as rpa_ec, but every device workspace
+ * (orbitals, pair transforms, pair densities, weights, PAW and split
+ * operands, the chi0 accumulator, the Cholesky buffers and the uploaded host
+ * tables) is carved out of one static device array of 128 MiB per GPU, set
+ * up by rpa_create and held until the process ends. The call makes no
+ * hipMalloc, hipFree, pinned-host or library allocation; host tables are
+ * copied from ordinary host memory with hipMemcpyAsync.
+ *  - A problem whose workspaces exceed 128 MiB is rejected with
+ *    RPA_ERR_NOMEM before any kernel runs (rpa_last_error names the buffer
+ *    and the bytes needed). Small spheres and band counts fit: e.g. NG ~ 120
+ *    with 64 states on a 16^3 grid takes a few MiB, while NG ~ 1500 with 16
+ *    frequencies needs 600 MiB for chi0 alone and does not.
+ *  - Every call on a GPU shares that GPU's array, which keeps the last call's
+ *    contents; the kernels clear what must start at zero. Calls that overlap
+ *    on one GPU (different streams or host threads, any context) race: order
+ *    them. rpa_check reports a non-positive pivot of the last call, as for
+ *    rpa_ec, until another call on the same GPU reuses the array.
+ *  - The stage profiler records nothing during this call. */
+int rpa_ec_noalloc(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                   const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, void* stream);
+
 /* E_c(q) for nq q-points that share the same (k, k+q) state-set pairs (as with
  * Gamma-only sampling) - Eq. rpa_c's q sum. Orbitals are built once; each q
  * has its own G-sphere, PAW table and chi0. Outputs: ec_dev DEVICE double

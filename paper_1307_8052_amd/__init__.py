@@ -256,6 +256,22 @@ class Context:
                               ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()), _stream()), self._h)
         return ec, F
 
+    def ec_noalloc(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, freq: Freq, precision="fp64",
+                   out=None):
+        """rpa_ec_noalloc: E_c(q) with every workspace in the library's per-device scratch (no allocation
+        by the library). Pass preallocated `out` = (ec [1], F [nw]) device tensors to allocate nothing here
+        either; returns (ec, F)."""
+        torch = _torch()
+        if out is None:
+            out = (torch.empty(1, dtype=torch.float64, device=self.device),
+                   torch.empty(freq.nw, dtype=torch.float64, device=self.device))
+        ec, F = out
+        a, b, q, fr = self._arrays(ks), self._arrays(kqs), qs.struct(), freq.struct()
+        _check(self._L.rpa_ec_noalloc(self._h, a, b, len(ks), ctypes.byref(q), ctypes.byref(fr), _prec(precision),
+                                      ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()), _stream()),
+               self._h)
+        return ec, F
+
     def ec_batched(self, ks: Sequence[States], kqs: Sequence[States], qspecs: Sequence[QSpec], freq: Freq,
                    precision="fp64", use_graph: bool = False, out=None):
         """E_c(q) for every q of qspecs sharing the same state sets; returns (ec [nq + 1], F [nq, nw]) on the

@@ -76,6 +76,9 @@ SIGNATURES = {
                                  c_void_p, c_void_p, c_void_p]),
     "rpa_ec": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
                        ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p, c_void_p]),
+    "rpa_ec_noalloc": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
+                               ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p,
+                               c_void_p]),
     "rpa_ec_batched": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int, c_int,
                                ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p, c_int,
                                c_void_p]),

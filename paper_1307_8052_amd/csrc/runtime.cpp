@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -36,6 +37,31 @@ int fail(int code, const std::string& msg) {
 
 constexpr double kDeltaF = 1e-8;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Device scratch of the allocation-free entry point (rpa_ec_noalloc): every workspace of that call is
+// carved out of this array, one copy per device, held until the process ends. Host code never uses its
+// name as an address: rpa_create looks up each device's copy once with hipGetSymbolAddress and keeps the
+// pointer in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device; filled under g_scratch_mu
+
+// the device's scratch address (device must be current); looked up once per device
+int scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RPA_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return RPA_OK;
+}
 
 struct DevBuf {
     void* p = nullptr;
@@ -82,6 +108,13 @@ struct rpa_ctx {
     bool capturing = false;
     bool pair_reg = true;   // register-resident pair transforms where supported
     int max_chunk = 0;      // upper bound on the pairs of one chunk (0: set by the workspace budget alone)
+    // arena mode (rpa_ec_noalloc): workspaces are carved from the device scratch instead of hipMalloc'd, and
+    // host tables are staged in ordinary host memory instead of a pinned arena
+    void* scratch = nullptr;            // this device's scratch (set at rpa_create)
+    char* arena = nullptr;              // non-null while a call runs in arena mode
+    size_t arena_cap = 0, arena_off = 0;
+    std::map<std::string, DevBuf> abufs;
+    std::vector<char> host_stage;
     // non-blocking stream the batch sequence is captured on (the legacy default stream cannot be)
     hipStream_t cap_stream = nullptr;
     // look-ahead of the blocked Cholesky: the trailing update of each step runs on
@@ -166,6 +199,23 @@ struct Fnv {
 
 // ---------------------------------------------------------------- buffers
 int get_buf(rpa_ctx* c, const char* name, size_t bytes, hipStream_t s, void** out) {
+    if (c->arena) {
+        DevBuf& a = c->abufs[name];
+        if (a.p && a.bytes >= bytes) {
+            *out = a.p;
+            return RPA_OK;
+        }
+        const size_t want = (std::max<size_t>(bytes, 256) + 255) & ~size_t(255);
+        if (c->arena_off + want > c->arena_cap)
+            return fail(RPA_ERR_NOMEM, std::string("workspace ") + name + " does not fit the device scratch of " +
+                                           std::to_string(c->arena_cap) + " bytes (" +
+                                           std::to_string(c->arena_off + want) + " needed so far)");
+        a.p = c->arena + c->arena_off;
+        a.bytes = want;
+        c->arena_off += want;
+        *out = a.p;
+        return RPA_OK;
+    }
     DevBuf& b = c->bufs[name];
     if (b.bytes >= bytes && b.p) {
         *out = b.p;
@@ -214,6 +264,21 @@ struct Upload {
 int do_upload(rpa_ctx* c, Upload& u, hipStream_t s, const char* bufname) {
     if (u.total == 0) return RPA_OK;
     if (c->staged_valid) HIP_TRY(hipEventSynchronize(c->staged));
+    if (c->arena) {
+        // arena mode: ordinary host memory, kept until the copy's event has completed
+        if (c->host_stage.size() < u.total) c->host_stage.resize(u.total);
+        void* dev = nullptr;
+        int rc = get_buf(c, bufname, u.total, s, &dev);
+        if (rc) return rc;
+        for (auto& it : u.items) {
+            if (it.bytes) std::memcpy(c->host_stage.data() + it.off, it.src, it.bytes);
+            *it.dst = static_cast<char*>(dev) + it.off;
+        }
+        HIP_TRY(hipMemcpyAsync(dev, c->host_stage.data(), u.total, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(c->staged, s));
+        c->staged_valid = true;
+        return RPA_OK;
+    }
     if (c->pinned_bytes < u.total) {
         if (c->pinned) HIP_TRY(hipHostFree(c->pinned));
         c->pinned = nullptr;
@@ -562,6 +627,7 @@ int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
                        (size_t)(g.NGp + 127) / 128 * 128 * 16;
     size_t budget = (size_t)6 << 30;
     if (c->cap) budget = std::min(budget, c->cap / 4);
+    if (c->arena) budget = std::min(budget, c->arena_cap / 4);
     size_t pc = budget / per;
     pc = std::max<size_t>(pc, 64);
     pc = std::min<size_t>(pc, 1 << 20);
@@ -687,7 +753,7 @@ int prepare_q(Batch& B, QJob& Q, Upload& up) {
     return RPA_OK;
 }
 
-void* buf(Batch& B, const char* name) { return B.c->bufs[B.prefix + name].p; }
+void* buf(Batch& B, const char* name) { return (B.c->arena ? B.c->abufs : B.c->bufs)[B.prefix + name].p; }
 
 // Work buffers, sized once for every q of the batch (never grown while launching).
 struct WorkSizes {
@@ -1682,8 +1748,10 @@ int rpa_create(rpa_ctx** out, const rpa_cell* cell, int device, size_t cap) {
         delete c;
         return fail(RPA_ERR_HIP, "hipEventCreate failed");
     }
-    // the Cholesky look-ahead streams, created once here
-    rc = ensure_lookahead(c);
+    // set-up for the allocation-free entry point: this device's scratch address and the Cholesky
+    // look-ahead streams, so that no call has to create them later
+    rc = scratch_address(device, &c->scratch);
+    if (!rc) rc = ensure_lookahead(c);
     if (rc) {
         const std::string msg = g_err;
         rpa_destroy(c);
@@ -1813,6 +1881,32 @@ int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, cons
     QJob& Q = B.qj[0];
     HIP_TRY(launch_chi_out(Q.cr, Q.ci, B.ld, Q.qp.NG, B.nw, static_cast<double*>(chi0_out), B.s));
     return RPA_OK;
+}
+
+int rpa_ec_noalloc(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                   const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, void* stream) {
+    if (!c) return fail(RPA_ERR_INPUT, "NULL context");
+    if (!c->scratch) return fail(RPA_ERR_HIP, "device scratch not set up");
+    if (c->capturing) return fail(RPA_ERR_INPUT, "context busy");
+    // arena mode for the duration of the call: workspaces from the scratch, no profiler events
+    struct Arena {
+        rpa_ctx* c;
+        bool prof;
+        explicit Arena(rpa_ctx* c_) : c(c_), prof(c_->prof) {
+            c->arena = static_cast<char*>(c->scratch);
+            c->arena_cap = kScratchBytes;
+            c->arena_off = 0;
+            c->abufs.clear();
+            c->prof = false;
+        }
+        ~Arena() {
+            c->arena = nullptr;
+            c->arena_off = 0;
+            c->abufs.clear();
+            c->prof = prof;
+        }
+    } arena(c);
+    return rpa_ec(c, k, kq, nk, qs, fr, prec, ec_dev, F_dev, stream);
 }
 
 int rpa_ec(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, const rpa_freq* fr,
