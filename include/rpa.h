@@ -156,6 +156,14 @@ int rpa_pair_density(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, co
 int rpa_chi0(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
              const rpa_freq* fr, rpa_precision prec, void* chi0_out, void* stream);
 
+/* rpa_chi0, added into chi0_inout instead of overwriting it: the k sum of
+ * Eq. chi0 over calls, e.g. one k-point (or one group of k-points) at a time
+ * with only that group's orbitals resident. Same arguments and layout as
+ * rpa_chi0; chi0_inout DEVICE complex128 [nw][NG][NG] must hold a full
+ * Hermitian matrix per frequency (zeros before the first call). */
+int rpa_chi0_add(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                 const rpa_freq* fr, rpa_precision prec, void* chi0_inout, void* stream);
+
 /* E_c(q) from a given chi0 (Eq. rpa, Table 1 step 13):
  * F(w) = ln det(1 - K) + Tr K with K = v^1/2 chi0 v^1/2, v^1/2_G = sqrt(4 pi)/|q+G|,
  * ln det from an FP64 Cholesky factorisation; E_c = sum_i weight_i F(w_i)/2 pi.

@@ -246,6 +246,17 @@ class Context:
                                 ctypes.c_void_p(out.data_ptr()), _stream()), self._h)
         return out
 
+    def chi0_add(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, freq: Freq, chi0, precision="fp64"):
+        """chi0 += the contribution of these state sets (rpa_chi0_add); chi0 is a device complex128
+        [nw, NG, NG] tensor, updated in place and returned."""
+        torch = _torch()
+        if chi0.dtype != torch.complex128 or not chi0.is_contiguous() or tuple(chi0.shape) != (freq.nw, qs.NG, qs.NG):
+            raise ValueError("chi0 must be a contiguous complex128 [nw, NG, NG] device tensor")
+        a, b, q, fr = self._arrays(ks), self._arrays(kqs), qs.struct(), freq.struct()
+        _check(self._L.rpa_chi0_add(self._h, a, b, len(ks), ctypes.byref(q), ctypes.byref(fr), _prec(precision),
+                                    ctypes.c_void_p(chi0.data_ptr()), _stream()), self._h)
+        return chi0
+
     def ec(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, freq: Freq, precision="fp64"):
         """E_c(q) (device double [1]) and F(w) (device double [nw]); asynchronous."""
         torch = _torch()

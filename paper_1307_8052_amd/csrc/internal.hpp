@@ -134,6 +134,10 @@ hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr,
 // 64 x 128 tiles (ntiles = sum over 64-row blocks I of I/2 + 1), FP32 partial sums
 // added into FP64 every 8 K-steps; four waves of 64 x 32, or eight of 32 x 32
 hipError_t launch_herk_split4(const HerkSplit2Args& h, int eight_waves, hipStream_t s);
+// 128 x 128 lower tiles over NGq (ntiles = nT (nT + 1)/2, nT = NGq/128), eight waves of 32 x 64, FP32
+// accumulation over the whole call (bounded chunks: kSplit6Chunk pairs), added into the FP64 C at the end
+constexpr int kSplit6Chunk = 8192;
+hipError_t launch_herk_split6(const HerkSplit2Args& h, hipStream_t s);
 
 // -K = -v_i v_j chi_ij on the lower triangle (in place, planar), zero padding,
 // and Tr K per frequency.
@@ -162,7 +166,7 @@ hipError_t launch_fill_pattern(float* f, size_t nf, double* d, size_t nd, hipStr
 template <typename T>
 hipError_t launch_rho_out(const T* rre, const T* rim, int npairs, int NG, int NGp, double* out, hipStream_t s);
 
-hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out,
+hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, int add, double* out,
                           hipStream_t s);
 
 // ------------------------------------------------------------------ adjoint

@@ -574,7 +574,7 @@ __global__ void k_rho_out(const T* __restrict__ rre, const T* __restrict__ rim, 
 }
 
 __global__ void k_chi_out(const double* __restrict__ Cre, const double* __restrict__ Cim, int ldC, long long sC,
-                          int NG, double* __restrict__ out) {
+                          int NG, int add, double* __restrict__ out) {
     const int i = blockIdx.x, w = blockIdx.y;
     const double* cr = Cre + (size_t)w * sC;
     const double* ci = Cim + (size_t)w * sC;
@@ -583,6 +583,10 @@ __global__ void k_chi_out(const double* __restrict__ Cre, const double* __restri
         double re, im;
         if (j <= i) { re = cr[(size_t)i * ldC + j]; im = ci[(size_t)i * ldC + j]; }
         else { re = cr[(size_t)j * ldC + i]; im = -ci[(size_t)j * ldC + i]; }
+        if (add) {
+            re += o[2 * j];
+            im += o[2 * j + 1];
+        }
         o[2 * j] = re;
         o[2 * j + 1] = im;
     }
@@ -699,9 +703,10 @@ hipError_t launch_fill_pattern(float* f, size_t nf, double* d, size_t nd, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out, hipStream_t s) {
+hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, int add, double* out,
+                          hipStream_t s) {
     hipLaunchKernelGGL(k_chi_out, dim3((unsigned)NG, (unsigned)nw), dim3(256), 0, s, Cre, Cim, ldC,
-                       (long long)ldC * ldC, NG, out);
+                       (long long)ldC * ldC, NG, add, out);
     return hipGetLastError();
 }
 

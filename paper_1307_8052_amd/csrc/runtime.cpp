@@ -618,10 +618,10 @@ int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
     if (prec == RPA_FP64) return 0;
     auto it = c->tune.find(tune_key(prec, NGp));
     if (it != c->tune.end()) return it->second;
-    return ((NGp + 127) / 128 >= 4) ? 5 : 1;
+    return ((NGp + 127) / 128 >= 4) ? 6 : 1;
 }
 
-int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
+int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem, int variant) {
     const PairGeom& g = qp.g;
     const size_t per = (size_t)g.N3 * g.ncols * 2 * elem + 2 * (size_t)g.NGp * elem + (size_t)nw * 8 +
                        (size_t)(g.NGp + 127) / 128 * 128 * 16;
@@ -632,6 +632,8 @@ int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem) {
     pc = std::max<size_t>(pc, 64);
     pc = std::min<size_t>(pc, 1 << 20);
     if (c->max_chunk > 0) pc = std::min<size_t>(pc, (size_t)c->max_chunk);
+    // variant 6 keeps the sum over one chunk in FP32: its chunks are bounded
+    if (variant == 6) pc = std::min<size_t>(pc, (size_t)kSplit6Chunk);
     return (int)pc;
 }
 
@@ -777,7 +779,8 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
             P = std::max(P, (int)K.pn.size());
             if (!K.pn.empty()) nn_max = std::max(nn_max, K.k->nbands);
         }
-        Q.Pc = std::max(1, std::min(P, chunk_size(c, Q.qp, B.nw, el)));
+        Q.variant = default_variant(c, B.prec, g.NGp);
+        Q.Pc = std::max(1, std::min(P, chunk_size(c, Q.qp, B.nw, el, Q.variant)));
         const int Pc = Q.Pc;
         const int nproj = B.poff.empty() ? 0 : B.poff.back();
         // band window of a chunk: at most all bands of the k set
@@ -806,7 +809,6 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
             W.scales = std::max(W.scales, (size_t)(B.nw + 1 + 256) * sizeof(float));
         }
         B.ld = std::max(B.ld, g.NGp);
-        Q.variant = default_variant(c, B.prec, g.NGp);
     }
     // every (q, w) matrix at one leading dimension: all real parts, then all imaginary parts, so that
     // matrix b = q nw + w sits at b * ld^2 and the E_c stage treats the batch as one set of matrices
@@ -948,9 +950,10 @@ template <typename T>
 int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const double* aw, int lda) {
     rpa_ctx* c = B.c;
     const int NGp = Q.qp.NGp;
-    // the first update of an accumulator: variants 4 and 5 store instead of adding (their tiles cover the
-    // whole lower triangle, padding included, which is all the E_c stage and the chi0 output read); the
-    // others add into a zero-filled accumulator
+    // the first update of an accumulator: variants 4, 5 and 6 store instead of adding (their tiles cover the
+    // lower triangle of this q-point's padded sphere, which is all the chi0 output reads; the E_c stage
+    // assigns zero to the rest of a batch's common leading dimension); variant 1 adds into a zero-filled
+    // accumulator
     const bool store_first = Q.fresh && sizeof(T) == 4 && Q.variant >= 4;
     if (Q.fresh && !store_first) HIP_TRY(zero_accumulator(B, Q));
     Q.fresh = false;
@@ -1016,12 +1019,19 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.nw = B.nw;
             h.fp16 = fp16;
             h.scales = scales;
-            // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
-            const int nR = NGp / kTile;
-            h.ntiles = 0;
-            for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
             h.overwrite = store_first;
-            HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
+            if (Q.variant == 6) {
+                // 128 x 128 lower tiles over NGq
+                const int nT = NGq / 128;
+                h.ntiles = nT * (nT + 1) / 2;
+                HIP_TRY(launch_herk_split6(h, B.s));
+            } else {
+                // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
+                const int nR = NGp / kTile;
+                h.ntiles = 0;
+                for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
+                HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
+            }
         } else {
             HerkSplitArgs h{};
             h.Are = reinterpret_cast<const float*>(rre);
@@ -1864,8 +1874,8 @@ int rpa_pair_density(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, cons
     return prec == RPA_FP64 ? run(double()) : run(float());
 }
 
-int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, const rpa_freq* fr,
-             rpa_precision prec, void* chi0_out, void* stream) {
+static int chi0_impl(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, const rpa_freq* fr,
+                     rpa_precision prec, void* chi0_out, int add, void* stream) {
     int rc = check_common(c, k, kq, nk, qs);
     if (rc) return rc;
     if (!chi0_out) return fail(RPA_ERR_INPUT, "NULL chi0_out");
@@ -1879,8 +1889,18 @@ int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, cons
     rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
     if (rc) return rc;
     QJob& Q = B.qj[0];
-    HIP_TRY(launch_chi_out(Q.cr, Q.ci, B.ld, Q.qp.NG, B.nw, static_cast<double*>(chi0_out), B.s));
+    HIP_TRY(launch_chi_out(Q.cr, Q.ci, B.ld, Q.qp.NG, B.nw, add, static_cast<double*>(chi0_out), B.s));
     return RPA_OK;
+}
+
+int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, const rpa_freq* fr,
+             rpa_precision prec, void* chi0_out, void* stream) {
+    return chi0_impl(c, k, kq, nk, qs, fr, prec, chi0_out, 0, stream);
+}
+
+int rpa_chi0_add(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                 const rpa_freq* fr, rpa_precision prec, void* chi0_inout, void* stream) {
+    return chi0_impl(c, k, kq, nk, qs, fr, prec, chi0_inout, 1, stream);
 }
 
 int rpa_ec_noalloc(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
@@ -2081,9 +2101,9 @@ int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs) {
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
     if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
-    if (variant != 1 && variant != 4 && variant != 5)
-        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 4 (64x128 pipelined, FP64 accumulation) and 5 "
-                                   "(as 4, eight waves)");
+    if (variant != 1 && variant != 4 && variant != 5 && variant != 6)
+        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 4 (64x128 pipelined, FP64 accumulation), 5 "
+                                   "(as 4, eight waves) and 6 (128x128, eight waves of 32x64, bounded chunks)");
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     c->tune[tune_key(prec, NGp)] = variant;
     return RPA_OK;
@@ -2134,19 +2154,20 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e300;
     int bestv = 1;
-    // only the variants that accumulate the pair sum in FP64 are candidates
-    for (int v : {1, 4, 5}) {
+    // each variant on the pairs of one of its chunks; compared by time per pair
+    for (int v : {1, 4, 5, 6}) {
         Q.variant = v;
+        const int kv = v == 6 ? std::min(npairs, kSplit6Chunk) : npairs;
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipEventRecord(e0, s));
-            rc = enqueue_update<float>(B, Q, npairs, rre, rim, static_cast<const double*>(aw), lda);
+            rc = enqueue_update<float>(B, Q, kv, rre, rim, static_cast<const double*>(aw), lda);
             if (rc) break;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0) tmin = std::min(tmin, (double)ms);
+            if (rep > 0) tmin = std::min(tmin, (double)ms / kv * npairs);
         }
         if (rc) break;
         if (tmin < best) {
@@ -2167,7 +2188,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (save) {
         FILE* f = std::fopen(path, "w");
         if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
-        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 4 / 5 = pipelined 64x128)\n");
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 4 / 5 = pipelined 64x128, 6 = 128x128)\n");
         for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
         std::fclose(f);
         return RPA_OK;
@@ -2178,7 +2199,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int p, ng, v;
-        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || v == 4 || v == 5) && ng > 0)
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || (v >= 4 && v <= 6)) && ng > 0)
             c->tune[tune_key((rpa_precision)p, ng)] = v;
     }
     std::fclose(f);

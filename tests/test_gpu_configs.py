@@ -101,3 +101,21 @@ def test_uneven_batch_reduced(rpa):
         ref = oracle_q(wl1)
         print(f"q{i} NG={ngs[i]}: E={eager[i]:.12f} ref={ref['E']:.12f}", flush=True)
         assert abs(eager[i] - ref["E"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_chi0_add_sums_over_k(rpa, slab, prec):
+    """rpa_chi0_add one k-point at a time gives the chi0 of rpa_chi0 over both k-points (Eq. chi0's k sum),
+    and the oracle's."""
+    wl, ref = slab
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        both = ctx.chi0(ks, kqs, qs, fr, prec)
+        acc = torch.zeros_like(both)
+        for i in range(len(ks)):
+            ctx.chi0_add([ks[i]], [kqs[i]], qs, fr, acc, prec)
+        ctx.check()
+    both, acc = both.cpu().numpy(), acc.cpu().numpy()
+    print(f"{prec}: chi0_add vs chi0 {_rel(acc, both):.3e}, vs oracle {_rel(acc, ref['chi']):.3e}", flush=True)
+    assert _rel(acc, both) < 1e-13
+    assert _rel(acc, ref["chi"]) < (1e-12 if prec == "fp64" else 2e-4)

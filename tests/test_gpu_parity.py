@@ -295,12 +295,12 @@ def test_o2box_reduced_bands(rpa, iq):
     assert abs(ecb - ref["E"]) < 1e-6
 
 
-@pytest.mark.parametrize("variant", [1, 4, 5])
+@pytest.mark.parametrize("variant", [1, 4, 5, 6])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_split_kernel_variants(rpa, variant, prec):
-    """The split rank-k kernels (64x64 tiles; 64x128 pipelined with FP64 accumulation, four or eight waves)
-    against the oracle on the 16^3 workload (NG = 126) and a tiny grid (NG = 15: one tile, mostly
-    padding)."""
+    """The split rank-k kernels (64x64 tiles; 64x128 pipelined with FP64 accumulation, four or eight waves;
+    128x128 with eight waves of 32x64) against the oracle on the 16^3 workload (NG = 126) and a tiny grid
+    (NG = 15: one tile, mostly padding)."""
     for wl in (synth.config0(), synth.tiny(grid=(8, 8, 8))):
         ref = oracle_q(wl)
         ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
@@ -463,7 +463,7 @@ def test_split_accumulate_branch(rpa, prec, case):
     nchunks = sum((p + chunk - 1) // chunk for p in npairs)
     assert nchunks >= 3
     with rpa.Context(wl.A, wl.grid) as ctx:
-        assert ctx.tune_get(len(gm), prec) == 5
+        assert ctx.tune_get(len(gm), prec) == 6
         ctx.set_chunk_pairs(chunk)
         chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
         ec, _ = ctx.ec(ks, kqs, qs, fr, prec)
