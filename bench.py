@@ -1,26 +1,36 @@
 #!/usr/bin/env python
 """Benchmark of the chi0 / E_c(q) path on one MI355X.
 
-Workload: the O2-in-box configuration - 12 x 12 x 13 bohr cell, 48^3 grid, one
-k-point (Gamma), 16 occupied + 800 unoccupied plane-wave states (about 11,900
-coefficients each), 2 PAW atoms x 13 projectors, 1500-1503 G-vectors, 16
-imaginary frequencies, three q-points (q -> 0 with the optical head, 0.1 and
-0.2 x 2 pi / 12 along x). Inputs are seeded synthetic data of that shape and
-are resident on the device before timing starts.
+Default workload: the metal slab in its precision form - 9 x 9 x 36 bohr cell,
+40 x 40 x 160 grid, 8 k-points (2 x 2 x 2, Gamma-centred, w_k = 1/8), 120 + 3000
+plane-wave states per k (about 32,000 coefficients each) with Fermi-smeared
+occupations (T = 0.01 Ha, every pair with f_n - f_m > 1e-8: about 0.9 million
+transitions per k), 20 PAW atoms x 18 projectors, NG = 4011 G-vectors at
+q = 0.1 x 2 pi/9 along x, 16 imaginary frequencies. Inputs are seeded synthetic
+data of that shape, resident on the device before timing starts.
 
-One step = E_c(q) for all three q-points through the C ABI: orbitals, pair
-densities, PAW correction, optical row, weights, grouped rank-k update of
-chi0 and the FP64 Cholesky log-determinant with the frequency sum.
+One step = the complete chi0 contribution of one k-point (Eq. chi0's k sum,
+Table 1 steps 3-11): orbitals, pair densities (FP32 FFTs), PAW correction,
+weights and the grouped rank-k update on BF16 (or FP16) hi/lo MFMA, added into
+the q-point's chi0 (rpa_chi0 for the first k of a pass over the 8 k-points,
+rpa_chi0_add for the others). ms/q-point = 8 steps + the E_c stage (FP64
+Cholesky log-determinant and frequency sum, Eq. rpa), which is timed apart on
+the chi0 of one complete pass.
 
-value = useful chi0 flops (4 NG^2 P nw per q, the Hermitian complex count)
-        per second of the whole step, split precision (FP32 FFT, BF16x3 MFMA).
-The FP64 path is timed on the same inputs for the split-vs-FP64 comparison.
+value = useful chi0 flops (4 NG^2 P nw per k, the Hermitian complex count) per
+second of the timed steps. The FP64 path is timed on the first --fp64-kpoints
+k-points, and E_c(q) of split and FP64 is compared on the chi0 of those same
+k-points (all 8 with --fp64-kpoints 8).
+
+--workload o2box runs the O2-in-box line instead (12 x 12 x 13 bohr, 48^3 grid,
+16 + 800 states, NG ~ 1500, three q-points in one batched call per step).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -31,55 +41,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "chi0 build TFLOP/s + ms/q-point for E_c at 1e-6 Ha, split-precision vs FP64"
 PEAK_TFLOPS = {"split_bf16": 2500.0, "split_fp16": 2500.0, "fp64": 78.6}
+HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 4: ("k_herk_split4", "k_herk_split2.hip"),
+                5: ("k_herk_split5", "k_herk_split2.hip"), 6: ("k_herk_split6", "k_herk_split2.hip")}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_inputs(rpa, wl, device):
-    fr = rpa.Freq(wl.omega, wl.omega_weight)
-    ks = [rpa.States.from_synth(s, wl.paw, device) for s in wl.kpoints]
-    import synth
-    qspecs = []
-    for qp in wl.qpoints:
-        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
-        Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
-        qspecs.append(rpa.QSpec(qp.q, gm, Q, optical=qp.optical, qhat=qp.qhat, Dpaw=synth.paw_d_table(wl.paw),
-                                weight=qp.weight, device=device))
-    return ks, qspecs, fr
+def npairs(s, t):
+    return int(np.sum(s.f[:, None] - t.f[None, :] > 1e-8))
 
 
-def run_steps(torch, ctx, ks, qspecs, fr, prec, steps, profile=False, use_graph=False):
-    """`steps` passes of E_c(q) over all q-points (one batched call per step)."""
-    if steps <= 0:
-        return 0.0, None, None
-    out = None
-    torch.cuda.synchronize()
-    if profile:
-        ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        out = ctx.ec_batched(ks, ks, qspecs, fr, prec, use_graph=use_graph, out=out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.check()
-    prof = ctx.profile_get() if profile else None
-    if profile:
-        ctx.profile(False)
-    ecs = [float(x) for x in out[0].cpu().numpy()[: len(qspecs)]]
-    return (t1 - t0), ecs, prof
-
-
-HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 4: ("k_herk_split4", "k_herk_split2.hip"),
-                5: ("k_herk_split5", "k_herk_split2.hip")}
-
-
-def measured_traffic(kernel, src):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if that summary was
-    taken on the current source of the kernel (sha256 recorded in it); None otherwise."""
+def measured_traffic(kernel, src, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary for this workload, if
+    that summary was taken on the current source of the kernel (sha256 recorded in it); None otherwise."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_o2box_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -93,57 +71,336 @@ def measured_traffic(kernel, src):
     return float(fields["bytes_per_launch"])
 
 
-def cpu_baseline(wl, iq=1, n_sample_occ=8):
-    """The FP64 oracle on a bounded sample of the same workload: the chi0 build of
-    q-point iq (orbitals, pair densities, PAW, weights, grouped update) for the
-    pairs of the first n_sample_occ occupied states with every unoccupied state."""
+def executed_mfma_flops(variant, NG, P, nw):
+    """MFMA flops the split kernel issues for one q and P pairs: its lower-triangle tiles incl. the diagonal,
+    K padded to 32 per chunk (ignored here: chunks are large), 12 real 16-bit products per complex
+    multiply-add (4 real products x 3 split terms)."""
+    if variant == 6:
+        nt = (NG + 127) // 128
+        elems = nt * (nt + 1) // 2 * 128 * 128
+    elif variant >= 4:
+        nr = (NG + 63) // 64
+        elems = sum(i // 2 + 1 for i in range(nr)) * 64 * 128
+    else:
+        nT = (NG + 63) // 64
+        elems = nT * (nT + 1) / 2 * 64 * 64
+    return elems * nw * P * 12 * 2
+
+
+# ------------------------------------------------------------------------------------------ CPU baseline
+def _oracle_sample(path):
+    """Child process: the FP64 oracle's chi0 build of the sample saved at `path`; prints one JSON line."""
     import oracle
+    z = np.load(path)
+    A, grid, q, ecut = z["A"], tuple(int(x) for x in z["grid"]), z["q"], float(z["ecut"])
+    C, P, eps, f = z["C"], z["P"], z["eps"], z["f"]
+    omega, wk, vol = z["omega"], float(z["wk"]), float(abs(np.linalg.det(z["A"])))
+    times = []
+    for _ in range(int(z["repeats"])):
+        t0 = time.perf_counter()
+        gm = oracle.gsphere(A, q, ecut)
+        pairs = oracle.pair_list(f, f)
+        phi = oracle.orbitals(C, z["miller"], grid)
+        rho = oracle.pseudo_pair_density(phi, phi, pairs, gm, grid)
+        rho += oracle.paw_correction(P, P, pairs, z["Q"], z["offsets"])
+        a = oracle.transition_weights(eps, eps, f, f, pairs, wk, vol, omega)
+        chi = oracle.chi0_grouped(rho, a)
+        times.append(time.perf_counter() - t0)
+    flops = 4.0 * len(gm) ** 2 * pairs[0].size * omega.size
+    print(json.dumps({"times": times, "flops": flops, "pairs": int(pairs[0].size), "bands": int(C.shape[0]),
+                      "NG": int(len(gm)), "chi0_max": float(np.abs(chi).max())}), flush=True)
+
+
+def cpu_baseline(wl, iq, band_stride, label):
+    """The FP64 oracle timed on the host on a band subset of k-point 0 (every band_stride-th band and all
+    the transitions among them): median of 3 runs with every core, and one run in a child process pinned to
+    one CPU with one BLAS thread."""
+    import tempfile
     import synth
-    try:
-        import threadpoolctl
-        blas = max((d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()), default=1)
-    except Exception:
-        blas = 1
-    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    qp = wl.qpoints[iq]
     s = wl.kpoints[0]
+    qp = wl.qpoints[iq]
+    keep = np.arange(0, s.nbands, band_stride)
+    import paper_1307_8052_amd as rpa
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    fd, path = tempfile.mkstemp(suffix=".npz")
+    os.close(fd)
+    base = dict(A=wl.A, grid=np.asarray(wl.grid), q=qp.q, ecut=qp.ecut, miller=s.miller, C=s.C[keep],
+                P=s.P[keep], eps=s.eps[keep], f=s.f[keep], omega=wl.omega, wk=s.weight,
+                Q=synth.paw_q_table(wl.paw, wl.A, qp.q, gm), offsets=wl.paw.offsets)
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        np.savez(path, repeats=3, **base)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", path],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(r.stderr[-2000:])
+        allc = json.loads(r.stdout.strip().splitlines()[-1])
+        one = None
+        if hasattr(os, "sched_setaffinity"):
+            np.savez(path, repeats=1, **base)
+            cpu0 = sorted(os.sched_getaffinity(0))[0]
+            env1 = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+            r1 = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", path],
+                                capture_output=True, text=True, env=env1,
+                                preexec_fn=lambda: os.sched_setaffinity(0, {cpu0}))
+            if r1.returncode == 0:
+                one = json.loads(r1.stdout.strip().splitlines()[-1])
+    finally:
+        os.unlink(path)
+    med = float(np.median(allc["times"]))
+    out = {"value": allc["flops"] / med / 1e12, "unit": "TFLOP/s", "cores": int(ncpu), "kind": "oracle",
+           "sample": f"{label}: chi0 build (orbitals, pair densities, PAW, weights, grouped update) of the "
+                     f"{allc['pairs']} transitions among {allc['bands']} bands (every {band_stride}th band of "
+                     f"k-point 0), NG = {allc['NG']}, {wl.omega.size} frequencies; median of "
+                     f"{len(allc['times'])} runs {med:.1f} s",
+           "seconds_median": med, "seconds_runs": allc["times"]}
+    if one:
+        out["one_core"] = {"value": one["flops"] / one["times"][0] / 1e12, "unit": "TFLOP/s", "cores": 1,
+                           "seconds": one["times"][0]}
+    return out
+
+
+# ------------------------------------------------------------------------------------------ slab
+def slab_inputs(rpa, wl, dev):
+    import synth
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    ks = [rpa.States.from_synth(s, wl.paw, dev) for s in wl.kpoints]
+    qp = wl.qpoints[0]
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    qs = rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight, device=dev)
+    return ks, qs, fr
+
+
+def k_step(ctx, ks, qs, fr, chi, i, prec):
+    """chi0 contribution of k-point i mod 8: overwrite at the first k of a pass, add for the others."""
+    k = i % len(ks)
+    if k == 0:
+        out = ctx.chi0([ks[0]], [ks[0]], qs, fr, prec)
+        chi.copy_(out)
+        del out
+    else:
+        ctx.chi0_add([ks[k]], [ks[k]], qs, fr, chi, prec)
+
+
+def run_slab(args, torch, rpa, synth):
+    dev = "cuda:0"
+    t = time.perf_counter()
+    wl = synth.config2(device=dev)
+    log(f"metal-slab workload generated in {time.perf_counter() - t:.1f} s")
+    ks, qs, fr = slab_inputs(rpa, wl, dev)
+    nk, nw, NG = len(ks), fr.nw, qs.NG
+    P = [npairs(s, s) for s in wl.kpoints]
+    flops_k = [4.0 * NG * NG * p * nw for p in P]
+    log(f"NG = {NG}, pairs per k = {P}")
+    ctx = rpa.Context(wl.A, wl.grid, device=0)
+    prec = args.precision
+    variant = ctx.tune_get(NG, prec)
+    chi = torch.empty((nw, NG, NG), dtype=torch.complex128, device=dev)
+
+    # the chi0 build for one k reuses the call's internal buffers: build them at full size with the
+    # first rpa_chi0, so that no step allocates
+    for i in range(args.warmup):
+        k_step(ctx, ks, qs, fr, chi, i, prec)
+        torch.cuda.synchronize()
+    ctx.check()
+
+    # timed steps: one k-point each, a pass over the 8 k-points every 8 steps
+    torch.cuda.synchronize()
+    ctx.profile(True)
     t0 = time.perf_counter()
-    gm = oracle.gsphere(wl.A, qp.q, qp.ecut)
-    Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
-    phi = oracle.orbitals(s.C, s.miller, wl.grid)
-    n_all, m_all = oracle.pair_list(s.f, s.f)
-    sel = n_all < n_sample_occ
-    pairs = (n_all[sel], m_all[sel])
-    rho = oracle.pseudo_pair_density(phi, phi, pairs, gm, wl.grid)
-    rho += oracle.paw_correction(s.P, s.P, pairs, Q, wl.paw.offsets)
-    a = oracle.transition_weights(s.eps, s.eps, s.f, s.f, pairs, s.weight, wl.volume, wl.omega)
-    chi = oracle.chi0_grouped(rho, a)
-    t1 = time.perf_counter()
-    P = pairs[0].size
-    flops = 4.0 * len(gm) ** 2 * P * wl.omega.size
-    return {"value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": int(max(ncpu, blas)),
-            "kind": "oracle",
-            "sample": f"chi0 build of q-point {iq} (NG={len(gm)}) for {P} pairs (first {n_sample_occ} occupied "
-                      f"states x all unoccupied), orbitals included; {t1 - t0:.1f} s",
-            "seconds": t1 - t0, "chi0_norm": float(np.abs(chi).max())}
+    for i in range(args.steps):
+        k_step(ctx, ks, qs, fr, chi, i, prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.check()
+    prof = ctx.profile_get()
+    ctx.profile(False)
+    flops_timed = sum(flops_k[i % nk] for i in range(args.steps))
+    value = flops_timed / dt / 1e12
+    ms_step = dt / args.steps * 1e3
+    log(f"split: {ms_step:.1f} ms per k-step, {value:.1f} TFLOP/s")
+    log("stage ms (timed region): " + ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items()))
+    # complete the last pass untimed, so that chi holds the q-point's whole chi0
+    for i in range(args.steps, (args.steps + nk - 1) // nk * nk if args.steps % nk else args.steps):
+        k_step(ctx, ks, qs, fr, chi, i, prec)
+    if args.steps < nk:
+        for i in range(args.steps, nk):
+            k_step(ctx, ks, qs, fr, chi, i, prec)
+
+    # E_c stage on the complete chi0 (second call timed)
+    ec_full, F_full = ctx.ec_from_chi0(qs, fr, chi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ec_full, F_full = ctx.ec_from_chi0(qs, fr, chi)
+    torch.cuda.synchronize()
+    ms_ec = (time.perf_counter() - t0) * 1e3
+    ctx.check()
+    ec_split_full = float(ec_full.cpu()[0])
+    ms_q = nk * ms_step + ms_ec
+    log(f"E_c(q) split, all {nk} k-points: {ec_split_full:.12f} Ha; E_c stage {ms_ec:.1f} ms; {ms_q:.0f} ms/q")
+
+    # FP64 on the first n64 k-points, split on the same ones, E_c of both partial sums
+    n64 = max(0, min(args.fp64_kpoints, nk))
+    fp64 = None
+    if n64:
+        chi64 = torch.empty_like(chi)
+        ms64 = []
+        ctx.profile(True)
+        for i in range(n64):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k_step(ctx, ks, qs, fr, chi64, i, "fp64")
+            torch.cuda.synchronize()
+            ms64.append((time.perf_counter() - t0) * 1e3)
+            log(f"fp64 k-step {i}: {ms64[-1]:.0f} ms")
+        ctx.check()
+        prof64 = ctx.profile_get()
+        ctx.profile(False)
+        e64, F64 = ctx.ec_from_chi0(qs, fr, chi64)
+        ctx.check()
+        ec64 = float(e64.cpu()[0])
+        if n64 == nk:
+            ecs = ec_split_full
+        else:
+            for i in range(n64):
+                k_step(ctx, ks, qs, fr, chi, i, prec)
+            es, _ = ctx.ec_from_chi0(qs, fr, chi)
+            ctx.check()
+            ecs = float(es.cpu()[0])
+        del chi64
+        ms_step64 = float(np.mean(ms64))
+        herk64_ms, _ = prof64["herk"]
+        herk64_flops = sum(flops_k[:n64])
+        fp64 = {"value": sum(flops_k[:n64]) / (sum(ms64) * 1e-3) / 1e12, "unit": "TFLOP/s",
+                "ms_per_k_step": ms_step64, "ms_per_q": nk * ms_step64 + ms_ec, "kpoints_timed": n64,
+                "herk_tflops": herk64_flops / (herk64_ms * 1e-3) / 1e12,
+                "herk_frac_of_fp64_peak": herk64_flops / (herk64_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+                "stage_ms_per_k": {k: v[0] / n64 for k, v in prof64.items()},
+                "ec_partial": ec64, "ec_split_partial": ecs, "ec_split_minus_fp64_ha": ecs - ec64}
+        log(f"fp64: {ms_step64:.0f} ms per k-step; E_c over k-points 0..{n64 - 1}: fp64 {ec64:.12f} "
+            f"split {ecs:.12f} diff {ecs - ec64:.3e} Ha")
+
+    # roofline of the split rank-k kernel over the timed steps
+    stage_ms = {k: v[0] / args.steps for k, v in prof.items()}
+    dominant = max(stage_ms, key=stage_ms.get)
+    herk_ms, herk_n = prof["herk"]
+    achieved = flops_timed / (herk_ms * 1e-3) / 1e12
+    executed = sum(executed_mfma_flops(variant, NG, P[i % nk], nw) for i in range(args.steps))
+    peak = PEAK_TFLOPS[prec]
+    kname, ksrc = HERK_KERNELS[variant]
+    roofline = {"kernel": f"{kname} (grouped complex rank-k update of chi0, split {prec[6:]} hi/lo)",
+                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(kname, ksrc, "slab"), "avg_launch_ms": herk_ms / max(herk_n, 1),
+                "launches": herk_n, "algorithmic_flops_per_launch": flops_timed / max(herk_n, 1),
+                "executed_mfma_tflops": executed / (herk_ms * 1e-3) / 1e12,
+                "executed_mfma_frac": executed / (herk_ms * 1e-3) / 1e12 / peak,
+                "dominant_stage": dominant}
+    out = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{prec[6:]}x3 MFMA / f32 FFT / f64 log-det",
+        "data": "synthetic",
+        "config": {"workload": "metal slab: 9x9x36 bohr, 40x40x160 grid, 8 k-points, 120+3000 Fermi-smeared "
+                               "states per k (T = 0.01 Ha), 20x18 PAW projectors, NG = %d, 16 imaginary "
+                               "frequencies; one step = one k-point's chi0 contribution" % NG,
+                   "precision": prec, "NG": NG, "pairs_per_k": P, "nw": nw, "kpoints": nk},
+        "ms_per_q": ms_q, "ms_ec_stage": ms_ec,
+        "ec_split": ec_split_full,
+        "ec_split_minus_fp64_ha": fp64 and fp64["ec_split_minus_fp64_ha"],
+        "speedup_vs_fp64": fp64 and fp64["ms_per_q"] / ms_q,
+        "stage_ms": stage_ms,
+        "fp64": fp64,
+        "roofline": roofline,
+    }
+    ctx.close()
+    return out, wl
+
+
+# ------------------------------------------------------------------------------------------ O2 box
+def run_o2box(args, torch, rpa, synth):
+    dev = "cuda:0"
+    wl = synth.config1()
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    ks = [rpa.States.from_synth(s, wl.paw, dev) for s in wl.kpoints]
+    qspecs = []
+    for qp in wl.qpoints:
+        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+        qspecs.append(rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), optical=qp.optical,
+                                qhat=qp.qhat, Dpaw=synth.paw_d_table(wl.paw), weight=qp.weight, device=dev))
+    P = npairs(wl.kpoints[0], wl.kpoints[0])
+    NGs = [q.NG for q in qspecs]
+    nw = fr.nw
+    flops_step = sum(4.0 * ng * ng * P * nw for ng in NGs)
+    ctx = rpa.Context(wl.A, wl.grid, device=0)
+
+    def steps(prec, n, profile=False):
+        out = None
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            out = ctx.ec_batched(ks, ks, qspecs, fr, prec, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.check()
+        prof = ctx.profile_get() if profile else None
+        ctx.profile(False)
+        return dt, [float(x) for x in out[0].cpu().numpy()[:len(qspecs)]], prof
+
+    prec = args.precision
+    variant = ctx.tune_get(NGs[0], prec)
+    steps(prec, args.warmup)
+    dt, ec_split, prof = steps(prec, args.steps, True)
+    steps("fp64", 1)
+    dt64, ec64, prof64 = steps("fp64", args.steps, True)
+    ms_step, ms_step64 = dt / args.steps * 1e3, dt64 / args.steps * 1e3
+    herk_ms, herk_n = prof["herk"]
+    achieved = flops_step * args.steps / (herk_ms * 1e-3) / 1e12
+    executed = sum(executed_mfma_flops(variant, ng, P, nw) for ng in NGs) * args.steps
+    kname, ksrc = HERK_KERNELS[variant]
+    peak = PEAK_TFLOPS[prec]
+    out = {
+        "metric": METRIC, "value": flops_step * args.steps / dt / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"{prec[6:]}x3 MFMA / f32 FFT / f64 log-det",
+        "data": "synthetic",
+        "config": {"workload": "O2-in-box: 12x12x13 bohr, 48^3 grid, Gamma, 16+800 states, 2x13 PAW projectors, "
+                               "3 q-points (optical, 0.1, 0.2 x 2pi/12), 16 imaginary frequencies; one step = "
+                               "E_c of the three q-points", "precision": prec, "NG": NGs, "pairs_per_q": P,
+                   "nw": nw},
+        "ms_per_q": ms_step / len(NGs), "ec_split": ec_split, "ec_fp64": ec64,
+        "ec_split_minus_fp64_ha": [a - b for a, b in zip(ec_split, ec64)],
+        "speedup_vs_fp64": ms_step64 / ms_step,
+        "stage_ms": {k: v[0] / args.steps for k, v in prof.items()},
+        "fp64": {"value": flops_step * args.steps / dt64 / 1e12, "unit": "TFLOP/s", "ms_per_step": ms_step64,
+                 "ms_per_q": ms_step64 / len(NGs), "stage_ms": {k: v[0] / args.steps for k, v in prof64.items()}},
+        "roofline": {"kernel": f"{kname} (grouped complex rank-k update of chi0, split {prec[6:]} hi/lo)",
+                     "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": measured_traffic(kname, ksrc, "o2box"),
+                     "avg_launch_ms": herk_ms / max(herk_n, 1), "launches": herk_n,
+                     "algorithmic_flops_per_launch": flops_step * args.steps / max(herk_n, 1),
+                     "executed_mfma_tflops": executed / (herk_ms * 1e-3) / 1e12,
+                     "executed_mfma_frac": executed / (herk_ms * 1e-3) / 1e12 / peak},
+    }
+    ctx.close()
+    return out, wl
 
 
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--oracle-sample":
+        _oracle_sample(sys.argv[2])
+        return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=8, help="timed steps (slab: one k-point each)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="slab", choices=["slab", "o2box"])
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "split_fp16"])
-    ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: steps)")
-    ap.add_argument("--n-unocc", type=int, default=800)
+    ap.add_argument("--fp64-kpoints", type=int, default=2,
+                    help="slab: k-points run through the FP64 path for its timing and the E_c comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
-    ap.add_argument("--variant", type=int, default=0,
-                    help="force the split rank-k kernel variant (1, 4, 5); 0 keeps the library's choice")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the per-q loop and adjoint timings")
-    ap.add_argument("--cpu-sample-occ", type=int, default=8,
-                    help="occupied states in the oracle's sample (all unoccupied states paired with each)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -160,132 +417,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    dev = "cuda:0"
-    t = time.perf_counter()
-    wl = synth.config1(n_unocc=args.n_unocc)
-    log(f"workload generated in {time.perf_counter() - t:.1f} s")
-    ks, qspecs, fr = make_inputs(rpa, wl, dev)
-    P = int(np.sum(ks[0].f[:, None] - ks[0].f[None, :] > 1e-8))
-    NGs = [qs.NG for qs in qspecs]
-    nw = fr.nw
-    flops_step = sum(4.0 * ng * ng * P * nw for ng in NGs)
-    herk_flops_step = flops_step
-
-    ctx = rpa.Context(wl.A, wl.grid, device=0)
-    if args.variant:
-        for ng in NGs:
-            ctx.tune_set(ng, args.variant, args.precision)
-    ctx_variant = ctx.tune_get(NGs[0], args.precision)
-    # split path
-    run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.warmup)
-    dt, ec_split, prof = run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.steps, profile=True)
-    ms_step = dt / args.steps * 1e3
-    value = flops_step * args.steps / dt / 1e12
-    log(f"split: {ms_step:.2f} ms/step, {value:.2f} TFLOP/s, E_c = {ec_split}")
-    log("stage ms (timed region): " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in prof.items()))
-    # the same step replayed from a captured graph (launch overhead removed)
-    ms_step_graph, ec_graph = None, None
-    if not args.no_graph:
-        run_steps(torch, ctx, ks, qspecs, fr, args.precision, 1, use_graph=True)
-        dtg, ec_graph, _ = run_steps(torch, ctx, ks, qspecs, fr, args.precision, args.steps, use_graph=True)
-        ms_step_graph = dtg / args.steps * 1e3
-        log(f"split (graph replay): {ms_step_graph:.2f} ms/step")
-
-    # the same q-points as a loop of single-q calls, and the adjoint of one q-point
-    extras = {}
-    if not args.no_extras:
-        def loop_step():
-            for qs in qspecs:
-                ctx.ec(ks, ks, qs, fr, args.precision)
-        loop_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            loop_step()
-        torch.cuda.synchronize()
-        extras["per_q_loop_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
-        log(f"per-q loop: {extras['per_q_loop_ms_per_step']:.2f} ms/step")
-        ctx.ec_backward(ks[0], ks[0], qspecs[1], fr)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ecb, _ = ctx.ec_backward(ks[0], ks[0], qspecs[1], fr)
-        torch.cuda.synchronize()
-        extras["adjoint_fp64_ms_q1"] = (time.perf_counter() - t0) * 1e3
-        ctx.check()
-        log(f"adjoint (FP64, q-point 1, E_c and dE_c/d(eps, C, P)): {extras['adjoint_fp64_ms_q1']:.1f} ms")
-
-    # FP64 path on the same inputs
-    k64 = args.fp64_steps if args.fp64_steps is not None else args.steps
-    if k64 > 0:
-        run_steps(torch, ctx, ks, qspecs, fr, "fp64", 1)
-        dt64, ec64, prof64 = run_steps(torch, ctx, ks, qspecs, fr, "fp64", k64, profile=True)
-        ms_step64 = dt64 / k64 * 1e3
-        value64 = flops_step * k64 / dt64 / 1e12
-        log(f"fp64: {ms_step64:.2f} ms/step, {value64:.2f} TFLOP/s, E_c = {ec64}")
-
-    # roofline of the dominant kernel of the split step
-    stage_ms = {k: v[0] / args.steps for k, v in prof.items()}
-    dominant = max(stage_ms, key=stage_ms.get)
-    herk_ms, herk_n = prof["herk"]
-    # MFMA flops the split kernel issues: its lower-triangle tiles incl. the diagonal, K padded to 32,
-    # 12 real 16-bit products per complex multiply-add (4 real products x 3 split terms)
-    executed = 0.0
-    for ng in NGs:
-        if ctx_variant >= 4:
-            nr = (ng + 63) // 64
-            elems = sum(i // 2 + 1 for i in range(nr)) * 64 * 128
-        else:
-            tm = 64 if ctx_variant == 1 else 128
-            nT = (ng + tm - 1) // tm
-            elems = nT * (nT + 1) / 2 * tm * tm
-        executed += elems * nw * ((P + 31) // 32 * 32) * 12 * 2
-    executed *= args.steps
-    herk_avg_ms = herk_ms / max(herk_n, 1)
-    achieved = herk_flops_step * args.steps / (herk_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    variant = ctx_variant
-    kname, ksrc = HERK_KERNELS[variant]
-    roofline = {"kernel": f"{kname} (grouped complex rank-k update of chi0, variant {variant})", "bound": "mfma",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(kname, ksrc), "avg_launch_ms": herk_avg_ms, "launches": herk_n,
-                "algorithmic_flops_per_launch": herk_flops_step / len(NGs),
-                "executed_mfma_tflops": executed / (herk_ms * 1e-3) / 1e12,
-                "executed_mfma_frac": executed / (herk_ms * 1e-3) / 1e12 / peak,
-                "dominant_stage": dominant}
-    fp64 = None
-    if k64 > 0:
-        herk64_ms, herk64_n = prof64["herk"]
-        fp64 = {"value": value64, "unit": "TFLOP/s", "ms_per_step": ms_step64, "ms_per_q": ms_step64 / len(NGs),
-                "steps": k64, "ec": ec64,
-                "herk_tflops": herk_flops_step * k64 / (herk64_ms * 1e-3) / 1e12,
-                "herk_frac_of_fp64_peak": herk_flops_step * k64 / (herk64_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
-                "stage_ms": {k: v[0] / k64 for k, v in prof64.items()}}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16x3 MFMA / f32 FFT / f64 log-det" if args.precision == "split_bf16"
-        else "fp16x3 MFMA / f32 FFT / f64 log-det",
-        "data": "synthetic",
-        "config": {"workload": "O2-in-box: 12x12x13 bohr, 48^3 grid, Gamma, 16+%d states, 2x13 PAW projectors, "
-                               "3 q-points (optical, 0.1, 0.2 x 2pi/12), 16 imaginary frequencies" % args.n_unocc,
-                   "precision": args.precision, "NG": NGs, "pairs_per_q": P, "nw": nw},
-        "ms_per_q": ms_step / len(NGs),
-        "ec_split": ec_split, "ec_fp64": fp64 and fp64["ec"],
-        "ec_split_minus_fp64_ha": fp64 and [a - b for a, b in zip(ec_split, fp64["ec"])],
-        "ec_split_minus_fp64_rel": fp64 and [(a - b) / abs(b) for a, b in zip(ec_split, fp64["ec"])],
-        "ms_per_step_graph": ms_step_graph,
-        "ec_graph_equals_eager": None if ec_graph is None else ec_graph == ec_split,
-        "speedup_vs_fp64": fp64 and fp64["ms_per_step"] / ms_step,
-        **extras,
-        "stage_ms": stage_ms,
-        "fp64": fp64,
-        "roofline": roofline,
-    }
-    ctx.close()
+    if args.workload == "slab":
+        out, wl = run_slab(args, torch, rpa, synth)
+        band_stride, label = 80, "metal slab"
+    else:
+        out, wl = run_o2box(args, torch, rpa, synth)
+        band_stride, label = 4, "O2-in-box q-point 0"
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(wl, n_sample_occ=args.cpu_sample_occ)
+        out["cpu_baseline"] = cpu_baseline(wl, 0, band_stride, label)
     print(json.dumps(out), flush=True)
 
 

@@ -241,7 +241,10 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
  *       sums added into FP64 every 8 K-steps;
  *   5 = variant 4 with eight waves per workgroup, two per SIMD (bit-identical
  *       to 4).
- * Without an entry, NG >= 385 uses variant 5, smaller spheres variant 1.
+ *   6 = 128x128 tiles, eight waves of 32x64, FP32 accumulation over a chunk of
+ *       at most 8192 pairs, added into FP64 per chunk.
+ * Without an entry, NG >= 385 uses variant 6, smaller spheres variant 1
+ * (rpa_set_autotune: calls record an entry per size bucket).
  *  rpa_autotune     times the variants on synthetic operands of the given
  *                   shape on `stream` (synchronizes) and records the fastest.
  *  rpa_tune_set/get force / read the choice (FP64 has variant 0 only;
@@ -257,6 +260,16 @@ int rpa_autotune(rpa_ctx* ctx, rpa_precision prec, int NG, int npairs, int nw, v
  * z through LDS); path 1 always runs the LDS radix passes. Both give the same
  * result up to rounding order. RPA_ERR_INPUT for another value. */
 int rpa_set_pair_path(rpa_ctx* ctx, int path);
+
+/* Split precisions: with enable = 1 (the default) the first call whose
+ * sphere falls in a new size bucket (NG padded to 64, rounded up to 128 up
+ * to 2048 and to 256 beyond) times the rank-k variants on synthetic operands
+ * of that bucket (one chunk of the call's pairs, its frequencies; the call
+ * synchronizes its stream once) and records the fastest for the bucket, as
+ * rpa_autotune does. Not under graph capture and not in rpa_ec_noalloc, which
+ * use the recorded or default variant. enable = 0 keeps the defaults and
+ * rpa_tune_set choices. */
+int rpa_set_autotune(rpa_ctx* ctx, int enable);
 
 /* Upper bound on the pairs of one chunk (the K of one grouped rank-k update,
  * Eq. zher_multi's group). 0 (default): the chunk is as large as the workspace

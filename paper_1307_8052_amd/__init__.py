@@ -341,6 +341,10 @@ class Context:
         """0: register-resident pair transforms where the grid allows, 1: LDS radix passes."""
         _check(self._L.rpa_set_pair_path(self._h, int(path)), self._h)
 
+    def set_autotune(self, enable: bool):
+        """Split precisions: time the rank-k variants for each new sphere-size bucket (default on)."""
+        _check(self._L.rpa_set_autotune(self._h, int(bool(enable))), self._h)
+
     def set_chunk_pairs(self, max_pairs: int):
         """Upper bound on the pairs of one grouped rank-k update (0: set by the workspace budget)."""
         _check(self._L.rpa_set_chunk_pairs(self._h, int(max_pairs)), self._h)

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librpa_mi355x.so")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["k_fft.hip", "k_fft_reg.hip", "k_la.hip", "k_herk_split.hip", "k_herk_split2.hip", "k_adjoint.hip", "runtime.cpp"]
+SOURCES = ["k_fft.hip", "k_fft_reg.hip", "k_la.hip", "k_paw.hip", "k_herk_split.hip", "k_herk_split2.hip", "k_adjoint.hip",
+           "runtime.cpp"]
 ARCH = os.environ.get("RPA_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

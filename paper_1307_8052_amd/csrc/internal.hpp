@@ -81,6 +81,13 @@ template <typename T>
 hipError_t launch_paw_add(const T* Yre, const T* Yim, const int32_t* pn, int nlo, const int32_t* pm,
                           const double* Pkq, int ldP, int nprojtot, int npairs, int NG, int NGp, T* rho_re,
                           T* rho_im, hipStream_t s);
+// PAW term as an MFMA GEMM (k_paw.hip): Z_m = Q P'_m for m = m_lo .. m_lo + nslots - 1 into Zr/Zi
+// [nslots][nproj][NGp], then rho[p] += conj(P_k[pn[p]]) Z_{pm[p]} for the npairs pairs (pm within the
+// slots); NGp a multiple of 64
+template <typename T>
+hipError_t launch_paw_mfma(const double* Pk, const double* Pkq, int ldP, const int32_t* pn, const int32_t* pm,
+                           int npairs, int m_lo, int nslots, const int32_t* proj_off, const int32_t* qoff, int natoms,
+                           int nproj, const double* Q, int NG, int NGp, T* Zr, T* Zi, T* rre, T* rim, hipStream_t s);
 
 template <typename T>
 hipError_t launch_optical_row(const double* Ck, const double* Ckq, int nQ, const double* wq, const double* Pk,

@@ -96,6 +96,7 @@ struct rpa_ctx {
     double prof_ms[16] = {0};
     long long prof_n[16] = {0};
     int last_nq = 0;
+    std::vector<int> last_qorder;   // caller's q index of each job of the last E_c evaluation
     // rank-k update variant per (precision, padded NG): 1 = 64x64 tiles, 4 / 5 = pipelined 64x128 tiles
     // with FP64 accumulation
     // (4: four waves, 5: eight waves per workgroup)
@@ -108,6 +109,7 @@ struct rpa_ctx {
     bool capturing = false;
     bool pair_reg = true;   // register-resident pair transforms where supported
     int max_chunk = 0;      // upper bound on the pairs of one chunk (0: set by the workspace budget alone)
+    bool autotune = true;   // split precisions: time the rank-k variants for each new sphere-size bucket
     // arena mode (rpa_ec_noalloc): workspaces are carved from the device scratch instead of hipMalloc'd, and
     // host tables are staged in ordinary host memory instead of a pinned arena
     void* scratch = nullptr;            // this device's scratch (set at rpa_create)
@@ -591,6 +593,16 @@ struct QJob {
     double* ec = nullptr;
     double* F = nullptr;
     bool fresh = false;   // the accumulator holds nothing yet (no update has run into it)
+    int ld = 0;           // leading dimension of this q-point's chi0 / -K matrices (its class's)
+    int orig = 0;         // index of this q-point in the caller's list (jobs are ordered by class)
+};
+
+// q-points whose matrices share one leading dimension: adjacent jobs q0 .. q0 + nq - 1, accumulators at cr
+// (all real parts) and ci (all imaginary parts), one matrix every ld^2 doubles
+struct QClass {
+    int ld = 0, q0 = 0, nq = 0;
+    double* cr = nullptr;
+    double* ci = nullptr;
 };
 
 struct Batch {
@@ -609,16 +621,36 @@ struct Batch {
     std::vector<KSet> ks;
     std::vector<QJob> qj;
     bool m_major = false;            // forward chi0: pairs ordered by m, then n (orbital reuse in cache)
-    int ld = 0;                      // leading dimension of every chi0 / -K matrix of the batch (max NGp)
+    bool allow_paw_mfma = true;      // the adjoint keeps the factorised VALU PAW term (its own tables)
+    bool paw_mfma = false;           // set by presize: PAW correction as an MFMA GEMM per band m
+    int ld = 0;                      // the largest leading dimension of the batch's chi0 / -K matrices
+    std::vector<QClass> cls;         // the q-points grouped by leading dimension
     bool fp64() const { return prec == RPA_FP64; }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
 };
+
+int autotune_run(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, hipStream_t s);
+
+// sphere sizes that share one autotuning result: the padded sphere rounded up to 128 (up to 2048) or 256
+int tune_bucket(int NGp) {
+    const int g = NGp <= 2048 ? 128 : 256;
+    return (NGp + g - 1) / g * g;
+}
 
 int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
     if (prec == RPA_FP64) return 0;
     auto it = c->tune.find(tune_key(prec, NGp));
     if (it != c->tune.end()) return it->second;
     return ((NGp + 127) / 128 >= 4) ? 6 : 1;
+}
+
+// Leading dimension of a q-point's matrices in a batch of nq: its padded sphere alone, or, with several
+// q-points, the padded sphere rounded up to 128 (up to 2048) or 256 (beyond), so that spheres of similar
+// size share one batched factorisation at most 1/8 of padding per dimension
+int class_ld(int NGp, int nq) {
+    if (nq <= 1 || NGp <= 1024) return NGp;
+    const int g = NGp <= 2048 ? 128 : 256;
+    return (NGp + g - 1) / g * g;
 }
 
 int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem, int variant) {
@@ -759,7 +791,7 @@ void* buf(Batch& B, const char* name) { return (B.c->arena ? B.c->abufs : B.c->b
 
 // Work buffers, sized once for every q of the batch (never grown while launching).
 struct WorkSizes {
-    size_t tbuf = 0, rho = 0, weights = 0, paw_y = 0, pack = 0, scales = 0, chi = 0;
+    size_t tbuf = 0, rho = 0, weights = 0, paw_y = 0, paw_z = 0, pack = 0, scales = 0, chi = 0;
     size_t cholL = 0, cholP = 0, small = 0, phi_k = 0, phi_kq = 0;
 };
 
@@ -779,21 +811,34 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
             P = std::max(P, (int)K.pn.size());
             if (!K.pn.empty()) nn_max = std::max(nn_max, K.k->nbands);
         }
+        if (!B.fp64() && c->autotune && !c->arena && !c->capturing && P > 0 &&
+            !c->tune.count(tune_key(B.prec, g.NGp))) {
+            // the first call with a sphere of this size bucket times the rank-k variants on it
+            const int b = tune_bucket(g.NGp);
+            if (!c->tune.count(tune_key(B.prec, b))) {
+                int rc = autotune_run(c, B.prec, b, std::max(256, std::min(P, kSplit6Chunk)), B.nw, B.s);
+                if (rc) return rc;
+            }
+            c->tune[tune_key(B.prec, g.NGp)] = c->tune[tune_key(B.prec, b)];
+        }
         Q.variant = default_variant(c, B.prec, g.NGp);
         Q.Pc = std::max(1, std::min(P, chunk_size(c, Q.qp, B.nw, el, Q.variant)));
         const int Pc = Q.Pc;
         const int nproj = B.poff.empty() ? 0 : B.poff.back();
-        // band window of a chunk: at most all bands of the k set
-        int win = 1;
+        // band windows of a chunk: n (factorised VALU PAW term) and m (MFMA PAW term)
+        int win = 1, mspan = 1;
         for (auto& K : B.ks) {
             for (size_t p0 = 0; p0 < K.pn.size(); p0 += Pc) {
                 const size_t p1 = std::min(K.pn.size(), p0 + Pc);
-                int lo = K.pn[p0], hi = K.pn[p0];
+                int lo = K.pn[p0], hi = K.pn[p0], mlo = K.pm[p0], mhi = K.pm[p0];
                 for (size_t i = p0; i < p1; ++i) {
                     lo = std::min(lo, (int)K.pn[i]);
                     hi = std::max(hi, (int)K.pn[i]);
+                    mlo = std::min(mlo, (int)K.pm[i]);
+                    mhi = std::max(mhi, (int)K.pm[i]);
                 }
                 win = std::max(win, hi - lo + 1);
+                mspan = std::max(mspan, mhi - mlo + 1);
             }
         }
         (void)nn_max;
@@ -801,29 +846,46 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         W.rho = std::max(W.rho, 2 * (size_t)Pc * g.NGp * el);
         const int lda = (Pc + 3) / 4 * 4;
         W.weights = std::max(W.weights, (size_t)std::max(B.nw, 1) * lda * sizeof(double));
-        if (nproj > 0) W.paw_y = std::max(W.paw_y, 2 * (size_t)win * nproj * g.NGp * el);
+        if (nproj > 0) {
+            W.paw_y = std::max(W.paw_y, 2 * (size_t)win * nproj * g.NGp * el);
+            W.paw_z = std::max(W.paw_z, 2 * (size_t)mspan * nproj * g.NGp * el);
+        }
         if (!B.fp64()) {
             const int NGq = (g.NGp + 127) / 128 * 128;
             const size_t blk = (size_t)((Pc + 31) / 32) * NGq * 32;
             W.pack = std::max(W.pack, blk * (2 * sizeof(float) + 4 * sizeof(unsigned short)));
             W.scales = std::max(W.scales, (size_t)(B.nw + 1 + 256) * sizeof(float));
         }
-        B.ld = std::max(B.ld, g.NGp);
+        B.ld = std::max(B.ld, Q.ld);
     }
-    // every (q, w) matrix at one leading dimension: all real parts, then all imaginary parts, so that
-    // matrix b = q nw + w sits at b * ld^2 and the E_c stage treats the batch as one set of matrices
-    const size_t nmat = B.qj.size() * (size_t)B.nw, ld2 = (size_t)B.ld * B.ld;
-    if (need_ec || need_chi) W.chi = 2 * nmat * ld2 * sizeof(double);
+    // the MFMA PAW term needs Z for every band m of a chunk's span; the factorised VALU form (Y for every
+    // band n) serves the adjoint and spans too wide for that
+    B.paw_mfma = B.allow_paw_mfma && W.paw_z > 0 && W.paw_z <= ((size_t)2 << 30);
+    if (B.paw_mfma) W.paw_y = 0;
+    else W.paw_z = 0;
+    // per class of q-points with one leading dimension: all real parts, then all imaginary parts, so that
+    // matrix b = (q - q0) nw + w of the class sits at b * ld^2 and the E_c stage factorises the class as
+    // one set of matrices
+    const size_t nmat = B.qj.size() * (size_t)B.nw;
+    size_t chi_doubles = 0, cls_mat_max = 0, panel_max = 0;
+    for (auto& C : B.cls) {
+        const size_t cm = (size_t)C.nq * B.nw;
+        chi_doubles += 2 * cm * (size_t)C.ld * C.ld;
+        cls_mat_max = std::max(cls_mat_max, cm);
+        panel_max = std::max(panel_max, cm * (size_t)C.ld);
+    }
+    if (need_ec || need_chi) W.chi = chi_doubles * sizeof(double);
     if (need_ec) {
-        W.cholL = 2 * nmat * kTile * kTile * sizeof(double);
-        W.cholP = 2 * 2 * nmat * 2 * kTile * (size_t)B.ld * sizeof(double);   // two pairs of panels in flight
+        W.cholL = 2 * cls_mat_max * kTile * kTile * sizeof(double);
+        W.cholP = 2 * 2 * panel_max * 2 * kTile * sizeof(double);   // two pairs of panels in flight
         W.small = nmat * (2 * sizeof(double) + sizeof(int)) + 64;
     }
     struct NB {
         const char* n;
         size_t b;
     } list[] = {{"phi_k", W.phi_k}, {"phi_kq", W.phi_kq}, {"tbuf", W.tbuf}, {"rho", W.rho},
-                {"weights", W.weights}, {"paw_y", W.paw_y}, {"split_pack", W.pack}, {"split_scales", W.scales},
+                {"weights", W.weights}, {"paw_y", W.paw_y}, {"paw_z", W.paw_z}, {"split_pack", W.pack},
+                {"split_scales", W.scales},
                 {"chi", W.chi}, {"chol_L", W.cholL}, {"chol_panel", W.cholP}, {"ec_small", W.small}};
     for (auto& e : list) {
         if (!e.b) continue;
@@ -833,9 +895,15 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     }
     if (W.chi) {
         double* base = static_cast<double*>(buf(B, "chi"));
-        for (size_t qi = 0; qi < B.qj.size(); ++qi) {
-            B.qj[qi].cr = base + qi * B.nw * ld2;
-            B.qj[qi].ci = base + (nmat + qi * B.nw) * ld2;
+        for (auto& C : B.cls) {
+            const size_t l2 = (size_t)C.ld * C.ld, cm = (size_t)C.nq * B.nw;
+            C.cr = base;
+            C.ci = base + cm * l2;
+            for (int i = 0; i < C.nq; ++i) {
+                B.qj[C.q0 + i].cr = C.cr + (size_t)i * B.nw * l2;
+                B.qj[C.q0 + i].ci = C.ci + (size_t)i * B.nw * l2;
+            }
+            base += 2 * cm * l2;
         }
     }
     return RPA_OK;
@@ -907,7 +975,21 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
                                             static_cast<const cplx<T>*>(B.d_tw[2]), rre, rim, B.s));
     }
     const int nproj = nproj_total(K.k);
-    if (nproj > 0) {
+    if (nproj > 0 && B.paw_mfma) {
+        int mlo = K.pm[p0], mhi = K.pm[p0];
+        for (int i = p0; i < p0 + np; ++i) {
+            mlo = std::min(mlo, (int)K.pm[i]);
+            mhi = std::max(mhi, (int)K.pm[i]);
+        }
+        const int nm = mhi - mlo + 1;
+        T* Zr = static_cast<T*>(buf(B, "paw_z"));
+        T* Zi = Zr + (size_t)nm * nproj * g.NGp;
+        ProfScope ps_(c, S_PAW, B.s);
+        HIP_TRY(launch_paw_mfma<T>(static_cast<const double*>(K.k->P), static_cast<const double*>(K.kq->P), nproj, pn,
+                                   pm, np, mlo, nm, static_cast<const int32_t*>(B.d_poff),
+                                   static_cast<const int32_t*>(B.d_qoff), K.k->natoms, nproj,
+                                   static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Zr, Zi, rre, rim, B.s));
+    } else if (nproj > 0) {
         int nlo = K.pn[p0], nhi = K.pn[p0];
         for (int i = p0; i < p0 + np; ++i) {
             nlo = std::min(nlo, (int)K.pn[i]);
@@ -940,7 +1022,7 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
 // chi0(w) += rho diag(a(w)) rho^H for one chunk, with the job's kernel variant
 // chi0 accumulator of one job: nw matrices of ld x ld, real and imaginary blocks
 hipError_t zero_accumulator(Batch& B, QJob& Q) {
-    const size_t n = (size_t)B.nw * B.ld * B.ld / 2;   // complex pairs of doubles per block
+    const size_t n = (size_t)B.nw * Q.ld * Q.ld / 2;   // complex pairs of doubles per block
     hipError_t e = launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(Q.cr), n, B.s);
     if (e != hipSuccess) return e;
     return launch_fill_zero<double>(reinterpret_cast<cplx<double>*>(Q.ci), n, B.s);
@@ -971,8 +1053,8 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
         h.alpha = 0;
         h.Cre = Q.cr;
         h.Cim = Q.ci;
-        h.sC = (long long)B.ld * B.ld;
-        h.ldC = B.ld;
+        h.sC = (long long)Q.ld * Q.ld;
+        h.ldC = Q.ld;
         h.r0 = 0;
         h.nT = NGp / kTile;
         h.nbatch = B.nw;
@@ -1014,8 +1096,8 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.lda = lda;
             h.Cre = Q.cr;
             h.Cim = Q.ci;
-            h.sC = (long long)B.ld * B.ld;
-            h.ldC = B.ld;
+            h.sC = (long long)Q.ld * Q.ld;
+            h.ldC = Q.ld;
             h.nw = B.nw;
             h.fp16 = fp16;
             h.scales = scales;
@@ -1042,8 +1124,8 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.lda = lda;
             h.Cre = Q.cr;
             h.Cim = Q.ci;
-            h.sC = (long long)B.ld * B.ld;
-            h.ldC = B.ld;
+            h.sC = (long long)Q.ld * Q.ld;
+            h.ldC = Q.ld;
             h.nT = NGp / kTile;
             h.nw = B.nw;
             h.fp16 = fp16;
@@ -1140,14 +1222,17 @@ int ensure_lookahead(rpa_ctx* c) {
 // tile, and la2_stream order for its rest); every rest before the solve that reads its block column.
 // A pair buffer is overwritten by the solves of pair p+2, after the main stream has waited for b_p
 // (at a'_{p+1}) and for the rests on la2_stream.
-int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
+int enqueue_ec_class(Batch& B, const QClass& C, bool from_full, const void* chi_full, double* Lblocks) {
     rpa_ctx* c = B.c;
-    const int nw = B.nw, ld = B.ld;
-    const int nq = (int)B.qj.size();
+    const int nw = B.nw, ld = C.ld;
+    const int nq = C.nq, q0 = C.q0;
     const int nb = nq * nw;
-    double* logdet = static_cast<double*>(buf(B, "ec_small"));
-    double* trk = logdet + nb;
-    int* failv = reinterpret_cast<int*>(trk + nb);
+    // per-matrix scalars of the whole batch: ln det [all], Tr K [all], failure flags [all]; this class's
+    // matrices are entries q0 nw .. (q0 + nq) nw - 1
+    const int nbt = (int)B.qj.size() * nw;
+    double* logdet = static_cast<double*>(buf(B, "ec_small")) + (size_t)q0 * nw;
+    double* trk = logdet + nbt;
+    int* failv = reinterpret_cast<int*>(static_cast<double*>(buf(B, "ec_small")) + 2 * (size_t)nbt) + (size_t)q0 * nw;
     double* Lre = static_cast<double*>(buf(B, "chol_L"));
     double* Lim = Lre + (size_t)nb * kTile * kTile;
     double* Pbase = static_cast<double*>(buf(B, "chol_panel"));
@@ -1155,17 +1240,17 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     const size_t pslot = (size_t)kTile * ld;   // one slot of one matrix
     const size_t pmat = 2 * pslot;             // both slots of one matrix (the matrix stride)
     const size_t ppart = (size_t)nb * pmat;    // the real (or imaginary) part of a pair buffer
-    double* cr = B.qj[0].cr;
-    double* ci = B.qj[0].ci;
+    double* cr = C.cr;
+    double* ci = C.ci;
     const long long ld2 = (long long)ld * ld;
     int rc = ensure_lookahead(c);
     if (rc) return rc;
     hipStream_t M = B.s, S = c->la_stream, S2 = c->la2_stream;
     hipEvent_t evA = c->la_ev[0], evD = c->la2_ev[0], evR = c->la2_ev[1], evR2 = c->la2_ev[2];
     ProfScope ps_(c, S_CHOL, M);
-    HIP_TRY(launch_zero(logdet, 2 * nb, failv, nb, M));
+    HIP_TRY(launch_zero(logdet, nb, failv, nb, M));
     for (int qi = 0; qi < nq; ++qi) {
-        QJob& Q = B.qj[qi];
+        QJob& Q = B.qj[q0 + qi];
         if (from_full) {
             HIP_TRY(launch_build_negk_from_full(static_cast<const double*>(chi_full), Q.qp.NG, Q.cr, Q.ci, ld, nw,
                                                 static_cast<const double*>(Q.d_vs), trk + qi * nw, M));
@@ -1322,9 +1407,18 @@ int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lbloc
     if (pending_r2) HIP_TRY(hipStreamWaitEvent(M, evR2, 0));
     if (pending_b) HIP_TRY(hipStreamWaitEvent(M, c->la_ev[1 + (last_p & 1)], 0));
     for (int qi = 0; qi < nq; ++qi) {
-        QJob& Q = B.qj[qi];
+        QJob& Q = B.qj[q0 + qi];
         HIP_TRY(launch_finalize(logdet + qi * nw, trk + qi * nw, failv + qi * nw,
                                 static_cast<const double*>(B.d_ow), nw, Q.F, Q.ec, M));
+    }
+    return RPA_OK;
+}
+
+// E_c of every job of the batch, one class of equal leading dimension after the other
+int enqueue_ec_all(Batch& B, bool from_full, const void* chi_full, double* Lblocks = nullptr) {
+    for (const QClass& C : B.cls) {
+        int rc = enqueue_ec_class(B, C, from_full, chi_full, Lblocks);
+        if (rc) return rc;
     }
     return RPA_OK;
 }
@@ -1334,6 +1428,8 @@ void remember_fail_flags(Batch& B) {
     B.c->last_fail = reinterpret_cast<int*>(reinterpret_cast<double*>(sm) + B.qj.size() * 2 * B.nw);
     B.c->last_nw = B.nw;
     B.c->last_nq = (int)B.qj.size();
+    B.c->last_qorder.clear();
+    for (auto& Q : B.qj) B.c->last_qorder.push_back(Q.orig);
 }
 
 int check_common(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs) {
@@ -1372,12 +1468,29 @@ int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, cons
                 return fail(RPA_ERR_INPUT, "optical limit with a degenerate transition (n = " + std::to_string(K.pn[p]) +
                                                ", m = " + std::to_string(K.pm[p]) + ": eps_m == eps_n)");
     }
-    B.qj.resize(nq);
+    // every q-point's plan, then the jobs in class order (leading dimension descending, caller's order
+    // within a class); the uploads point into the jobs, so they are registered after the reordering
+    std::vector<QPlan> plans(nq);
+    std::vector<int> order(nq);
     for (int j = 0; j < nq; ++j) {
-        QJob& Q = B.qj[j];
-        Q.qs = &qs[j];
-        rc = plan_q(c, &qs[j], Q.qp, need_ec);
+        rc = plan_q(c, &qs[j], plans[j], need_ec);
         if (rc) return rc;
+        order[j] = j;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return class_ld(plans[a].NGp, nq) > class_ld(plans[b].NGp, nq);
+    });
+    B.qj.resize(nq);
+    B.cls.clear();
+    for (int i = 0; i < nq; ++i) {
+        const int j = order[i];
+        QJob& Q = B.qj[i];
+        Q.qs = &qs[j];
+        Q.orig = j;
+        Q.qp = std::move(plans[j]);
+        Q.ld = class_ld(Q.qp.NGp, nq);
+        if (B.cls.empty() || B.cls.back().ld != Q.ld) B.cls.push_back(QClass{Q.ld, i, 0, nullptr, nullptr});
+        B.cls.back().nq += 1;
         rc = prepare_q(B, Q, up);
         if (rc) return rc;
     }
@@ -1889,7 +2002,7 @@ static int chi0_impl(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int 
     rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
     if (rc) return rc;
     QJob& Q = B.qj[0];
-    HIP_TRY(launch_chi_out(Q.cr, Q.ci, B.ld, Q.qp.NG, B.nw, add, static_cast<double*>(chi0_out), B.s));
+    HIP_TRY(launch_chi_out(Q.cr, Q.ci, Q.ld, Q.qp.NG, B.nw, add, static_cast<double*>(chi0_out), B.s));
     return RPA_OK;
 }
 
@@ -1964,6 +2077,8 @@ int rpa_ec_from_chi0(rpa_ctx* c, const rpa_qspec* qs, const rpa_freq* fr, const 
     Q.qs = qs;
     rc = plan_q(c, qs, Q.qp, true);
     if (rc) return rc;
+    Q.ld = Q.qp.NGp;
+    B.cls.assign(1, QClass{Q.ld, 0, 1, nullptr, nullptr});
     Upload up;
     up.add(Q.qp.vsqrt, &Q.d_vs);
     up.add(B.ow, &B.d_ow);
@@ -2009,9 +2124,9 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
     auto enqueue_all = [&]() -> int {
         int r = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
         if (r) return r;
-        for (int j = 0; j < nq; ++j) {
-            B.qj[j].ec = ec_dev + j;
-            B.qj[j].F = F_dev ? F_dev + (size_t)j * B.nw : nullptr;
+        for (auto& Q : B.qj) {
+            Q.ec = ec_dev + Q.orig;
+            Q.F = F_dev ? F_dev + (size_t)Q.orig * B.nw : nullptr;
         }
         r = enqueue_ec_all(B, false, nullptr);
         if (r) return r;
@@ -2075,6 +2190,7 @@ int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, const
     Batch B;
     rc = begin(B, c, fr, RPA_FP64, stream);
     if (rc) return rc;
+    B.allow_paw_mfma = false;
     rc = plan_batch(B, k, kq, 1, qs, 1, true, false, "tables");
     if (rc) return rc;
     if (B.ks[0].pn.empty()) return fail(RPA_ERR_INPUT, "no transitions (f_n - f_m > 1e-8) in the state sets");
@@ -2120,7 +2236,22 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     if (prec == RPA_FP64) return RPA_OK;
     if (NG <= 0 || npairs <= 0 || nw <= 0) return fail(RPA_ERR_INPUT, "bad tuning shape");
     HIP_TRY(hipSetDevice(c->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return autotune_run(c, prec, NG, npairs, nw, static_cast<hipStream_t>(stream));
+}
+
+int rpa_set_autotune(rpa_ctx* c, int enable) {
+    if (!c) return fail(RPA_ERR_INPUT, "NULL context");
+    c->autotune = enable != 0;
+    return RPA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Time the split rank-k variants on synthetic operands of one shape (stream-ordered, synchronizes) and record
+// the fastest for the padded sphere of NG.
+int autotune_run(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, hipStream_t s) {
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     Batch B;
     B.c = c;
@@ -2133,6 +2264,7 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     QJob& Q = B.qj[0];
     Q.qp.NG = NG;
     Q.qp.NGp = NGp;
+    Q.ld = NGp;
     const int lda = (npairs + 3) / 4 * 4;
     const int NGq = (NGp + 127) / 128 * 128;
     const size_t blk = (size_t)((npairs + 31) / 32) * NGq * 32;
@@ -2182,6 +2314,10 @@ int rpa_autotune(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, voi
     c->tune_ms[tune_key(prec, NGp)] = best;
     return RPA_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (!c || !path) return fail(RPA_ERR_INPUT, "NULL argument");
@@ -2242,7 +2378,10 @@ int rpa_check(rpa_ctx* c, void* stream) {
     HIP_TRY(hipMemcpy(f.data(), c->last_fail, sizeof(int) * n, hipMemcpyDeviceToHost));
     for (int i = 0; i < n; ++i)
         if (f[i])
-            return fail(RPA_ERR_NOT_PD, "1 - K not positive definite at q index " + std::to_string(i / c->last_nw) +
+            return fail(RPA_ERR_NOT_PD, "1 - K not positive definite at q index " +
+                                            std::to_string((size_t)(i / c->last_nw) < c->last_qorder.size()
+                                                               ? c->last_qorder[i / c->last_nw]
+                                                               : i / c->last_nw) +
                                             ", frequency index " + std::to_string(i % c->last_nw) + " (pivot " +
                                             std::to_string(f[i] - 1) + ")");
     return RPA_OK;

@@ -237,7 +237,12 @@ def raw_coefficients(rng, A, kpt, miller, nb):
     NQ = miller.shape[0]
     if nb > NQ:
         raise ValueError(f"{nb} bands need at least as many plane waves (have {NQ})")
-    return (rng.standard_normal((nb, NQ)) + 1j * rng.standard_normal((nb, NQ))) * env[None, :]
+    # same draws as (N + 1j N) * env, built in place (no large temporaries)
+    X = np.empty((nb, NQ), dtype=np.complex128)
+    X.real = rng.standard_normal((nb, NQ))
+    X.imag = rng.standard_normal((nb, NQ))
+    X *= env[None, :]
+    return X
 
 
 def projector_map(rng, A, kpt, miller, paw, overlap_spread=0.5):
@@ -267,10 +272,16 @@ def projector_map(rng, A, kpt, miller, paw, overlap_spread=0.5):
     return np.ascontiguousarray(beta * Pi)
 
 
-def paw_orthonormal_states(C0, Pi, paw):
+def paw_orthonormal_states(C0, Pi, paw, device=None):
     """Gram-Schmidt of the rows of C0 under the PAW overlap: returns (C, P) with P = C Pi and
     sum_Q C_n^* C_m + sum_a sum_ij conj(P_ni) s^a_ij P_mj = delta_nm (positive diagonal of the
-    triangular factor, the generalised form of QR with diag(R) > 0)."""
+    triangular factor, the generalised form of QR with diag(R) > 0).
+
+    device: None for numpy on the host; a torch device string (e.g. "cuda:0") to run the Gram matrix,
+    its Cholesky factor and the triangular solves there in complex128 (same result up to rounding; for
+    the large workloads, whose host generation takes minutes)."""
+    if device is not None:
+        return _paw_orthonormal_states_torch(C0, Pi, paw, device)
     P0 = C0 @ Pi
     off = paw.offsets
     G = C0.conj() @ C0.T
@@ -283,6 +294,38 @@ def paw_orthonormal_states(C0, Pi, paw):
     C = scipy_linalg.solve_triangular(Mc, C0, lower=True)
     P = scipy_linalg.solve_triangular(Mc, P0, lower=True)
     return np.ascontiguousarray(C), np.ascontiguousarray(P)
+
+
+def _paw_orthonormal_states_torch(C0, Pi, paw, device):
+    import torch
+    c0 = torch.from_numpy(C0).to(device)
+    pi = torch.from_numpy(np.ascontiguousarray(Pi)).to(device)
+    p0 = c0 @ pi
+    off = paw.offsets
+    G = c0.conj() @ c0.T
+    for a in range(len(paw.nproj)):
+        pa = p0[:, off[a]:off[a + 1]]
+        sa = torch.from_numpy(np.asarray(paw.s[a], dtype=np.complex128)).to(device)
+        G += pa.conj() @ sa @ pa.T
+    G = 0.5 * (G + G.conj().T)
+    M = torch.linalg.cholesky(G)
+    Mc = M.conj()
+
+    def lower_solve(L, R):
+        # forward substitution by row blocks: X_i = L_ii^-1 (R_i - L_i,<i X_<i), all matrix products
+        X = torch.empty_like(R)
+        bs = 256
+        for i0 in range(0, L.shape[0], bs):
+            i1 = min(L.shape[0], i0 + bs)
+            rhs = R[i0:i1] - L[i0:i1, :i0] @ X[:i0] if i0 else R[i0:i1]
+            X[i0:i1] = torch.linalg.inv(L[i0:i1, i0:i1]) @ rhs
+        return X
+
+    C = lower_solve(Mc, c0)
+    P = lower_solve(Mc, p0)
+    out = np.ascontiguousarray(C.cpu().numpy()), np.ascontiguousarray(P.cpu().numpy())
+    del c0, pi, p0, G, M, Mc, C, P
+    return out
 
 
 def draw_projections(rng, nb, nproj_total):
@@ -341,7 +384,7 @@ def paw_d_table(paw: Paw) -> np.ndarray:
 # configurations
 # ----------------------------------------------------------------------------
 def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
-              extra_kq=False, w0=1.0, paw_model="overlap"):
+              extra_kq=False, w0=1.0, paw_model="overlap", device=None):
     """Draw a workload from one seeded generator.
 
     paw_model "overlap" draws, in this order: per k the raw coefficients and the levels; s^a, R_a,
@@ -366,10 +409,13 @@ def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
             raw.append((k, kweights[ik], miller, C0, eps, f))
         paw = draw_paw(rng, A, nproj)
         pis = []
-        for (k, w, miller, C0, eps, f) in raw:
+        for i in range(len(raw)):
+            k, w, miller, C0, eps, f = raw[i]
+            raw[i] = None                  # the raw draw is released once orthonormalised
             Pi = projector_map(rng, A, k, miller, paw)
             pis.append(Pi)
-            C, P = paw_orthonormal_states(C0, Pi, paw)
+            C, P = paw_orthonormal_states(C0, Pi, paw, device)
+            del C0
             sets.append(StateSet(kpt=np.asarray(k, dtype=np.float64), weight=float(w), miller=miller,
                                  C=C, eps=eps, f=f, P=P))
         if extra_kq:
@@ -377,7 +423,7 @@ def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
             for s, Pi in zip(sets, pis):
                 C0 = raw_coefficients(rng, A, s.kpt, s.miller, s.nbands)
                 eps2, f2 = levels(rng)
-                C2, P2 = paw_orthonormal_states(C0, Pi, paw)
+                C2, P2 = paw_orthonormal_states(C0, Pi, paw, device)
                 kq.append(StateSet(kpt=s.kpt.copy(), weight=s.weight, miller=s.miller, C=C2,
                                    eps=eps2, f=f2, P=P2))
     elif paw_model == "independent":
@@ -479,7 +525,7 @@ def config1(seed: int = 1, n_occ: int = 16, n_unocc: int = 800, nw: int = 16,
 
 
 def config2(seed: int = 2, n_below: int = 120, n_above: int = 3000, nk: int = 8, nw: int = 16,
-            target_ng: int = 4000, T: float = 0.01, paw_model: str = "overlap") -> Workload:
+            target_ng: int = 4000, T: float = 0.01, paw_model: str = "overlap", device=None) -> Workload:
     """Metal-slab scale: 9x9x36 bohr, 40x40x160 grid, 2x2x2 Gamma-centred k (independent sets,
     w_k = 1/8), 120 + 3000 Fermi-smeared states (T = 0.01 Ha), 20 atoms x 18 projectors,
     ~4000 G, 16 frequencies, q = (0.1 2pi/9, 0, 0)."""
@@ -490,7 +536,7 @@ def config2(seed: int = 2, n_below: int = 120, n_above: int = 3000, nk: int = 8,
     q = np.array([0.1 * TWO_PI / 9.0, 0.0, 0.0])
     qps = [QPoint(q=q, ecut=ecut_for_count(A, q, target_ng))]
     return _assemble("cfg2-slab", A, (40, 40, 160), seed, kpts, [1.0 / len(kpts)] * len(kpts),
-                     _fermi(n_below, n_above, T), [18] * 20, qps, nw, paw_model=paw_model)
+                     _fermi(n_below, n_above, T), [18] * 20, qps, nw, paw_model=paw_model, device=device)
 
 
 def config3_qpoints(seed: int = 3, nq: int = 64):
@@ -509,12 +555,12 @@ def config3_qpoints(seed: int = 3, nq: int = 64):
 
 
 def config3(seed: int = 3, n_occ: int = 60, n_unocc: int = 1500, nq: int = 64, nw: int = 16,
-            paw_model: str = "overlap") -> Workload:
+            paw_model: str = "overlap", device=None) -> Workload:
     """Batching form: 9x9x36 bohr, 40x40x160 grid, Gamma, 60 + 1500 states, 64 q-points of a
     4x4x4 Monkhorst-Pack mesh without Gamma, G-sphere sizes log-uneven in [200, 3000]."""
     A, qps = config3_qpoints(seed, nq)
     return _assemble("cfg3-batched", A, (40, 40, 160), seed, [np.zeros(3)], [1.0],
-                     _gapped(n_occ, n_unocc), [18] * 20, qps, nw, paw_model=paw_model)
+                     _gapped(n_occ, n_unocc), [18] * 20, qps, nw, paw_model=paw_model, device=device)
 
 
 def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), target_ng=15,

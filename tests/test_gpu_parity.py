@@ -444,9 +444,10 @@ def test_o2box_full_size_chi0_band_subset(rpa, o2box_full, prec):
     assert abs(dE) < (1e-10 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("variant", [5, 6])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 @pytest.mark.parametrize("case", ["o2box_chunks", "slab_two_k"])
-def test_split_accumulate_branch(rpa, prec, case):
+def test_split_accumulate_branch(rpa, prec, case, variant):
     """Updates after the first one into a q-point's accumulator (the branch that reads C and adds): the pair
     sum split into chunks by a bound on the chunk size, over one k set at NG = 1500 (4 x 40 pairs in chunks
     of 64) and over two k sets of the metal slab at NG ~ 500 (chunks of 48). chi0 element by element and
@@ -463,7 +464,7 @@ def test_split_accumulate_branch(rpa, prec, case):
     nchunks = sum((p + chunk - 1) // chunk for p in npairs)
     assert nchunks >= 3
     with rpa.Context(wl.A, wl.grid) as ctx:
-        assert ctx.tune_get(len(gm), prec) == 6
+        ctx.tune_set(len(gm), variant, prec)
         ctx.set_chunk_pairs(chunk)
         chi = ctx.chi0(ks, kqs, qs, fr, prec).cpu().numpy()
         ec, _ = ctx.ec(ks, kqs, qs, fr, prec)
@@ -501,6 +502,7 @@ def test_nan_workspace_does_not_reach_an_uneven_batch(rpa):
     bad = torch.zeros((len(wl.omega), nbig, nbig), dtype=torch.complex128, device="cuda:0")
     bad.diagonal(dim1=1, dim2=2).fill_(1e3)
     with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_autotune(False)
         # the batch first, so that its workspace is allocated and the failed call below writes into it
         e0, _ = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
         ctx.check()
@@ -514,6 +516,7 @@ def test_nan_workspace_does_not_reach_an_uneven_batch(rpa):
         got = e1.cpu().numpy().copy()
     assert np.array_equal(first, got)
     with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_autotune(False)
         e2, _ = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")
         ctx.check()
         fresh = e2.cpu().numpy().copy()
@@ -525,5 +528,22 @@ def test_nan_workspace_does_not_reach_an_uneven_batch(rpa):
 def test_autotune_records_a_variant(rpa):
     with rpa.Context(np.eye(3) * 10.0, (16, 16, 16)) as ctx:
         v = ctx.autotune(NG=700, npairs=512, nw=4, precision="split_bf16")
-        assert v in (1, 4, 5)
+        assert v in (1, 4, 5, 6)
         assert ctx.tune_get(700, "split_bf16") == v
+
+
+def test_calls_autotune_per_size_bucket(rpa):
+    """A split call with a sphere in a new size bucket records a variant for it (and the call's result stays
+    within the split bound of the FP64 path)."""
+    wl = synth.config1(n_occ=2, n_unocc=20, which_q=(1,))
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ng = len(gm)
+        before = ctx.tune_get(ng, "split_bf16")
+        e, _ = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        e64, _ = ctx.ec(ks, kqs, qs, fr, "fp64")
+        ctx.check()
+        after = ctx.tune_get(ng, "split_bf16")
+        print(f"NG={ng}: default variant {before}, tuned {after}", flush=True)
+        assert after in (1, 4, 5, 6)
+        assert abs(float(e.cpu()[0]) - float(e64.cpu()[0])) < 1e-6
