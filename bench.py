@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 METRIC = "chi0 build TFLOP/s + ms/q-point for E_c at 1e-6 Ha, split-precision vs FP64"
 PEAK_TFLOPS = {"split_bf16": 2500.0, "split_fp16": 2500.0, "fp64": 78.6}
 HERK_KERNELS = {1: ("k_herk_split", "k_herk_split.hip"), 4: ("k_herk_split4", "k_herk_split2.hip"),
-                5: ("k_herk_split5", "k_herk_split2.hip"), 6: ("k_herk_split6", "k_herk_split2.hip")}
+                5: ("k_herk_split5", "k_herk_split2.hip")}
 
 
 def log(*a):
@@ -75,10 +75,7 @@ def executed_mfma_flops(variant, NG, P, nw):
     """MFMA flops the split kernel issues for one q and P pairs: its lower-triangle tiles incl. the diagonal,
     K padded to 32 per chunk (ignored here: chunks are large), 12 real 16-bit products per complex
     multiply-add (4 real products x 3 split terms)."""
-    if variant == 6:
-        nt = (NG + 127) // 128
-        elems = nt * (nt + 1) // 2 * 128 * 128
-    elif variant >= 4:
+    if variant >= 4:
         nr = (NG + 63) // 64
         elems = sum(i // 2 + 1 for i in range(nr)) * 64 * 128
     else:

@@ -75,7 +75,16 @@ typedef struct {
  *           proj_off[a] .. proj_off[a+1]-1 of P.
  *  P        DEVICE complex128 [nbands][proj_off[natoms]]: P^a_ni = <p~^a_i|psi~_n>.
  *  kpt      Cartesian k (bohr^-1); enters only the optical-limit momentum.
- *  weight   Brillouin-zone weight w_k of this k-point (1/N_k).            */
+ *  weight   Brillouin-zone weight w_k of this k-point (1/N_k).
+ *  dfde     HOST [nbands] -df/d eps >= 0 of every band (partially occupied,
+ *           e.g. Fermi-smeared, bands), or NULL. When set, an optical q-point
+ *           gets the intraband (n = m) head of chi0 at q -> 0:
+ *             chi0_00(i w) += -(1/Omega) w_k sum_n (-df/de)_n (qhat.v_n)^2 / w^2,
+ *           with the band velocity qhat.v_n the n = m element of Eq. n_q0's
+ *           numerator (momentum plus the PAW nabla term of Eq. nabla).
+ *           Not supported by rpa_ec_backward (RPA_ERR_UNSUPPORTED).
+ * A spin-polarised system is passed as one state set per spin channel
+ * (occupations in [0, 1]); chi0 is their sum (the spin index of Eq. chi0). */
 typedef struct {
     int nbands;
     int nQ;
@@ -88,6 +97,7 @@ typedef struct {
     const void* P;
     double kpt[3];
     double weight;
+    const double* dfde;
 } rpa_states;
 
 /* One q-point - Eq. rpa_c, Eq. n_G_2, Eq. n_q0.
@@ -163,6 +173,23 @@ int rpa_chi0(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, co
  * Hermitian matrix per frequency (zeros before the first call). */
 int rpa_chi0_add(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
                  const rpa_freq* fr, rpa_precision prec, void* chi0_inout, void* stream);
+
+/* chi0_GG'(q, w + i eta) at real frequencies (Sec. 5: the response function
+ * of TDDFT, GW and BSE), summed over nk state-set pairs as rpa_chi0: Eq. chi0
+ * with i w -> w + i eta and the two orderings of each transition paired as on
+ * the imaginary axis, so every pair carries the complex weight
+ *   a_nm(w) = (w_k/Omega)(f_n - f_m)[1/(w + i eta + e_n - e_m) - 1/(w + i eta - e_n + e_m)]
+ * (at w = 0, eta = w' this is the imaginary-axis weight at i w'). chi0(w) is
+ * not Hermitian; it is computed as A_w + i B_w from two Hermitian grouped
+ * updates with the real weights Re a and Im a. Optical q-points carry the
+ * same head as rpa_chi0 (Eq. n_q0), and sets with dfde the intraband head
+ * (1/Omega) w_k sum_n (-df/de)_n (qhat.v_n)^2 / (w + i eta)^2.
+ *  omega    HOST [nw] real frequencies (Ha, any sign), 1 <= nw <= 256.
+ *  eta      broadening (Ha), > 0.
+ *  chi0_out DEVICE complex128 [nw][NG][NG] (full matrices, gmiller order).
+ * RPA_ERR_INPUT for a bad frequency list or eta. */
+int rpa_chi0_real(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                  const double* omega, int nw, double eta, rpa_precision prec, void* chi0_out, void* stream);
 
 /* E_c(q) from a given chi0 (Eq. rpa, Table 1 step 13):
  * F(w) = ln det(1 - K) + Tr K with K = v^1/2 chi0 v^1/2, v^1/2_G = sqrt(4 pi)/|q+G|,
@@ -241,9 +268,7 @@ int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, con
  *       sums added into FP64 every 8 K-steps;
  *   5 = variant 4 with eight waves per workgroup, two per SIMD (bit-identical
  *       to 4).
- *   6 = 128x128 tiles, eight waves of 32x64, FP32 accumulation over a chunk of
- *       at most 8192 pairs, added into FP64 per chunk.
- * Without an entry, NG >= 385 uses variant 6, smaller spheres variant 1
+ * Without an entry, NG >= 385 uses variant 5, smaller spheres variant 1
  * (rpa_set_autotune: calls record an entry per size bucket).
  *  rpa_autotune     times the variants on synthetic operands of the given
  *                   shape on `stream` (synchronizes) and records the fastest.

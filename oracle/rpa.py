@@ -37,6 +37,24 @@ R10 Optical limit (Eq. n_q0, Eq. nabla, Eq. Q_q0): at q = 0 the G = 0 element
     pseudo part uses the exact plane-wave momentum (the paper's GPU form).
 R11 Frequency grid (Sec. 2.1): Gauss-Legendre nodes t on [-1, 1],
     x = (t+1)/2, w = w0 x/(1-x), d w = w0/(1-x)^2 dx, w0 = 1 Ha.
+R12 Spin (Sec. 2.2: the spin index is implicit in Eq. chi0): a spin-polarised
+    system is passed as one state set per spin channel, occupations in [0, 1];
+    chi0 is the sum over the sets.
+R14 Real frequencies (Sec. 5: chi0 on the real axis for TDDFT, GW and BSE): Eq.
+    chi0 with i w -> w + i eta, the two orderings of each transition paired as
+    in R7:
+        a_nm(w) = (w_k/Omega)(f_n - f_m)[1/(w + i eta + e_n - e_m) - 1/(w + i eta - (e_n - e_m))],
+    complex, so chi0(w) = sum a rho rho^H is not Hermitian; at w = 0,
+    eta = w' it is R7's weight at i w'. The intraband head of R13 becomes
+    +(1/Omega) sum w_k (-df/de)(qhat.v)^2 / (w + i eta)^2.
+R13 Intraband head at q -> 0 (the paper's systems are insulators or need no
+    such term; for partially occupied bands the n = m terms of Eq. chi0 do not
+    vanish as q -> 0): with -df/de of every band supplied, the head gets
+        -(1/Omega) sum_sets w_k sum_n (-df/de)_n (qhat.v_n)^2 / w^2,
+    qhat.v_n the diagonal of Eq. n_q0's numerator (the band velocity). This is
+    the small-q limit of the n = m terms of Eq. chi0 summed over a
+    time-reversal-symmetric k set (the imaginary O(q^2) part is a total
+    derivative over the Brillouin zone and drops out).
 """
 from __future__ import annotations
 
@@ -119,6 +137,16 @@ def pair_list(f_k, f_kq, delta_f=1e-8):
     f_kq = np.asarray(f_kq)
     n_idx, m_idx = np.nonzero(f_k[:, None] - f_kq[None, :] > delta_f)
     return n_idx.astype(np.int64), m_idx.astype(np.int64)
+
+
+def transition_weights_real(eps_k, eps_kq, f_k, f_kq, pairs, w_k, volume, omega, eta):
+    """Complex weights at real frequencies (R14):
+    a_nm(w) = (w_k/Omega)(f_n - f_m)[1/(w + i eta + e_n - e_m) - 1/(w + i eta - (e_n - e_m))]; [P, nw]."""
+    n, m = pairs
+    d = (np.asarray(eps_k)[n] - np.asarray(eps_kq)[m])[:, None]
+    df = (np.asarray(f_k)[n] - np.asarray(f_kq)[m])[:, None]
+    z = np.asarray(omega, dtype=np.float64)[None, :] + 1j * eta
+    return (w_k / volume) * df * (1.0 / (z + d) - 1.0 / (z - d))
 
 
 def transition_weights(eps_k, eps_kq, f_k, f_kq, pairs, w_k, volume, omega):
@@ -215,6 +243,41 @@ def optical_head(C_k, miller_k, kpt, A, P_k, Dtab, offsets, eps, pairs, qhat):
         paw += np.einsum("pi,ij,pj->p", np.conj(P_k[n_idx][:, lo:hi]), Da, P_k[m_idx][:, lo:hi])
     de = np.asarray(eps)[m_idx] - np.asarray(eps)[n_idx]
     return (pseudo - 1j * paw) / de
+
+
+def band_velocity(C_k, miller_k, kpt, A, P_k, Dtab, offsets, qhat):
+    """qhat . v_n of every band: the n = m element of Eq. n_q0's numerator,
+    sum_Q |C_n(Q)|^2 qhat.(k+G_Q) - i qhat.sum_a sum_ij conj(P_ni) D^a_ij P_nj (R13); real [nb]."""
+    nb = np.asarray(C_k).shape[0]
+    idx = np.arange(nb)
+    pseudo = momentum_pw(C_k, miller_k, kpt, A, (idx, idx), qhat)
+    paw = np.zeros(nb, dtype=np.complex128)
+    if len(offsets) > 1:
+        Dq = np.tensordot(np.asarray(qhat, dtype=np.float64), Dtab, axes=(0, 0))
+        qoff = 0
+        for a in range(len(offsets) - 1):
+            lo, hi = offsets[a], offsets[a + 1]
+            npj = hi - lo
+            Da = Dq[qoff:qoff + npj * npj].reshape(npj, npj)
+            qoff += npj * npj
+            Pa = np.asarray(P_k)[:, lo:hi]
+            paw += np.einsum("ni,ij,nj->n", np.conj(Pa), Da, Pa)
+    return np.real(pseudo - 1j * paw)
+
+
+def intraband_head(sets, A, Dtab, offsets, qhat, omega):
+    """The intraband addition to chi0_00 at q -> 0 (R13):
+    -(1/Omega) sum_sets w_k sum_n (-df/de)_n (qhat.v_n)^2 / w^2 over the sets that carry -df/de; [nw]."""
+    volume = abs(np.linalg.det(A))
+    s = 0.0
+    for st in sets:
+        mdf = getattr(st, "dfde", None)
+        if mdf is None:
+            continue
+        v = band_velocity(st.C, st.miller, st.kpt, A, st.P, Dtab, offsets, qhat)
+        s += st.weight * float(np.sum(np.asarray(mdf) * v * v))
+    w = np.asarray(omega, dtype=np.float64)
+    return -(s / volume) / (w * w)
 
 
 # ---------------------------------------------------------------------------
@@ -373,6 +436,31 @@ def chi0_q(A, grid, ksets, kqsets, gmiller, Qtab, offsets, omega, optical=False,
                                     Dtab, delta_f)
         a = transition_weights(sk.eps, skq.eps, sk.f, skq.f, pairs, sk.weight, volume, omega)
         chi += chi0_grouped(rho, a)
+    if optical and any(getattr(s, "dfde", None) is not None for s in ksets):
+        zero = np.nonzero(np.all(np.asarray(gmiller) == 0, axis=1))[0]
+        if zero.size:
+            chi[:, zero[0], zero[0]] += intraband_head(ksets, A, Dtab, offsets, qhat, omega)
+    return chi
+
+
+def chi0_q_real(A, grid, ksets, kqsets, gmiller, Qtab, offsets, omega, eta, optical=False, qhat=None,
+                Dtab=None, delta_f=1e-8):
+    """chi0(q, w + i eta) at real frequencies (R14), summed over k; complex128 [nw, NG, NG], not Hermitian."""
+    volume = abs(np.linalg.det(A))
+    chi = np.zeros((len(omega), len(gmiller), len(gmiller)), dtype=np.complex128)
+    for sk, skq in zip(ksets, kqsets):
+        pairs, rho = pair_densities(A, grid, sk, skq, gmiller, Qtab, offsets, optical, qhat,
+                                    Dtab, delta_f)
+        a = transition_weights_real(sk.eps, skq.eps, sk.f, skq.f, pairs, sk.weight, volume, omega, eta)
+        for w in range(len(omega)):
+            chi[w] += (rho.T * a[:, w][None, :]) @ np.conj(rho)
+    if optical and any(getattr(s, "dfde", None) is not None for s in ksets):
+        zero = np.nonzero(np.all(np.asarray(gmiller) == 0, axis=1))[0]
+        if zero.size:
+            # R13's -s/w^2 on the imaginary axis is s/(i w)^2; at w + i eta it is s/(w + i eta)^2
+            s_over = -intraband_head(ksets, A, Dtab, offsets, qhat, np.ones(1))[0]
+            z = np.asarray(omega, dtype=np.float64) + 1j * eta
+            chi[:, zero[0], zero[0]] += s_over / (z * z)
     return chi
 
 

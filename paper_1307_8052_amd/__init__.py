@@ -91,7 +91,7 @@ class States:
     """One k (or k+q) state set; C and P live on the device, the rest on the host."""
 
     def __init__(self, C, miller, eps, f, P=None, proj_off=None, kpt=(0.0, 0.0, 0.0), weight=1.0,
-                 device="cuda"):
+                 device="cuda", dfde=None):
         torch = _torch()
         self.device = device
         self.C = _dev_c128(C, device)
@@ -108,10 +108,12 @@ class States:
             self.natoms = natoms
         self.kpt = _f64(kpt)
         self.weight = float(weight)
+        self.dfde = None if dfde is None else _f64(dfde)
 
     @classmethod
     def from_synth(cls, s, paw, device="cuda"):
-        return cls(s.C, s.miller, s.eps, s.f, s.P, paw.offsets, s.kpt, s.weight, device)
+        return cls(s.C, s.miller, s.eps, s.f, s.P, paw.offsets, s.kpt, s.weight, device,
+                   dfde=getattr(s, "dfde", None))
 
     def struct(self) -> RpaStates:
         st = RpaStates()
@@ -127,6 +129,7 @@ class States:
         for i in range(3):
             st.kpt[i] = float(self.kpt[i])
         st.weight = self.weight
+        st.dfde = _ptr_f64(self.dfde) if self.dfde is not None else ctypes.cast(None, _capi.P_f64)
         return st
 
 
@@ -244,6 +247,18 @@ class Context:
         a, b, q, fr = self._arrays(ks), self._arrays(kqs), qs.struct(), freq.struct()
         _check(self._L.rpa_chi0(self._h, a, b, len(ks), ctypes.byref(q), ctypes.byref(fr), _prec(precision),
                                 ctypes.c_void_p(out.data_ptr()), _stream()), self._h)
+        return out
+
+    def chi0_real(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, omega, eta: float,
+                  precision="fp64"):
+        """chi0(q, w + i eta) at the real frequencies `omega` (rpa_chi0_real); complex128 [nw, NG, NG]."""
+        torch = _torch()
+        om = _f64(omega)
+        out = torch.empty((om.size, qs.NG, qs.NG), dtype=torch.complex128, device=self.device)
+        a, b, q = self._arrays(ks), self._arrays(kqs), qs.struct()
+        _check(self._L.rpa_chi0_real(self._h, a, b, len(ks), ctypes.byref(q), _ptr_f64(om), int(om.size),
+                                     float(eta), _prec(precision), ctypes.c_void_p(out.data_ptr()), _stream()),
+               self._h)
         return out
 
     def chi0_add(self, ks: Sequence[States], kqs: Sequence[States], qs: QSpec, freq: Freq, chi0, precision="fp64"):

@@ -43,6 +43,7 @@ class RpaStates(ctypes.Structure):
         ("P", c_void_p),
         ("kpt", c_double * 3),
         ("weight", c_double),
+        ("dfde", P_f64),
     ]
 
 
@@ -72,6 +73,8 @@ SIGNATURES = {
                                  ctypes.POINTER(RpaQSpec), c_int, P_i32, P_i32, c_int, c_void_p, c_void_p]),
     "rpa_chi0": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
                          ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p]),
+    "rpa_chi0_real": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
+                              ctypes.POINTER(RpaQSpec), P_f64, c_int, c_double, c_int, c_void_p, c_void_p]),
     "rpa_chi0_add": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
                              ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p]),
     "rpa_ec_from_chi0": (c_int, [c_void_p, ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_void_p,

@@ -43,6 +43,43 @@ template <typename T> RPA_HD cplx<T> cmulc(cplx<T> a, cplx<T> b) {
 template <int S, typename T> RPA_HD cplx<T> imul(cplx<T> a) { return S > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x); }
 
 // ---------------------------------------------------------------------------
+// products with constants known in double (roots of unity, 1/N). In FP32 a
+// constant is held as two floats, hi = fl(c) and lo = fl(c - hi), and the
+// product as x hi + x lo with one fused multiply-add: the result then carries
+// only the rounding of the arithmetic, which differs from pair to pair and
+// averages out in chi0, and not the representation error of the constant,
+// which shifts every transform of every pair the same way (a bias of a few
+// 1e-7 in |rho(G)|^2 with singly rounded constants). FP64 multiplies plainly.
+// ---------------------------------------------------------------------------
+template <typename T> struct Split2 {
+    T hi, lo;
+};
+template <typename T> RPA_HD Split2<T> split2(double c) {
+    Split2<T> r;
+    r.hi = T(c);
+    r.lo = sizeof(T) == 4 ? T(c - (double)r.hi) : T(0);
+    return r;
+}
+template <typename T> RPA_HD T mulk(T x, Split2<T> c) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(x, c.hi, x * c.lo);
+    else return x * c.hi;
+}
+template <typename T> RPA_HD cplx<T> scalek(cplx<T> a, Split2<T> c) { return mk(mulk(a.x, c), mulk(a.y, c)); }
+// a * (c + i s) with c, s split
+template <typename T> RPA_HD cplx<T> cmulk(cplx<T> a, Split2<T> c, Split2<T> s) {
+    if constexpr (sizeof(T) == 4) {
+        const float rl = a.x * c.lo - a.y * s.lo, il = a.x * s.lo + a.y * c.lo;
+        return mk(__builtin_fmaf(a.x, c.hi, __builtin_fmaf(-a.y, s.hi, rl)),
+                  __builtin_fmaf(a.x, s.hi, __builtin_fmaf(a.y, c.hi, il)));
+    } else {
+        return a * mk(c.hi, s.hi);
+    }
+}
+template <typename T> RPA_HD cplx<T> cmulk(cplx<T> a, double c, double s) {
+    return cmulk(a, split2<T>(c), split2<T>(s));
+}
+
+// ---------------------------------------------------------------------------
 // compile-time roots of unity: cos and sin of 2 pi e / R by Taylor series on
 // the reduced argument (exact to double rounding for |x| <= pi).
 // ---------------------------------------------------------------------------
@@ -99,10 +136,10 @@ template <int DIR, typename T> struct Dft<2, DIR, T> {
 
 template <int DIR, typename T> struct Dft<3, DIR, T> {
     static RPA_HD void run(cplx<T>* v) {
-        const T h = T(0.86602540378443864676372317075294);  // sin(2 pi/3)
+        const Split2<T> h = split2<T>(0.86602540378443864676372317075294);  // sin(2 pi/3)
         cplx<T> a = v[0], t1 = v[1] + v[2], t2 = v[1] - v[2];
         cplx<T> m = a - scale(t1, T(0.5));
-        cplx<T> r = imul<DIR>(scale(t2, h));
+        cplx<T> r = imul<DIR>(scalek(t2, h));
         v[0] = a + t1;
         v[1] = m + r;
         v[2] = m - r;
@@ -122,17 +159,17 @@ template <int DIR, typename T> struct Dft<4, DIR, T> {
 
 template <int DIR, typename T> struct Dft<5, DIR, T> {
     static RPA_HD void run(cplx<T>* v) {
-        const T c1 = T(0.30901699437494742410229341718282);   // cos(2 pi/5)
-        const T c2 = T(-0.80901699437494742410229341718282);  // cos(4 pi/5)
-        const T s1 = T(0.95105651629515357211643933337938);   // sin(2 pi/5)
-        const T s2 = T(0.58778525229247312916870595463907);   // sin(4 pi/5)
+        const Split2<T> c1 = split2<T>(0.30901699437494742410229341718282);   // cos(2 pi/5)
+        const Split2<T> c2 = split2<T>(-0.80901699437494742410229341718282);  // cos(4 pi/5)
+        const Split2<T> s1 = split2<T>(0.95105651629515357211643933337938);   // sin(2 pi/5)
+        const Split2<T> s2 = split2<T>(0.58778525229247312916870595463907);   // sin(4 pi/5)
         cplx<T> a = v[0];
         cplx<T> t1 = v[1] + v[4], t2 = v[2] + v[3];
         cplx<T> t3 = v[1] - v[4], t4 = v[2] - v[3];
-        cplx<T> m1 = a + scale(t1, c1) + scale(t2, c2);
-        cplx<T> m2 = a + scale(t1, c2) + scale(t2, c1);
-        cplx<T> r1 = imul<DIR>(scale(t3, s1) + scale(t4, s2));
-        cplx<T> r2 = imul<DIR>(scale(t3, s2) - scale(t4, s1));
+        cplx<T> m1 = a + scalek(t1, c1) + scalek(t2, c2);
+        cplx<T> m2 = a + scalek(t1, c2) + scalek(t2, c1);
+        cplx<T> r1 = imul<DIR>(scalek(t3, s1) + scalek(t4, s2));
+        cplx<T> r2 = imul<DIR>(scalek(t3, s2) - scalek(t4, s1));
         v[0] = a + t1 + t2;
         v[1] = m1 + r1;
         v[4] = m1 - r1;
@@ -159,8 +196,7 @@ RPA_HD void dft_split(cplx<T>* x) {
             if (e == 0) {
                 y[n2 * A + k1] = t[k1];
             } else {
-                cplx<T> w = mk(T(W.c[e]), T(DIR * W.s[e]));
-                y[n2 * A + k1] = t[k1] * w;
+                y[n2 * A + k1] = cmulk(t[k1], W.c[e], DIR * W.s[e]);
             }
         }
     }
@@ -211,8 +247,7 @@ RPA_HD void reg_split(cplx<T>* x) {
             if (e == 0) {
                 y[n2 * A + k1] = t[k1];
             } else {
-                cplx<T> w = mk(T(W.c[e]), T(DIR * W.s[e]));
-                y[n2 * A + k1] = t[k1] * w;
+                y[n2 * A + k1] = cmulk(t[k1], W.c[e], DIR * W.s[e]);
             }
         }
     }
@@ -275,10 +310,14 @@ inline bool make_plan(int n, FftPlan* p) {
     return true;
 }
 
+// entries of a twiddle table of an N-point axis: N, and N more low parts in FP32
+template <typename T> RPA_HD int twiddle_len(int N) { return sizeof(T) == 4 ? 2 * N : N; }
+
 // One Stockham pass over items [item0, item0 + nitems) with stride `step`.
 // Work item w -> (line l, butterfly j); `line_fast` picks which index varies
 // fastest across consecutive items. Element (l, e) lives at addr(l, e).
-// `tw` holds exp(-2 pi i t / N) for t < N.
+// `tw` holds exp(-2 pi i t / N) for t < N; in FP32 followed by the N low
+// parts (twiddle_len entries in all).
 template <int R, int DIR, typename T, class Addr>
 RPA_HD void stockham_pass(const cplx<T>* in, cplx<T>* out, int N, int Ns, int nlines, bool line_fast,
                           Addr addr, const cplx<T>* tw, int item0, int step) {
@@ -296,9 +335,19 @@ RPA_HD void stockham_pass(const cplx<T>* in, cplx<T>* out, int N, int Ns, int nl
         if (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cplx<T> t = tw[r * k * twstep];
-                if (DIR > 0) t.y = -t.y;
-                v[r] = v[r] * t;
+                const int ti = r * k * twstep;
+                cplx<T> t = tw[ti];
+                if constexpr (sizeof(T) == 4) {
+                    cplx<T> tl = tw[N + ti];
+                    if (DIR > 0) {
+                        t.y = -t.y;
+                        tl.y = -tl.y;
+                    }
+                    v[r] = cmulk(v[r], Split2<T>{t.x, tl.x}, Split2<T>{t.y, tl.y});
+                } else {
+                    if (DIR > 0) t.y = -t.y;
+                    v[r] = v[r] * t;
+                }
             }
         }
         Dft<R, DIR, T>::run(v);

@@ -81,6 +81,25 @@ template <typename T>
 hipError_t launch_paw_add(const T* Yre, const T* Yim, const int32_t* pn, int nlo, const int32_t* pm,
                           const double* Pkq, int ldP, int nprojtot, int npairs, int NG, int NGp, T* rho_re,
                           T* rho_im, hipStream_t s);
+// Intraband head at q -> 0: term[b] = weight (-df/de)[b] (qhat.v_n)^2 for n = band[b] (band velocity from
+// the coefficients, the table wq = qhat.(k + G_Q) and the PAW nabla table Dq), then
+// head[w * stride] += -(sum of terms) inv_volume / omega[w]^2 (nw <= 256)
+hipError_t launch_band_drude(const double* C, int nQ, const double* wq, const double* P, int ldP, const double* Dq,
+                             const int32_t* proj_off, const int32_t* qoff, int natoms, const int32_t* band,
+                             const double* mdf, int nbands, double weight, double* term, hipStream_t s);
+hipError_t launch_add_drude(const double* term, int nterms, const double* omega, int nw, double inv_volume,
+                            double* head, long long stride, hipStream_t s);
+
+// Real frequencies w + i eta (2 nw weight rows: Re a for w < nw, Im a for nw + w; the chi0 of the call is
+// A_w + i B_w with Hermitian A_w, B_w accumulated from those rows)
+hipError_t launch_weights_real(const double* epsk, const double* epskq, const double* fk, const double* fkq,
+                               const int32_t* pn, const int32_t* pm, int npairs, const double* omega, int nw,
+                               double eta, double prefac, double* a, int lda, hipStream_t s);
+hipError_t launch_add_drude_real(const double* term, int nterms, const double* omega, int nw, double eta,
+                                 double inv_volume, double* head, long long stride, hipStream_t s);
+hipError_t launch_chi_out_real(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out,
+                               hipStream_t s);
+
 // PAW term as an MFMA GEMM (k_paw.hip): Z_m = Q P'_m for m = m_lo .. m_lo + nslots - 1 into Zr/Zi
 // [nslots][nproj][NGp], then rho[p] += conj(P_k[pn[p]]) Z_{pm[p]} for the npairs pairs (pm within the
 // slots); NGp a multiple of 64
@@ -141,10 +160,7 @@ hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr,
 // 64 x 128 tiles (ntiles = sum over 64-row blocks I of I/2 + 1), FP32 partial sums
 // added into FP64 every 8 K-steps; four waves of 64 x 32, or eight of 32 x 32
 hipError_t launch_herk_split4(const HerkSplit2Args& h, int eight_waves, hipStream_t s);
-// 128 x 128 lower tiles over NGq (ntiles = nT (nT + 1)/2, nT = NGq/128), eight waves of 32 x 64, FP32
-// accumulation over the whole call (bounded chunks: kSplit6Chunk pairs), added into the FP64 C at the end
-constexpr int kSplit6Chunk = 8192;
-hipError_t launch_herk_split6(const HerkSplit2Args& h, hipStream_t s);
+
 
 // -K = -v_i v_j chi_ij on the lower triangle (in place, planar), zero padding,
 // and Tr K per frequency.

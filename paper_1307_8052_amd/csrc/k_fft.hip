@@ -60,11 +60,11 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(cplx<T>* data, int N, 
                                                           const cplx<T>* __restrict__ twg) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
-    cplx<T>* a = tw + N;
+    cplx<T>* a = tw + twiddle_len<T>(N);
     cplx<T>* b = a + (size_t)LB * N;
     const long long l0 = (long long)blockIdx.x * LB;
     const int nl = (int)min((long long)LB, nlines - l0);
-    for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = twg[t];
+    for (int t = threadIdx.x; t < twiddle_len<T>(N); t += blockDim.x) tw[t] = twg[t];
     auto gaddr = [&](int l, int e) -> long long {
         const long long L = l0 + l;
         return (L / inner_count) * outer_stride + (L % inner_count) * inner_stride + (long long)e * es;
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_xy(const cplx<T>* __restri
     const int N1 = g.N1, N2 = g.N2, N3 = g.N3, K1 = g.K1, K2 = g.K2;
     const int plane = N1 * N2;
     cplx<T>* tw1 = reinterpret_cast<cplx<T>*>(smem);
-    cplx<T>* tw2 = tw1 + N1;
-    cplx<T>* A = tw2 + N2;
+    cplx<T>* tw2 = tw1 + twiddle_len<T>(N1);
+    cplx<T>* A = tw2 + twiddle_len<T>(N2);
     cplx<T>* B = A + (size_t)PPW * plane;
     int* kx = reinterpret_cast<int*>(B + (size_t)PPW * plane);
     int* ky = kx + K1;
@@ -114,8 +114,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_xy(const cplx<T>* __restri
     const int p0 = blockIdx.x * PPW;
     const int np = min(PPW, npairs - p0);
     const size_t vol = (size_t)plane * N3;
-    for (int t = threadIdx.x; t < N1; t += blockDim.x) tw1[t] = tw1g[t];
-    for (int t = threadIdx.x; t < N2; t += blockDim.x) tw2[t] = tw2g[t];
+    for (int t = threadIdx.x; t < twiddle_len<T>(N1); t += blockDim.x) tw1[t] = tw1g[t];
+    for (int t = threadIdx.x; t < twiddle_len<T>(N2); t += blockDim.x) tw2[t] = tw2g[t];
     for (int t = threadIdx.x; t < K1; t += blockDim.x) kx[t] = kxg[t];
     for (int t = threadIdx.x; t < K2; t += blockDim.x) ky[t] = kyg[t];
 
@@ -157,12 +157,12 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_z_gather(const cplx<T>* __
     extern __shared__ __align__(16) unsigned char smem[];
     const int N3 = g.N3, ncols = g.ncols;
     cplx<T>* tw3 = reinterpret_cast<cplx<T>*>(smem);
-    cplx<T>* A = tw3 + N3;
+    cplx<T>* A = tw3 + twiddle_len<T>(N3);
     cplx<T>* B = A + (size_t)CB * N3;
     const size_t p = blockIdx.x;
     const int c0 = blockIdx.y * CB;
     const int nc = min(CB, ncols - c0);
-    for (int t = threadIdx.x; t < N3; t += blockDim.x) tw3[t] = tw3g[t];
+    for (int t = threadIdx.x; t < twiddle_len<T>(N3); t += blockDim.x) tw3[t] = tw3g[t];
     for (int f = threadIdx.x; f < N3 * nc; f += blockDim.x) {
         const int z = f / nc, c = f - z * nc;
         A[z * CB + c] = tbuf[(p * N3 + z) * ncols + c0 + c];
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_z_gather(const cplx<T>* __
     auto az = [CB](int l, int e) { return e * CB + l; };
     cplx<T>* rz = run_stages<-1>(A, B, g.p3, N3, nc, true, az, tw3);
 
-    const T invN = T(1.0 / ((double)g.N1 * g.N2 * N3));
+    const Split2<T> invN = split2<T>(1.0 / ((double)g.N1 * g.N2 * N3));
     const int e0 = col_start[c0], e1 = col_start[c0 + nc];
     T* ore = rre + p * g.NGp;
     T* oim = rim + p * g.NGp;
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_z_gather(const cplx<T>* __
         const int kz = col_kz[i] >> 16;      // packed (kz << 16) | column
         const int c = col_kz[i] & 0xffff;
         const cplx<T> v = rz[kz * CB + (c - c0)];
-        ore[gi] = v.x * invN;
-        oim[gi] = v.y * invN;
+        ore[gi] = mulk(v.x, invN);
+        oim[gi] = mulk(v.y, invN);
     }
     if (blockIdx.y == 0) {
         for (int gi = g.NG + threadIdx.x; gi < g.NGp; gi += blockDim.x) {
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_z_gather(const cplx<T>* __
 template <typename T>
 size_t fft_axis_lines(int N) {
     size_t per = kLdsBudget / sizeof(cplx<T>);
-    size_t lb = (per - N) / (2 * (size_t)N);
+    size_t lb = (per - twiddle_len<T>(N)) / (2 * (size_t)N);
     return lb < 1 ? 1 : lb;
 }
 
@@ -228,7 +228,7 @@ hipError_t launch_fft_axis(cplx<T>* data, int nb, int N1, int N2, int N3, int ax
     else if (axis == 1) { N = N2; es = N1; ic = N1; is = 1; os = (long long)N1 * N2; nlines = (long long)nb * N3 * N1; }
     else { N = N3; es = (long long)N1 * N2; ic = (long long)N1 * N2; is = 1; os = V; nlines = (long long)nb * N1 * N2; }
     const int LB = (int)fft_axis_lines<T>(N);
-    const size_t lds = ((size_t)N + 2 * (size_t)LB * N) * sizeof(cplx<T>);
+    const size_t lds = ((size_t)twiddle_len<T>(N) + 2 * (size_t)LB * N) * sizeof(cplx<T>);
     const unsigned blocks = (unsigned)((nlines + LB - 1) / LB);
     if (dir > 0)
         hipLaunchKernelGGL((k_fft_axis<T, 1>), dim3(blocks), dim3(kFftThreads), lds, s, data, N, plan, es, ic, is, os,
@@ -242,7 +242,7 @@ hipError_t launch_fft_axis(cplx<T>* data, int nb, int N1, int N2, int N3, int ax
 template <typename T>
 int pair_xy_ppw(const PairGeom& g) {
     const size_t plane = (size_t)g.N1 * g.N2;
-    const size_t fixed = (g.N1 + g.N2) * sizeof(cplx<T>) + (g.K1 + g.K2) * sizeof(int);
+    const size_t fixed = (twiddle_len<T>(g.N1) + twiddle_len<T>(g.N2)) * sizeof(cplx<T>) + (g.K1 + g.K2) * sizeof(int);
     const size_t per = 2 * plane * sizeof(cplx<T>);
     size_t budget = kLdsBudget;
     if (fixed + per > budget) budget = 160 * 1024;
@@ -260,7 +260,8 @@ hipError_t launch_pair_xy(const cplx<T>* phik, const cplx<T>* phikq, const int32
     const int PPW = pair_xy_ppw<T>(g);
     if (PPW < 1) return hipErrorInvalidValue;
     const size_t plane = (size_t)g.N1 * g.N2;
-    const size_t lds = (g.N1 + g.N2) * sizeof(cplx<T>) + 2 * PPW * plane * sizeof(cplx<T>) + (g.K1 + g.K2) * sizeof(int);
+    const size_t lds = (twiddle_len<T>(g.N1) + twiddle_len<T>(g.N2)) * sizeof(cplx<T>) +
+                       2 * PPW * plane * sizeof(cplx<T>) + (g.K1 + g.K2) * sizeof(int);
     dim3 grid((unsigned)((npairs + PPW - 1) / PPW), (unsigned)g.N3);
     hipLaunchKernelGGL(k_pair_xy<T>, grid, dim3(kFftThreads), lds, s, phik, phikq, pn, pm, npairs, g, PPW, kx_grid,
                        ky_grid, tw1, tw2, tbuf);
@@ -273,10 +274,10 @@ hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom&
                                 hipStream_t s) {
     if (!npairs) return hipSuccess;
     size_t per = kLdsBudget / sizeof(cplx<T>);
-    int CB = (int)((per - g.N3) / (2 * (size_t)g.N3));
+    int CB = (int)((per - twiddle_len<T>(g.N3)) / (2 * (size_t)g.N3));
     if (CB > g.ncols) CB = g.ncols;
     if (CB < 1) return hipErrorInvalidValue;
-    const size_t lds = ((size_t)g.N3 + 2 * (size_t)CB * g.N3) * sizeof(cplx<T>);
+    const size_t lds = ((size_t)twiddle_len<T>(g.N3) + 2 * (size_t)CB * g.N3) * sizeof(cplx<T>);
     dim3 grid((unsigned)npairs, (unsigned)((g.ncols + CB - 1) / CB));
     hipLaunchKernelGGL(k_pair_z_gather<T>, grid, dim3(kFftThreads), lds, s, tbuf, g, CB, col_start, col_g, col_kz, tw3,
                        rho_re, rho_im);

@@ -81,9 +81,9 @@ __device__ __forceinline__ void fft_column_quad(cplx<T>* col, int r) {
 #pragma unroll
     for (int k = 1; k < M; ++k) {
         const int e1 = k % N, e2 = (2 * k) % N, e3 = (3 * k) % N;
-        const T c = r == 1 ? T(W.c[e1]) : r == 2 ? T(W.c[e2]) : T(W.c[e3]);
-        const T sn = r == 1 ? T(-W.s[e1]) : r == 2 ? T(-W.s[e2]) : T(-W.s[e3]);
-        if (r != 0) v[k] = v[k] * mk(c, sn);
+        const double c = r == 1 ? W.c[e1] : r == 2 ? W.c[e2] : W.c[e3];
+        const double sn = r == 1 ? -W.s[e1] : r == 2 ? -W.s[e2] : -W.s[e3];
+        if (r != 0) v[k] = cmulk(v[k], c, sn);
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ 
         for (int z = 0; z < N3; ++z) Z[c * LD + z] = v[z];
     }
     __syncthreads();
-    const T invN = T(1.0 / ((double)g.N1 * g.N2 * N3));
+    const Split2<T> invN = split2<T>(1.0 / ((double)g.N1 * g.N2 * N3));
     const int e0 = col_start[c0], e1 = col_start[c0 + nc];
     T* ore = rre + p * g.NGp;
     T* oim = rim + p * g.NGp;
@@ -250,8 +250,8 @@ __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ 
         const int kz = col_kz[i] >> 16;  // packed (kz << 16) | column
         const int cc = col_kz[i] & 0xffff;
         const cplx<T> v = Z[(cc - c0) * LD + kz];
-        ore[gi] = v.x * invN;
-        oim[gi] = v.y * invN;
+        ore[gi] = mulk(v.x, invN);
+        oim[gi] = mulk(v.y, invN);
     }
     if (blockIdx.y == 0) {
         for (int gi = g.NG + threadIdx.x; gi < g.NGp; gi += CB) {

@@ -522,178 +522,6 @@ __global__ __launch_bounds__(512, 1) void k_herk_split5(HerkSplit2Args h) {
 }
 
 
-// Variant 6: 128x128 lower tiles, eight waves of 32 rows x 64 columns (two per SIMD), FP32 accumulation
-// over the whole launch (the pair chunk), added into the FP64 accumulator C once at the end. A wave's
-// 32 x 64 tile takes 24 KB of fragment reads from LDS per K-step for 96 MFMAs (the 32 x 32 waves of
-// variant 5: 16 KB for 48), and a workgroup stages 64 KB per K-step for 768 MFMAs (variant 5: 48 KB for
-// 384). The rounding of the FP32 sum grows with the chunk, so the runtime bounds the chunks of this
-// variant (kSplit6Chunk pairs); chunks are summed in FP64 in C.
-// Per 16 x 16 block and K-step, with A = a(w) rho split in the kernel and B = rho pre-split:
-//   Re += Arl Brh + Arh Brl + Ail Bih + Aih Bil + Arh Brh + Aih Bih
-//   Im += Ail Brh + Aih Brl - Arl Bih - Arh Bil + Aih Brh - Arh Bih
-// (the small products first; the negated A planes come from one XOR per register).
-template <bool F16>
-__global__ __launch_bounds__(512, 1) void k_herk_split6(HerkSplit2Args h) {
-    typedef typename H<F16>::v8 hv;
-    constexpr int T = 128;
-    __shared__ __align__(16) u16 sA[2][4][T][KS];
-    __shared__ __align__(16) u16 sB[2][4][T][KS];
-
-    const int b = blockIdx.x;
-    const int xcd = b % kXcds, local = b / kXcds;
-    const int tile = (local / h.nw) * kXcds + xcd;
-    const int w = local % h.nw;
-    if (tile >= h.ntiles) return;
-    // lower-triangle tile t = I (I + 1)/2 + J, J <= I
-    int I = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
-    while (I * (I + 1) / 2 > tile) --I;
-    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
-    const int J = tile - I * (I + 1) / 2;
-    const int ci = I * T, cj = J * T;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
-    const double* aw = h.w + (size_t)w * h.lda;
-    const float sa = (F16 && h.scales) ? h.scales[w] : 1.0f;
-    const float sb = (F16 && h.scales) ? h.scales[h.nw] : 1.0f;
-    const int K = h.K;
-
-    // staging: A row ar, pairs ak .. ak+7 (FP32, scaled by a(w) and split here); B column br, 16-byte chunk bc
-    // of each of the four pre-split planes
-    const int ar = tid >> 2, ak = (tid & 3) * 8;
-    const int br = tid >> 2, bc = tid & 3;
-    v4f pxr[2], pxi[2];
-    double pw[8];
-    v8u16 pb[4];
-    const int nkb = (K + KS - 1) / KS;
-    auto fetch = [&](int kb) {
-        const size_t oa = ((size_t)kb * h.NGq + ci + ar) * KS + ak;
-        const size_t ob = ((size_t)kb * h.NGq + cj + br) * KS + bc * 8;
-        pxr[0] = *reinterpret_cast<const v4f*>(h.Xre + oa);
-        pxr[1] = *reinterpret_cast<const v4f*>(h.Xre + oa + 4);
-        pxi[0] = *reinterpret_cast<const v4f*>(h.Xim + oa);
-        pxi[1] = *reinterpret_cast<const v4f*>(h.Xim + oa + 4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) pb[q] = *reinterpret_cast<const v8u16*>(h.B[q] + ob);
-        const int k0 = kb * KS + ak;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) pw[e] = aw[min(k0 + e, K - 1)];
-    };
-    auto store = [&](int kb, int buf) {
-        const int k0 = kb * KS + ak;
-        v8u16 xrh, xrl, xih, xil;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float wk = (k0 + e < K) ? (float)pw[e] * sa : 0.f;
-            u16 a, c;
-            split<F16>(pxr[e >> 2][e & 3] * wk, a, c);
-            xrh[e] = a;
-            xrl[e] = c;
-            split<F16>(pxi[e >> 2][e & 3] * wk, a, c);
-            xih[e] = a;
-            xil[e] = c;
-        }
-        const int oa = swz(ar, ak >> 3);
-        *reinterpret_cast<v8u16*>(&sA[buf][0][ar][oa]) = xrh;
-        *reinterpret_cast<v8u16*>(&sA[buf][1][ar][oa]) = xrl;
-        *reinterpret_cast<v8u16*>(&sA[buf][2][ar][oa]) = xih;
-        *reinterpret_cast<v8u16*>(&sA[buf][3][ar][oa]) = xil;
-        const int ob = swz(br, bc);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<v8u16*>(&sB[buf][q][br][ob]) = pb[q];
-    };
-
-    v4f accR[2][4], accI[2][4];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            accR[x][y] = v4f{0, 0, 0, 0};
-            accI[x][y] = v4f{0, 0, 0, 0};
-        }
-
-    fetch(0);
-    store(0, 0);
-    fetch(min(1, nkb - 1));
-    const int rr = lane & 15, kc = lane >> 4;
-    for (int kb = 0; kb < nkb; ++kb) {
-        __syncthreads();
-        const int cur = kb & 1;
-        hv af[2][4], an[2][2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            const int row = wr + 16 * x + rr;
-            const int o = swz(row, kc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) af[x][q] = *reinterpret_cast<const hv*>(&sA[cur][q][row][o]);
-            an[x][0] = neg8(af[x][0]);
-            an[x][1] = neg8(af[x][1]);
-        }
-        store(kb + 1, cur ^ 1);
-        fetch(min(kb + 2, nkb - 1));
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int row = wc + 16 * y + rr;
-            const int o = swz(row, kc);
-            hv bf[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bf[q] = *reinterpret_cast<const hv*>(&sB[cur][q][row][o]);
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                v4f r = accR[x][y], im = accI[x][y];
-                r = H<F16>::mfma(af[x][1], bf[0], r);
-                r = H<F16>::mfma(af[x][0], bf[1], r);
-                r = H<F16>::mfma(af[x][3], bf[2], r);
-                r = H<F16>::mfma(af[x][2], bf[3], r);
-                r = H<F16>::mfma(af[x][0], bf[0], r);
-                r = H<F16>::mfma(af[x][2], bf[2], r);
-                im = H<F16>::mfma(af[x][3], bf[0], im);
-                im = H<F16>::mfma(af[x][2], bf[1], im);
-                im = H<F16>::mfma(an[x][1], bf[2], im);
-                im = H<F16>::mfma(an[x][0], bf[3], im);
-                im = H<F16>::mfma(af[x][2], bf[0], im);
-                im = H<F16>::mfma(an[x][0], bf[2], im);
-                accR[x][y] = r;
-                accI[x][y] = im;
-            }
-        }
-    }
-
-    const double inv = 1.0 / ((double)sa * (double)sb);
-    double* Cre = h.Cre + (size_t)w * h.sC;
-    double* Cim = h.Cim + (size_t)w * h.sC;
-    // C += acc (C = acc for the first update of a fresh accumulator: nothing read), one row block x at a
-    // time, all loads of the block before its stores; rows and columns past ldC are skipped
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-        double cre[4][4] = {}, cim[4][4] = {};
-        if (!h.overwrite) {
-#pragma unroll
-            for (int y = 0; y < 4; ++y)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                    const int col = cj + wc + 16 * y + (lane & 15);
-                    const size_t o = (row < h.ldC && col < h.ldC) ? (size_t)row * h.ldC + col : 0;
-                    cre[y][r] = Cre[o];
-                    cim[y][r] = Cim[o];
-                }
-        }
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = ci + wr + 16 * x + 4 * (lane >> 4) + r;
-                const int col = cj + wc + 16 * y + (lane & 15);
-                if (row < h.ldC && col < h.ldC) {
-                    const size_t o = (size_t)row * h.ldC + col;
-                    Cre[o] = cre[y][r] + (double)accR[x][y][r] * inv;
-                    Cim[o] = cim[y][r] + (double)accI[x][y][r] * inv;
-                }
-            }
-    }
-}
-
 }  // namespace
 
 hipError_t launch_pack_split(const float* rre, const float* rim, int K, int ldr, int NGq, const float* scales, int nw,
@@ -724,17 +552,6 @@ hipError_t launch_herk_split4(const HerkSplit2Args& h, int eight_waves, hipStrea
         else
             hipLaunchKernelGGL(k_herk_split4<false>, dim3(blocks), dim3(256), 0, s, h);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_herk_split6(const HerkSplit2Args& h, hipStream_t s) {
-    if (h.ntiles <= 0 || h.nw <= 0 || h.K <= 0) return hipSuccess;
-    const int per_xcd = (h.ntiles + kXcds - 1) / kXcds;
-    const unsigned blocks = (unsigned)(per_xcd * h.nw * kXcds);
-    if (h.fp16)
-        hipLaunchKernelGGL(k_herk_split6<true>, dim3(blocks), dim3(512), 0, s, h);
-    else
-        hipLaunchKernelGGL(k_herk_split6<false>, dim3(blocks), dim3(512), 0, s, h);
     return hipGetLastError();
 }
 

@@ -134,7 +134,128 @@ __global__ __launch_bounds__(256) void k_optical_row(const double* __restrict__ 
     }
 }
 
+// Intraband head at q -> 0: term[b] = w (-df/de)_n (qhat.v_n)^2 for the listed bands n = band[b], with the
+// band velocity qhat.v_n = sum_Q |C_n(Q)|^2 wq(Q) - i sum_a sum_ij conj(P_ni) Dq_ij P_nj (the diagonal of
+// the optical row's numerator); one workgroup per band
+__global__ __launch_bounds__(256) void k_band_drude(const double* __restrict__ C, int nQ,
+                                                    const double* __restrict__ wq, const double* __restrict__ P,
+                                                    int ldP, const double* __restrict__ Dq,
+                                                    const int32_t* __restrict__ proj_off,
+                                                    const int32_t* __restrict__ qoff, int natoms,
+                                                    const int32_t* __restrict__ band, const double* __restrict__ mdf,
+                                                    double weight, double* __restrict__ term) {
+    __shared__ double red[2][256];
+    const int b = blockIdx.x;
+    const size_t n = band[b];
+    double mr = 0, di = 0;
+    for (int q = threadIdx.x; q < nQ; q += blockDim.x) {
+        const cplx<double> c = ld_c128(C, n * nQ + q);
+        mr += (c.x * c.x + c.y * c.y) * wq[q];
+    }
+    const int nq2 = natoms > 0 ? qoff[natoms] : 0;
+    for (int e = threadIdx.x; e < nq2; e += blockDim.x) {
+        int a = 0;
+        while (a + 1 < natoms && qoff[a + 1] <= e) ++a;
+        const int np = proj_off[a + 1] - proj_off[a];
+        const int r = e - qoff[a], i = r / np, j = r - i * np;
+        const cplx<double> t = cmulc(ld_c128(P, n * ldP + proj_off[a] + i), ld_c128(P, n * ldP + proj_off[a] + j));
+        di += t.y * Dq[e];
+    }
+    red[0][threadIdx.x] = mr;
+    red[1][threadIdx.x] = di;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // real part of (mom - i paw): mom is real (|C|^2 weights), paw = i * di for real antisymmetric D
+        const double v = red[0][0] + red[1][0];
+        term[b] = weight * mdf[b] * v * v;
+    }
+}
+
+// chi0_00(w) += -(sum of the terms)/(Omega w^2), one thread per frequency
+__global__ void k_add_drude(const double* __restrict__ term, int nterms, const double* __restrict__ omega, int nw,
+                            double inv_volume, double* __restrict__ head, long long stride) {
+    const int w = threadIdx.x;
+    if (w >= nw) return;
+    double s = 0;
+    for (int b = 0; b < nterms; ++b) s += term[b];
+    head[(size_t)w * stride] += -s * inv_volume / (omega[w] * omega[w]);
+}
+
 // ---------------------------------------------------------------- weights
+// Real frequencies w + i eta: rows w < nw hold Re a, rows nw + w hold Im a, with
+// a = prefac (f_n - f_m) [1/(w + i eta + d) - 1/(w + i eta - d)], d = e_n - e_m
+__global__ void k_weights_real(const double* __restrict__ epsk, const double* __restrict__ epskq,
+                               const double* __restrict__ fk, const double* __restrict__ fkq,
+                               const int32_t* __restrict__ pn, const int32_t* __restrict__ pm, int npairs,
+                               const double* __restrict__ omega, int nw, double eta, double prefac,
+                               double* __restrict__ a, int lda) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= lda) return;
+    if (p >= npairs) {
+        for (int w = 0; w < 2 * nw; ++w) a[(size_t)w * lda + p] = 0.0;
+        return;
+    }
+    const double d = epsk[pn[p]] - epskq[pm[p]];
+    const double df = fk[pn[p]] - fkq[pm[p]];
+    for (int w = 0; w < nw; ++w) {
+        const double x = omega[w];
+        // 1/(x + d + i eta) - 1/(x - d + i eta)
+        const double u = x + d, v = x - d, e2 = eta * eta;
+        const double du = u * u + e2, dv = v * v + e2;
+        const double re = u / du - v / dv;
+        const double im = -eta / du + eta / dv;
+        a[(size_t)w * lda + p] = prefac * df * re;
+        a[(size_t)(nw + w) * lda + p] = prefac * df * im;
+    }
+}
+
+// Real-frequency intraband head: head[w] += s Re(1/(Omega z^2)), head[nw + w] += s Im(1/(Omega z^2)),
+// z = w + i eta, s the sum of the terms
+__global__ void k_add_drude_real(const double* __restrict__ term, int nterms, const double* __restrict__ omega,
+                                 int nw, double eta, double inv_volume, double* __restrict__ head, long long stride) {
+    const int w = threadIdx.x;
+    if (w >= nw) return;
+    double s = 0;
+    for (int b = 0; b < nterms; ++b) s += term[b];
+    const double x = omega[w];
+    // 1/z^2 = (x^2 - eta^2 - 2 i x eta)/((x^2 - eta^2)^2 + 4 x^2 eta^2)
+    const double rr = x * x - eta * eta, ii = -2.0 * x * eta, den = rr * rr + ii * ii;
+    head[(size_t)w * stride] += s * inv_volume * rr / den;
+    head[(size_t)(nw + w) * stride] += s * inv_volume * ii / den;
+}
+
+// out[w] = A_w + i B_w for the Hermitian accumulators A_w (row block w) and B_w (row block nw + w), each
+// stored as its lower triangle (real and imaginary planes)
+__global__ void k_chi_out_real(const double* __restrict__ Cre, const double* __restrict__ Cim, int ldC,
+                               long long sC, int NG, int nw, double* __restrict__ out) {
+    const int i = blockIdx.x, w = blockIdx.y;
+    const double* ar = Cre + (size_t)w * sC;
+    const double* ai = Cim + (size_t)w * sC;
+    const double* br = Cre + (size_t)(nw + w) * sC;
+    const double* bi = Cim + (size_t)(nw + w) * sC;
+    double* o = out + 2 * ((size_t)w * NG * NG + (size_t)i * NG);
+    for (int j = threadIdx.x; j < NG; j += blockDim.x) {
+        double are, aim, bre, bim;
+        if (j <= i) {
+            const size_t e = (size_t)i * ldC + j;
+            are = ar[e]; aim = ai[e]; bre = br[e]; bim = bi[e];
+        } else {
+            const size_t e = (size_t)j * ldC + i;
+            are = ar[e]; aim = -ai[e]; bre = br[e]; bim = -bi[e];
+        }
+        // (are + i aim) + i (bre + i bim)
+        o[2 * j] = are - bim;
+        o[2 * j + 1] = aim + bre;
+    }
+}
+
 __global__ void k_weights(const double* __restrict__ epsk, const double* __restrict__ epskq,
                           const double* __restrict__ fk, const double* __restrict__ fkq, const int32_t* __restrict__ pn,
                           const int32_t* __restrict__ pm, int npairs, const double* __restrict__ omega, int nw,
@@ -628,12 +749,52 @@ hipError_t launch_optical_row(const double* Ck, const double* Ckq, int nQ, const
     return hipGetLastError();
 }
 
+hipError_t launch_band_drude(const double* C, int nQ, const double* wq, const double* P, int ldP, const double* Dq,
+                             const int32_t* proj_off, const int32_t* qoff, int natoms, const int32_t* band,
+                             const double* mdf, int nbands, double weight, double* term, hipStream_t s) {
+    if (!nbands) return hipSuccess;
+    hipLaunchKernelGGL(k_band_drude, dim3((unsigned)nbands), dim3(256), 0, s, C, nQ, wq, P, ldP, Dq, proj_off, qoff,
+                       natoms, band, mdf, weight, term);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_drude(const double* term, int nterms, const double* omega, int nw, double inv_volume,
+                            double* head, long long stride, hipStream_t s) {
+    if (nw > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_add_drude, dim3(1), dim3(256), 0, s, term, nterms, omega, nw, inv_volume, head, stride);
+    return hipGetLastError();
+}
+
 hipError_t launch_weights(const double* epsk, const double* epskq, const double* fk, const double* fkq,
                           const int32_t* pn, const int32_t* pm, int npairs, const double* omega, int nw, double prefac,
                           double* a, int lda, hipStream_t s) {
     if (!lda) return hipSuccess;
     hipLaunchKernelGGL(k_weights, dim3((unsigned)((lda + 255) / 256)), dim3(256), 0, s, epsk, epskq, fk, fkq, pn, pm,
                        npairs, omega, nw, prefac, a, lda);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights_real(const double* epsk, const double* epskq, const double* fk, const double* fkq,
+                               const int32_t* pn, const int32_t* pm, int npairs, const double* omega, int nw,
+                               double eta, double prefac, double* a, int lda, hipStream_t s) {
+    if (!lda) return hipSuccess;
+    hipLaunchKernelGGL(k_weights_real, dim3((unsigned)((lda + 255) / 256)), dim3(256), 0, s, epsk, epskq, fk, fkq, pn,
+                       pm, npairs, omega, nw, eta, prefac, a, lda);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_drude_real(const double* term, int nterms, const double* omega, int nw, double eta,
+                                 double inv_volume, double* head, long long stride, hipStream_t s) {
+    if (nw > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_add_drude_real, dim3(1), dim3(256), 0, s, term, nterms, omega, nw, eta, inv_volume, head,
+                       stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi_out_real(const double* Cre, const double* Cim, int ldC, int NG, int nw, double* out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_chi_out_real, dim3((unsigned)NG, (unsigned)nw), dim3(256), 0, s, Cre, Cim, ldC,
+                       (long long)ldC * ldC, NG, nw, out);
     return hipGetLastError();
 }
 

@@ -368,6 +368,8 @@ int check_states(const rpa_ctx* c, const rpa_states* s, const char* tag) {
         }
     for (int n = 0; n < s->nbands; ++n) {
         if (!(s->f[n] >= 0.0 && s->f[n] <= 2.0)) return fail(RPA_ERR_INPUT, t + ": occupation outside [0, 2]");
+        if (s->dfde && !(s->dfde[n] >= 0.0 && std::isfinite(s->dfde[n])))
+            return fail(RPA_ERR_INPUT, t + ": -df/de negative or not finite");
         if (!std::isfinite(s->eps[n])) return fail(RPA_ERR_INPUT, t + ": non-finite eigenvalue");
         if (n > 0 && s->eps[n] < s->eps[n - 1]) return fail(RPA_ERR_INPUT, t + ": eigenvalues not ascending");
         if (n > 0 && s->f[n] > s->f[n - 1] + kDeltaF)
@@ -546,10 +548,13 @@ std::vector<int32_t> scatter_map(const rpa_ctx* c, const rpa_states* s) {
 
 template <typename T>
 std::vector<cplx<T>> twiddles(int N) {
-    std::vector<cplx<T>> t(N);
+    // exp(-2 pi i t/N); in FP32 followed by the low parts fl(value - hi) (twiddle_len entries)
+    std::vector<cplx<T>> t(twiddle_len<T>(N));
     for (int i = 0; i < N; ++i) {
         const double a = kTwoPi * i / N;
-        t[i] = mk(T(std::cos(a)), T(-std::sin(a)));
+        const double c = std::cos(a), sn = -std::sin(a);
+        t[i] = mk(T(c), T(sn));
+        if (sizeof(T) == 4) t[N + i] = mk(T(c - (double)t[i].x), T(sn - (double)t[i].y));
     }
     return t;
 }
@@ -569,6 +574,9 @@ struct KSet {
     std::vector<int32_t> zcolk, zcolkq;   // (x, y) columns of the grid that hold coefficients, y * N1 + x
     std::vector<double> epsk, epskq, fk, fkq;
     std::vector<int32_t> nlist_all;  // n = 0 .. nbands-1
+    std::vector<int32_t> drude_band; // bands with -df/de > 0 (intraband head at q -> 0) and their -df/de
+    std::vector<double> drude_mdf;
+    void* d_drude_band = nullptr; void* d_drude_mdf = nullptr;
     void* d_pn = nullptr; void* d_pm = nullptr;
     void* d_mapk = nullptr; void* d_mapkq = nullptr;
     void* d_zcolk = nullptr; void* d_zcolkq = nullptr;
@@ -622,6 +630,9 @@ struct Batch {
     std::vector<QJob> qj;
     bool m_major = false;            // forward chi0: pairs ordered by m, then n (orbital reuse in cache)
     bool allow_paw_mfma = true;      // the adjoint keeps the factorised VALU PAW term (its own tables)
+    bool realfreq = false;           // real frequencies w + i eta: nw = 2 nw_user weight rows (Re, Im)
+    double eta = 0.0;
+    int nw_user = 0;
     bool paw_mfma = false;           // set by presize: PAW correction as an MFMA GEMM per band m
     int ld = 0;                      // the largest leading dimension of the batch's chi0 / -K matrices
     std::vector<QClass> cls;         // the q-points grouped by leading dimension
@@ -641,7 +652,7 @@ int default_variant(const rpa_ctx* c, rpa_precision prec, int NGp) {
     if (prec == RPA_FP64) return 0;
     auto it = c->tune.find(tune_key(prec, NGp));
     if (it != c->tune.end()) return it->second;
-    return ((NGp + 127) / 128 >= 4) ? 6 : 1;
+    return ((NGp + 127) / 128 >= 4) ? 5 : 1;
 }
 
 // Leading dimension of a q-point's matrices in a batch of nq: its padded sphere alone, or, with several
@@ -664,8 +675,7 @@ int chunk_size(const rpa_ctx* c, const QPlan& qp, int nw, size_t elem, int varia
     pc = std::max<size_t>(pc, 64);
     pc = std::min<size_t>(pc, 1 << 20);
     if (c->max_chunk > 0) pc = std::min<size_t>(pc, (size_t)c->max_chunk);
-    // variant 6 keeps the sum over one chunk in FP32: its chunks are bounded
-    if (variant == 6) pc = std::min<size_t>(pc, (size_t)kSplit6Chunk);
+    (void)variant;
     return (int)pc;
 }
 
@@ -750,6 +760,19 @@ int prepare_kset(Batch& B, KSet& K, Upload& up, const int32_t* pn_in = nullptr, 
     K.nlist_all.resize(k->nbands);
     std::iota(K.nlist_all.begin(), K.nlist_all.end(), 0);
     up.add(K.nlist_all, &K.d_nlist);
+    K.drude_band.clear();
+    K.drude_mdf.clear();
+    if (k->dfde) {
+        for (int n = 0; n < k->nbands; ++n)
+            if (k->dfde[n] > 0.0) {
+                K.drude_band.push_back(n);
+                K.drude_mdf.push_back(k->dfde[n]);
+            }
+        if (!K.drude_band.empty()) {
+            up.add(K.drude_band, &K.d_drude_band);
+            up.add(K.drude_mdf, &K.d_drude_mdf);
+        }
+    }
     return RPA_OK;
 }
 
@@ -791,7 +814,7 @@ void* buf(Batch& B, const char* name) { return (B.c->arena ? B.c->abufs : B.c->b
 
 // Work buffers, sized once for every q of the batch (never grown while launching).
 struct WorkSizes {
-    size_t tbuf = 0, rho = 0, weights = 0, paw_y = 0, paw_z = 0, pack = 0, scales = 0, chi = 0;
+    size_t tbuf = 0, rho = 0, weights = 0, paw_y = 0, paw_z = 0, pack = 0, scales = 0, chi = 0, drude = 0;
     size_t cholL = 0, cholP = 0, small = 0, phi_k = 0, phi_kq = 0;
 };
 
@@ -800,6 +823,7 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
     const size_t el = B.elem();
     for (auto& K : B.ks) {
+        W.drude += K.drude_band.size() * sizeof(double);
         W.phi_k = std::max(W.phi_k, (size_t)K.k->nbands * vol * 2 * el);
         if (!same_set(K.k, K.kq)) W.phi_kq = std::max(W.phi_kq, (size_t)K.kq->nbands * vol * 2 * el);
     }
@@ -816,7 +840,7 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
             // the first call with a sphere of this size bucket times the rank-k variants on it
             const int b = tune_bucket(g.NGp);
             if (!c->tune.count(tune_key(B.prec, b))) {
-                int rc = autotune_run(c, B.prec, b, std::max(256, std::min(P, kSplit6Chunk)), B.nw, B.s);
+                int rc = autotune_run(c, B.prec, b, std::max(256, std::min(P, 8192)), B.nw, B.s);
                 if (rc) return rc;
             }
             c->tune[tune_key(B.prec, g.NGp)] = c->tune[tune_key(B.prec, b)];
@@ -884,7 +908,8 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         const char* n;
         size_t b;
     } list[] = {{"phi_k", W.phi_k}, {"phi_kq", W.phi_kq}, {"tbuf", W.tbuf}, {"rho", W.rho},
-                {"weights", W.weights}, {"paw_y", W.paw_y}, {"paw_z", W.paw_z}, {"split_pack", W.pack},
+                {"weights", W.weights}, {"paw_y", W.paw_y}, {"paw_z", W.paw_z}, {"drude", W.drude},
+                {"split_pack", W.pack},
                 {"split_scales", W.scales},
                 {"chi", W.chi}, {"chol_L", W.cholL}, {"chol_panel", W.cholP}, {"ec_small", W.small}};
     for (auto& e : list) {
@@ -1032,7 +1057,7 @@ template <typename T>
 int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const double* aw, int lda) {
     rpa_ctx* c = B.c;
     const int NGp = Q.qp.NGp;
-    // the first update of an accumulator: variants 4, 5 and 6 store instead of adding (their tiles cover the
+    // the first update of an accumulator: variants 4 and 5 store instead of adding (their tiles cover the
     // lower triangle of this q-point's padded sphere, which is all the chi0 output reads; the E_c stage
     // assigns zero to the rest of a batch's common leading dimension); variant 1 adds into a zero-filled
     // accumulator
@@ -1102,18 +1127,11 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
             h.fp16 = fp16;
             h.scales = scales;
             h.overwrite = store_first;
-            if (Q.variant == 6) {
-                // 128 x 128 lower tiles over NGq
-                const int nT = NGq / 128;
-                h.ntiles = nT * (nT + 1) / 2;
-                HIP_TRY(launch_herk_split6(h, B.s));
-            } else {
-                // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
-                const int nR = NGp / kTile;
-                h.ntiles = 0;
-                for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
-                HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
-            }
+            // 64-row blocks I of the lower triangle, each with column blocks 0 .. I/2 of 128
+            const int nR = NGp / kTile;
+            h.ntiles = 0;
+            for (int I = 0; I < nR; ++I) h.ntiles += I / 2 + 1;
+            HIP_TRY(launch_herk_split4(h, Q.variant == 5, B.s));
         } else {
             HerkSplitArgs h{};
             h.Are = reinterpret_cast<const float*>(rre);
@@ -1170,11 +1188,19 @@ int enqueue_chi0(Batch& B) {
                 if (rc) return rc;
                 {
                     ProfScope ps_(c, S_WEIGHTS, B.s);
-                    HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
-                                           static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
-                                           static_cast<const int32_t*>(K.d_pn) + p0,
-                                           static_cast<const int32_t*>(K.d_pm) + p0, np,
-                                           static_cast<const double*>(B.d_om), B.nw, prefac, aw, lda, B.s));
+                    if (B.realfreq)
+                        HIP_TRY(launch_weights_real(
+                            static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
+                            static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
+                            static_cast<const int32_t*>(K.d_pn) + p0, static_cast<const int32_t*>(K.d_pm) + p0, np,
+                            static_cast<const double*>(B.d_om), B.nw_user, B.eta, prefac, aw, lda, B.s));
+                    else
+                        HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk),
+                                               static_cast<const double*>(K.d_epskq),
+                                               static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
+                                               static_cast<const int32_t*>(K.d_pn) + p0,
+                                               static_cast<const int32_t*>(K.d_pm) + p0, np,
+                                               static_cast<const double*>(B.d_om), B.nw, prefac, aw, lda, B.s));
                 }
                 rc = enqueue_update<T>(B, Q, np, rre, rim, aw, lda);
                 if (rc) return rc;
@@ -1183,6 +1209,33 @@ int enqueue_chi0(Batch& B) {
     }
     for (auto& Q : B.qj)
         if (Q.fresh) HIP_TRY(zero_accumulator(B, Q));
+    // intraband head of the optical q-points (sets that carry -df/de): term per band, then the head of every
+    // frequency's accumulator
+    for (auto& Q : B.qj) {
+        if (!Q.qs->optical || Q.qp.g0 < 0) continue;
+        double* term = static_cast<double*>(buf(B, "drude"));
+        int nt = 0;
+        for (size_t ik = 0; ik < B.ks.size(); ++ik) {
+            KSet& K = B.ks[ik];
+            if (K.drude_band.empty()) continue;
+            ProfScope ps_(c, S_OPTICAL, B.s);
+            HIP_TRY(launch_band_drude(static_cast<const double*>(K.k->C), K.k->nQ, static_cast<const double*>(Q.d_wq[ik]),
+                                      static_cast<const double*>(K.k->P), nproj_total(K.k),
+                                      static_cast<const double*>(Q.d_Dq), static_cast<const int32_t*>(B.d_poff),
+                                      static_cast<const int32_t*>(B.d_qoff), K.k->natoms,
+                                      static_cast<const int32_t*>(K.d_drude_band),
+                                      static_cast<const double*>(K.d_drude_mdf), (int)K.drude_band.size(),
+                                      K.k->weight, term + nt, B.s));
+            nt += (int)K.drude_band.size();
+        }
+        if (nt > 0 && B.realfreq)
+            HIP_TRY(launch_add_drude_real(term, nt, static_cast<const double*>(B.d_om), B.nw_user, B.eta,
+                                          1.0 / c->volume, Q.cr + (size_t)Q.qp.g0 * Q.ld + Q.qp.g0,
+                                          (long long)Q.ld * Q.ld, B.s));
+        else if (nt > 0)
+            HIP_TRY(launch_add_drude(term, nt, static_cast<const double*>(B.d_om), B.nw, 1.0 / c->volume,
+                                     Q.cr + (size_t)Q.qp.g0 * Q.ld + Q.qp.g0, (long long)Q.ld * Q.ld, B.s));
+    }
     return RPA_OK;
 }
 
@@ -1797,6 +1850,8 @@ uint64_t batch_key(const rpa_states* k, const rpa_states* kq, int nk, int nq, co
         if (s->natoms > 0) h.bytes(s->proj_off, sizeof(int32_t) * (s->natoms + 1));
         h.bytes(s->kpt, sizeof(s->kpt));
         h.val(s->weight);
+        h.val(s->dfde != nullptr);
+        if (s->dfde) h.bytes(s->dfde, sizeof(double) * s->nbands);
     };
     for (int i = 0; i < nk; ++i) {
         st(&k[i]);
@@ -2011,6 +2066,34 @@ int rpa_chi0(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, cons
     return chi0_impl(c, k, kq, nk, qs, fr, prec, chi0_out, 0, stream);
 }
 
+int rpa_chi0_real(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                  const double* omega, int nw, double eta, rpa_precision prec, void* chi0_out, void* stream) {
+    int rc = check_common(c, k, kq, nk, qs);
+    if (rc) return rc;
+    if (!chi0_out) return fail(RPA_ERR_INPUT, "NULL chi0_out");
+    if (nw <= 0 || nw > 256 || !omega) return fail(RPA_ERR_INPUT, "need 1 to 256 real frequencies");
+    for (int i = 0; i < nw; ++i)
+        if (!std::isfinite(omega[i])) return fail(RPA_ERR_INPUT, "non-finite frequency");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(RPA_ERR_INPUT, "eta must be positive");
+    Batch B;
+    rc = begin(B, c, nullptr, prec, stream);
+    if (rc) return rc;
+    B.realfreq = true;
+    B.eta = eta;
+    B.nw_user = nw;
+    B.nw = 2 * nw;
+    B.om.assign(omega, omega + nw);
+    B.ow.assign(nw, 0.0);
+    B.m_major = true;
+    rc = plan_batch(B, k, kq, nk, qs, 1, false, true, "tables");
+    if (rc) return rc;
+    rc = prec == RPA_FP64 ? enqueue_chi0<double>(B) : enqueue_chi0<float>(B);
+    if (rc) return rc;
+    QJob& Q = B.qj[0];
+    HIP_TRY(launch_chi_out_real(Q.cr, Q.ci, Q.ld, Q.qp.NG, nw, static_cast<double*>(chi0_out), B.s));
+    return RPA_OK;
+}
+
 int rpa_chi0_add(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
                  const rpa_freq* fr, rpa_precision prec, void* chi0_inout, void* stream) {
     return chi0_impl(c, k, kq, nk, qs, fr, prec, chi0_inout, 1, stream);
@@ -2187,6 +2270,8 @@ int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, const
     if (!same && (!deps_kq || !dC_kq)) return fail(RPA_ERR_INPUT, "distinct k+q set needs its own gradient outputs");
     if (k->natoms > 0 && (!dP_k || (!same && !dP_kq))) return fail(RPA_ERR_INPUT, "NULL projection gradient");
     if ((long long)c->N[0] * c->N[1] > 16 * 256) return fail(RPA_ERR_UNSUPPORTED, "adjoint needs N1*N2 <= 4096");
+    if (qs->optical && (k->dfde || kq->dfde))
+        return fail(RPA_ERR_UNSUPPORTED, "the adjoint has no intraband head (state sets with -df/de)");
     Batch B;
     rc = begin(B, c, fr, RPA_FP64, stream);
     if (rc) return rc;
@@ -2217,9 +2302,9 @@ int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs) {
 int rpa_tune_set(rpa_ctx* c, rpa_precision prec, int NG, int variant) {
     if (!c) return fail(RPA_ERR_INPUT, "NULL context");
     if (prec == RPA_FP64) return variant == 0 ? RPA_OK : fail(RPA_ERR_INPUT, "FP64 has one kernel variant (0)");
-    if (variant != 1 && variant != 4 && variant != 5 && variant != 6)
-        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 4 (64x128 pipelined, FP64 accumulation), 5 "
-                                   "(as 4, eight waves) and 6 (128x128, eight waves of 32x64, bounded chunks)");
+    if (variant != 1 && variant != 4 && variant != 5)
+        return fail(RPA_ERR_INPUT, "split variants are 1 (64x64), 4 (64x128 pipelined, FP64 accumulation) and 5 "
+                                   "(as 4, eight waves)");
     const int NGp = (NG + kTile - 1) / kTile * kTile;
     c->tune[tune_key(prec, NGp)] = variant;
     return RPA_OK;
@@ -2286,10 +2371,10 @@ int autotune_run(rpa_ctx* c, rpa_precision prec, int NG, int npairs, int nw, hip
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e300;
     int bestv = 1;
-    // each variant on the pairs of one of its chunks; compared by time per pair
-    for (int v : {1, 4, 5, 6}) {
+    // each variant on the same operands, compared by time per pair
+    for (int v : {1, 4, 5}) {
         Q.variant = v;
-        const int kv = v == 6 ? std::min(npairs, kSplit6Chunk) : npairs;
+        const int kv = npairs;
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipEventRecord(e0, s));
@@ -2324,7 +2409,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     if (save) {
         FILE* f = std::fopen(path, "w");
         if (!f) return fail(RPA_ERR_INPUT, std::string("cannot write ") + path);
-        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 4 / 5 = pipelined 64x128, 6 = 128x128)\n");
+        std::fprintf(f, "# precision padded_NG variant (1 = 64x64, 4 / 5 = pipelined 64x128)\n");
         for (auto& kv : c->tune) std::fprintf(f, "%d %d %d\n", (int)(kv.first >> 32), (int)(kv.first & 0xffffffff), kv.second);
         std::fclose(f);
         return RPA_OK;
@@ -2335,7 +2420,7 @@ int rpa_tune_cache_io(rpa_ctx* c, const char* path, int save) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int p, ng, v;
-        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || (v >= 4 && v <= 6)) && ng > 0)
+        if (std::sscanf(line, "%d %d %d", &p, &ng, &v) == 3 && (v == 1 || v == 4 || v == 5) && ng > 0)
             c->tune[tune_key((rpa_precision)p, ng)] = v;
     }
     std::fclose(f);

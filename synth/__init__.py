@@ -132,6 +132,7 @@ class StateSet:
     eps: np.ndarray          # float64 [nb], ascending
     f: np.ndarray            # float64 [nb], in [0, 2], non-increasing
     P: np.ndarray            # complex128 [nb, sum Np]
+    dfde: Optional[np.ndarray] = None   # float64 [nb], -df/d eps (Fermi-smeared sets), else None
 
     @property
     def nbands(self):
@@ -212,20 +213,22 @@ def orthonormal_coefficients(rng, A, kpt, miller, nb):
     return np.ascontiguousarray(Qm.T)
 
 
-def gapped_levels(rng, n_occ, n_unocc, occ_range=(-0.8, -0.3), unocc_range=(0.0, 3.0)):
+def gapped_levels(rng, n_occ, n_unocc, occ_range=(-0.8, -0.3), unocc_range=(0.0, 3.0), fmax=2.0):
+    """Sorted levels, f = fmax below the gap (2: both spins in one set; 1: one spin channel)."""
     eo = np.sort(rng.uniform(occ_range[0], occ_range[1], n_occ))
     eu = np.sort(rng.uniform(unocc_range[0], unocc_range[1], n_unocc))
     eps = np.concatenate([eo, eu])
-    f = np.concatenate([np.full(n_occ, 2.0), np.zeros(n_unocc)])
+    f = np.concatenate([np.full(n_occ, float(fmax)), np.zeros(n_unocc)])
     return eps, f
 
 
-def fermi_levels(rng, n_below, n_above, T=0.01, mu=0.0):
+def fermi_levels(rng, n_below, n_above, T=0.01, mu=0.0, fmax=2.0):
+    """Sorted levels around mu with Fermi-Dirac occupations f = fmax/(1 + e^{(eps - mu)/T})."""
     eb = np.sort(rng.uniform(-0.8, 0.0, n_below))
     ea = np.sort(rng.uniform(0.0, 3.0, n_above))
     eps = np.concatenate([eb, ea])
     x = np.clip((eps - mu) / T, -700.0, 700.0)
-    f = 2.0 / (1.0 + np.exp(x))
+    f = float(fmax) / (1.0 + np.exp(x))
     return eps, f
 
 
@@ -400,33 +403,42 @@ def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
     nproj_total = int(sum(nproj))
     sets = []
     kq = None
+    channels = levels if isinstance(levels, (list, tuple)) else [levels]
     if paw_model == "overlap":
         raw = []
         for ik, k in enumerate(kpts):
             miller = wavefunction_sphere(A, k, ecut_wf)
-            C0 = raw_coefficients(rng, A, k, miller, levels(None, dry=True))
-            eps, f = levels(rng)
-            raw.append((k, kweights[ik], miller, C0, eps, f))
+            for lev in channels:
+                C0 = raw_coefficients(rng, A, k, miller, lev(None, dry=True))
+                eps, f = lev(rng)
+                raw.append((ik, k, kweights[ik], miller, C0, eps, f))
         paw = draw_paw(rng, A, nproj)
         pis = []
+        pi_k = {}
         for i in range(len(raw)):
-            k, w, miller, C0, eps, f = raw[i]
+            ik, k, w, miller, C0, eps, f = raw[i]
             raw[i] = None                  # the raw draw is released once orthonormalised
-            Pi = projector_map(rng, A, k, miller, paw)
+            if ik not in pi_k:             # one projector map per k, shared by its spin channels
+                pi_k[ik] = projector_map(rng, A, k, miller, paw)
+            Pi = pi_k[ik]
             pis.append(Pi)
             C, P = paw_orthonormal_states(C0, Pi, paw, device)
             del C0
+            lev = channels[i % len(channels)]
+            dfde = lev.dfde(f) if hasattr(lev, "dfde") else None
             sets.append(StateSet(kpt=np.asarray(k, dtype=np.float64), weight=float(w), miller=miller,
-                                 C=C, eps=eps, f=f, P=P))
+                                 C=C, eps=eps, f=f, P=P, dfde=dfde))
         if extra_kq:
             kq = []
-            for s, Pi in zip(sets, pis):
+            for i, (s, Pi) in enumerate(zip(sets, pis)):
                 C0 = raw_coefficients(rng, A, s.kpt, s.miller, s.nbands)
-                eps2, f2 = levels(rng)
+                eps2, f2 = channels[i % len(channels)](rng)
                 C2, P2 = paw_orthonormal_states(C0, Pi, paw, device)
                 kq.append(StateSet(kpt=s.kpt.copy(), weight=s.weight, miller=s.miller, C=C2,
                                    eps=eps2, f=f2, P=P2))
     elif paw_model == "independent":
+        if len(channels) != 1:
+            raise ValueError("spin channels need the overlap projection model")
         pend = []
         for ik, k in enumerate(kpts):
             miller = wavefunction_sphere(A, k, ecut_wf)
@@ -456,6 +468,21 @@ def _assemble(name, A, grid, seed, kpts, kweights, levels, nproj, qpoints, nw,
     return wl
 
 
+def _spin_gapped(n_occ, n_unocc, moment):
+    """Two spin channels (f in [0, 1]) with n_occ + moment/2 and n_occ - moment/2 occupied states and the
+    same number of bands in each."""
+    up, dn = n_occ + moment // 2, n_occ - moment // 2
+    nb = n_occ + n_unocc
+
+    def channel(n_o):
+        def levels(rng, dry=False):
+            if dry:
+                return nb
+            return gapped_levels(rng, n_o, nb - n_o, fmax=1.0)
+        return levels
+    return [channel(up), channel(dn)]
+
+
 def _gapped(n_occ, n_unocc):
     def levels(rng, dry=False):
         if dry:
@@ -464,11 +491,13 @@ def _gapped(n_occ, n_unocc):
     return levels
 
 
-def _fermi(n_below, n_above, T):
+def _fermi(n_below, n_above, T, fmax=2.0):
     def levels(rng, dry=False):
         if dry:
             return n_below + n_above
-        return fermi_levels(rng, n_below, n_above, T)
+        return fermi_levels(rng, n_below, n_above, T, fmax=fmax)
+    # -df/d eps of f = fmax/(1 + e^{(eps - mu)/T}) from f itself
+    levels.dfde = lambda f: f * (fmax - f) / (fmax * T)
     return levels
 
 
@@ -507,7 +536,7 @@ def config0(seed: int = 0, n_occ: int = 4, n_unocc: int = 60, nw: int = 8, extra
 
 def config1(seed: int = 1, n_occ: int = 16, n_unocc: int = 800, nw: int = 16,
             target_ng: int = 1500, grid=(48, 48, 48), which_q=(0, 1, 2),
-            paw_model: str = "overlap") -> Workload:
+            paw_model: str = "overlap", spin_moment: int = 0) -> Workload:
     """O2-in-box scale: 12x12x13 bohr, 48^3 grid, Gamma, 16 occupied + 800 unoccupied,
     2 atoms x 13 projectors, ~1500 G, 16 frequencies, q = 0 (optical), 0.1, 0.2 x 2pi/12 along x."""
     A = np.diag([12.0, 12.0, 13.0])
@@ -520,8 +549,9 @@ def config1(seed: int = 1, n_occ: int = 16, n_unocc: int = 800, nw: int = 16,
         else:
             q = np.array([0.1 * i * TWO_PI / 12.0, 0.0, 0.0])
             qs.append(QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), weight=1.0 / 3))
+    levels = _spin_gapped(n_occ, n_unocc, spin_moment) if spin_moment else _gapped(n_occ, n_unocc)
     return _assemble("cfg1-o2box", A, grid, seed, [np.zeros(3)], [1.0],
-                     _gapped(n_occ, n_unocc), [13, 13], qs, nw, paw_model=paw_model)
+                     levels, [13, 13], qs, nw, paw_model=paw_model)
 
 
 def config2(seed: int = 2, n_below: int = 120, n_above: int = 3000, nk: int = 8, nw: int = 16,
@@ -565,7 +595,7 @@ def config3(seed: int = 3, n_occ: int = 60, n_unocc: int = 1500, nq: int = 64, n
 
 def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), target_ng=15,
          q_frac=(0.1, 0.0, 0.0), nw=8, seed=11, optical=False, extra_kq=False, ecut_wf_scale=None,
-         paw_model="overlap"):
+         paw_model="overlap", spin_moment=None, fermi_T=None):
     """Small cases on tiny grids for direct-sum checks and ragged shapes."""
     A = np.diag(np.asarray(L, dtype=np.float64))
     B = reciprocal_rows(A)
@@ -573,5 +603,11 @@ def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), ta
     if optical:
         q = np.zeros(3)
     qp = QPoint(q=q, ecut=ecut_for_count(A, q, target_ng), optical=optical)
-    return _assemble("tiny", A, grid, seed, [np.zeros(3)], [1.0], _gapped(n_occ, n_unocc),
+    if fermi_T is not None:
+        levels = _fermi(n_occ, n_unocc, fermi_T)
+    elif spin_moment is None:
+        levels = _gapped(n_occ, n_unocc)
+    else:
+        levels = _spin_gapped(n_occ, n_unocc, spin_moment)
+    return _assemble("tiny", A, grid, seed, [np.zeros(3)], [1.0], levels,
                      list(nproj), [qp], nw, extra_kq=extra_kq, paw_model=paw_model)

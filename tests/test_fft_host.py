@@ -67,3 +67,39 @@ def test_register_lengths_match_numpy(lib):
 def test_register_unsupported_length_is_rejected(lib):
     x = np.zeros(7, dtype=np.complex128)
     assert lib.fft_reg_host(7, -1, x.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p)) == -1
+
+
+def _f32_bias(lib, fn, N, direction, nlines=4000, seed=7):
+    """Mean over random lines of (|X_32|^2 - |X|^2)/|X|^2 per output bin, weighted by |X|^2, and the
+    statistical noise of that mean; X the exact transform (numpy, FP64) of the same FP32 input."""
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((nlines, N)) + 1j * rng.standard_normal((nlines, N))).astype(np.complex64)
+    out = np.empty_like(x)
+    rc = fn(N, direction, nlines, x.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 0
+    xd = x.astype(np.complex128)
+    ref = np.fft.fft(xd, axis=1) if direction < 0 else np.fft.ifft(xd, axis=1) * N
+    a64 = np.abs(ref) ** 2
+    rel = (np.abs(out.astype(np.complex128)) ** 2 - a64) / a64
+    w = a64 / a64.sum(axis=0, keepdims=True)
+    bias = (rel * w).sum(axis=0)
+    noise = np.sqrt(((rel - bias) ** 2 * w * w).sum(axis=0))
+    return bias, noise, np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N", [40, 48, 160])
+def test_fp32_transforms_carry_no_systematic_bias(lib, N):
+    """FP32 transforms multiply by roots of unity held as two floats (the value and its remainder): their
+    outputs then carry the rounding of the arithmetic alone, which averages over lines, and no systematic
+    shift of |X|^2 from rounded constants. The mean over 4000 random lines stays within a few standard
+    errors of zero, and far below the ~1e-7 that singly rounded FP32 constants produce."""
+    fns = [lib.fft_lines_host_f32]
+    if N in _reg_sizes(lib):
+        fns.append(lib.fft_reg_host_f32)
+    for fn in fns:
+        fn.restype = ctypes.c_int
+        for direction in (-1, 1):
+            bias, noise, err = _f32_bias(lib, fn, N, direction)
+            assert err < 1e-6
+            assert np.max(np.abs(bias)) < 2e-8, (fn.__name__, direction, np.max(np.abs(bias)))
+            assert np.median(np.abs(bias) / noise) < 3.0

@@ -106,3 +106,39 @@ def test_autograd_function(rpa):
         assert torch.allclose(C.grad, g["C_k"], rtol=1e-12, atol=1e-18)
         assert torch.allclose(P.grad, g["P_k"], rtol=1e-12, atol=1e-18)
         assert torch.allclose(eps.grad, g["eps_k"].cpu(), rtol=1e-12, atol=1e-18)
+
+
+@pytest.mark.parametrize("iq", [0, 1])
+def test_adjoint_full_o2box_directional_derivatives(rpa, iq):
+    """The differentiation form at O2-in-box size: all 16 + 800 states (12,800 pairs, NG ~ 1500), the optical
+    q-point and q = 0.1 x 2 pi/12. The gradient's directional derivative along 10 random unit directions of
+    (C, P, eps) equals the central difference (step 1e-5) of the library's FP64 E_c."""
+    wl = synth.config1(which_q=(iq,))
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    s = wl.kpoints[0]
+    rng = np.random.default_rng(40 + iq)
+    D = synth.paw_d_table(wl.paw)
+    qp = wl.qpoints[0]
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, g = ctx.ec_backward(ks[0], ks[0], qs, fr)
+        gC, gP, ge = g["C_k"].cpu().numpy(), g["P_k"].cpu().numpy(), g["eps_k"].cpu().numpy()
+
+        def energy(C, P, eps):
+            st = rpa.States(C, s.miller, eps, s.f, P, wl.paw.offsets, s.kpt, s.weight)
+            e, _ = ctx.ec([st], [st], qs, fr, "fp64")
+            return float(e.cpu()[0])
+
+        e0 = energy(s.C, s.P, s.eps)
+        assert abs(e0 - float(ec.cpu()[0])) < 1e-12
+        h = 1e-5
+        for trial in range(10):
+            dC = rng.standard_normal(s.C.shape) + 1j * rng.standard_normal(s.C.shape)
+            dP = rng.standard_normal(s.P.shape) + 1j * rng.standard_normal(s.P.shape)
+            de = rng.standard_normal(s.eps.shape)
+            nrm = np.sqrt(np.sum(np.abs(dC) ** 2) + np.sum(np.abs(dP) ** 2) + np.sum(de ** 2))
+            dC, dP, de = dC / nrm, dP / nrm, de / nrm
+            fd = (energy(s.C + h * dC, s.P + h * dP, s.eps + h * de)
+                  - energy(s.C - h * dC, s.P - h * dP, s.eps - h * de)) / (2 * h)
+            pred = float(np.real(np.sum(np.conj(gC) * dC)) + np.real(np.sum(np.conj(gP) * dP)) + np.sum(ge * de))
+            print(f"q{iq} direction {trial}: fd={fd:.10e} adjoint={pred:.10e} diff={fd - pred:.2e}", flush=True)
+            assert abs(fd - pred) < 1e-6 * max(1.0, abs(pred))

@@ -119,3 +119,26 @@ def test_chi0_add_sums_over_k(rpa, slab, prec):
     print(f"{prec}: chi0_add vs chi0 {_rel(acc, both):.3e}, vs oracle {_rel(acc, ref['chi']):.3e}", flush=True)
     assert _rel(acc, both) < 1e-13
     assert _rel(acc, ref["chi"]) < (1e-12 if prec == "fp64" else 2e-4)
+
+
+@pytest.mark.parametrize("iq", [0, 1])
+def test_spin_polarised_o2box_reduced(rpa, iq):
+    """Spin-polarised O2-in-box shape (two channels with f in [0, 1], 5 + 39 and 3 + 41 states: a moment
+    of 2, as in the O2 triplet), optical and finite q: chi0 and E_c of the two channels together against
+    the oracle (Eq. chi0 with the spin sum written out as two state sets)."""
+    wl = synth.config1(n_occ=4, n_unocc=40, which_q=(0, 1), spin_moment=2)
+    assert len(wl.kpoints) == 2 and wl.kpoints[0].f.max() == 1.0
+    ref = oracle_q(wl, iq)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl, iq)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        chi = ctx.chi0(ks, kqs, qs, fr, "fp64").cpu().numpy()
+        ec, F = ctx.ec(ks, kqs, qs, fr, "fp64")
+        ecs, _ = ctx.ec(ks, kqs, qs, fr, "split_bf16")
+        ctx.check()
+    ec, ecs = float(ec.cpu()[0]), float(ecs.cpu()[0])
+    r = _rel(chi, ref["chi"])
+    print(f"spin q{iq}: NG={len(gm)} chi rel={r:.3e} E={ec:.12f} ref={ref['E']:.12f} split dE={ecs - ref['E']:.3e}",
+          flush=True)
+    assert r < 1e-12
+    assert abs(ec - ref["E"]) < 1e-10
+    assert abs(ecs - ref["E"]) < 1e-6
