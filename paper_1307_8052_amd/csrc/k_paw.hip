@@ -33,34 +33,50 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-// Z[s][ai][g] for m = m_lo + s: sum_j Q[qoff_a + i Np_a + j][g] P'[m][a j]; zero for g >= NG
+// Z[s][ai][g] for m = m_lo + s: sum_j Q[qoff_a + i Np_a + j][g] P'[m][a j]; zero for g >= NG. A thread
+// takes kZSlots consecutive bands m, so each element of Q is read once per kZSlots bands.
+constexpr int kZSlots = 8;
 template <typename T>
-__global__ __launch_bounds__(256) void k_paw_z(const double* __restrict__ Pkq, int ldP, int m_lo,
+__global__ __launch_bounds__(256) void k_paw_z(const double* __restrict__ Pkq, int ldP, int m_lo, int nslots,
                                                const int32_t* __restrict__ proj_off, const int32_t* __restrict__ qoff,
                                                int natoms, int nproj, const double* __restrict__ Q, int NG, int NGp,
                                                T* __restrict__ Zr, T* __restrict__ Zi) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int ai = blockIdx.y;
-    const int s = blockIdx.z;
+    const int s0 = blockIdx.z * kZSlots;
     if (g >= NGp) return;
     int a = 0;
     while (a + 1 < natoms && proj_off[a + 1] <= ai) ++a;
     const int lo = proj_off[a], np = proj_off[a + 1] - lo, i = ai - lo;
-    const size_t m = (size_t)(m_lo + s);
-    double sr = 0.0, si = 0.0;
+    const int ns = min(kZSlots, nslots - s0);
+    double sr[kZSlots], si[kZSlots];
+#pragma unroll
+    for (int t = 0; t < kZSlots; ++t) {
+        sr[t] = 0.0;
+        si[t] = 0.0;
+    }
     if (g < NG) {
         const double* qrow = Q + 2 * ((size_t)(qoff[a] + i * np) * NG + g);
-        const double* prow = Pkq + 2 * (m * ldP + lo);
         for (int j = 0; j < np; ++j) {
             const double qr = qrow[2 * (size_t)j * NG], qi = qrow[2 * (size_t)j * NG + 1];
-            const double pr = prow[2 * j], pi = prow[2 * j + 1];
-            sr += qr * pr - qi * pi;
-            si += qr * pi + qi * pr;
+#pragma unroll
+            for (int t = 0; t < kZSlots; ++t) {
+                // slots past the last are clamped to it (computed and not stored)
+                const size_t m = (size_t)(m_lo + s0 + min(t, ns - 1));
+                const double pr = Pkq[2 * (m * ldP + lo + j)], pi = Pkq[2 * (m * ldP + lo + j) + 1];
+                sr[t] += qr * pr - qi * pi;
+                si[t] += qr * pi + qi * pr;
+            }
         }
     }
-    const size_t o = ((size_t)s * nproj + ai) * NGp + g;
-    Zr[o] = T(sr);
-    Zi[o] = T(si);
+#pragma unroll
+    for (int t = 0; t < kZSlots; ++t) {
+        if (t < ns) {
+            const size_t o = ((size_t)(s0 + t) * nproj + ai) * NGp + g;
+            Zr[o] = T(sr[t]);
+            Zi[o] = T(si[t]);
+        }
+    }
 }
 
 // One workgroup per (64 G-vectors, 64 consecutive pairs of the chunk). The pairs of the window are taken
@@ -166,9 +182,9 @@ hipError_t launch_paw_mfma(const double* Pk, const double* Pkq, int ldP, const i
                            int nproj, const double* Q, int NG, int NGp, T* Zr, T* Zi, T* rre, T* rim, hipStream_t s) {
     if (!npairs || !nproj) return hipSuccess;
     if (NGp % 64) return hipErrorInvalidValue;
-    dim3 gz((unsigned)((NGp + 255) / 256), (unsigned)nproj, (unsigned)nslots);
-    hipLaunchKernelGGL(k_paw_z<T>, gz, dim3(256), 0, s, Pkq, ldP, m_lo, proj_off, qoff, natoms, nproj, Q, NG, NGp, Zr,
-                       Zi);
+    dim3 gz((unsigned)((NGp + 255) / 256), (unsigned)nproj, (unsigned)((nslots + kZSlots - 1) / kZSlots));
+    hipLaunchKernelGGL(k_paw_z<T>, gz, dim3(256), 0, s, Pkq, ldP, m_lo, nslots, proj_off, qoff, natoms, nproj, Q, NG,
+                       NGp, Zr, Zi);
     dim3 gm((unsigned)(NGp / 64), (unsigned)((npairs + 63) / 64));
     hipLaunchKernelGGL(k_paw_mm<T>, gm, dim3(256), 0, s, Zr, Zi, nproj, Pk, ldP, pn, pm, npairs, m_lo, NGp, rre, rim);
     return hipGetLastError();
