@@ -611,3 +611,98 @@ def tiny(grid=(8, 8, 8), L=(7.0, 7.5, 8.0), n_occ=2, n_unocc=5, nproj=(2, 3), ta
         levels = _spin_gapped(n_occ, n_unocc, spin_moment)
     return _assemble("tiny", A, grid, seed, [np.zeros(3)], [1.0], levels,
                      list(nproj), [qp], nw, extra_kq=extra_kq, paw_model=paw_model)
+
+
+# ----------------------------------------------------------------------------
+# a cubic crystal with point symmetry: state sets of irreducible-zone k-points for the unfolding
+# (Eq. kmap, Eq. trans_wfs; Table 1 steps 4 and 7)
+# ----------------------------------------------------------------------------
+# one atom at the origin and six at +-a/4 along the axes (stored in [0, 1)): an orbit of the full cubic
+# group, so every cubic operation maps atoms onto atoms, some of them across a lattice vector
+CUBIC_ATOMS = np.array([[0.0, 0.0, 0.0], [0.25, 0.0, 0.0], [0.75, 0.0, 0.0], [0.0, 0.25, 0.0],
+                        [0.0, 0.75, 0.0], [0.0, 0.0, 0.25], [0.0, 0.0, 0.75]])
+
+
+@dataclasses.dataclass
+class SymWorkload:
+    A: np.ndarray
+    grid: tuple
+    atoms: np.ndarray        # (Na, 3) fractional positions
+    paw: Paw                 # s and p projectors per atom (Np = 4: s, p_x, p_y, p_z)
+    sets: List[StateSet]     # state sets at the requested k-points
+    qpoint: QPoint
+    omega: np.ndarray
+    omega_weight: np.ndarray
+
+
+def atom_images(U, atoms):
+    """(atom_map, atom_shift) of the fractional operation x -> U x: T^-1 R_a = R_b + L_a."""
+    Ui = np.rint(np.linalg.inv(np.asarray(U, dtype=np.float64))).astype(np.int64)
+    amap, shift = [], []
+    for x in atoms:
+        y = Ui @ x
+        for b, xb in enumerate(atoms):
+            d = y - xb
+            if np.allclose(d, np.rint(d), atol=1e-12):
+                amap.append(b)
+                shift.append(np.rint(d).astype(np.int32))
+                break
+        else:
+            raise ValueError("the atoms are not closed under the operation")
+    return np.asarray(amap, dtype=np.int32), np.asarray(shift, dtype=np.int32).reshape(-1, 3)
+
+
+def cartesian_op(U, A):
+    A = np.asarray(A, dtype=np.float64)
+    return A.T @ np.asarray(U, dtype=np.float64) @ np.linalg.inv(A.T)
+
+
+def sp_rotation_blocks(U, A, natoms):
+    """Flat D blocks [natoms * 16] for s + p projector functions: p_i(T y) = sum_j D_ij p_j(y) gives
+    D = 1 for s and the Cartesian matrix of the operation for (p_x, p_y, p_z)."""
+    blk = np.zeros((4, 4))
+    blk[0, 0] = 1.0
+    blk[1:, 1:] = cartesian_op(U, A)
+    return np.tile(blk.reshape(-1), natoms)
+
+
+def sp_projector_map(A, kpt, miller, paw, beta=1.0):
+    """Pi[Q, 4a + i] = beta <p~^a_i|e^{i(k+G_Q).r}> for real s and p Gaussian projector functions:
+    e^{i K.R_a} (1, i K_x, i K_y, i K_z) e^{-|K|^2 sigma^2/2}, K = k + G_Q; [NQ, 4 Na]."""
+    B = reciprocal_rows(A)
+    K = cart(miller, B, kpt)
+    g = np.exp(-0.5 * paw.sigma ** 2 * (K[:, 0] ** 2 + K[:, 1] ** 2 + K[:, 2] ** 2))
+    cols = []
+    for a in range(len(paw.nproj)):
+        ph = np.exp(1j * (K @ paw.R[a])) * g
+        cols += [ph, 1j * K[:, 0] * ph, 1j * K[:, 1] * ph, 1j * K[:, 2] * ph]
+    return beta * np.stack(cols, axis=1)
+
+
+def symmetric_cubic(kpoints, seed=21, L=7.0, grid=(12, 12, 12), n_occ=3, n_unocc=9, target_ng=19,
+                    q=(0.09, -0.05, 0.07), nw=8, beta=0.35):
+    """State sets at the given Cartesian k-points of a simple-cubic crystal (CUBIC_ATOMS, s + p
+    projectors with s^a = diag(0.3, -0.1, -0.1, -0.1), the same for every atom, so that the PAW overlap
+    and the Q table are invariant under every cubic operation). Per k-point, in order: raw coefficients
+    and gapped levels, then the PAW orthonormalisation with the s + p projector map. q in units of
+    2 pi / L."""
+    rng = np.random.default_rng(seed)
+    A = L * np.eye(3)
+    atoms = CUBIC_ATOMS.copy()
+    na = atoms.shape[0]
+    paw = Paw(nproj=[4] * na, s=[np.diag([0.3, -0.1, -0.1, -0.1]) for _ in range(na)], R=atoms @ A,
+              D=[np.zeros((3, 4, 4)) for _ in range(na)], sigma=0.6)
+    qv = np.asarray(q, dtype=np.float64) * 2 * np.pi / L
+    qp = QPoint(q=qv, ecut=ecut_for_count(A, qv, target_ng))
+    levels = _gapped(n_occ, n_unocc)
+    sets = []
+    for k in kpoints:
+        k = np.asarray(k, dtype=np.float64)
+        miller = wavefunction_sphere(A, k, 4.0 * qp.ecut)
+        C0 = raw_coefficients(rng, A, k, miller, n_occ + n_unocc)
+        eps, f = levels(rng)
+        C, P = paw_orthonormal_states(C0, sp_projector_map(A, k, miller, paw, beta), paw)
+        sets.append(StateSet(kpt=k, weight=1.0 / len(kpoints), miller=miller, C=C, eps=eps, f=f, P=P))
+    omega, ow = frequency_grid(nw)
+    return SymWorkload(A=A, grid=tuple(grid), atoms=atoms, paw=paw, sets=sets, qpoint=qp, omega=omega,
+                       omega_weight=ow)
