@@ -36,6 +36,14 @@ def ec_torch(A, grid, C_k, C_kq, miller_k, miller_kq, eps_k, eps_kq, f_k, f_kq, 
     With same_set=True the k+q arguments are ignored and the k tensors are used
     for both sides, so that their gradient carries both contributions.
     """
+    X, a = _pair_terms(A, grid, C_k, C_kq, miller_k, miller_kq, eps_k, eps_kq, f_k, f_kq, P_k, P_kq, w_k,
+                       gmiller, Qtab, offsets, q, omega, optical, qhat, Dtab, kpt, same_set)
+    return _ec_from_terms([(X, a)], omega, omega_weight)
+
+
+def _pair_terms(A, grid, C_k, C_kq, miller_k, miller_kq, eps_k, eps_kq, f_k, f_kq, P_k, P_kq, w_k,
+                gmiller, Qtab, offsets, q, omega, optical, qhat, Dtab, kpt, same_set):
+    """One (k, k+q) pair's share of Eq. chi0: X = v^1/2 rho [pairs, NG] and the weights a [pairs, nw]."""
     if same_set:
         C_kq, eps_kq, P_kq, miller_kq, f_kq = C_k, eps_k, P_k, miller_k, f_k
     grid = tuple(int(g) for g in grid)
@@ -96,10 +104,18 @@ def ec_torch(A, grid, C_k, C_kq, miller_k, miller_kq, eps_k, eps_kq, f_k, f_kq, 
 
     vs = _t(R.coulomb_sqrt(A, q, gmiller, optical)).to(torch.complex128)
     X = rho * vs[None, :]                                                                  # [P, NG]
+    return X, a
+
+
+def _ec_from_terms(terms, omega, omega_weight):
+    """Eq. rpa from K(w) = sum over the pairs' terms of X^T diag(a(w)) conj(X) (Eq. chi0's k sum)."""
     E = torch.zeros((), dtype=torch.float64)
     wq = _t(omega_weight)
     for w in range(len(omega)):
-        K = (X.T * a[:, w].to(torch.complex128)[None, :]) @ torch.conj(X)
+        K = None
+        for X, a in terms:
+            Kt = (X.T * a[:, w].to(torch.complex128)[None, :]) @ torch.conj(X)
+            K = Kt if K is None else K + Kt
         K = 0.5 * (K + torch.conj(K.T))
         lam = torch.linalg.eigvalsh(K)
         F = torch.sum(torch.log1p(-lam) + lam)
@@ -130,3 +146,34 @@ def ec_and_grad(A, grid, sk, skq, gmiller, Qtab, offsets, q, omega, omega_weight
     if not same:
         grads.update(eps_kq=ekq.grad.numpy().copy(), C_kq=Ckq.grad.numpy().copy(), P_kq=Pkq.grad.numpy().copy())
     return float(E.detach()), grads
+
+
+def ec_and_grad_sets(A, grid, ksets, kqsets, gmiller, Qtab, offsets, q, omega, omega_weight, optical=False,
+                     qhat=(1.0, 0.0, 0.0), Dtab=None):
+    """E_c(q) of several (k, k+q) set pairs (Eq. chi0's k sum) and its gradient per listing: pair i gets
+    leaves of its own (its k+q set shares its k set's leaves when it is the same object), so grads[i] is
+    the derivative with respect to the inputs of that listing. Returns (E, [grads dict per pair])."""
+    leaves, terms = [], []
+    for sk, skq in zip(ksets, kqsets):
+        same = skq is sk
+        Ck = torch.tensor(np.asarray(sk.C), dtype=torch.complex128, requires_grad=True)
+        ek = torch.tensor(np.asarray(sk.eps), dtype=torch.float64, requires_grad=True)
+        Pk = torch.tensor(np.asarray(sk.P), dtype=torch.complex128, requires_grad=True)
+        if same:
+            Ckq, ekq, Pkq = Ck, ek, Pk
+        else:
+            Ckq = torch.tensor(np.asarray(skq.C), dtype=torch.complex128, requires_grad=True)
+            ekq = torch.tensor(np.asarray(skq.eps), dtype=torch.float64, requires_grad=True)
+            Pkq = torch.tensor(np.asarray(skq.P), dtype=torch.complex128, requires_grad=True)
+        leaves.append((same, Ck, ek, Pk, Ckq, ekq, Pkq))
+        terms.append(_pair_terms(A, grid, Ck, Ckq, sk.miller, skq.miller, ek, ekq, sk.f, skq.f, Pk, Pkq, sk.weight,
+                                 gmiller, Qtab, offsets, q, omega, optical, qhat, Dtab, sk.kpt, same))
+    E = _ec_from_terms(terms, omega, omega_weight)
+    E.backward()
+    out = []
+    for same, Ck, ek, Pk, Ckq, ekq, Pkq in leaves:
+        g = {"eps_k": ek.grad.numpy().copy(), "C_k": Ck.grad.numpy().copy(), "P_k": Pk.grad.numpy().copy()}
+        if not same:
+            g.update(eps_kq=ekq.grad.numpy().copy(), C_kq=Ckq.grad.numpy().copy(), P_kq=Pkq.grad.numpy().copy())
+        out.append(g)
+    return float(E.detach()), out

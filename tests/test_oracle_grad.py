@@ -87,3 +87,37 @@ def test_two_level_spacing_derivative():
     dE_dD = 0.5 * ((2 * D + b) / (2 * np.sqrt(D * D + b * D)) - 1.0)
     assert abs(g["eps_k"][1] - dE_dD) < 1e-9 * abs(dE_dD)
     assert abs(g["eps_k"][0] + dE_dD) < 1e-9 * abs(dE_dD)
+
+
+def test_gradient_over_several_set_pairs():
+    """ec_and_grad_sets (Eq. chi0's k sum over two listings: (s, t) and (t', t') with t' a copy of t at
+    half weight): its E equals the numpy oracle's over the same pairs, and each listing's gradient
+    matches central finite differences that move only that listing's inputs."""
+    wl = synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=3, target_ng=15, nw=8, extra_kq=True)
+    s, t = wl.kpoints[0], wl.kq_sets()[0]
+    t2 = _replace(t, weight=0.5)
+    qp = wl.qpoints[0]
+    gm = oracle.gsphere(wl.A, qp.q, qp.ecut)
+    Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
+
+    def ec(ks, kqs):
+        return oracle.ec_q(wl.A, wl.grid, ks, kqs, gm, Q, wl.paw.offsets, qp.q, wl.omega, wl.omega_weight)[0]
+
+    E0 = ec([s, t2], [t, t2])
+    E, g = G.ec_and_grad_sets(wl.A, wl.grid, [s, t2], [t, t2], gm, Q, wl.paw.offsets, qp.q, wl.omega,
+                              wl.omega_weight)
+    assert abs(E - E0) < 1e-12 * max(1.0, abs(E0))
+    assert set(g[0]) == {"eps_k", "C_k", "P_k", "eps_kq", "C_kq", "P_kq"} and set(g[1]) == {"eps_k", "C_k", "P_k"}
+    rng = np.random.default_rng(3)
+    h = 1e-5
+    dC = rng.standard_normal(t.C.shape) + 1j * rng.standard_normal(t.C.shape)
+    dP = rng.standard_normal(t.P.shape) + 1j * rng.standard_normal(t.P.shape)
+    # listing 0's k+q set (t) alone
+    fd = (ec([s, t2], [_replace(t, C=t.C + h * dC), t2]) - ec([s, t2], [_replace(t, C=t.C - h * dC), t2])) / (2 * h)
+    pred = float(np.real(np.sum(np.conj(g[0]["C_kq"]) * dC)))
+    assert abs(fd - pred) < 1e-6 * max(1.0, abs(pred)), (fd, pred)
+    # listing 1 (t2 in both roles)
+    p, m = _replace(t2, P=t2.P + h * dP), _replace(t2, P=t2.P - h * dP)
+    fd = (ec([s, p], [t, p]) - ec([s, m], [t, m])) / (2 * h)
+    pred = float(np.real(np.sum(np.conj(g[1]["P_k"]) * dP)))
+    assert abs(fd - pred) < 1e-6 * max(1.0, abs(pred)), (fd, pred)
