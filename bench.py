@@ -19,11 +19,14 @@ the chi0 of one complete pass.
 
 value = useful chi0 flops (4 NG^2 P nw per k, the Hermitian complex count) per
 second of the timed steps. The FP64 path is timed on the first --fp64-kpoints
-k-points, and E_c(q) of split and FP64 is compared on the chi0 of those same
-k-points (all 8 with --fp64-kpoints 8).
+k-points (default: all 8), and E_c(q) of split and FP64 is compared on the chi0
+of those same k-points (the whole q-point by default).
 
 --workload o2box runs the O2-in-box line instead (12 x 12 x 13 bohr, 48^3 grid,
-16 + 800 states, NG ~ 1500, three q-points in one batched call per step).
+16 + 800 states, NG ~ 1500, three q-points in one batched call per step), and
+--workload qmesh the batching form (64 q-points with log-uneven spheres, NG
+200-3000, on the slab cell at Gamma; one step = E_c of all 64 in one batched
+call, timed against a loop of single-q calls).
 """
 from __future__ import annotations
 
@@ -330,6 +333,8 @@ def run_o2box(args, torch, rpa, synth):
 
     def steps(prec, n, profile=False):
         out = None
+        if n <= 0:
+            return 0.0, None, None
         torch.cuda.synchronize()
         if profile:
             ctx.profile(True)
@@ -471,8 +476,9 @@ def main():
     ap.add_argument("--qmesh-bands", type=int, nargs=2, default=(8, 60), metavar=("OCC", "UNOCC"),
                     help="qmesh: occupied and empty states at Gamma (the full form is 60 1500)")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "split_fp16"])
-    ap.add_argument("--fp64-kpoints", type=int, default=2,
-                    help="slab: k-points run through the FP64 path for its timing and the E_c comparison")
+    ap.add_argument("--fp64-kpoints", type=int, default=8,
+                    help="slab: k-points run through the FP64 path for its timing and the E_c comparison "
+                         "(8: the whole q-point)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 

@@ -83,8 +83,14 @@ typedef struct {
  *           with the band velocity qhat.v_n the n = m element of Eq. n_q0's
  *           numerator (momentum plus the PAW nabla term of Eq. nabla).
  *           Not supported by rpa_ec_backward (RPA_ERR_UNSUPPORTED).
+ *  sym      HOST pointer to a symmetry operation (rpa_symop), or NULL. When
+ *           set, C, miller, P, eps, f and dfde are those of a k-point k1 of the
+ *           irreducible zone, and the set used is the one unfolded to
+ *           kpt = (-1)^s T k1 + G0 (weight: that of kpt). Not supported by
+ *           rpa_ec_backward (RPA_ERR_UNSUPPORTED).
  * A spin-polarised system is passed as one state set per spin channel
  * (occupations in [0, 1]); chi0 is their sum (the spin index of Eq. chi0). */
+typedef struct rpa_symop rpa_symop;
 typedef struct {
     int nbands;
     int nQ;
@@ -98,7 +104,44 @@ typedef struct {
     double kpt[3];
     double weight;
     const double* dfde;
+    const rpa_symop* sym;
 } rpa_states;
+
+/* A point operation of the crystal carrying a state set of the irreducible
+ * zone at k1 to k = (-1)^s T k1 + G0 of the full zone - Eq. kmap, Eq.
+ * trans_wfs (psi_nk(r) = psi_nk1(T^-1 r), complex conjugated with time
+ * reversal) and Table 1 steps 4 and 7 (projections at k from rotated
+ * projector functions).
+ *  rot           U, integer, det +-1: T maps fractional real-space
+ *                coordinates x -> U x (r = sum_i x_i a_i); the Cartesian
+ *                matrix A^T U A^-T must be orthogonal (RPA_ERR_INPUT).
+ *  time_reversal s: 1 = the states are also complex conjugated.
+ *  gshift        G0 in Miller units (reduces k to the caller's zone).
+ *  kibz          Cartesian k1 (the Bloch phase of atoms mapped across a
+ *                lattice vector).
+ *  atom_map      HOST int32 [natoms]: b(a), the atom with T^-1 R_a = R_b + L_a;
+ *                atoms a and b carry the same number of projectors.
+ *  atom_shift    HOST int32 [natoms][3]: L_a in lattice units.
+ *  proj_rot      HOST double [sum_a Np_a^2]: D^a, row-major (i, j), the
+ *                rotation of atom a's projector functions,
+ *                p^a_i(T y) = sum_j D^a_ij p^a_j(y) (real projector
+ *                functions). NULL allowed only when natoms = 0.
+ * The library unfolds in reciprocal space: the periodic part is
+ * u_k(r) = e^{-i G0.r} [conj] u_k1(T^-1 r), whose coefficient at Miller
+ * (-1)^s U^-T m - g0 is C_k1(m) (conjugated with time reversal) - the grid
+ * function that the remap r -> T^-1 r of the transformed orbital gives, with
+ * no pass over the grid - and rotates the projections,
+ *   P^a_k,i = e^{i k1.L_a} sum_j D^a_ij P^b_k1,j   (conjugated with time reversal).
+ * The transformed Miller indices must fit the grid (RPA_ERR_ALIAS otherwise). */
+struct rpa_symop {
+    int32_t rot[3][3];
+    int32_t time_reversal;
+    int32_t gshift[3];
+    double kibz[3];
+    const int32_t* atom_map;
+    const int32_t* atom_shift;
+    const double* proj_rot;
+};
 
 /* One q-point - Eq. rpa_c, Eq. n_G_2, Eq. n_q0.
  *  q        Cartesian q (bohr^-1).
@@ -243,20 +286,40 @@ int rpa_ec_batched(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int 
                    const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
                    void* stream);
 
-/* Gradient of E_c(q) (FP64 path, one (k, k+q) state-set pair): given the
- * upstream derivative dEc (DEVICE double [1], e.g. 1.0), writes
- *  deps_k  DEVICE double [nbands_k]           dE/d eps_n at k
- *  dC_k    DEVICE complex128 [nbands_k][nQ_k]  dE/dRe C + i dE/dIm C
- *  dP_k    DEVICE complex128 [nbands_k][nproj] (may be NULL without PAW atoms)
- * and the same for the k+q set; when kq is the same set as k (same C, P and
- * Miller pointers) both roles are summed into the k outputs and the kq
- * outputs are ignored. Occupations are held fixed; C and P are free
- * variables (no re-orthonormalisation). E_c(q) is written to ec_dev.
- * The pair densities are recomputed chunk by chunk, (1 - K)^-1 is formed
- * from the Cholesky factor, and rho_bar = sum_w c_w 2 a(w) W(w) rho is taken
- * back through the optical row, the PAW term, the pruned pair FFT and the
- * orbital FFT. RPA_ERR_UNSUPPORTED if N1*N2 > 4096. */
-int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, const rpa_qspec* qs,
+/* rpa_ec_batched with a (k, k+q) state-set list of its own for every q-point
+ * (a k-mesh, where the k+q sets differ from q to q) - Eq. rpa_c's q sum over
+ * Eq. chi0's k sum. q-point j uses k[j][0 .. nk[j]-1] and kq[j][0 .. nk[j]-1]
+ * (HOST arrays of HOST pointers; the sets follow the rpa_states rules, and a
+ * set listed under several q-points is read by each of them). Outputs, graph
+ * capture and replay as for rpa_ec_batched (the per-q lists are part of the
+ * replay key). The jobs of all q-points share one planning pass, one upload
+ * and the batched factorisation of every (q, w) matrix. Errors: as
+ * rpa_ec_batched; RPA_ERR_INPUT for nk[j] <= 0 or a NULL list. */
+int rpa_ec_batched_sets(rpa_ctx* ctx, int nq, const rpa_states* const* k, const rpa_states* const* kq, const int* nk,
+                        const rpa_qspec* qs, const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev,
+                        int use_graph, void* stream);
+
+/* Gradient of E_c(q) (FP64 path) with respect to the inputs of nk (k, k+q)
+ * state-set pairs (Eq. chi0's k sum): given the upstream derivative dEc
+ * (DEVICE double [1], e.g. 1.0), writes for pair i, at the offset that is the
+ * sum of the sizes of pairs 0 .. i-1,
+ *  deps_k  DEVICE double [sum_i nbands_k_i]            dE/d eps_n at k_i
+ *  dC_k    DEVICE complex128 [sum_i nbands_k_i nQ_k_i] dE/dRe C + i dE/dIm C
+ *  dP_k    DEVICE complex128 [sum_i nbands_k_i nproj]  (may be NULL without PAW atoms)
+ * and the same for the k+q sets (deps_kq, dC_kq, dP_kq, sized by the kq
+ * sets; may be NULL when every kq[i] is the same set as k[i]). When kq[i] is
+ * the same set as k[i] (same C, P and Miller pointers) both roles of pair i
+ * are summed into its k slot and its kq slot is left untouched; a set listed
+ * in several pairs gets one gradient per listing (their sum is its total).
+ * Occupations are held fixed; C and P are free variables (no
+ * re-orthonormalisation). E_c(q) is written to ec_dev.
+ * chi0 of all pairs, its Cholesky factor and W(w) = v^1/2 [(1 - K)^-1 - 1]
+ * v^1/2 are formed once; then every pair's densities are recomputed chunk by
+ * chunk and rho_bar = sum_w c_w 2 a(w) W(w) rho is taken back through the
+ * optical row, the PAW term, the pruned pair FFT and the orbital FFT.
+ * RPA_ERR_UNSUPPORTED if N1*N2 > 4096, for sets with -df/de at an optical
+ * q-point and for sets with a symmetry operation. */
+int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
                     const rpa_freq* fr, const double* dEc, double* ec_dev, double* deps_k, void* dC_k, void* dP_k,
                     double* deps_kq, void* dC_kq, void* dP_kq, void* stream);
 

@@ -16,7 +16,7 @@ import numpy as np
 from . import _capi
 from ._capi import PRECISION, RpaCell, RpaFreq, RpaQSpec, RpaStates
 
-__all__ = ["RpaError", "Context", "States", "QSpec", "Freq", "gsphere", "PRECISION", "library_path",
+__all__ = ["RpaError", "Context", "States", "SymOp", "QSpec", "Freq", "gsphere", "PRECISION", "library_path",
            "ec_autograd"]
 
 
@@ -87,11 +87,38 @@ def gsphere(A, grid, q, ecut: float) -> np.ndarray:
     return out[: ng.value]
 
 
+class SymOp:
+    """A point operation carrying a state set at k1 (irreducible zone) to k = (-1)^s T k1 + G0 (rpa_symop):
+    rot U (fractional x -> U x), time reversal s, gshift G0 (Miller units), kibz = k1 (Cartesian), and for
+    PAW atoms the atom map b(a), lattice shifts L_a (T^-1 R_a = R_b + L_a) and the flat D blocks."""
+
+    def __init__(self, rot, time_reversal, gshift, kibz, atom_map=None, atom_shift=None, proj_rot=None):
+        self.rot = _i32(rot).reshape(3, 3)
+        self.time_reversal = int(bool(time_reversal))
+        self.gshift = _i32(gshift).reshape(3)
+        self.kibz = _f64(kibz).reshape(3)
+        self.atom_map = None if atom_map is None else _i32(atom_map)
+        self.atom_shift = None if atom_shift is None else _i32(atom_shift).reshape(-1, 3)
+        self.proj_rot = None if proj_rot is None else _f64(proj_rot)
+        st = _capi.RpaSymop()
+        for i in range(3):
+            for j in range(3):
+                st.rot[i][j] = int(self.rot[i, j])
+            st.gshift[i] = int(self.gshift[i])
+            st.kibz[i] = float(self.kibz[i])
+        st.time_reversal = self.time_reversal
+        st.atom_map = _ptr_i32(self.atom_map) if self.atom_map is not None else ctypes.cast(None, _capi.P_i32)
+        st.atom_shift = _ptr_i32(self.atom_shift) if self.atom_shift is not None else ctypes.cast(None, _capi.P_i32)
+        st.proj_rot = _ptr_f64(self.proj_rot) if self.proj_rot is not None else ctypes.cast(None, _capi.P_f64)
+        self._st = st
+
+
 class States:
-    """One k (or k+q) state set; C and P live on the device, the rest on the host."""
+    """One k (or k+q) state set; C and P live on the device, the rest on the host. With `sym` (a SymOp)
+    the arrays are those at the operation's kibz and the set used is the one unfolded to `kpt`."""
 
     def __init__(self, C, miller, eps, f, P=None, proj_off=None, kpt=(0.0, 0.0, 0.0), weight=1.0,
-                 device="cuda", dfde=None):
+                 device="cuda", dfde=None, sym=None):
         torch = _torch()
         self.device = device
         self.C = _dev_c128(C, device)
@@ -109,6 +136,7 @@ class States:
         self.kpt = _f64(kpt)
         self.weight = float(weight)
         self.dfde = None if dfde is None else _f64(dfde)
+        self.sym = sym
 
     @classmethod
     def from_synth(cls, s, paw, device="cuda"):
@@ -130,6 +158,7 @@ class States:
             st.kpt[i] = float(self.kpt[i])
         st.weight = self.weight
         st.dfde = _ptr_f64(self.dfde) if self.dfde is not None else ctypes.cast(None, _capi.P_f64)
+        st.sym = ctypes.pointer(self.sym._st) if self.sym is not None else ctypes.POINTER(_capi.RpaSymop)()
         return st
 
 
@@ -318,34 +347,84 @@ class Context:
                                       int(bool(use_graph)), _stream()), self._h)
         return ec, F
 
-    def ec_backward(self, k: States, kq: States, qs: QSpec, freq: Freq, dEc=1.0):
-        """E_c(q) and its gradient (FP64) for one (k, k+q) pair of state sets.
+    def ec_batched_sets(self, sets, qspecs: Sequence[QSpec], freq: Freq, precision="fp64", use_graph: bool = False,
+                        out=None):
+        """E_c(q) for every q of qspecs, q-point j with its own state-set lists sets[j] = (ks, kqs)
+        (rpa_ec_batched_sets); returns (ec [nq + 1], F [nq, nw]) on the device, as ec_batched."""
+        torch = _torch()
+        nq = len(qspecs)
+        if len(sets) != nq:
+            raise ValueError("one (ks, kqs) pair of lists per q-point")
+        if out is None:
+            out = (torch.empty(nq + 1, dtype=torch.float64, device=self.device),
+                   torch.empty((nq, freq.nw), dtype=torch.float64, device=self.device))
+        ec, F = out
+        ka = [self._arrays(ks) for ks, _ in sets]
+        kqa = [self._arrays(kqs) for _, kqs in sets]
+        PS = ctypes.POINTER(RpaStates)
+        kp = (PS * nq)(*[ctypes.cast(a, PS) for a in ka])
+        kqp = (PS * nq)(*[ctypes.cast(a, PS) for a in kqa])
+        nk = (ctypes.c_int * nq)(*[len(ks) for ks, kqs in sets])
+        for ks, kqs in sets:
+            if len(ks) != len(kqs):
+                raise ValueError("k and k+q lists of a q-point differ in length")
+        qarr = (RpaQSpec * nq)()
+        for i, q in enumerate(qspecs):
+            qarr[i] = q.struct()
+        fr = freq.struct()
+        _check(self._L.rpa_ec_batched_sets(self._h, nq, kp, kqp, nk, qarr, ctypes.byref(fr), _prec(precision),
+                                           ctypes.c_void_p(ec.data_ptr()), ctypes.c_void_p(F.data_ptr()),
+                                           int(bool(use_graph)), _stream()), self._h)
+        return ec, F
 
-        Returns (ec [1], grads) with grads = dict(eps_k, C_k, P_k[, eps_kq, C_kq, P_kq]) as device tensors;
-        complex gradients are dE/dRe + i dE/dIm. With kq the same set as k only the k entries are returned
-        (both roles summed)."""
+    def ec_backward(self, k, kq, qs: QSpec, freq: Freq, dEc=1.0):
+        """E_c(q) and its gradient (FP64) for one (k, k+q) pair of state sets, or for lists of pairs
+        (Eq. chi0's k sum).
+
+        Returns (ec [1], grads) with grads = dict(eps_k, C_k, P_k[, eps_kq, C_kq, P_kq]) as device tensors
+        (a list of such dicts, one per pair, when k and kq are lists); complex gradients are dE/dRe + i
+        dE/dIm. With kq[i] the same set as k[i] only the k entries of pair i are returned (both roles
+        summed)."""
         torch = _torch()
         dev = self.device
+        single = isinstance(k, States)
+        ks, kqs = ([k], [kq]) if single else (list(k), list(kq))
+        if len(ks) != len(kqs):
+            raise ValueError("k and k+q lists differ in length")
         dE = torch.as_tensor(dEc, dtype=torch.float64, device=dev).reshape(1).contiguous()
         ec = torch.empty(1, dtype=torch.float64, device=dev)
-        same = kq is k
-
-        def outs(s):
-            return (torch.empty(s.C.shape[0], dtype=torch.float64, device=dev),
-                    torch.empty_like(s.C), torch.empty_like(s.P))
-        ek, Ck, Pk = outs(k)
-        eq, Cq, Pq = (None, None, None) if same else outs(kq)
-        a, b, q, fr = k.struct(), kq.struct(), qs.struct(), freq.struct()
+        same = [b is a for a, b in zip(ks, kqs)]
+        nbk = [int(s.C.shape[0]) for s in ks]
+        nbq = [int(s.C.shape[0]) for s in kqs]
+        ek = torch.empty(sum(nbk), dtype=torch.float64, device=dev)
+        Ck = torch.empty(sum(s.C.numel() for s in ks), dtype=torch.complex128, device=dev)
+        Pk = torch.empty(sum(s.P.numel() for s in ks), dtype=torch.complex128, device=dev)
+        distinct = not all(same)
+        eq = torch.empty(sum(nbq), dtype=torch.float64, device=dev) if distinct else None
+        Cq = torch.empty(sum(s.C.numel() for s in kqs), dtype=torch.complex128, device=dev) if distinct else None
+        Pq = torch.empty(sum(s.P.numel() for s in kqs), dtype=torch.complex128, device=dev) if distinct else None
+        a, b, q, fr = self._arrays(ks), self._arrays(kqs), qs.struct(), freq.struct()
 
         def ptr(t):
             return ctypes.c_void_p(t.data_ptr()) if t is not None else None
-        _check(self._L.rpa_ec_backward(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(q), ctypes.byref(fr),
-                                       ptr(dE), ptr(ec), ptr(ek), ptr(Ck), ptr(Pk), ptr(eq), ptr(Cq), ptr(Pq),
-                                       _stream()), self._h)
-        grads = {"eps_k": ek, "C_k": Ck, "P_k": Pk}
-        if not same:
-            grads.update(eps_kq=eq, C_kq=Cq, P_kq=Pq)
-        return ec, grads
+        _check(self._L.rpa_ec_backward(self._h, a, b, len(ks), ctypes.byref(q), ctypes.byref(fr), ptr(dE), ptr(ec),
+                                       ptr(ek), ptr(Ck), ptr(Pk), ptr(eq), ptr(Cq), ptr(Pq), _stream()), self._h)
+        out = []
+        oe = oc = op = qe = qc = qp_ = 0
+        for s, t, sm in zip(ks, kqs, same):
+            g = {"eps_k": ek[oe:oe + s.C.shape[0]], "C_k": Ck[oc:oc + s.C.numel()].view(s.C.shape),
+                 "P_k": Pk[op:op + s.P.numel()].view(s.P.shape)}
+            if not sm:
+                g.update(eps_kq=eq[qe:qe + t.C.shape[0]], C_kq=Cq[qc:qc + t.C.numel()].view(t.C.shape),
+                         P_kq=Pq[qp_:qp_ + t.P.numel()].view(t.P.shape))
+            oe += s.C.shape[0]
+            oc += s.C.numel()
+            op += s.P.numel()
+            qe += t.C.shape[0]
+            qc += t.C.numel()
+            qp_ += t.P.numel()
+            out.append(g)
+        return ec, (out[0] if single else out)
 
     def autotune(self, NG: int, npairs: int, nw: int = 16, precision="split_bf16") -> int:
         """Time the split rank-k kernel variants for this shape; returns the recorded variant."""

@@ -30,6 +30,18 @@ class RpaCell(ctypes.Structure):
     _fields_ = [("A", c_double * 9), ("n", c_int * 3)]
 
 
+class RpaSymop(ctypes.Structure):
+    _fields_ = [
+        ("rot", (ctypes.c_int32 * 3) * 3),
+        ("time_reversal", ctypes.c_int32),
+        ("gshift", ctypes.c_int32 * 3),
+        ("kibz", c_double * 3),
+        ("atom_map", P_i32),
+        ("atom_shift", P_i32),
+        ("proj_rot", P_f64),
+    ]
+
+
 class RpaStates(ctypes.Structure):
     _fields_ = [
         ("nbands", c_int),
@@ -44,6 +56,7 @@ class RpaStates(ctypes.Structure):
         ("kpt", c_double * 3),
         ("weight", c_double),
         ("dfde", P_f64),
+        ("sym", ctypes.POINTER(RpaSymop)),
     ]
 
 
@@ -87,7 +100,11 @@ SIGNATURES = {
     "rpa_ec_batched": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int, c_int,
                                ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p, c_int,
                                c_void_p]),
-    "rpa_ec_backward": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates),
+    "rpa_ec_batched_sets": (c_int, [c_void_p, c_int, ctypes.POINTER(ctypes.POINTER(RpaStates)),
+                                    ctypes.POINTER(ctypes.POINTER(RpaStates)), ctypes.POINTER(c_int),
+                                    ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_int, c_void_p, c_void_p,
+                                    c_int, c_void_p]),
+    "rpa_ec_backward": (c_int, [c_void_p, ctypes.POINTER(RpaStates), ctypes.POINTER(RpaStates), c_int,
                                 ctypes.POINTER(RpaQSpec), ctypes.POINTER(RpaFreq), c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rpa_autotune": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p]),

@@ -189,6 +189,9 @@ hipError_t launch_fill_pattern(float* f, size_t nf, double* d, size_t nd, hipStr
 template <typename T>
 hipError_t launch_rho_out(const T* rre, const T* rim, int npairs, int NG, int NGp, double* out, hipStream_t s);
 
+hipError_t launch_conj_copy(const double* in, size_t n, double* out, hipStream_t s);
+hipError_t launch_rotate_proj(const double* Pin, int nb, int nproj, const int32_t* tab, const double* D,
+                              const double* ph, int tr, double* Pout, hipStream_t s);
 hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG, int nw, int add, double* out,
                           hipStream_t s);
 

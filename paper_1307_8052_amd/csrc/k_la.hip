@@ -871,6 +871,56 @@ hipError_t launch_chi_out(const double* Cre, const double* Cim, int ldC, int NG,
     return hipGetLastError();
 }
 
+// Coefficients of a state set unfolded with time reversal (Eq. trans_wfs): the complex conjugate, element by
+// element (the plane-wave labels are transformed on the host).
+__global__ __launch_bounds__(256) void k_conj_copy(const double* __restrict__ in, size_t n, double* __restrict__ out) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double2 v = reinterpret_cast<const double2*>(in)[i];
+        reinterpret_cast<double2*>(out)[i] = make_double2(v.x, -v.y);
+    }
+}
+
+// Projections at k from those at k1 (Table 1 step 7): output column c = (atom a, projector i) reads the
+// block of atom b(a), P_k[n][c] = ph_c sum_j D[row_c + j] P_k1[n][src_c + j], conjugated with time
+// reversal; tab[3c .. 3c+2] = (src_c, Np, row_c), ph = (cos, sin) of k1.L_a per column.
+__global__ __launch_bounds__(256) void k_rotate_proj(const double* __restrict__ Pin, int nb, int nproj,
+                                                     const int32_t* __restrict__ tab, const double* __restrict__ D,
+                                                     const double* __restrict__ ph, int tr,
+                                                     double* __restrict__ Pout) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nb * nproj) return;
+    const int n = (int)(idx / nproj), c = (int)(idx % nproj);
+    const int src = tab[3 * c], np = tab[3 * c + 1], row = tab[3 * c + 2];
+    const double* p = Pin + 2 * ((size_t)n * nproj + src);
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < np; ++j) {
+        const double d = D[row + j];
+        sr += d * p[2 * j];
+        si += d * p[2 * j + 1];
+    }
+    const double cr = ph[2 * c], ci = ph[2 * c + 1];
+    const double outr = cr * sr - ci * si, outi = cr * si + ci * sr;
+    Pout[2 * idx] = outr;
+    Pout[2 * idx + 1] = tr ? -outi : outi;
+}
+
+hipError_t launch_conj_copy(const double* in, size_t n, double* out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_conj_copy, dim3((unsigned)blocks), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate_proj(const double* Pin, int nb, int nproj, const int32_t* tab, const double* D,
+                              const double* ph, int tr, double* Pout, hipStream_t s) {
+    const size_t n = (size_t)nb * nproj;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_rotate_proj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Pin, nb, nproj, tab, D, ph,
+                       tr, Pout);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_rho_out(const T* rre, const T* rim, int npairs, int NG, int NGp, double* out, hipStream_t s) {
     if (!npairs) return hipSuccess;

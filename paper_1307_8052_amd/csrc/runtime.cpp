@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -603,6 +604,8 @@ struct QJob {
     bool fresh = false;   // the accumulator holds nothing yet (no update has run into it)
     int ld = 0;           // leading dimension of this q-point's chi0 / -K matrices (its class's)
     int orig = 0;         // index of this q-point in the caller's list (jobs are ordered by class)
+    int k0 = 0, k1 = -1;  // the (k, k+q) sets of this q-point: B.ks[k0 .. k1-1] (k1 < 0: every set)
+    bool uses(size_t ik) const { return k1 < 0 || ((int)ik >= k0 && (int)ik < k1); }
 };
 
 // q-points whose matrices share one leading dimension: adjacent jobs q0 .. q0 + nq - 1, accumulators at cr
@@ -611,6 +614,22 @@ struct QClass {
     int ld = 0, q0 = 0, nq = 0;
     double* cr = nullptr;
     double* ci = nullptr;
+};
+
+// A state set given at k1 of the irreducible zone with a point operation (Eq. kmap, Eq. trans_wfs, Table 1
+// steps 4 and 7) becomes a plain state set: its plane-wave labels are transformed on the host, and these
+// device jobs, first in the call's launch sequence, conjugate its coefficients (time reversal) and rotate
+// its projections.
+struct UnfoldJob {
+    const double* C_in = nullptr;
+    double* C_out = nullptr;      // time reversal only
+    size_t nC = 0;
+    const double* P_in = nullptr;
+    double* P_out = nullptr;
+    int nb = 0, nproj = 0, tr = 0;
+    std::vector<int32_t> tab;     // per output column: source column base, Np, row offset of its D row
+    std::vector<double> D, ph;    // the D blocks; per output column the Bloch phase (re, im)
+    void* d_tab = nullptr; void* d_D = nullptr; void* d_ph = nullptr;
 };
 
 struct Batch {
@@ -636,6 +655,9 @@ struct Batch {
     bool paw_mfma = false;           // set by presize: PAW correction as an MFMA GEMM per band m
     int ld = 0;                      // the largest leading dimension of the batch's chi0 / -K matrices
     std::vector<QClass> cls;         // the q-points grouped by leading dimension
+    std::deque<rpa_states> usets;              // state sets unfolded from the irreducible zone
+    std::deque<std::vector<int32_t>> umiller;  // their plane-wave labels
+    std::deque<UnfoldJob> ujobs;
     bool fp64() const { return prec == RPA_FP64; }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
 };
@@ -692,6 +714,132 @@ int begin(Batch& B, rpa_ctx* c, const rpa_freq* fr, rpa_precision prec, void* st
         B.nw = fr->nw;
         B.om.assign(fr->omega, fr->omega + fr->nw);
         B.ow.assign(fr->weight, fr->weight + fr->nw);
+    }
+    return RPA_OK;
+}
+
+// The set at k = (-1)^s T k1 + G0 from the set `s` at k1 and its operation (validated here): labels
+// m -> (-1)^s U^-T m - g0 (the coefficient of e^{i G.r} in u_k(r) = e^{-i G0.r} [conj] u_k1(T^-1 r)),
+// coefficients conjugated with time reversal, projections P^a_k,i = e^{i k1.L_a} sum_j D^a_ij P^b_k1,j
+// (conjugated with time reversal).
+int unfold_set(Batch& B, const rpa_states* s, const std::string& tag, Upload& up, const rpa_states** out) {
+    rpa_ctx* c = B.c;
+    const rpa_symop* o = s->sym;
+    const std::string t = tag + ": symmetry operation";
+    const int32_t(*U)[3] = o->rot;
+    const long long det = (long long)U[0][0] * ((long long)U[1][1] * U[2][2] - (long long)U[1][2] * U[2][1]) -
+                          (long long)U[0][1] * ((long long)U[1][0] * U[2][2] - (long long)U[1][2] * U[2][0]) +
+                          (long long)U[0][2] * ((long long)U[1][0] * U[2][1] - (long long)U[1][1] * U[2][0]);
+    if (det != 1 && det != -1) return fail(RPA_ERR_INPUT, t + ": det U must be +1 or -1");
+    if (o->time_reversal != 0 && o->time_reversal != 1) return fail(RPA_ERR_INPUT, t + ": time_reversal not 0 or 1");
+    // U^-1 = adj(U) / det
+    long long Ui[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+            Ui[i][j] = ((long long)U[r0][c0] * U[r1][c1] - (long long)U[r0][c1] * U[r1][c0]) * det;
+        }
+    // Cartesian T = A^T U A^-T, with A^-1[e][j] = B[j][e] / 2 pi
+    double T[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int e = 0; e < 3; ++e) {
+            double v = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) v += c->A[i][a] * U[i][j] * c->B[j][e] / kTwoPi;
+            T[a][e] = v;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int e = 0; e < 3; ++e) {
+            double v = 0.0;
+            for (int i = 0; i < 3; ++i) v += T[a][i] * T[e][i];
+            if (std::fabs(v - (a == e ? 1.0 : 0.0)) > 1e-9)
+                return fail(RPA_ERR_INPUT, t + ": U is not a rotation of this lattice (A^T U A^-T not orthogonal)");
+        }
+    const double sgn = o->time_reversal ? -1.0 : 1.0;
+    double kn = 0.0, kd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double v = 0.0;
+        for (int e = 0; e < 3; ++e) v += sgn * T[a][e] * o->kibz[e];
+        for (int i = 0; i < 3; ++i) v += o->gshift[i] * c->B[i][a];
+        kd = std::max(kd, std::fabs(v - s->kpt[a]));
+        kn = std::max(kn, std::fabs(s->kpt[a]));
+    }
+    if (kd > 1e-9 * (1.0 + kn)) return fail(RPA_ERR_INPUT, t + ": kpt differs from (-1)^s T kibz + G0");
+    B.umiller.emplace_back(3 * (size_t)s->nQ);
+    std::vector<int32_t>& m2 = B.umiller.back();
+    const long long is = o->time_reversal ? -1 : 1;
+    for (int q = 0; q < s->nQ; ++q) {
+        const int32_t* m = s->miller + 3 * q;
+        for (int e = 0; e < 3; ++e)
+            m2[3 * q + e] = (int32_t)(is * (Ui[0][e] * m[0] + Ui[1][e] * m[1] + Ui[2][e] * m[2]) - o->gshift[e]);
+    }
+    rpa_states d = *s;
+    d.miller = m2.data();
+    d.sym = nullptr;
+    B.ujobs.emplace_back();
+    UnfoldJob& J = B.ujobs.back();
+    J.nb = s->nbands;
+    J.tr = o->time_reversal;
+    if (o->time_reversal) {
+        void* p = nullptr;
+        int rc = get_buf(c, (B.prefix + "sym:C:" + tag).c_str(), 16 * (size_t)s->nbands * s->nQ, B.s, &p);
+        if (rc) return rc;
+        J.C_in = static_cast<const double*>(s->C);
+        J.C_out = static_cast<double*>(p);
+        J.nC = (size_t)s->nbands * s->nQ;
+        d.C = p;
+    }
+    if (s->natoms > 0) {
+        if (!o->atom_map || !o->atom_shift || !o->proj_rot)
+            return fail(RPA_ERR_INPUT, t + ": NULL atom_map, atom_shift or proj_rot with PAW atoms present");
+        const int na = s->natoms, np_tot = nproj_total(s);
+        size_t doff = 0;
+        for (int a = 0; a < na; ++a) {
+            const int b = o->atom_map[a];
+            const int np = s->proj_off[a + 1] - s->proj_off[a];
+            if (b < 0 || b >= na) return fail(RPA_ERR_INPUT, t + ": atom_map entry out of range");
+            if (s->proj_off[b + 1] - s->proj_off[b] != np)
+                return fail(RPA_ERR_SHAPE, t + ": atom_map pairs atoms with different projector counts");
+            double L[3];
+            for (int e = 0; e < 3; ++e)
+                L[e] = o->atom_shift[3 * a] * c->A[0][e] + o->atom_shift[3 * a + 1] * c->A[1][e] +
+                       o->atom_shift[3 * a + 2] * c->A[2][e];
+            const double arg = o->kibz[0] * L[0] + o->kibz[1] * L[1] + o->kibz[2] * L[2];
+            for (int i = 0; i < np; ++i) {
+                J.tab.push_back(s->proj_off[b]);
+                J.tab.push_back(np);
+                J.tab.push_back((int32_t)(doff + (size_t)i * np));
+                J.ph.push_back(std::cos(arg));
+                J.ph.push_back(std::sin(arg));
+            }
+            doff += (size_t)np * np;
+        }
+        J.D.assign(o->proj_rot, o->proj_rot + doff);
+        for (double v : J.D)
+            if (!std::isfinite(v)) return fail(RPA_ERR_INPUT, t + ": non-finite proj_rot entry");
+        void* p = nullptr;
+        int rc = get_buf(c, (B.prefix + "sym:P:" + tag).c_str(), 16 * (size_t)s->nbands * np_tot, B.s, &p);
+        if (rc) return rc;
+        J.P_in = static_cast<const double*>(s->P);
+        J.P_out = static_cast<double*>(p);
+        J.nproj = np_tot;
+        d.P = p;
+        up.add(J.tab, &J.d_tab);
+        up.add(J.D, &J.d_D);
+        up.add(J.ph, &J.d_ph);
+    }
+    B.usets.push_back(d);
+    *out = &B.usets.back();
+    return RPA_OK;
+}
+
+int enqueue_unfold(Batch& B) {
+    for (const UnfoldJob& J : B.ujobs) {
+        if (J.C_out) HIP_TRY(launch_conj_copy(J.C_in, J.nC, J.C_out, B.s));
+        if (J.P_out)
+            HIP_TRY(launch_rotate_proj(J.P_in, J.nb, J.nproj, static_cast<const int32_t*>(J.d_tab),
+                                       static_cast<const double*>(J.d_D), static_cast<const double*>(J.d_ph), J.tr,
+                                       J.P_out, B.s));
     }
     return RPA_OK;
 }
@@ -792,6 +940,7 @@ int prepare_q(Batch& B, QJob& Q, Upload& up) {
         Q.wq.resize(B.ks.size());
         Q.d_wq.assign(B.ks.size(), nullptr);
         for (size_t i = 0; i < B.ks.size(); ++i) {
+            if (!Q.uses(i)) continue;
             const rpa_states* k = B.ks[i].k;
             Q.wq[i].resize(k->nQ);
             for (int j = 0; j < k->nQ; ++j) {
@@ -1158,6 +1307,8 @@ int enqueue_update(Batch& B, QJob& Q, int np, const T* rre, const T* rim, const 
 template <typename T>
 int enqueue_chi0(Batch& B) {
     rpa_ctx* c = B.c;
+    int urc = enqueue_unfold(B);
+    if (urc) return urc;
     // every accumulator starts fresh: its first update stores or zero-fills it (one with no update at all
     // is zero-filled at the end)
     for (auto& Q : B.qj) Q.fresh = true;
@@ -1177,6 +1328,7 @@ int enqueue_chi0(Batch& B) {
         }
         const double prefac = K.k->weight / c->volume;
         for (auto& Q : B.qj) {
+            if (!Q.uses(ik)) continue;
             const int Pc = Q.Pc;
             const int lda = (Pc + 3) / 4 * 4;
             T* rre = static_cast<T*>(buf(B, "rho"));
@@ -1217,7 +1369,7 @@ int enqueue_chi0(Batch& B) {
         int nt = 0;
         for (size_t ik = 0; ik < B.ks.size(); ++ik) {
             KSet& K = B.ks[ik];
-            if (K.drude_band.empty()) continue;
+            if (K.drude_band.empty() || !Q.uses(ik)) continue;
             ProfScope ps_(c, S_OPTICAL, B.s);
             HIP_TRY(launch_band_drude(static_cast<const double*>(K.k->C), K.k->nQ, static_cast<const double*>(Q.d_wq[ik]),
                                       static_cast<const double*>(K.k->P), nproj_total(K.k),
@@ -1495,26 +1647,55 @@ int check_common(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk
 }
 
 // plan every (k, q) of a call: validation, tables, one upload, buffer sizes
+// qk (optional, nq + 1 entries): q-point j uses the sets qk[j] .. qk[j+1]-1 of k and kq; without it every
+// q-point uses all nk of them.
 int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, int nq,
                bool need_ec, bool need_chi, const char* table_buf, const int32_t* pn = nullptr,
-               const int32_t* pm = nullptr, int npairs = -1) {
+               const int32_t* pm = nullptr, int npairs = -1, const int* qk = nullptr) {
+    auto q_uses = [&](int j, int i) { return !qk || (i >= qk[j] && i < qk[j + 1]); };
     rpa_ctx* c = B.c;
     Upload up;
     int rc = prepare_common(B, &k[0], up);
     if (rc) return rc;
     B.ks.resize(nk);
+    // sets with a symmetry operation are unfolded once each (a k+q set that is its k set stays shared)
+    std::map<const rpa_states*, const rpa_states*> unfolded;
+    auto resolve = [&](const rpa_states* s, const std::string& tag, const rpa_states** out) -> int {
+        if (!s->sym) {
+            *out = s;
+            return RPA_OK;
+        }
+        auto it = unfolded.find(s);
+        if (it != unfolded.end()) {
+            *out = it->second;
+            return RPA_OK;
+        }
+        int r = check_states(c, s, tag.c_str());
+        if (r) return r;
+        r = unfold_set(B, s, tag, up, out);
+        if (r) return r;
+        unfolded[s] = *out;
+        return RPA_OK;
+    };
     for (int i = 0; i < nk; ++i) {
-        B.ks[i].k = &k[i];
-        B.ks[i].kq = &kq[i];
+        rc = resolve(&k[i], "k" + std::to_string(i), &B.ks[i].k);
+        if (rc) return rc;
+        if (same_set(&k[i], &kq[i]) && k[i].sym == kq[i].sym) {
+            B.ks[i].kq = B.ks[i].k;
+        } else {
+            rc = resolve(&kq[i], "kq" + std::to_string(i), &B.ks[i].kq);
+            if (rc) return rc;
+        }
         for (int j = 0; j < nq; ++j) {
-            rc = check_pair(c, &k[i], &kq[i], &qs[j]);
+            if (!q_uses(j, i)) continue;
+            rc = check_pair(c, B.ks[i].k, B.ks[i].kq, &qs[j]);
             if (rc) return rc;
         }
         rc = prepare_kset(B, B.ks[i], up, pn, pm, npairs);
         if (rc) return rc;
         // the optical head divides by eps_m - eps_n (Eq. n_q0): no degenerate transition
         bool optical = false;
-        for (int j = 0; j < nq; ++j) optical = optical || qs[j].optical;
+        for (int j = 0; j < nq; ++j) optical = optical || (qs[j].optical && q_uses(j, i));
         const KSet& K = B.ks[i];
         for (size_t p = 0; optical && p < K.pn.size(); ++p)
             if (K.k->eps[K.pn[p]] == K.kq->eps[K.pm[p]])
@@ -1540,6 +1721,10 @@ int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, cons
         QJob& Q = B.qj[i];
         Q.qs = &qs[j];
         Q.orig = j;
+        if (qk) {
+            Q.k0 = qk[j];
+            Q.k1 = qk[j + 1];
+        }
         Q.qp = std::move(plans[j]);
         Q.ld = class_ld(Q.qp.NGp, nq);
         if (B.cls.empty() || B.cls.back().ld != Q.ld) B.cls.push_back(QClass{Q.ld, i, 0, nullptr, nullptr});
@@ -1576,65 +1761,67 @@ struct BwChunk {
     void *d_ns = nullptr, *d_nl = nullptr, *d_ms = nullptr, *d_ml = nullptr;
 };
 
-int backward(Batch& B, const double* dEc, double* ec_dev, double* deps_k, double* dC_k, double* dP_k,
-             double* deps_kq, double* dC_kq, double* dP_kq) {
+// gradient outputs of one state set (offsets into the caller's concatenated arrays)
+struct BwOut {
+    double* deps = nullptr;
+    double* dC = nullptr;
+    double* dP = nullptr;
+};
+
+// host tables of one (k, k+q) set pair: per-chunk band groupings and the global ones for the energies
+struct BwSet {
+    std::vector<BwChunk> ch;
+    Csr gn, gm;
+    void *d_gns = nullptr, *d_gnl = nullptr, *d_gms = nullptr, *d_gml = nullptr;
+};
+
+// The forward pass (chi0 of every set, E_c, the Cholesky factor, W(w)) once, then every set's pairs are
+// recomputed chunk by chunk and taken back to its eps, C and P. outk[i] / outkq[i]: the gradient slots of
+// the k and k+q set of pair i (for a k+q set that is its k set, both roles go to outk[i]).
+int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOut>& outk,
+             const std::vector<BwOut>& outkq) {
     rpa_ctx* c = B.c;
-    KSet& K = B.ks[0];
     QJob& Q = B.qj[0];
     const PairGeom& g = Q.qp.g;
     const int NG = Q.qp.NG, NGp = Q.qp.NGp, nw = B.nw;
-    const int P = (int)K.pn.size();
-    const bool same = same_set(K.k, K.kq);
-    const int nbk = K.k->nbands, nbq = K.kq->nbands;
-    const int nproj = nproj_total(K.k);
+    const int nproj = nproj_total(B.ks[0].k);
     const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
-    if (same) {
-        deps_kq = deps_k;
-        dC_kq = dC_k;
-        dP_kq = dP_k;
-    }
-    // host tables: per-chunk band groupings and the global ones for the energies
     const int Pc = Q.Pc;
-    std::vector<BwChunk> ch;
-    for (int p0 = 0; p0 < P; p0 += Pc) {
-        BwChunk x;
-        x.p0 = p0;
-        x.np = std::min(Pc, P - p0);
-        x.nlo = x.nhi = K.pn[p0];
-        x.mlo = x.mhi = K.pm[p0];
-        for (int i = p0; i < p0 + x.np; ++i) {
-            x.nlo = std::min(x.nlo, (int)K.pn[i]);
-            x.nhi = std::max(x.nhi, (int)K.pn[i]);
-            x.mlo = std::min(x.mlo, (int)K.pm[i]);
-            x.mhi = std::max(x.mhi, (int)K.pm[i]);
+    const size_t nks = B.ks.size();
+    std::vector<BwSet> sets(nks);
+    int maxm = 1, maxn = 1, maxP = 1;
+    size_t maxphib = 1;
+    for (size_t ik = 0; ik < nks; ++ik) {
+        KSet& K = B.ks[ik];
+        BwSet& S = sets[ik];
+        const int P = (int)K.pn.size();
+        const bool same = same_set(K.k, K.kq);
+        const int nbk = K.k->nbands, nbq = K.kq->nbands;
+        for (int p0 = 0; p0 < P; p0 += Pc) {
+            BwChunk x;
+            x.p0 = p0;
+            x.np = std::min(Pc, P - p0);
+            x.nlo = x.nhi = K.pn[p0];
+            x.mlo = x.mhi = K.pm[p0];
+            for (int i = p0; i < p0 + x.np; ++i) {
+                x.nlo = std::min(x.nlo, (int)K.pn[i]);
+                x.nhi = std::max(x.nhi, (int)K.pn[i]);
+                x.mlo = std::min(x.mlo, (int)K.pm[i]);
+                x.mhi = std::max(x.mhi, (int)K.pm[i]);
+            }
+            x.byn = group_pairs(K.pn, p0, x.np, x.nlo, x.nhi, true);
+            x.bym = group_pairs(K.pm, p0, x.np, x.mlo, x.mhi, true);
+            maxm = std::max(maxm, x.mhi - x.mlo + 1);
+            maxn = std::max(maxn, x.nhi - x.nlo + 1);
+            S.ch.push_back(std::move(x));
         }
-        x.byn = group_pairs(K.pn, p0, x.np, x.nlo, x.nhi, true);
-        x.bym = group_pairs(K.pm, p0, x.np, x.mlo, x.mhi, true);
-        ch.push_back(std::move(x));
+        S.gn = group_pairs(K.pn, 0, P, 0, nbk - 1, false);
+        S.gm = group_pairs(K.pm, 0, P, 0, nbq - 1, false);
+        maxP = std::max(maxP, P);
+        maxphib = std::max(maxphib, (size_t)(nbk + (same ? 0 : nbq)) * vol);
     }
-    Csr gn = group_pairs(K.pn, 0, P, 0, nbk - 1, false);
-    Csr gm = group_pairs(K.pm, 0, P, 0, nbq - 1, false);
-    void *d_gns, *d_gnl, *d_gms, *d_gml;
-    Upload up;
-    for (auto& x : ch) {
-        up.add(x.byn.start, &x.d_ns);
-        up.add(x.byn.list, &x.d_nl);
-        up.add(x.bym.start, &x.d_ms);
-        up.add(x.bym.list, &x.d_ml);
-    }
-    up.add(gn.start, &d_gns);
-    up.add(gn.list, &d_gnl);
-    up.add(gm.start, &d_gms);
-    up.add(gm.list, &d_gml);
-    int rc = do_upload(c, up, B.s, "bw_tables");
-    if (rc) return rc;
 
-    // buffers
-    int maxm = 1, maxn = 1;
-    for (auto& x : ch) {
-        maxm = std::max(maxm, x.mhi - x.mlo + 1);
-        maxn = std::max(maxn, x.nhi - x.nlo + 1);
-    }
+    // buffers (sized for every set)
     const size_t mat = (size_t)nw * NGp * NGp;
     void *pB, *pX, *pL, *pY, *pG, *pdE, *pu, *pcw, *pZ, *pU, *pgn, *pT, *pPb;
     struct NB {
@@ -1644,13 +1831,12 @@ int backward(Batch& B, const double* dEc, double* ec_dev, double* deps_k, double
     } list[] = {{"bw_B", 2 * mat * 8, &pB}, {"bw_X", 2 * mat * 8, &pX},
                 {"bw_L", (size_t)(NGp / kTile) * 2 * nw * kTile * kTile * 8, &pL},
                 {"bw_Y", 2 * (size_t)Pc * NGp * 8, &pY}, {"bw_g", 2 * (size_t)Pc * NGp * 8, &pG},
-                {"bw_dEda", (size_t)nw * ((Pc + 3) / 4 * 4) * 8, &pdE}, {"bw_u", (size_t)std::max(P, 1) * 8, &pu},
+                {"bw_dEda", (size_t)nw * ((Pc + 3) / 4 * 4) * 8, &pdE}, {"bw_u", (size_t)maxP * 8, &pu},
                 {"bw_cw", 64 * 8, &pcw}, {"bw_Z", 4 * (size_t)Pc * std::max(nproj, 1) * 8, &pZ},
                 {"bw_U", 2 * (size_t)maxm * std::max(nproj, 1) * NGp * 8, &pU}, {"bw_gnum", 2 * (size_t)Pc * 8, &pgn},
-                {"bw_tadj", (size_t)Pc * g.N3 * g.ncols * 16, &pT},
-                {"bw_phibar", (size_t)(nbk + (same ? 0 : nbq)) * vol * 16, &pPb}};
+                {"bw_tadj", (size_t)Pc * g.N3 * g.ncols * 16, &pT}, {"bw_phibar", maxphib * 16, &pPb}};
     for (auto& e : list) {
-        rc = get_buf(c, e.n, e.b, B.s, e.p);
+        int rc = get_buf(c, e.n, e.b, B.s, e.p);
         if (rc) return rc;
     }
     double* Lb = static_cast<double*>(pL);
@@ -1665,11 +1851,10 @@ int backward(Batch& B, const double* dEc, double* ec_dev, double* deps_k, double
     double *Ur = static_cast<double*>(pU), *Ui = Ur + (size_t)maxm * std::max(nproj, 1) * NGp;
     double* gnum = static_cast<double*>(pgn);
     cplx<double>* tadj = static_cast<cplx<double>*>(pT);
-    cplx<double>* phib_k = static_cast<cplx<double>*>(pPb);
-    cplx<double>* phib_kq = same ? phib_k : phib_k + (size_t)nbk * vol;
+    (void)maxn;
 
     // forward: chi0, E_c, and the factor L with its inverted diagonal blocks
-    rc = enqueue_chi0<double>(B);
+    int rc = enqueue_chi0<double>(B);
     if (rc) return rc;
     Q.ec = ec_dev;
     Q.F = nullptr;
@@ -1715,115 +1900,158 @@ int backward(Batch& B, const double* dEc, double* ec_dev, double* deps_k, double
     HIP_TRY(launch_build_w(Br_, Bi_, NG, NGp, nw, static_cast<const double*>(Q.d_vs), B.s));
     HIP_TRY(launch_freq_coeffs(dEc, static_cast<const double*>(B.d_ow), nw, cw, B.s));
 
-    // outputs and accumulators start at zero
-    HIP_TRY(launch_zero_d(deps_k, nbk, B.s));
-    HIP_TRY(launch_zero_d(dC_k, 2 * (size_t)nbk * K.k->nQ, B.s));
-    if (nproj) HIP_TRY(launch_zero_d(dP_k, 2 * (size_t)nbk * nproj, B.s));
-    if (!same) {
-        HIP_TRY(launch_zero_d(deps_kq, nbq, B.s));
-        HIP_TRY(launch_zero_d(dC_kq, 2 * (size_t)nbq * K.kq->nQ, B.s));
-        if (nproj) HIP_TRY(launch_zero_d(dP_kq, 2 * (size_t)nbq * nproj, B.s));
-    }
-    HIP_TRY(launch_zero_d(reinterpret_cast<double*>(phib_k), 2 * (size_t)(nbk + (same ? 0 : nbq)) * vol, B.s));
-    HIP_TRY(launch_zero_d(u, std::max(P, 1), B.s));
-
-    const double* phik = static_cast<const double*>(buf(B, "phi_k"));
-    const double* phikq = same ? phik : static_cast<const double*>(buf(B, "phi_kq"));
-    const double prefac = K.k->weight / c->volume;
     const int lda = (Pc + 3) / 4 * 4;
     double* rre = static_cast<double*>(buf(B, "rho"));
     double* rim = rre + (size_t)Pc * NGp;
     double* aw = static_cast<double*>(buf(B, "weights"));
-    for (auto& x : ch) {
-        const int p0 = x.p0, np = x.np;
-        const int32_t* pn = static_cast<const int32_t*>(K.d_pn) + p0;
-        const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
-        rc = enqueue_pairs<double>(B, Q, K, 0, reinterpret_cast<const cplx<double>*>(phik),
-                                   reinterpret_cast<const cplx<double>*>(phikq), p0, np, rre, rim);
+    for (size_t ik = 0; ik < nks; ++ik) {
+        KSet& K = B.ks[ik];
+        BwSet& S = sets[ik];
+        const int P = (int)K.pn.size();
+        const bool same = same_set(K.k, K.kq);
+        const int nbk = K.k->nbands, nbq = K.kq->nbands;
+        double* deps_k = outk[ik].deps;
+        double* dC_k = outk[ik].dC;
+        double* dP_k = outk[ik].dP;
+        double* deps_kq = same ? deps_k : outkq[ik].deps;
+        double* dC_kq = same ? dC_k : outkq[ik].dC;
+        double* dP_kq = same ? dP_k : outkq[ik].dP;
+        // this set's outputs start at zero (a set with no transitions keeps a zero gradient)
+        HIP_TRY(launch_zero_d(deps_k, nbk, B.s));
+        HIP_TRY(launch_zero_d(dC_k, 2 * (size_t)nbk * K.k->nQ, B.s));
+        if (nproj) HIP_TRY(launch_zero_d(dP_k, 2 * (size_t)nbk * nproj, B.s));
+        if (!same) {
+            HIP_TRY(launch_zero_d(deps_kq, nbq, B.s));
+            HIP_TRY(launch_zero_d(dC_kq, 2 * (size_t)nbq * K.kq->nQ, B.s));
+            if (nproj) HIP_TRY(launch_zero_d(dP_kq, 2 * (size_t)nbq * nproj, B.s));
+        }
+        if (P == 0) continue;
+        Upload up;
+        for (auto& x : S.ch) {
+            up.add(x.byn.start, &x.d_ns);
+            up.add(x.byn.list, &x.d_nl);
+            up.add(x.bym.start, &x.d_ms);
+            up.add(x.bym.list, &x.d_ml);
+        }
+        up.add(S.gn.start, &S.d_gns);
+        up.add(S.gn.list, &S.d_gnl);
+        up.add(S.gm.start, &S.d_gms);
+        up.add(S.gm.list, &S.d_gml);
+        rc = do_upload(c, up, B.s, "bw_tables");
         if (rc) return rc;
-        HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
-                               static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq), pn, pm, np,
-                               static_cast<const double*>(B.d_om), nw, prefac, aw, lda, B.s));
-        HIP_TRY(launch_zero_d(gr, 2 * (size_t)Pc * NGp, B.s));
-        for (int w = 0; w < nw; ++w) {
-            GemmArgs gy{};
-            gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = 1;
-            gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
-            gy.Br = Br_ + (size_t)w * NGp * NGp; gy.Bi = Bi_ + (size_t)w * NGp * NGp; gy.sB = 0; gy.bK = 1; gy.bJ = NGp;
-            gy.Cr = Yr; gy.Ci = Yi; gy.sC = 0; gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
-            HIP_TRY(launch_gemm_c64(gy, B.s));
-            HIP_TRY(launch_grad_weights(rre, rim, Yr, Yi, NG, NGp, aw, lda, w, cw, gr, gi, dEda, np, B.s));
+        cplx<double>* phib_k = static_cast<cplx<double>*>(pPb);
+        cplx<double>* phib_kq = same ? phib_k : phib_k + (size_t)nbk * vol;
+        HIP_TRY(launch_zero_d(reinterpret_cast<double*>(phib_k), 2 * (size_t)(nbk + (same ? 0 : nbq)) * vol, B.s));
+        HIP_TRY(launch_zero_d(u, std::max(P, 1), B.s));
+        // this set's orbitals (the forward pass left those of the last set in the buffers)
+        cplx<double>* phik_c = nullptr;
+        cplx<double>* phikq_c = nullptr;
+        if (nks > 1) {
+            rc = enqueue_orbitals<double>(B, K.k, K.d_mapk, K.zcolk, K.d_zcolk, "phi_k", &phik_c);
+            if (rc) return rc;
+            if (!same) {
+                rc = enqueue_orbitals<double>(B, K.kq, K.d_mapkq, K.zcolkq, K.d_zcolkq, "phi_kq", &phikq_c);
+                if (rc) return rc;
+            }
         }
-        HIP_TRY(launch_pair_eps(dEda, lda, nw, static_cast<const double*>(K.d_epsk),
-                                static_cast<const double*>(K.d_epskq), static_cast<const double*>(K.d_fk),
-                                static_cast<const double*>(K.d_fkq), pn, pm, np, static_cast<const double*>(B.d_om),
-                                prefac, u + p0, B.s));
-        const bool opt = Q.qs->optical && Q.qp.g0 >= 0;
-        if (opt)
-            HIP_TRY(launch_optical_adj(rre, rim, gr, gi, Q.qp.g0, NGp, static_cast<const double*>(K.d_epsk),
-                                       static_cast<const double*>(K.d_epskq), pn, pm, np, u + p0, gnum, B.s));
-        const int32_t* ns = static_cast<const int32_t*>(x.d_ns);
-        const int32_t* nl = static_cast<const int32_t*>(x.d_nl);
-        const int32_t* ms = static_cast<const int32_t*>(x.d_ms);
-        const int32_t* ml = static_cast<const int32_t*>(x.d_ml);
-        const int nn = x.nhi - x.nlo + 1, nm = x.mhi - x.mlo + 1;
-        if (nproj > 0) {
-            double* Yn = static_cast<double*>(buf(B, "paw_y"));
-            double* Yni = Yn + (size_t)nn * nproj * NGp;
-            HIP_TRY(launch_paw_y<double>(static_cast<const double*>(K.k->P), nproj,
-                                         static_cast<const int32_t*>(K.d_nlist) + x.nlo, nn,
-                                         static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
-                                         K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), NG, NGp, Yn, Yni,
-                                         B.s));
-            HIP_TRY(launch_paw_u(static_cast<const double*>(K.kq->P), nproj, x.mlo, nm,
-                                 static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
-                                 K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), NG, NGp, Ur, Ui, B.s));
-            HIP_TRY(launch_paw_adj(gr, gi, NG, NGp, Yn, Yni, x.nlo, Ur, Ui, x.mlo, nproj, pn, pm, np, Zm, Zn, B.s));
-            HIP_TRY(launch_paw_reduce(Zn, ns, nl, nn, nproj, dP_k, x.nlo, opt ? gnum : nullptr,
-                                      static_cast<const double*>(K.kq->P), pm, static_cast<const double*>(Q.d_Dq),
-                                      static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
-                                      K.k->natoms, 0, B.s));
-            HIP_TRY(launch_paw_reduce(Zm, ms, ml, nm, nproj, dP_kq, x.mlo, opt ? gnum : nullptr,
-                                      static_cast<const double*>(K.k->P), pn, static_cast<const double*>(Q.d_Dq),
-                                      static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
-                                      K.k->natoms, 1, B.s));
+        const double* phik = static_cast<const double*>(buf(B, "phi_k"));
+        const double* phikq = same ? phik : static_cast<const double*>(buf(B, "phi_kq"));
+        const double prefac = K.k->weight / c->volume;
+        for (auto& x : S.ch) {
+            const int p0 = x.p0, np = x.np;
+            const int32_t* pn = static_cast<const int32_t*>(K.d_pn) + p0;
+            const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
+            rc = enqueue_pairs<double>(B, Q, K, (int)ik, reinterpret_cast<const cplx<double>*>(phik),
+                                       reinterpret_cast<const cplx<double>*>(phikq), p0, np, rre, rim);
+            if (rc) return rc;
+            HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
+                                   static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq), pn, pm,
+                                   np, static_cast<const double*>(B.d_om), nw, prefac, aw, lda, B.s));
+            HIP_TRY(launch_zero_d(gr, 2 * (size_t)Pc * NGp, B.s));
+            for (int w = 0; w < nw; ++w) {
+                GemmArgs gy{};
+                gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = 1;
+                gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
+                gy.Br = Br_ + (size_t)w * NGp * NGp; gy.Bi = Bi_ + (size_t)w * NGp * NGp; gy.sB = 0; gy.bK = 1;
+                gy.bJ = NGp;
+                gy.Cr = Yr; gy.Ci = Yi; gy.sC = 0; gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
+                HIP_TRY(launch_gemm_c64(gy, B.s));
+                HIP_TRY(launch_grad_weights(rre, rim, Yr, Yi, NG, NGp, aw, lda, w, cw, gr, gi, dEda, np, B.s));
+            }
+            HIP_TRY(launch_pair_eps(dEda, lda, nw, static_cast<const double*>(K.d_epsk),
+                                    static_cast<const double*>(K.d_epskq), static_cast<const double*>(K.d_fk),
+                                    static_cast<const double*>(K.d_fkq), pn, pm, np,
+                                    static_cast<const double*>(B.d_om), prefac, u + p0, B.s));
+            const bool opt = Q.qs->optical && Q.qp.g0 >= 0;
+            if (opt)
+                HIP_TRY(launch_optical_adj(rre, rim, gr, gi, Q.qp.g0, NGp, static_cast<const double*>(K.d_epsk),
+                                           static_cast<const double*>(K.d_epskq), pn, pm, np, u + p0, gnum, B.s));
+            const int32_t* ns = static_cast<const int32_t*>(x.d_ns);
+            const int32_t* nl = static_cast<const int32_t*>(x.d_nl);
+            const int32_t* ms = static_cast<const int32_t*>(x.d_ms);
+            const int32_t* ml = static_cast<const int32_t*>(x.d_ml);
+            const int nn = x.nhi - x.nlo + 1, nm = x.mhi - x.mlo + 1;
+            if (nproj > 0) {
+                double* Yn = static_cast<double*>(buf(B, "paw_y"));
+                double* Yni = Yn + (size_t)nn * nproj * NGp;
+                HIP_TRY(launch_paw_y<double>(static_cast<const double*>(K.k->P), nproj,
+                                             static_cast<const int32_t*>(K.d_nlist) + x.nlo, nn,
+                                             static_cast<const int32_t*>(B.d_poff),
+                                             static_cast<const int32_t*>(B.d_qoff), K.k->natoms, nproj,
+                                             static_cast<const double*>(Q.qs->Qpaw), NG, NGp, Yn, Yni, B.s));
+                HIP_TRY(launch_paw_u(static_cast<const double*>(K.kq->P), nproj, x.mlo, nm,
+                                     static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                     K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), NG, NGp, Ur, Ui,
+                                     B.s));
+                HIP_TRY(launch_paw_adj(gr, gi, NG, NGp, Yn, Yni, x.nlo, Ur, Ui, x.mlo, nproj, pn, pm, np, Zm, Zn,
+                                       B.s));
+                HIP_TRY(launch_paw_reduce(Zn, ns, nl, nn, nproj, dP_k, x.nlo, opt ? gnum : nullptr,
+                                          static_cast<const double*>(K.kq->P), pm, static_cast<const double*>(Q.d_Dq),
+                                          static_cast<const int32_t*>(B.d_poff),
+                                          static_cast<const int32_t*>(B.d_qoff), K.k->natoms, 0, B.s));
+                HIP_TRY(launch_paw_reduce(Zm, ms, ml, nm, nproj, dP_kq, x.mlo, opt ? gnum : nullptr,
+                                          static_cast<const double*>(K.k->P), pn, static_cast<const double*>(Q.d_Dq),
+                                          static_cast<const int32_t*>(B.d_poff),
+                                          static_cast<const int32_t*>(B.d_qoff), K.k->natoms, 1, B.s));
+            }
+            if (opt) {
+                const double* wq = static_cast<const double*>(Q.d_wq[ik]);
+                HIP_TRY(launch_optical_c(gnum, ns, nl, pm, static_cast<const double*>(K.kq->C), K.k->nQ, wq, 0, nn,
+                                         dC_k + 2 * (size_t)x.nlo * K.k->nQ, B.s));
+                HIP_TRY(launch_optical_c(gnum, ms, ml, pn, static_cast<const double*>(K.k->C), K.kq->nQ, wq, 1, nm,
+                                         dC_kq + 2 * (size_t)x.mlo * K.kq->nQ, B.s));
+            }
+            HIP_TRY(launch_zadj(gr, gi, NGp, np, g, static_cast<const int32_t*>(Q.d_cs),
+                                static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
+                                static_cast<const cplx<double>*>(B.d_tw[2]), tadj, B.s));
+            HIP_TRY(launch_xyadj(tadj, g, ms, ml, pn, reinterpret_cast<const cplx<double>*>(phik), x.mlo, nm, 1,
+                                 static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
+                                 static_cast<const cplx<double>*>(B.d_tw[0]),
+                                 static_cast<const cplx<double>*>(B.d_tw[1]), phib_kq, B.s));
+            HIP_TRY(launch_xyadj(tadj, g, ns, nl, pm, reinterpret_cast<const cplx<double>*>(phikq), x.nlo, nn, 0,
+                                 static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
+                                 static_cast<const cplx<double>*>(B.d_tw[0]),
+                                 static_cast<const cplx<double>*>(B.d_tw[1]), phib_k, B.s));
         }
-        if (opt) {
-            const double* wq = static_cast<const double*>(Q.d_wq[0]);
-            HIP_TRY(launch_optical_c(gnum, ns, nl, pm, static_cast<const double*>(K.kq->C), K.k->nQ, wq, 0, nn,
-                                     dC_k + 2 * (size_t)x.nlo * K.k->nQ, B.s));
-            HIP_TRY(launch_optical_c(gnum, ms, ml, pn, static_cast<const double*>(K.k->C), K.kq->nQ, wq, 1, nm,
-                                     dC_kq + 2 * (size_t)x.mlo * K.kq->nQ, B.s));
+        // energies
+        HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(S.d_gns), static_cast<const int32_t*>(S.d_gnl), nbk,
+                                  1.0, deps_k, B.s));
+        HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(S.d_gms), static_cast<const int32_t*>(S.d_gml), nbq,
+                                  -1.0, deps_kq, B.s));
+        // coefficients: C_bar = unnormalised forward DFT of phi_bar, read at the plane-wave Miller indices
+        for (int side = 0; side < (same ? 1 : 2); ++side) {
+            cplx<double>* ph = side == 0 ? phib_k : phib_kq;
+            const int nb = side == 0 ? nbk : nbq;
+            for (int ax = 0; ax < 3; ++ax)
+                HIP_TRY(launch_fft_axis<double>(ph, nb, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
+                                                static_cast<const cplx<double>*>(B.d_tw[ax]), -1, B.s));
         }
-        HIP_TRY(launch_zadj(gr, gi, NGp, np, g, static_cast<const int32_t*>(Q.d_cs),
-                            static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
-                            static_cast<const cplx<double>*>(B.d_tw[2]), tadj, B.s));
-        HIP_TRY(launch_xyadj(tadj, g, ms, ml, pn, reinterpret_cast<const cplx<double>*>(phik), x.mlo, nm, 1,
-                             static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
-                             static_cast<const cplx<double>*>(B.d_tw[0]), static_cast<const cplx<double>*>(B.d_tw[1]),
-                             phib_kq, B.s));
-        HIP_TRY(launch_xyadj(tadj, g, ns, nl, pm, reinterpret_cast<const cplx<double>*>(phikq), x.nlo, nn, 0,
-                             static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
-                             static_cast<const cplx<double>*>(B.d_tw[0]), static_cast<const cplx<double>*>(B.d_tw[1]),
-                             phib_k, B.s));
+        HIP_TRY(launch_gather_c(phib_k, vol, static_cast<const int32_t*>(K.d_mapk), K.k->nQ, nbk, dC_k, B.s));
+        // with one state set both roles accumulated into the same phi_bar above
+        if (!same)
+            HIP_TRY(launch_gather_c(phib_kq, vol, static_cast<const int32_t*>(K.d_mapkq), K.kq->nQ, nbq, dC_kq,
+                                    B.s));
     }
-    // energies
-    HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(d_gns), static_cast<const int32_t*>(d_gnl), nbk, 1.0,
-                              deps_k, B.s));
-    HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(d_gms), static_cast<const int32_t*>(d_gml), nbq, -1.0,
-                              deps_kq, B.s));
-    // coefficients: C_bar = unnormalised forward DFT of phi_bar, read at the plane-wave Miller indices
-    for (int side = 0; side < (same ? 1 : 2); ++side) {
-        cplx<double>* ph = side == 0 ? phib_k : phib_kq;
-        const int nb = side == 0 ? nbk : nbq;
-        for (int ax = 0; ax < 3; ++ax)
-            HIP_TRY(launch_fft_axis<double>(ph, nb, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
-                                            static_cast<const cplx<double>*>(B.d_tw[ax]), -1, B.s));
-    }
-    HIP_TRY(launch_gather_c(phib_k, vol, static_cast<const int32_t*>(K.d_mapk), K.k->nQ, nbk, dC_k, B.s));
-    // with one state set both roles accumulated into the same phi_bar above
-    if (!same)
-        HIP_TRY(launch_gather_c(phib_kq, vol, static_cast<const int32_t*>(K.d_mapkq), K.kq->nQ, nbq, dC_kq, B.s));
     return RPA_OK;
 }
 
@@ -1852,6 +2080,24 @@ uint64_t batch_key(const rpa_states* k, const rpa_states* kq, int nk, int nq, co
         h.val(s->weight);
         h.val(s->dfde != nullptr);
         if (s->dfde) h.bytes(s->dfde, sizeof(double) * s->nbands);
+        h.val(s->sym != nullptr);
+        if (s->sym) {
+            const rpa_symop* o = s->sym;
+            h.bytes(o->rot, sizeof(o->rot));
+            h.val(o->time_reversal);
+            h.bytes(o->gshift, sizeof(o->gshift));
+            h.bytes(o->kibz, sizeof(o->kibz));
+            if (s->natoms > 0 && o->atom_map && o->atom_shift && o->proj_rot) {
+                h.bytes(o->atom_map, sizeof(int32_t) * s->natoms);
+                h.bytes(o->atom_shift, sizeof(int32_t) * 3 * s->natoms);
+                size_t nd = 0;
+                for (int a = 0; a < s->natoms; ++a) {
+                    const size_t np = (size_t)(s->proj_off[a + 1] - s->proj_off[a]);
+                    nd += np * np;
+                }
+                h.bytes(o->proj_rot, sizeof(double) * nd);
+            }
+        }
     };
     for (int i = 0; i < nk; ++i) {
         st(&k[i]);
@@ -2020,11 +2266,13 @@ int rpa_pair_density(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, cons
         QJob& Q = B.qj[0];
         cplx<T>* phik = nullptr;
         cplx<T>* phikq = nullptr;
-        int r = enqueue_orbitals<T>(B, k, K.d_mapk, K.zcolk, K.d_zcolk, "phi_k", &phik);
+        int r = enqueue_unfold(B);
         if (r) return r;
-        if (same_set(k, kq)) phikq = phik;
+        r = enqueue_orbitals<T>(B, K.k, K.d_mapk, K.zcolk, K.d_zcolk, "phi_k", &phik);
+        if (r) return r;
+        if (same_set(K.k, K.kq)) phikq = phik;
         else {
-            r = enqueue_orbitals<T>(B, kq, K.d_mapkq, K.zcolkq, K.d_zcolkq, "phi_kq", &phikq);
+            r = enqueue_orbitals<T>(B, K.kq, K.d_mapkq, K.zcolkq, K.d_zcolkq, "phi_kq", &phikq);
             if (r) return r;
         }
         const int NGp = Q.qp.NGp, Pc = Q.Pc;
@@ -2178,9 +2426,11 @@ int rpa_ec_from_chi0(rpa_ctx* c, const rpa_qspec* qs, const rpa_freq* fr, const 
     return RPA_OK;
 }
 
-int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs,
-                   const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
-                   void* stream) {
+// E_c of nq q-points in one call; qk (nq + 1 entries, optional): q-point j uses the sets qk[j] .. qk[j+1]-1
+// of k and kq (every set for every q-point without it)
+static int ec_batched_impl(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs,
+                           const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
+                           void* stream, const int* qk) {
     if (nq <= 0 || !qs) return fail(RPA_ERR_INPUT, "need at least one q-point");
     int rc = check_common(c, k, kq, nk, qs);
     if (rc) return rc;
@@ -2190,7 +2440,13 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
     rc = begin(B, c, fr, prec, stream);
     if (rc) return rc;
     B.m_major = true;
-    const uint64_t key = use_graph ? batch_key(k, kq, nk, nq, qs, fr, prec, ec_dev, F_dev, stream) : 0;
+    uint64_t key = use_graph ? batch_key(k, kq, nk, nq, qs, fr, prec, ec_dev, F_dev, stream) : 0;
+    if (use_graph && qk) {
+        Fnv h;
+        h.val(key);
+        h.bytes(qk, sizeof(int) * (size_t)(nq + 1));
+        key = h.h;
+    }
     if (use_graph && c->graph_exec && c->graph_key == key) {
         HIP_TRY(hipGraphLaunch(c->graph_exec, B.s));
         return RPA_OK;
@@ -2200,7 +2456,7 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
         B.prefix = "g:";
     }
     const std::string tables = B.prefix + "tables";
-    rc = plan_batch(B, k, kq, nk, qs, nq, true, false, tables.c_str());
+    rc = plan_batch(B, k, kq, nk, qs, nq, true, false, tables.c_str(), nullptr, nullptr, -1, qk);
     if (rc) return rc;
     std::vector<double> wq(nq);
     for (int j = 0; j < nq; ++j) wq[j] = qs[j].weight;
@@ -2260,27 +2516,76 @@ int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk
 }
 
 
-int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, const rpa_qspec* qs, const rpa_freq* fr,
-                    const double* dEc, double* ec_dev, double* deps_k, void* dC_k, void* dP_k, double* deps_kq,
-                    void* dC_kq, void* dP_kq, void* stream) {
-    int rc = check_common(c, k, kq, 1, qs);
+int rpa_ec_batched(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, int nq, const rpa_qspec* qs,
+                   const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev, int use_graph,
+                   void* stream) {
+    return ec_batched_impl(c, k, kq, nk, nq, qs, fr, prec, ec_dev, F_dev, use_graph, stream, nullptr);
+}
+
+int rpa_ec_batched_sets(rpa_ctx* c, int nq, const rpa_states* const* k, const rpa_states* const* kq, const int* nk,
+                        const rpa_qspec* qs, const rpa_freq* fr, rpa_precision prec, double* ec_dev, double* F_dev,
+                        int use_graph, void* stream) {
+    if (!c) return fail(RPA_ERR_INPUT, "NULL context");
+    if (nq <= 0 || !qs || !k || !kq || !nk) return fail(RPA_ERR_INPUT, "need nq > 0 and per-q set lists");
+    std::vector<rpa_states> fk, fkq;
+    std::vector<int> qk(nq + 1, 0);
+    for (int j = 0; j < nq; ++j) {
+        if (nk[j] <= 0 || !k[j] || !kq[j])
+            return fail(RPA_ERR_INPUT, "q-point " + std::to_string(j) + " has no (k, k+q) state-set pair");
+        for (int i = 0; i < nk[j]; ++i) {
+            fk.push_back(k[j][i]);
+            fkq.push_back(kq[j][i]);
+        }
+        qk[j + 1] = qk[j] + nk[j];
+    }
+    return ec_batched_impl(c, fk.data(), fkq.data(), (int)fk.size(), nq, qs, fr, prec, ec_dev, F_dev, use_graph,
+                           stream, qk.data());
+}
+
+int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
+                    const rpa_freq* fr, const double* dEc, double* ec_dev, double* deps_k, void* dC_k, void* dP_k,
+                    double* deps_kq, void* dC_kq, void* dP_kq, void* stream) {
+    int rc = check_common(c, k, kq, nk, qs);
     if (rc) return rc;
     if (!fr || !dEc || !ec_dev || !deps_k || !dC_k) return fail(RPA_ERR_INPUT, "NULL argument");
-    const bool same = same_set(k, kq);
-    if (!same && (!deps_kq || !dC_kq)) return fail(RPA_ERR_INPUT, "distinct k+q set needs its own gradient outputs");
-    if (k->natoms > 0 && (!dP_k || (!same && !dP_kq))) return fail(RPA_ERR_INPUT, "NULL projection gradient");
     if ((long long)c->N[0] * c->N[1] > 16 * 256) return fail(RPA_ERR_UNSUPPORTED, "adjoint needs N1*N2 <= 4096");
-    if (qs->optical && (k->dfde || kq->dfde))
-        return fail(RPA_ERR_UNSUPPORTED, "the adjoint has no intraband head (state sets with -df/de)");
+    // gradient slots: set i of k (of kq) at the sum of the sizes of sets 0 .. i-1 of k (of kq)
+    std::vector<BwOut> outk(nk), outkq(nk);
+    size_t ek = 0, ck = 0, pk = 0, eq = 0, cq = 0, pq = 0;
+    bool any_distinct = false;
+    for (int i = 0; i < nk; ++i) {
+        if (qs->optical && (k[i].dfde || kq[i].dfde))
+            return fail(RPA_ERR_UNSUPPORTED, "the adjoint has no intraband head (state sets with -df/de)");
+        if (k[i].sym || kq[i].sym)
+            return fail(RPA_ERR_UNSUPPORTED, "the adjoint takes state sets without a symmetry operation");
+        const bool same = same_set(&k[i], &kq[i]);
+        any_distinct = any_distinct || !same;
+        const size_t np = (size_t)(k[i].natoms > 0 ? k[i].proj_off[k[i].natoms] : 0);
+        outk[i].deps = deps_k + ek;
+        outk[i].dC = static_cast<double*>(dC_k) + ck;
+        outk[i].dP = dP_k ? static_cast<double*>(dP_k) + pk : nullptr;
+        ek += (size_t)k[i].nbands;
+        ck += 2 * (size_t)k[i].nbands * k[i].nQ;
+        pk += 2 * (size_t)k[i].nbands * np;
+        outkq[i].deps = deps_kq ? deps_kq + eq : nullptr;
+        outkq[i].dC = dC_kq ? static_cast<double*>(dC_kq) + cq : nullptr;
+        outkq[i].dP = dP_kq ? static_cast<double*>(dP_kq) + pq : nullptr;
+        eq += (size_t)kq[i].nbands;
+        cq += 2 * (size_t)kq[i].nbands * kq[i].nQ;
+        pq += 2 * (size_t)kq[i].nbands * np;
+    }
+    if (any_distinct && (!deps_kq || !dC_kq)) return fail(RPA_ERR_INPUT, "distinct k+q sets need their own gradient outputs");
+    if (k[0].natoms > 0 && (!dP_k || (any_distinct && !dP_kq))) return fail(RPA_ERR_INPUT, "NULL projection gradient");
     Batch B;
     rc = begin(B, c, fr, RPA_FP64, stream);
     if (rc) return rc;
     B.allow_paw_mfma = false;
-    rc = plan_batch(B, k, kq, 1, qs, 1, true, false, "tables");
+    rc = plan_batch(B, k, kq, nk, qs, 1, true, false, "tables");
     if (rc) return rc;
-    if (B.ks[0].pn.empty()) return fail(RPA_ERR_INPUT, "no transitions (f_n - f_m > 1e-8) in the state sets");
-    return backward(B, dEc, ec_dev, deps_k, static_cast<double*>(dC_k), static_cast<double*>(dP_k), deps_kq,
-                    static_cast<double*>(dC_kq), static_cast<double*>(dP_kq));
+    size_t total = 0;
+    for (auto& K : B.ks) total += K.pn.size();
+    if (total == 0) return fail(RPA_ERR_INPUT, "no transitions (f_n - f_m > 1e-8) in the state sets");
+    return backward(B, dEc, ec_dev, outk, outkq);
 }
 
 int rpa_set_pair_path(rpa_ctx* ctx, int path) {

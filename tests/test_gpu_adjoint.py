@@ -37,6 +37,40 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+@pytest.mark.parametrize("optical", [False, True])
+def test_adjoint_over_several_set_pairs(rpa, optical):
+    """Eq. chi0's k sum in the adjoint: listings (s, t) and (t', t') with t' a copy of t at half weight
+    (k-point weights 1 and 1/2) in one call; each listing's gradient against the oracle's reference.
+    At the optical q-point both listings use their k set as k+q: (s, s) and (t', t')."""
+    wl = synth.tiny(grid=(10, 10, 10), n_occ=2, n_unocc=3, target_ng=12 if optical else 15, nw=8, extra_kq=True,
+                    optical=optical)
+    s, t = wl.kpoints[0], wl.kq_sets()[0]
+    t2 = synth.StateSet(kpt=t.kpt, weight=0.5, miller=t.miller, C=t.C, eps=t.eps, f=t.f, P=t.P)
+    qp = wl.qpoints[0]
+    gm = oracle.gsphere(wl.A, qp.q, qp.ecut)
+    Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
+    D = synth.paw_d_table(wl.paw)
+    okq = [s, t2] if optical else [t, t2]
+    E_ref, g_ref = G.ec_and_grad_sets(wl.A, wl.grid, [s, t2], okq, gm, Q, wl.paw.offsets, qp.q, wl.omega,
+                                      wl.omega_weight, qp.optical, qp.qhat, D)
+    dev = "cuda:0"
+    S = rpa.States.from_synth(s, wl.paw, dev)
+    T = rpa.States.from_synth(t, wl.paw, dev)
+    T2 = rpa.States.from_synth(t2, wl.paw, dev)
+    qs = rpa.QSpec(qp.q, gm, Q, optical=qp.optical, qhat=qp.qhat, Dpaw=D, device=dev)
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ec, g = ctx.ec_backward([S, T2], [S, T2] if optical else [T, T2], qs, fr)
+        ctx.check()
+    assert abs(float(ec.cpu()[0]) - E_ref) < 1e-10
+    for i, (gg, gr) in enumerate(zip(g, g_ref)):
+        assert set(gg) == set(gr)
+        for key in gr:
+            r = _rel(gg[key].cpu().numpy(), gr[key])
+            print(f"optical={optical} pair {i} {key}: rel={r:.3e}", flush=True)
+            assert r < 1e-9, (i, key)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_adjoint_matches_reference_gradient(rpa, case):
     wl = CASES[case]()
