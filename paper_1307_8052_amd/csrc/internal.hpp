@@ -23,6 +23,7 @@ struct PairGeom {
     int NG, NGp;          // sphere size and its padded size
     FftPlan p1, p2, p3;
     int x0, y0;           // grid index of the first kept x / y frequency (the kept sets wrap modulo N)
+    int nzc;              // columns that hold sphere entries (the only ones transformed along z)
 };
 
 // ----------------------------------------------------------------- FFT stages
@@ -64,12 +65,15 @@ hipError_t launch_grid_fft_z_reg(cplx<T>* data, int nb, int N1, int N2, int N3, 
 template <typename T>
 hipError_t launch_grid_fft_xy_reg(cplx<T>* data, int nb, int N1, int N2, int N3, int dir, hipStream_t s);
 template <typename T>
-hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
-                             const int32_t* col_g, const int32_t* col_kz, T* rho_re, T* rho_im, hipStream_t s);
+// zcol: the box column of each of the g.nzc columns that hold sphere entries; col_start and the column
+// bits of col_kz index that list
+hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                             const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, T* rho_re,
+                             T* rho_im, hipStream_t s);
 template <typename T>
-hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
-                                const int32_t* col_g, const int32_t* col_kz, const cplx<T>* tw3, T* rho_re,
-                                T* rho_im, hipStream_t s);
+hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                                const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz,
+                                const cplx<T>* tw3, T* rho_re, T* rho_im, hipStream_t s);
 
 // ------------------------------------------------------------ linear algebra
 template <typename T>

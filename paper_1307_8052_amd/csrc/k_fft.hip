@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_xy(const cplx<T>* __restri
 
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_pair_z_gather(const cplx<T>* __restrict__ tbuf, PairGeom g, int CB,
+                                                               const int32_t* __restrict__ zcol,
                                                                const int32_t* __restrict__ col_start,
                                                                const int32_t* __restrict__ col_g,
                                                                const int32_t* __restrict__ col_kz,
@@ -161,11 +162,11 @@ __global__ __launch_bounds__(kFftThreads) void k_pair_z_gather(const cplx<T>* __
     cplx<T>* B = A + (size_t)CB * N3;
     const size_t p = blockIdx.x;
     const int c0 = blockIdx.y * CB;
-    const int nc = min(CB, ncols - c0);
+    const int nc = min(CB, g.nzc - c0);
     for (int t = threadIdx.x; t < twiddle_len<T>(N3); t += blockDim.x) tw3[t] = tw3g[t];
     for (int f = threadIdx.x; f < N3 * nc; f += blockDim.x) {
         const int z = f / nc, c = f - z * nc;
-        A[z * CB + c] = tbuf[(p * N3 + z) * ncols + c0 + c];
+        A[z * CB + c] = tbuf[(p * N3 + z) * ncols + zcol[c0 + c]];
     }
     __syncthreads();
     auto az = [CB](int l, int e) { return e * CB + l; };
@@ -269,18 +270,19 @@ hipError_t launch_pair_xy(const cplx<T>* phik, const cplx<T>* phikq, const int32
 }
 
 template <typename T>
-hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
-                                const int32_t* col_g, const int32_t* col_kz, const cplx<T>* tw3, T* rho_re, T* rho_im,
-                                hipStream_t s) {
+hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                                const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz,
+                                const cplx<T>* tw3, T* rho_re, T* rho_im, hipStream_t s) {
     if (!npairs) return hipSuccess;
+    if (g.nzc < 1 || g.nzc > g.ncols) return hipErrorInvalidValue;
     size_t per = kLdsBudget / sizeof(cplx<T>);
     int CB = (int)((per - twiddle_len<T>(g.N3)) / (2 * (size_t)g.N3));
-    if (CB > g.ncols) CB = g.ncols;
+    if (CB > g.nzc) CB = g.nzc;
     if (CB < 1) return hipErrorInvalidValue;
     const size_t lds = ((size_t)twiddle_len<T>(g.N3) + 2 * (size_t)CB * g.N3) * sizeof(cplx<T>);
-    dim3 grid((unsigned)npairs, (unsigned)((g.ncols + CB - 1) / CB));
-    hipLaunchKernelGGL(k_pair_z_gather<T>, grid, dim3(kFftThreads), lds, s, tbuf, g, CB, col_start, col_g, col_kz, tw3,
-                       rho_re, rho_im);
+    dim3 grid((unsigned)npairs, (unsigned)((g.nzc + CB - 1) / CB));
+    hipLaunchKernelGGL(k_pair_z_gather<T>, grid, dim3(kFftThreads), lds, s, tbuf, g, CB, zcol, col_start, col_g,
+                       col_kz, tw3, rho_re, rho_im);
     return hipGetLastError();
 }
 
@@ -294,7 +296,8 @@ hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom&
                                           const PairGeom&, const int32_t*, const int32_t*, const cplx<T>*,          \
                                           const cplx<T>*, cplx<T>*, hipStream_t);                                   \
     template hipError_t launch_pair_z_gather<T>(const cplx<T>*, int, const PairGeom&, const int32_t*,              \
-                                                const int32_t*, const int32_t*, const cplx<T>*, T*, T*, hipStream_t);
+                                                const int32_t*, const int32_t*, const int32_t*, const cplx<T>*, T*,  \
+                                                T*, hipStream_t);
 RPA_INST(double)
 RPA_INST(float)
 #undef RPA_INST

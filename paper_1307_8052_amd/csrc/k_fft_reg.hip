@@ -218,6 +218,7 @@ __global__ __launch_bounds__((xy_threads<T, N1>())) void k_pair_xy_reg(const cpl
 
 template <typename T, int N3>
 __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ tbuf, PairGeom g,
+                                                    const int32_t* __restrict__ zcol,
                                                     const int32_t* __restrict__ col_start,
                                                     const int32_t* __restrict__ col_g,
                                                     const int32_t* __restrict__ col_kz, T* __restrict__ rre,
@@ -229,10 +230,10 @@ __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ 
     const size_t p = blockIdx.x;
     const int CB = blockDim.x;
     const int c0 = blockIdx.y * CB;
-    const int nc = min(CB, ncols - c0);
+    const int nc = min(CB, g.nzc - c0);
     const int c = threadIdx.x;
     if (c < nc) {
-        const cplx<T>* src = tbuf + p * N3 * ncols + c0 + c;
+        const cplx<T>* src = tbuf + p * N3 * ncols + zcol[c0 + c];
         cplx<T> v[N3];
 #pragma unroll
         for (int z = 0; z < N3; ++z) v[z] = src[(size_t)z * ncols];
@@ -452,18 +453,20 @@ hipError_t launch_pair_xy_reg(const cplx<T>* phik, const cplx<T>* phikq, const i
 }
 
 template <typename T>
-hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* col_start,
-                             const int32_t* col_g, const int32_t* col_kz, T* rho_re, T* rho_im, hipStream_t s) {
+hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                             const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, T* rho_re,
+                             T* rho_im, hipStream_t s) {
     if (!npairs) return hipSuccess;
     if (!pair_z_reg_supported<T>(g)) return hipErrorNotSupported;
+    if (g.nzc < 1 || g.nzc > g.ncols) return hipErrorInvalidValue;
     const int CB = z_block<T>();
     const size_t lds = (size_t)CB * (g.N3 + 1) * sizeof(cplx<T>);
-    dim3 grid((unsigned)npairs, (unsigned)((g.ncols + CB - 1) / CB));
+    dim3 grid((unsigned)npairs, (unsigned)((g.nzc + CB - 1) / CB));
     switch (g.N3) {
 #define RPA_CASE(L)                                                                                                \
     case L:                                                                                                        \
-        hipLaunchKernelGGL((k_pair_z_reg<T, L>), grid, dim3(CB), lds, s, tbuf, g, col_start, col_g, col_kz, rho_re, \
-                           rho_im);                                                                                \
+        hipLaunchKernelGGL((k_pair_z_reg<T, L>), grid, dim3(CB), lds, s, tbuf, g, zcol, col_start, col_g, col_kz,   \
+                           rho_re, rho_im);                                                                        \
         break;
         RPA_REG_SIZES(RPA_CASE)
 #undef RPA_CASE
@@ -480,7 +483,7 @@ hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g,
     template hipError_t launch_pair_xy_reg<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*, int, \
                                               const PairGeom&, cplx<T>*, hipStream_t);                           \
     template hipError_t launch_pair_z_reg<T>(const cplx<T>*, int, const PairGeom&, const int32_t*, const int32_t*, \
-                                             const int32_t*, T*, T*, hipStream_t);
+                                             const int32_t*, const int32_t*, T*, T*, hipStream_t);
 RPA_INST(double)
 RPA_INST(float)
 #undef RPA_INST

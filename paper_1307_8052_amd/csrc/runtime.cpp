@@ -395,22 +395,35 @@ struct QPlan {
     PairGeom g;
     int NG = 0, NGp = 0, g0 = -1;
     std::vector<int32_t> kx, ky, col_start, col_g, col_kz;
+    // the same entries over the columns that hold any (the forward z pass transforms only those)
+    std::vector<int32_t> zcol, zcol_start, zcol_kz;
     std::vector<double> vsqrt;
 };
 
-int plan_q(rpa_ctx* c, const rpa_qspec* qs, QPlan& P, bool need_coulomb) {
-    if (!qs) return fail(RPA_ERR_INPUT, "NULL qspec");
-    if (qs->NG <= 0 || !qs->gmiller) return fail(RPA_ERR_SHAPE, "empty G-sphere");
-    const int NG = qs->NG;
-    int lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = hi[d] = qs->gmiller[d];
-    }
-    for (int i = 0; i < NG; ++i)
+// Miller ranges of a sphere along each axis
+void sphere_box(const rpa_qspec* qs, int lo[3], int hi[3]) {
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = qs->gmiller[d];
+    for (int i = 0; i < qs->NG; ++i)
         for (int d = 0; d < 3; ++d) {
             lo[d] = std::min(lo[d], (int)qs->gmiller[3 * i + d]);
             hi[d] = std::max(hi[d], (int)qs->gmiller[3 * i + d]);
         }
+}
+
+// box (optional): {lo1, hi1, lo2, hi2}, the (m1, m2) columns the pair transform keeps when several q-points
+// share it; the sphere's own extent otherwise
+int plan_q(rpa_ctx* c, const rpa_qspec* qs, QPlan& P, bool need_coulomb, const int* box = nullptr) {
+    if (!qs) return fail(RPA_ERR_INPUT, "NULL qspec");
+    if (qs->NG <= 0 || !qs->gmiller) return fail(RPA_ERR_SHAPE, "empty G-sphere");
+    const int NG = qs->NG;
+    int lo[3], hi[3];
+    sphere_box(qs, lo, hi);
+    if (box) {
+        lo[0] = box[0];
+        hi[0] = box[1];
+        lo[1] = box[2];
+        hi[1] = box[3];
+    }
     for (int d = 0; d < 3; ++d)
         if (hi[d] - lo[d] + 1 > c->N[d]) return fail(RPA_ERR_ALIAS, "G-sphere wider than the grid");
     PairGeom& g = P.g;
@@ -453,6 +466,18 @@ int plan_q(rpa_ctx* c, const rpa_qspec* qs, QPlan& P, bool need_coulomb) {
         P.col_g[r] = i;
         P.col_kz[r] = (kz << 16) | col[i];
     }
+    std::vector<int32_t> cidx(g.ncols, -1);
+    P.zcol.clear();
+    P.zcol_start.assign(1, 0);
+    for (int k = 0; k < g.ncols; ++k)
+        if (P.col_start[k + 1] > P.col_start[k]) {
+            cidx[k] = (int32_t)P.zcol.size();
+            P.zcol.push_back(k);
+            P.zcol_start.push_back(P.col_start[k + 1]);
+        }
+    g.nzc = (int)P.zcol.size();
+    P.zcol_kz.resize(NG);
+    for (int r = 0; r < NG; ++r) P.zcol_kz[r] = (P.col_kz[r] & ~0xffff) | cidx[P.col_kz[r] & 0xffff];
     // Coulomb v^1/2 and the G = 0 index
     P.vsqrt.assign(g.NGp, 0.0);
     const double s4pi = std::sqrt(4.0 * kPi);
@@ -589,6 +614,7 @@ struct QJob {
     const rpa_qspec* qs = nullptr;
     QPlan qp;
     void* d_kx = nullptr; void* d_ky = nullptr; void* d_cs = nullptr; void* d_cg = nullptr; void* d_ckz = nullptr;
+    void* d_zc = nullptr; void* d_zcs = nullptr; void* d_zckz = nullptr;
     void* d_vs = nullptr;
     // optical limit: plane-wave momentum weights per k set and qhat.D
     std::vector<std::vector<double>> wq;
@@ -653,6 +679,8 @@ struct Batch {
     double eta = 0.0;
     int nw_user = 0;
     bool paw_mfma = false;           // set by presize: PAW correction as an MFMA GEMM per band m
+    bool share_xy = false;           // several q-points with shared sets: one pair transform per chunk for all
+    bool allow_share_xy = true;      // the adjoint keeps one q-point's own box
     int ld = 0;                      // the largest leading dimension of the batch's chi0 / -K matrices
     std::vector<QClass> cls;         // the q-points grouped by leading dimension
     std::deque<rpa_states> usets;              // state sets unfolded from the irreducible zone
@@ -931,6 +959,9 @@ int prepare_q(Batch& B, QJob& Q, Upload& up) {
     up.add(q.col_start, &Q.d_cs);
     up.add(q.col_g, &Q.d_cg);
     up.add(q.col_kz, &Q.d_ckz);
+    up.add(q.zcol, &Q.d_zc);
+    up.add(q.zcol_start, &Q.d_zcs);
+    up.add(q.zcol_kz, &Q.d_zckz);
     up.add(q.vsqrt, &Q.d_vs);
     if (Q.qs->optical) {
         double qh[3] = {Q.qs->qhat[0], Q.qs->qhat[1], Q.qs->qhat[2]};
@@ -976,14 +1007,12 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         W.phi_k = std::max(W.phi_k, (size_t)K.k->nbands * vol * 2 * el);
         if (!same_set(K.k, K.kq)) W.phi_kq = std::max(W.phi_kq, (size_t)K.kq->nbands * vol * 2 * el);
     }
+    int P = 0;
+    for (auto& K : B.ks) P = std::max(P, (int)K.pn.size());
+    // rank-k variant (new size buckets autotuned first) and pair chunk of every q-point; with a shared pair
+    // transform every q-point takes the smallest chunk
     for (auto& Q : B.qj) {
         const PairGeom& g = Q.qp.g;
-        int P = 0;
-        int nn_max = 1;
-        for (auto& K : B.ks) {
-            P = std::max(P, (int)K.pn.size());
-            if (!K.pn.empty()) nn_max = std::max(nn_max, K.k->nbands);
-        }
         if (!B.fp64() && c->autotune && !c->arena && !c->capturing && P > 0 &&
             !c->tune.count(tune_key(B.prec, g.NGp))) {
             // the first call with a sphere of this size bucket times the rank-k variants on it
@@ -996,6 +1025,14 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         }
         Q.variant = default_variant(c, B.prec, g.NGp);
         Q.Pc = std::max(1, std::min(P, chunk_size(c, Q.qp, B.nw, el, Q.variant)));
+    }
+    if (B.share_xy) {
+        int pc = B.qj.empty() ? 1 : B.qj[0].Pc;
+        for (auto& Q : B.qj) pc = std::min(pc, Q.Pc);
+        for (auto& Q : B.qj) Q.Pc = pc;
+    }
+    for (auto& Q : B.qj) {
+        const PairGeom& g = Q.qp.g;
         const int Pc = Q.Pc;
         const int nproj = B.poff.empty() ? 0 : B.poff.back();
         // band windows of a chunk: n (factorised VALU PAW term) and m (MFMA PAW term)
@@ -1014,7 +1051,6 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
                 mspan = std::max(mspan, mhi - mlo + 1);
             }
         }
-        (void)nn_max;
         W.tbuf = std::max(W.tbuf, (size_t)Pc * g.N3 * g.ncols * 2 * el);
         W.rho = std::max(W.rho, 2 * (size_t)Pc * g.NGp * el);
         const int lda = (Pc + 3) / 4 * 4;
@@ -1119,8 +1155,9 @@ int enqueue_orbitals(Batch& B, const rpa_states* s, void* d_map, const std::vect
 
 // rho for pairs [p0, p0 + np) of K into planar buffers rre/rim [np][NGp]
 template <typename T>
+// skip_xy: the chunk's x-y transform is already in tbuf (computed for another q-point of the same box)
 int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const cplx<T>* phikq, int p0, int np,
-                  T* rre, T* rim) {
+                  T* rre, T* rim, bool skip_xy = false) {
     rpa_ctx* c = B.c;
     const PairGeom& g = Q.qp.g;
     cplx<T>* tb = static_cast<cplx<T>*>(buf(B, "tbuf"));
@@ -1128,7 +1165,7 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
     const bool reg_xy = c->pair_reg && pair_xy_reg_supported<T>(g);
     const bool reg_z = c->pair_reg && pair_z_reg_supported<T>(g);
-    {
+    if (!skip_xy) {
         ProfScope ps_(c, S_PAIR_XY, B.s);
         if (reg_xy)
             HIP_TRY(launch_pair_xy_reg<T>(phik, phikq, pn, pm, np, g, tb, B.s));
@@ -1140,12 +1177,13 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     {
         ProfScope ps_(c, S_PAIR_Z, B.s);
         if (reg_z)
-            HIP_TRY(launch_pair_z_reg<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
-                                         static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz), rre,
-                                         rim, B.s));
+            HIP_TRY(launch_pair_z_reg<T>(tb, np, g, static_cast<const int32_t*>(Q.d_zc),
+                                         static_cast<const int32_t*>(Q.d_zcs), static_cast<const int32_t*>(Q.d_cg),
+                                         static_cast<const int32_t*>(Q.d_zckz), rre, rim, B.s));
         else
-            HIP_TRY(launch_pair_z_gather<T>(tb, np, g, static_cast<const int32_t*>(Q.d_cs),
-                                            static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
+            HIP_TRY(launch_pair_z_gather<T>(tb, np, g, static_cast<const int32_t*>(Q.d_zc),
+                                            static_cast<const int32_t*>(Q.d_zcs), static_cast<const int32_t*>(Q.d_cg),
+                                            static_cast<const int32_t*>(Q.d_zckz),
                                             static_cast<const cplx<T>*>(B.d_tw[2]), rre, rim, B.s));
     }
     const int nproj = nproj_total(K.k);
@@ -1327,35 +1365,50 @@ int enqueue_chi0(Batch& B) {
             if (rc) return rc;
         }
         const double prefac = K.k->weight / c->volume;
-        for (auto& Q : B.qj) {
-            if (!Q.uses(ik)) continue;
+        // one chunk of one q-point: pair densities (the x-y transform skipped when shared), weights, update
+        auto chunk = [&](QJob& Q, int p0, int np, bool skip_xy) -> int {
             const int Pc = Q.Pc;
             const int lda = (Pc + 3) / 4 * 4;
             T* rre = static_cast<T*>(buf(B, "rho"));
             T* rim = rre + (size_t)Pc * Q.qp.NGp;
             double* aw = static_cast<double*>(buf(B, "weights"));
+            int r = enqueue_pairs<T>(B, Q, K, (int)ik, phik, phikq, p0, np, rre, rim, skip_xy);
+            if (r) return r;
+            {
+                ProfScope ps_(c, S_WEIGHTS, B.s);
+                if (B.realfreq)
+                    HIP_TRY(launch_weights_real(
+                        static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
+                        static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
+                        static_cast<const int32_t*>(K.d_pn) + p0, static_cast<const int32_t*>(K.d_pm) + p0, np,
+                        static_cast<const double*>(B.d_om), B.nw_user, B.eta, prefac, aw, lda, B.s));
+                else
+                    HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk),
+                                           static_cast<const double*>(K.d_epskq),
+                                           static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
+                                           static_cast<const int32_t*>(K.d_pn) + p0,
+                                           static_cast<const int32_t*>(K.d_pm) + p0, np,
+                                           static_cast<const double*>(B.d_om), B.nw, prefac, aw, lda, B.s));
+            }
+            return enqueue_update<T>(B, Q, np, rre, rim, aw, lda);
+        };
+        if (B.share_xy) {
+            // chunk by chunk: the x-y transform once (with the first q-point), then every q-point's sphere
+            const int Pc = B.qj[0].Pc;
             for (int p0 = 0; p0 < P; p0 += Pc) {
                 const int np = std::min(Pc, P - p0);
-                rc = enqueue_pairs<T>(B, Q, K, (int)ik, phik, phikq, p0, np, rre, rim);
-                if (rc) return rc;
-                {
-                    ProfScope ps_(c, S_WEIGHTS, B.s);
-                    if (B.realfreq)
-                        HIP_TRY(launch_weights_real(
-                            static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
-                            static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
-                            static_cast<const int32_t*>(K.d_pn) + p0, static_cast<const int32_t*>(K.d_pm) + p0, np,
-                            static_cast<const double*>(B.d_om), B.nw_user, B.eta, prefac, aw, lda, B.s));
-                    else
-                        HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk),
-                                               static_cast<const double*>(K.d_epskq),
-                                               static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq),
-                                               static_cast<const int32_t*>(K.d_pn) + p0,
-                                               static_cast<const int32_t*>(K.d_pm) + p0, np,
-                                               static_cast<const double*>(B.d_om), B.nw, prefac, aw, lda, B.s));
+                for (size_t j = 0; j < B.qj.size(); ++j) {
+                    rc = chunk(B.qj[j], p0, np, j > 0);
+                    if (rc) return rc;
                 }
-                rc = enqueue_update<T>(B, Q, np, rre, rim, aw, lda);
-                if (rc) return rc;
+            }
+        } else {
+            for (auto& Q : B.qj) {
+                if (!Q.uses(ik)) continue;
+                for (int p0 = 0; p0 < P; p0 += Q.Pc) {
+                    rc = chunk(Q, p0, std::min(Q.Pc, P - p0), false);
+                    if (rc) return rc;
+                }
             }
         }
     }
@@ -1704,10 +1757,33 @@ int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, cons
     }
     // every q-point's plan, then the jobs in class order (leading dimension descending, caller's order
     // within a class); the uploads point into the jobs, so they are registered after the reordering
+    // q-points that share every (k, k+q) set share the product conj(phi_n) phi_m of each pair and its
+    // transform along x and y (Eq. fft: only the sphere differs from q to q), so the kept (m1, m2) box is the
+    // union of the spheres' boxes and the transform runs once per chunk for all of them
+    int ubox[4] = {0, 0, 0, 0};
+    B.share_xy = false;
+    if (!qk && nq > 1 && B.allow_share_xy) {
+        bool ok = true;
+        for (int j = 0; j < nq && ok; ++j) {
+            if (qs[j].NG <= 0 || !qs[j].gmiller) {
+                ok = false;
+                break;
+            }
+            int lo[3], hi[3];
+            sphere_box(&qs[j], lo, hi);
+            if (j == 0) {
+                ubox[0] = lo[0]; ubox[1] = hi[0]; ubox[2] = lo[1]; ubox[3] = hi[1];
+            } else {
+                ubox[0] = std::min(ubox[0], lo[0]); ubox[1] = std::max(ubox[1], hi[0]);
+                ubox[2] = std::min(ubox[2], lo[1]); ubox[3] = std::max(ubox[3], hi[1]);
+            }
+        }
+        B.share_xy = ok && ubox[1] - ubox[0] + 1 <= c->N[0] && ubox[3] - ubox[2] + 1 <= c->N[1];
+    }
     std::vector<QPlan> plans(nq);
     std::vector<int> order(nq);
     for (int j = 0; j < nq; ++j) {
-        rc = plan_q(c, &qs[j], plans[j], need_ec);
+        rc = plan_q(c, &qs[j], plans[j], need_ec, B.share_xy ? ubox : nullptr);
         if (rc) return rc;
         order[j] = j;
     }

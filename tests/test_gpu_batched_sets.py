@@ -62,3 +62,38 @@ def test_batched_sets_match_per_q_calls_and_oracle(rpa, prec):
         Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
         E, _, _ = oracle.ec_q(wl.A, wl.grid, ks, kqs, gm, Q, wl.paw.offsets, qp.q, wl.omega, wl.omega_weight)
         assert abs(e - E) < (1e-10 if prec == "fp64" else 1e-6), (e, E)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_shared_pair_transform_across_q(rpa, prec):
+    """q-points that share every state set share each chunk's x-y pair transform (one box covering all
+    spheres); with the same chunking as single-q calls the results agree with them to rounding (the wider
+    box can switch the y pass from quads of lanes to whole lines), and each q-point matches the oracle. Spheres of 9, 42 and 60 G-vectors, chunks of 7 pairs (several chunks,
+    a ragged last one)."""
+    wl = synth.tiny(grid=(12, 12, 12), L=(8.0, 8.5, 9.0), n_occ=3, n_unocc=9, target_ng=40)
+    Bm = oracle.reciprocal_rows(wl.A)
+    qpts = [synth.QPoint(q=f * Bm[0] + g * Bm[1] + h * Bm[2],
+                         ecut=synth.ecut_for_count(wl.A, f * Bm[0] + g * Bm[1] + h * Bm[2], n), weight=w)
+            for f, g, h, n, w in ((0.1, 0.0, 0.0, 40, 0.5), (0.3, 0.2, 0.1, 9, 0.3), (0.0, 0.3, 0.2, 60, 0.2))]
+    dev = "cuda:0"
+    ks = [rpa.States.from_synth(wl.kpoints[0], wl.paw, dev)]
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    qspecs = []
+    for qp in qpts:
+        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+        qspecs.append(rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight, device=dev))
+    ngs = sorted(q.NG for q in qspecs)
+    assert ngs[0] < ngs[1] < ngs[2]
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_chunk_pairs(7)
+        per_q = [float(ctx.ec(ks, ks, qs, fr, prec)[0].cpu()[0]) for qs in qspecs]
+        got = ctx.ec_batched(ks, ks, qspecs, fr, prec)[0].cpu().numpy()
+        ctx.check()
+    print(f"{prec}: per-q {per_q} batched {got[:3]}", flush=True)
+    assert np.allclose(got[:3], per_q, rtol=1e-12 if prec == "fp64" else 1e-6, atol=0)
+    for qp, e in zip(qpts, per_q):
+        gm = oracle.gsphere(wl.A, qp.q, qp.ecut)
+        Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
+        E, _, _ = oracle.ec_q(wl.A, wl.grid, wl.kpoints, wl.kpoints, gm, Q, wl.paw.offsets, qp.q, wl.omega,
+                              wl.omega_weight)
+        assert abs(e - E) < (1e-10 if prec == "fp64" else 1e-6), (e, E)

@@ -189,8 +189,9 @@ def test_not_positive_definite_is_reported(rpa):
 def test_stage_profiler(rpa):
     """The stage profiler the benchmark reads: every stage name is accepted, an unknown one is an input error;
     one batched split-precision call over two q-points times two packing groups and two rank-k launches (one
-    chunk per q), each with positive elapsed time, and one Cholesky stage; nothing is recorded after
-    profiling stops."""
+    chunk per q), each with positive elapsed time, one x-y pair transform (shared by the two q-points, whose
+    state sets are the same) and two z passes, and one Cholesky stage; nothing is recorded after profiling
+    stops."""
     wl = synth.config1(n_occ=2, n_unocc=20, which_q=(0, 1))
     qspecs = []
     for iq in range(2):
@@ -213,7 +214,7 @@ def test_stage_profiler(rpa):
     assert prof["herk"][1] == 2 and prof["herk"][0] > 0
     assert prof["split_pack"][1] == 2 and prof["split_pack"][0] > 0
     assert prof["cholesky"][1] == 1 and prof["cholesky"][0] > 0
-    assert prof["pair_xy"][1] >= 2
+    assert prof["pair_xy"][1] == 1 and prof["pair_z_gather"][1] == 2
     assert all(v[0] >= 0 for v in prof.values())
     assert all(v[1] == 0 for v in after.values())
 
@@ -327,7 +328,8 @@ def test_split_kernel_variants(rpa, variant, prec):
 @pytest.mark.parametrize("prec", ["fp64", "split_fp16"])
 def test_batched_graph_replays_match_per_q_calls(rpa, prec):
     """Several q-points in one call, captured into a graph and replayed three times with eager work and
-    synchronisations in between; every replay equals the per-q results, and the weighted sum is formed."""
+    synchronisations in between; every replay is bit-identical to the eager batched call, which agrees with
+    the per-q calls and the oracle, and the weighted sum is formed."""
     wl = synth.tiny(grid=(12, 12, 12), L=(8.0, 8.5, 9.0), n_occ=3, n_unocc=9, target_ng=40)
     Bm = 2 * np.pi * np.linalg.inv(wl.A).T
     qpts = [synth.QPoint(q=f * Bm[0] + g * Bm[1], ecut=synth.ecut_for_count(wl.A, f * Bm[0] + g * Bm[1], t),
@@ -348,8 +350,11 @@ def test_batched_graph_replays_match_per_q_calls(rpa, prec):
         ec0, F0 = ctx.ec_batched(ks, ks, qspecs, fr, prec, use_graph=False)
         ctx.check()
         eager = ec0.cpu().numpy().copy()
-        assert np.allclose(eager[:3], per_q, rtol=0, atol=1e-13)
-        assert abs(eager[3] - sum(q.weight * e for q, e in zip(qspecs, per_q))) < 1e-13
+        # the batch shares one x-y pair transform over the three spheres' box (a wider box can move the y
+        # pass from quads of lanes to whole lines: FP32 rounding, not bits, may differ from a single-q call)
+        rtol = 1e-12 if prec == "fp64" else 1e-6
+        assert np.allclose(eager[:3], per_q, rtol=rtol, atol=0)
+        assert abs(eager[3] - sum(q.weight * e for q, e in zip(qspecs, eager[:3]))) < 1e-13
         out = None
         for rep in range(3):
             out = ctx.ec_batched(ks, ks, qspecs, fr, prec, use_graph=True, out=out)
