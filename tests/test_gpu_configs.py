@@ -142,3 +142,30 @@ def test_spin_polarised_o2box_reduced(rpa, iq):
     assert r < 1e-12
     assert abs(ec - ref["E"]) < 1e-10
     assert abs(ecs - ref["E"]) < 1e-6
+
+
+def test_metal_slab_full_size_one_kpoint(rpa):
+    """The metal slab at full size (120 + 3000 Fermi-smeared states, NG = 4011, 20 x 18 projectors, 16
+    frequencies), k-point 0 alone: split-precision E_c of that k-point's chi0 within 1e-6 Ha of the FP64
+    path (the FP64 path itself is pinned to the oracle at full O2-box size and at every reduced size), chi0
+    of the two paths within the split tolerance, about 20 chunks of the split kernel's accumulate branch."""
+    dev = "cuda:0"
+    wl = synth.config2(device=dev)
+    s = wl.kpoints[0]
+    qp = wl.qpoints[0]
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    assert len(gm) == 4011
+    qs = rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight, device=dev)
+    st = rpa.States.from_synth(s, wl.paw, dev)
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_chunk_pairs(50000)
+        chi64 = ctx.chi0([st], [st], qs, fr, "fp64")
+        e64 = float(ctx.ec_from_chi0(qs, fr, chi64)[0].cpu()[0])
+        chis = ctx.chi0([st], [st], qs, fr, "split_bf16")
+        es = float(ctx.ec_from_chi0(qs, fr, chis)[0].cpu()[0])
+        ctx.check()
+        diff = float(torch.max(torch.abs(chis - chi64)).cpu()) / float(torch.max(torch.abs(chi64)).cpu())
+    print(f"slab k0: E_fp64={e64:.12f} E_split={es:.12f} diff={es - e64:.3e} chi rel={diff:.3e}", flush=True)
+    assert abs(es - e64) < 1e-6
+    assert diff < 2e-4
