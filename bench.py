@@ -26,7 +26,9 @@ of those same k-points (the whole q-point by default).
 16 + 800 states, NG ~ 1500, three q-points in one batched call per step), and
 --workload qmesh the batching form (64 q-points with log-uneven spheres, NG
 200-3000, on the slab cell at Gamma; one step = E_c of all 64 in one batched
-call, timed against a loop of single-q calls).
+call, timed against a loop of single-q calls), and --workload grad the
+differentiation form (E_c(q) and its gradient with respect to eigenvalues,
+coefficients and projections of all 16 + 800 states of the O2 box, FP64).
 """
 from __future__ import annotations
 
@@ -111,10 +113,37 @@ def _oracle_sample(path):
                       "NG": int(len(gm)), "chi0_max": float(np.abs(chi).max())}), flush=True)
 
 
-def cpu_baseline(wl, iq, band_stride, label):
+def _oracle_grad_sample(path):
+    """Child process: the FP64 oracle's E_c(q) and gradient (torch autograd on the CPU) of the sample saved
+    at `path`; prints one JSON line."""
+    import oracle
+    import oracle.grad as G
+    z = np.load(path)
+    A, grid, q, ecut = z["A"], tuple(int(x) for x in z["grid"]), z["q"], float(z["ecut"])
+
+    class S:
+        pass
+    s = S()
+    s.C, s.P, s.eps, s.f, s.miller = z["C"], z["P"], z["eps"], z["f"], z["miller"]
+    s.kpt, s.weight = z["kpt"], float(z["wk"])
+    omega, ow = z["omega"], z["omega_weight"]
+    times = []
+    for _ in range(int(z["repeats"])):
+        t0 = time.perf_counter()
+        gm = oracle.gsphere(A, q, ecut)
+        E, g = G.ec_and_grad(A, grid, s, s, gm, z["Q"], z["offsets"], q, omega, ow, False, (1.0, 0.0, 0.0), z["D"])
+        times.append(time.perf_counter() - t0)
+    P = int(oracle.pair_list(s.f, s.f)[0].size)
+    flops = 12.0 * len(gm) ** 2 * P * omega.size
+    print(json.dumps({"times": times, "flops": flops, "pairs": P, "bands": int(s.C.shape[0]), "NG": int(len(gm)),
+                      "ec": E}), flush=True)
+
+
+def cpu_baseline(wl, iq, band_stride, label, grad=False):
     """The FP64 oracle timed on the host on a band subset of k-point 0 (every band_stride-th band and all
     the transitions among them): median of 3 runs with every core, and one run in a child process pinned to
-    one CPU with one BLAS thread."""
+    one CPU with one BLAS thread. grad: E_c(q) and its gradient (the oracle's autograd reference) instead of
+    the chi0 build."""
     import tempfile
     import synth
     s = wl.kpoints[0]
@@ -126,11 +155,13 @@ def cpu_baseline(wl, iq, band_stride, label):
     os.close(fd)
     base = dict(A=wl.A, grid=np.asarray(wl.grid), q=qp.q, ecut=qp.ecut, miller=s.miller, C=s.C[keep],
                 P=s.P[keep], eps=s.eps[keep], f=s.f[keep], omega=wl.omega, wk=s.weight,
-                Q=synth.paw_q_table(wl.paw, wl.A, qp.q, gm), offsets=wl.paw.offsets)
+                Q=synth.paw_q_table(wl.paw, wl.A, qp.q, gm), offsets=wl.paw.offsets, kpt=s.kpt,
+                omega_weight=wl.omega_weight, D=synth.paw_d_table(wl.paw))
+    mode = "--oracle-grad-sample" if grad else "--oracle-sample"
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     try:
         np.savez(path, repeats=3, **base)
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", path],
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), mode, path],
                            capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(r.stderr[-2000:])
@@ -140,7 +171,7 @@ def cpu_baseline(wl, iq, band_stride, label):
             np.savez(path, repeats=1, **base)
             cpu0 = sorted(os.sched_getaffinity(0))[0]
             env1 = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-            r1 = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", path],
+            r1 = subprocess.run([sys.executable, os.path.abspath(__file__), mode, path],
                                 capture_output=True, text=True, env=env1,
                                 preexec_fn=lambda: os.sched_setaffinity(0, {cpu0}))
             if r1.returncode == 0:
@@ -149,9 +180,11 @@ def cpu_baseline(wl, iq, band_stride, label):
         os.unlink(path)
     med = float(np.median(allc["times"]))
     out = {"value": allc["flops"] / med / 1e12, "unit": "TFLOP/s", "cores": int(ncpu), "kind": "oracle",
-           "sample": f"{label}: chi0 build (orbitals, pair densities, PAW, weights, grouped update) of the "
-                     f"{allc['pairs']} transitions among {allc['bands']} bands (every {band_stride}th band of "
-                     f"k-point 0), NG = {allc['NG']}, {wl.omega.size} frequencies; median of "
+           "sample": f"{label}: "
+                     + ("E_c(q) and its gradient (torch autograd reference, eigenvalue log-determinant)"
+                        if grad else "chi0 build (orbitals, pair densities, PAW, weights, grouped update)")
+                     + f" of the {allc['pairs']} transitions among {allc['bands']} bands (every {band_stride}th "
+                     f"band of k-point 0), NG = {allc['NG']}, {wl.omega.size} frequencies; median of "
                      f"{len(allc['times'])} runs {med:.1f} s",
            "seconds_median": med, "seconds_runs": allc["times"]}
     if one:
@@ -272,13 +305,13 @@ def run_slab(args, torch, rpa, synth):
                 "ms_per_k_step": ms_step64, "ms_per_q": nk * ms_step64 + ms_ec, "kpoints_timed": n64,
                 "herk_tflops": herk64_flops / (herk64_ms * 1e-3) / 1e12,
                 "herk_frac_of_fp64_peak": herk64_flops / (herk64_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
-                "stage_ms_per_k": {k: v[0] / n64 for k, v in prof64.items()},
+                "stage_ms_per_k": {k: v[0] / n64 for k, v in prof64.items() if v[1]},
                 "ec_partial": ec64, "ec_split_partial": ecs, "ec_split_minus_fp64_ha": ecs - ec64}
         log(f"fp64: {ms_step64:.0f} ms per k-step; E_c over k-points 0..{n64 - 1}: fp64 {ec64:.12f} "
             f"split {ecs:.12f} diff {ecs - ec64:.3e} Ha")
 
     # roofline of the split rank-k kernel over the timed steps
-    stage_ms = {k: v[0] / args.steps for k, v in prof.items()}
+    stage_ms = {k: v[0] / args.steps for k, v in prof.items() if v[1]}
     dominant = max(stage_ms, key=stage_ms.get)
     herk_ms, herk_n = prof["herk"]
     achieved = flops_timed / (herk_ms * 1e-3) / 1e12
@@ -372,9 +405,10 @@ def run_o2box(args, torch, rpa, synth):
         "ms_per_q": ms_step / len(NGs), "ec_split": ec_split, "ec_fp64": ec64,
         "ec_split_minus_fp64_ha": [a - b for a, b in zip(ec_split, ec64)],
         "speedup_vs_fp64": ms_step64 / ms_step,
-        "stage_ms": {k: v[0] / args.steps for k, v in prof.items()},
+        "stage_ms": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
         "fp64": {"value": flops_step * args.steps / dt64 / 1e12, "unit": "TFLOP/s", "ms_per_step": ms_step64,
-                 "ms_per_q": ms_step64 / len(NGs), "stage_ms": {k: v[0] / args.steps for k, v in prof64.items()}},
+                 "ms_per_q": ms_step64 / len(NGs),
+                 "stage_ms": {k: v[0] / args.steps for k, v in prof64.items() if v[1]}},
         "roofline": {"kernel": f"{kname} (grouped complex rank-k update of chi0, split {prec[6:]} hi/lo)",
                      "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(kname, ksrc, "o2box"),
@@ -464,15 +498,92 @@ def run_qmesh(args, torch, rpa, synth):
     return out, wl
 
 
+# --------------------------------------------------------------------------------------- gradient
+def run_grad(args, torch, rpa, synth):
+    """The differentiation form at O2-in-box size: E_c(q) and its gradient with respect to the eigenvalues,
+    the plane-wave coefficients and the PAW projections of all 16 + 800 states at q = 0.1 x 2pi/12 (NG
+    1500, 16 frequencies, FP64). One step = one rpa_ec_backward call: the FP64 forward pass (chi0, Cholesky),
+    (1 - K)^-1 and W(omega), then per pair chunk the recomputed pair densities, the products W(omega) rho,
+    the PAW, optical and FFT adjoints, and the coefficient transforms. Timed beside the FP64 forward call."""
+    dev = "cuda:0"
+    wl = synth.config1(which_q=(1,))
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    ks = [rpa.States.from_synth(s, wl.paw, dev) for s in wl.kpoints]
+    qp = wl.qpoints[0]
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    qs = rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), optical=qp.optical, qhat=qp.qhat,
+                   Dpaw=synth.paw_d_table(wl.paw), weight=qp.weight, device=dev)
+    P = npairs(wl.kpoints[0], wl.kpoints[0])
+    NG, nw = qs.NG, fr.nw
+    flops_chi, flops_wrho = 4.0 * NG * NG * P * nw, 8.0 * NG * NG * P * nw
+    ctx = rpa.Context(wl.A, wl.grid, device=0)
+
+    def grads(n, profile=False):
+        ec = g = None
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            ec, g = ctx.ec_backward(ks[0], ks[0], qs, fr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.check()
+        prof = ctx.profile_get() if profile else None
+        ctx.profile(False)
+        return dt, ec, g, prof
+
+    def forward(n):
+        e = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            e, _ = ctx.ec(ks, ks, qs, fr, "fp64")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e
+
+    grads(args.warmup)
+    dt, ec, g, prof = grads(args.steps, True)
+    forward(1)
+    dtf, ef = forward(args.steps)
+    ms, msf = dt / args.steps * 1e3, dtf / args.steps * 1e3
+    gemm_ms, gemm_n = prof["adjoint_gemm"]
+    achieved = flops_wrho * args.steps / (gemm_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": (flops_chi + flops_wrho) * args.steps / dt / 1e12, "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "gradient of E_c(q) at O2-in-box size: 12x12x13 bohr, 48^3 grid, Gamma, 16+800 "
+                               "states, 2x13 PAW projectors, q = 0.1 x 2pi/12, 16 imaginary frequencies; one step "
+                               "= E_c(q) and dE_c/d(eps, C, P) of all states (FP64 forward and adjoint)",
+                   "NG": NG, "pairs": P, "nw": nw},
+        "value_counts": "chi0 (4 NG^2 P nw) + the adjoint's W(omega) rho products (8 NG^2 P nw) per gradient",
+        "ms_per_gradient": ms, "ms_forward_fp64": msf, "gradient_over_forward": ms / msf,
+        "ec_backward": float(ec.cpu()[0]), "ec_forward": float(ef.cpu()[0]),
+        "grad_norms": {k: float(v.abs().square().sum().sqrt()) for k, v in g.items()},
+        "stage_ms": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+        "roofline": {"kernel": "k_gemm_c64 (the adjoint's products W(omega) rho, complex FP64 MFMA)",
+                     "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                     "avg_launch_ms": gemm_ms / max(gemm_n, 1), "launches": gemm_n,
+                     "algorithmic_flops_per_launch": flops_wrho * args.steps / max(gemm_n, 1)},
+    }
+    ctx.close()
+    return out, wl
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--oracle-sample":
         _oracle_sample(sys.argv[2])
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--oracle-grad-sample":
+        _oracle_grad_sample(sys.argv[2])
         return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8, help="timed steps (slab: one k-point each)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="slab", choices=["slab", "o2box", "qmesh"])
+    ap.add_argument("--workload", default="slab", choices=["slab", "o2box", "qmesh", "grad"])
     ap.add_argument("--qmesh-bands", type=int, nargs=2, default=(8, 60), metavar=("OCC", "UNOCC"),
                     help="qmesh: occupied and empty states at Gamma (the full form is 60 1500)")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "split_fp16"])
@@ -502,12 +613,15 @@ def main():
     elif args.workload == "qmesh":
         out, wl = run_qmesh(args, torch, rpa, synth)
         band_stride, label = 4, "q mesh q-point 0"
+    elif args.workload == "grad":
+        out, wl = run_grad(args, torch, rpa, synth)
+        band_stride, label = 16, "gradient at O2-in-box size, q = 0.1"
     else:
         out, wl = run_o2box(args, torch, rpa, synth)
         band_stride, label = 4, "O2-in-box q-point 0"
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(wl, 0, band_stride, label)
+        out["cpu_baseline"] = cpu_baseline(wl, 0, band_stride, label, grad=args.workload == "grad")
     print(json.dumps(out), flush=True)
 
 

@@ -381,8 +381,12 @@ int rpa_check(rpa_ctx* ctx, void* stream);
  * groups of one stage: "orbitals", "pair_xy", "pair_z_gather", "paw",
  * "optical", "weights", "split_pack" (the split precisions' hi/lo packing and
  * FP16 scales ahead of each rank-k update), "herk" (the rank-k update kernel of
- * chi0 alone, one launch per pair chunk and frequency set) or "cholesky" (the
- * whole E_c stage).
+ * chi0 alone, one launch per pair chunk and frequency set), "cholesky" (the
+ * whole E_c stage), and for rpa_ec_backward "adjoint_inverse" ((1 - K)^-1 from
+ * the Cholesky factor and W(omega)), "adjoint_gemm" (the products W(omega) rho,
+ * one per pair chunk and frequency), "adjoint_pairs" (the z and x-y adjoint
+ * transforms with the orbital products) or "adjoint_rest" (weights, energies,
+ * PAW and optical adjoints, the coefficient transforms).
  * RPA_ERR_INPUT for an unknown stage name. */
 int rpa_profile(rpa_ctx* ctx, int enable);
 int rpa_profile_get(rpa_ctx* ctx, const char* stage, double* ms, long long* launches);

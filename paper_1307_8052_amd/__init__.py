@@ -465,7 +465,8 @@ class Context:
                self._h)
         return ec, F
 
-    STAGES = ("orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights", "split_pack", "herk", "cholesky")
+    STAGES = ("orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights", "split_pack", "herk", "cholesky",
+              "adjoint_inverse", "adjoint_gemm", "adjoint_pairs", "adjoint_rest")
 
     def profile(self, enable: bool = True):
         """Start (or stop) per-stage HIP-event timing; totals are cleared."""

@@ -246,6 +246,16 @@ hipError_t launch_xyadj(const cplx<double>* tadj, const PairGeom& g, const int32
                         const int32_t* other, const cplx<double>* phio, int band0, int nb, int side,
                         const int32_t* kx, const int32_t* ky, const cplx<double>* tw1, const cplx<double>* tw2,
                         cplx<double>* phibar, hipStream_t s);
+// Register form of the x-y adjoint for square grids of a register length divisible by 4 (FP64): seg holds
+// per segment (owner, first, end into list, slot); owners with several segments write partial
+// [slot][N3][N1 N2], which launch_xyadj_reduce adds into phibar (own[j]: such an owner, its slots
+// [ostart[j], ostart[j + 1])).
+bool xyadj_reg_supported(const PairGeom& g);
+hipError_t launch_xyadj_reg(const cplx<double>* tadj, const PairGeom& g, const int32_t* seg, int nseg,
+                            const int32_t* list, const int32_t* other, const cplx<double>* phio, int band0, int side,
+                            cplx<double>* phibar, cplx<double>* partial, hipStream_t s);
+hipError_t launch_xyadj_reduce(const cplx<double>* partial, size_t vol, const int32_t* own, const int32_t* ostart,
+                               int nown, int band0, cplx<double>* phibar, hipStream_t s);
 hipError_t launch_gather_c(const cplx<double>* ph, size_t vol, const int32_t* map, int nQ, int nb, double* dC,
                            hipStream_t s);
 hipError_t launch_zero_d(double* p, size_t n, hipStream_t s);

@@ -66,17 +66,14 @@ __device__ __forceinline__ cplx<T> quad_xchg(cplx<T> v) {
     return mk(quad_xchg<CTRL>(v.x), quad_xchg<CTRL>(v.y));
 }
 
-// Forward transform of one column of N (stride LD) by the four lanes of a quad: lane r takes the samples
-// 4 i + r and transforms them (length N/4), multiplies output k by w^(r k) (w = exp(-2 pi i / N)), and a
-// four-point transform across the quad (two lane exchanges) leaves outputs k + (N/4) s in lane r with
-// s = (r >> 1) + 2 (r & 1). A kept column thus costs a quarter of a whole-line transform per lane.
-template <typename T, int N, int LD>
-__device__ __forceinline__ void fft_column_quad(cplx<T>* col, int r) {
+// Forward transform of N samples spread over the four lanes of a quad: lane r holds the samples 4 i + r in
+// v[i] and transforms them (length N/4), multiplies output k by w^(r k) (w = exp(-2 pi i / N)), and a
+// four-point transform across the quad (two lane exchanges) leaves outputs k + (N/4) s in v[k] of lane r;
+// the return value is s = (r >> 1) + 2 (r & 1).
+template <typename T, int N>
+__device__ __forceinline__ int fft_quad_core(cplx<T> (&v)[N / 4], int r) {
     constexpr int M = N / 4;
     constexpr Roots<N> W{};
-    cplx<T> v[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) v[i] = col[(4 * i + r) * LD];
     RegFft<M, -1, T>::run(v);
 #pragma unroll
     for (int k = 1; k < M; ++k) {
@@ -94,9 +91,39 @@ __device__ __forceinline__ void fft_column_quad(cplx<T>* col, int r) {
         p = quad_xchg<0xB1>(u);
         v[k] = (r & 1) ? p - u : u + p;
     }
-    const int s = (r >> 1) + 2 * (r & 1);
+    return (r >> 1) + 2 * (r & 1);
+}
+
+// Forward transform of one column of N (stride LD) by the four lanes of a quad, in place. A kept column
+// thus costs a quarter of a whole-line transform per lane.
+template <typename T, int N, int LD>
+__device__ __forceinline__ void fft_column_quad(cplx<T>* col, int r) {
+    constexpr int M = N / 4;
+    cplx<T> v[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) v[i] = col[(4 * i + r) * LD];
+    const int s = fft_quad_core<T, N>(v, r);
 #pragma unroll
     for (int k = 0; k < M; ++k) col[(k + M * s) * LD] = v[k];
+}
+
+// Inverse transform (sign +1) of one line of N (stride STR) by a quad, in place, as conj(F(conj x)). The
+// samples i with (i - lo) mod N >= cnt are read as zero: the entries outside a kept range of cnt indices
+// starting at lo, which may hold anything.
+template <typename T, int N, int STR>
+__device__ __forceinline__ void ifft_line_quad(cplx<T>* line, int r, int lo, int cnt) {
+    constexpr int M = N / 4;
+    cplx<T> v[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        int d = 4 * i + r - lo;
+        if (d < 0) d += N;
+        const cplx<T> x = line[(4 * i + r) * STR];
+        v[i] = d < cnt ? mk(x.x, -x.y) : mk(T(0), T(0));
+    }
+    const int s = fft_quad_core<T, N>(v, r);
+#pragma unroll
+    for (int k = 0; k < M; ++k) line[(k + M * s) * STR] = mk(v[k].x, -v[k].y);
 }
 
 template <typename T, int N1, int N2>
@@ -259,6 +286,101 @@ __global__ __launch_bounds__(256) void k_pair_z_reg(const cplx<T>* __restrict__ 
             ore[gi] = T(0);
             oim[gi] = T(0);
         }
+    }
+}
+
+// Adjoint of the x-y pass of k_pair_xy_reg, with the product by the other orbital and the sum over the
+// pairs of one owner band (FP64 gradients). A workgroup takes one segment of an owner's pairs on one
+// z-plane; for each pair the kept K2 x K1 block of that plane's adjoint spectrum (tadj [pair][z][K2][K1])
+// goes into its place in the plane, each kept x-frequency column is taken back along y (kept rows only
+// read) and every row along x (kept columns only read), both by quads of lanes, and the result xbar is
+// multiplied by the other band's orbital:
+//   side 1 (owner m): acc += phi_n xbar,   side 0 (owner n): acc += phi_m conj(xbar).
+// seg holds per segment (owner, first, end into list, slot): the sum is added into phibar[band0 + owner]
+// where the owner has this one segment (slot < 0), else written to partial [slot][z][plane] and added by
+// k_xyadj_reduce. Tasks run z-plane by z-plane, so the orbital planes they read meet in L2.
+template <typename T, int N>
+constexpr int adj_threads() {
+    return (4 * N + 63) / 64 * 64;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((adj_threads<T, N>())) void k_xyadj_reg(const cplx<T>* __restrict__ tadj, PairGeom g,
+                                                     const int32_t* __restrict__ seg, int nseg,
+                                                     const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ other,
+                                                     const cplx<T>* __restrict__ phio, int band0, int side,
+                                                     cplx<T>* __restrict__ phibar, cplx<T>* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(smem);
+    constexpr int NT = adj_threads<T, N>(), LD = N + 1, plane = N * N, kA = (plane + NT - 1) / NT;
+    // each XCD (workgroup w runs on XCD w % 8) takes a contiguous range of tasks t = z nseg + segment
+    const unsigned ntask = gridDim.x, w = blockIdx.x;
+    const unsigned xcd = w & 7u, q = ntask >> 3, rq = ntask & 7u;
+    const unsigned t = xcd * q + min(xcd, rq) + (w >> 3);
+    const int z = (int)(t / (unsigned)nseg), sgi = (int)(t - (unsigned)z * nseg);
+    const int owner = seg[4 * sgi], e0 = seg[4 * sgi + 1], e1 = seg[4 * sgi + 2], slot = seg[4 * sgi + 3];
+    const int K1 = g.K1, K2 = g.K2, kk = K1 * K2;
+    const size_t vol = (size_t)plane * g.N3;
+    const int l = threadIdx.x;
+    cplx<T> acc[kA];
+#pragma unroll
+    for (int a = 0; a < kA; ++a) acc[a] = mk(T(0), T(0));
+    for (int e = e0; e < e1; ++e) {
+        const int p = list[e];
+        const cplx<T>* src = tadj + ((size_t)p * g.N3 + z) * kk;
+        __syncthreads();  // the previous pair's product has read the plane
+        for (int f = l; f < kk; f += NT) {
+            const int iy = f / K1, ix = f - iy * K1;
+            int kx = g.x0 + ix, ky = g.y0 + iy;
+            if (kx >= N) kx -= N;
+            if (ky >= N) ky -= N;
+            X[ky * LD + kx] = src[f];
+        }
+        __syncthreads();
+        if (l < 4 * K1) {
+            int kx = g.x0 + (l >> 2);
+            if (kx >= N) kx -= N;
+            ifft_line_quad<T, N, LD>(X + kx, l & 3, g.y0, K2);
+        }
+        __syncthreads();
+        if (l < 4 * N) ifft_line_quad<T, N, 1>(X + (l >> 2) * LD, l & 3, g.x0, K1);
+        __syncthreads();
+        // the other band's orbital on this plane
+        const cplx<T>* ph = phio + (size_t)other[p] * vol + (size_t)z * plane;
+        cplx<T> o[kA];
+#pragma unroll
+        for (int a = 0; a < kA; ++a) o[a] = ph[min(l + a * NT, plane - 1)];
+#pragma unroll
+        for (int a = 0; a < kA; ++a) {
+            const int f = l + a * NT;
+            if (f < plane) {
+                const cplx<T> xb = X[(f / N) * LD + f % N];
+                acc[a] = acc[a] + (side == 1 ? o[a] * xb : o[a] * conj(xb));
+            }
+        }
+    }
+    cplx<T>* out = slot < 0 ? phibar + (size_t)(band0 + owner) * vol + (size_t)z * plane
+                            : partial + ((size_t)slot * g.N3 + z) * plane;
+#pragma unroll
+    for (int a = 0; a < kA; ++a) {
+        const int f = l + a * NT;
+        if (f < plane) out[f] = slot < 0 ? out[f] + acc[a] : acc[a];
+    }
+}
+
+// phibar[band0 + own[j]] += the sum of its partial slots [ostart[j], ostart[j + 1]), in slot order
+template <typename T>
+__global__ __launch_bounds__(256) void k_xyadj_reduce(const cplx<T>* __restrict__ partial, size_t vol,
+                                                      const int32_t* __restrict__ own,
+                                                      const int32_t* __restrict__ ostart, int band0,
+                                                      cplx<T>* __restrict__ phibar) {
+    const int j = blockIdx.y, s0 = ostart[j], s1 = ostart[j + 1];
+    cplx<T>* out = phibar + (size_t)(band0 + own[j]) * vol;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < vol; i += (size_t)gridDim.x * blockDim.x) {
+        cplx<T> v = out[i];
+        for (int s = s0; s < s1; ++s) v = v + partial[(size_t)s * vol + i];
+        out[i] = v;
     }
 }
 
@@ -472,6 +594,53 @@ hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g,
 #undef RPA_CASE
         default: return hipErrorNotSupported;
     }
+    return hipGetLastError();
+}
+
+namespace {
+template <int L>
+hipError_t xyadj_case(long long tasks, const cplx<double>* tadj, const PairGeom& g, const int32_t* seg, int nseg,
+                      const int32_t* list, const int32_t* other, const cplx<double>* phio, int band0, int side,
+                      cplx<double>* phibar, cplx<double>* partial, hipStream_t s) {
+    if constexpr (L % 4 == 0 && L <= 64) {
+        const size_t lds = (size_t)L * (L + 1) * sizeof(cplx<double>);
+        hipLaunchKernelGGL((k_xyadj_reg<double, L>), dim3((unsigned)tasks), dim3(adj_threads<double, L>()), lds, s,
+                           tadj, g, seg, nseg, list, other, phio, band0, side, phibar, partial);
+        return hipGetLastError();
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+}  // namespace
+
+bool xyadj_reg_supported(const PairGeom& g) {
+    if (g.N1 != g.N2 || g.N1 % 4 != 0 || !reg_size(g.N1) || g.N1 > 64) return false;
+    return g.K1 >= 1 && g.K1 <= g.N1 && g.K2 >= 1 && g.K2 <= g.N2;
+}
+
+hipError_t launch_xyadj_reg(const cplx<double>* tadj, const PairGeom& g, const int32_t* seg, int nseg,
+                            const int32_t* list, const int32_t* other, const cplx<double>* phio, int band0, int side,
+                            cplx<double>* phibar, cplx<double>* partial, hipStream_t s) {
+    if (!nseg) return hipSuccess;
+    if (!xyadj_reg_supported(g)) return hipErrorNotSupported;
+    const long long tasks = (long long)nseg * g.N3;
+    if (tasks > 0x7fffffffLL) return hipErrorInvalidValue;
+    switch (g.N1) {
+#define RPA_CASE(L)                                                                                             \
+    case L:                                                                                                     \
+        return xyadj_case<L>(tasks, tadj, g, seg, nseg, list, other, phio, band0, side, phibar, partial, s);
+        RPA_REG_SIZES(RPA_CASE)
+#undef RPA_CASE
+        default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t launch_xyadj_reduce(const cplx<double>* partial, size_t vol, const int32_t* own, const int32_t* ostart,
+                               int nown, int band0, cplx<double>* phibar, hipStream_t s) {
+    if (nown <= 0) return hipSuccess;
+    const unsigned bx = (unsigned)std::min<size_t>((vol + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_xyadj_reduce<double>, dim3(bx, (unsigned)nown), dim3(256), 0, s, partial, vol, own, ostart,
+                       band0, phibar);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -132,9 +133,13 @@ struct rpa_ctx {
 namespace {
 
 // ---------------------------------------------------------------- profiler
-enum Stage { S_ORB = 0, S_PAIR_XY, S_PAIR_Z, S_PAW, S_OPTICAL, S_WEIGHTS, S_PACK, S_HERK, S_CHOL, S_OTHER, S_COUNT };
+enum Stage {
+    S_ORB = 0, S_PAIR_XY, S_PAIR_Z, S_PAW, S_OPTICAL, S_WEIGHTS, S_PACK, S_HERK, S_CHOL,
+    S_BW_INV, S_BW_GEMM, S_BW_PAIRS, S_BW_REST, S_COUNT
+};
 const char* kStageNames[S_COUNT] = {"orbitals", "pair_xy", "pair_z_gather", "paw", "optical", "weights",
-                                    "split_pack", "herk", "cholesky", "other"};
+                                    "split_pack", "herk", "cholesky", "adjoint_inverse", "adjoint_gemm",
+                                    "adjoint_pairs", "adjoint_rest"};
 
 hipEvent_t prof_event(rpa_ctx* c) {
     if (!c->pool.empty()) {
@@ -1831,9 +1836,51 @@ Csr group_pairs(const std::vector<int32_t>& key, int p0, int np, int lo, int hi,
     return c;
 }
 
+// The owner groups of a chunk cut into segments of at most sg pairs for the register x-y adjoint: one
+// workgroup per segment and z-plane. An owner with several segments sends each to a partial slot, which the
+// reduce kernel adds in afterwards (in slot order, so the result does not depend on the schedule).
+struct SegTab {
+    std::vector<int32_t> seg;          // per segment: owner, first, end (into the group's list), slot or -1
+    std::vector<int32_t> own, ostart;  // owners with several segments, and the ranges of their slots
+    int nseg = 0, nslots = 0;
+    void *d_seg = nullptr, *d_own = nullptr, *d_ostart = nullptr;
+};
+
+int count_slots(const Csr& c, int sg) {
+    int n = 0;
+    for (size_t b = 0; b + 1 < c.start.size(); ++b) {
+        const int cnt = c.start[b + 1] - c.start[b];
+        if (cnt > sg) n += (cnt + sg - 1) / sg;
+    }
+    return n;
+}
+
+// segments of at most 16 pairs, longer where the partial slots would pass slot_cap
+SegTab make_segments(const Csr& c, int slot_cap) {
+    int sg = 16;
+    while (count_slots(c, sg) > slot_cap) sg *= 2;
+    SegTab t;
+    t.ostart.push_back(0);
+    for (size_t b = 0; b + 1 < c.start.size(); ++b) {
+        const int e0 = c.start[b], e1 = c.start[b + 1], cnt = e1 - e0;
+        if (cnt <= 0) continue;
+        const bool split = cnt > sg;
+        for (int e = e0; e < e1; e += sg) {
+            t.seg.insert(t.seg.end(), {(int32_t)b, e, std::min(e + sg, e1), split ? t.nslots++ : -1});
+            t.nseg++;
+        }
+        if (split) {
+            t.own.push_back((int32_t)b);
+            t.ostart.push_back(t.nslots);
+        }
+    }
+    return t;
+}
+
 struct BwChunk {
     int p0, np, nlo, nhi, mlo, mhi;
     Csr byn, bym;
+    SegTab sn, sm;
     void *d_ns = nullptr, *d_nl = nullptr, *d_ms = nullptr, *d_ml = nullptr;
 };
 
@@ -1867,6 +1914,10 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
     std::vector<BwSet> sets(nks);
     int maxm = 1, maxn = 1, maxP = 1;
     size_t maxphib = 1;
+    // register x-y adjoint: partial slots of one orbital volume each, at most about 2 GiB of them
+    const bool reg_adj = c->pair_reg && xyadj_reg_supported(g);
+    const int slot_cap = (int)std::max<size_t>(1, ((size_t)2 << 30) / (vol * sizeof(cplx<double>)));
+    int maxslots = 1;
     for (size_t ik = 0; ik < nks; ++ik) {
         KSet& K = B.ks[ik];
         BwSet& S = sets[ik];
@@ -1887,6 +1938,11 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
             }
             x.byn = group_pairs(K.pn, p0, x.np, x.nlo, x.nhi, true);
             x.bym = group_pairs(K.pm, p0, x.np, x.mlo, x.mhi, true);
+            if (reg_adj) {
+                x.sn = make_segments(x.byn, slot_cap);
+                x.sm = make_segments(x.bym, slot_cap);
+                maxslots = std::max({maxslots, x.sn.nslots, x.sm.nslots});
+            }
             maxm = std::max(maxm, x.mhi - x.mlo + 1);
             maxn = std::max(maxn, x.nhi - x.nlo + 1);
             S.ch.push_back(std::move(x));
@@ -1899,7 +1955,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
 
     // buffers (sized for every set)
     const size_t mat = (size_t)nw * NGp * NGp;
-    void *pB, *pX, *pL, *pY, *pG, *pdE, *pu, *pcw, *pZ, *pU, *pgn, *pT, *pPb;
+    void *pB, *pX, *pL, *pY, *pG, *pdE, *pu, *pcw, *pZ, *pU, *pgn, *pT, *pPb, *pPart;
     struct NB {
         const char* n;
         size_t b;
@@ -1910,7 +1966,8 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                 {"bw_dEda", (size_t)nw * ((Pc + 3) / 4 * 4) * 8, &pdE}, {"bw_u", (size_t)maxP * 8, &pu},
                 {"bw_cw", 64 * 8, &pcw}, {"bw_Z", 4 * (size_t)Pc * std::max(nproj, 1) * 8, &pZ},
                 {"bw_U", 2 * (size_t)maxm * std::max(nproj, 1) * NGp * 8, &pU}, {"bw_gnum", 2 * (size_t)Pc * 8, &pgn},
-                {"bw_tadj", (size_t)Pc * g.N3 * g.ncols * 16, &pT}, {"bw_phibar", maxphib * 16, &pPb}};
+                {"bw_tadj", (size_t)Pc * g.N3 * g.ncols * 16, &pT}, {"bw_phibar", maxphib * 16, &pPb},
+                {"bw_part", reg_adj ? (size_t)maxslots * vol * 16 : 16, &pPart}};
     for (auto& e : list) {
         int rc = get_buf(c, e.n, e.b, B.s, e.p);
         if (rc) return rc;
@@ -1927,6 +1984,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
     double *Ur = static_cast<double*>(pU), *Ui = Ur + (size_t)maxm * std::max(nproj, 1) * NGp;
     double* gnum = static_cast<double*>(pgn);
     cplx<double>* tadj = static_cast<cplx<double>*>(pT);
+    cplx<double>* part = static_cast<cplx<double>*>(pPart);
     (void)maxn;
 
     // forward: chi0, E_c, and the factor L with its inverted diagonal blocks
@@ -1937,7 +1995,8 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
     rc = enqueue_ec_all(B, false, nullptr, Lb);
     if (rc) return rc;
     remember_fail_flags(B);
-    ProfScope ps_(c, S_OTHER, B.s);
+    {
+    ProfScope ps_(c, S_BW_INV, B.s);
     // X = L^-1 by blocked substitution on the identity, then (1 - K)^-1 = X^H X
     HIP_TRY(launch_identity(Br_, Bi_, NGp, NGp, nw, B.s));
     HIP_TRY(launch_zero_d(Xr, 2 * mat, B.s));  // columns right of each block row stay zero
@@ -1975,6 +2034,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
     }
     HIP_TRY(launch_build_w(Br_, Bi_, NG, NGp, nw, static_cast<const double*>(Q.d_vs), B.s));
     HIP_TRY(launch_freq_coeffs(dEc, static_cast<const double*>(B.d_ow), nw, cw, B.s));
+    }
 
     const int lda = (Pc + 3) / 4 * 4;
     double* rre = static_cast<double*>(buf(B, "rho"));
@@ -1993,6 +2053,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         double* dC_kq = same ? dC_k : outkq[ik].dC;
         double* dP_kq = same ? dP_k : outkq[ik].dP;
         // this set's outputs start at zero (a set with no transitions keeps a zero gradient)
+        std::optional<ProfScope> pz_(std::in_place, c, S_BW_REST, B.s);
         HIP_TRY(launch_zero_d(deps_k, nbk, B.s));
         HIP_TRY(launch_zero_d(dC_k, 2 * (size_t)nbk * K.k->nQ, B.s));
         if (nproj) HIP_TRY(launch_zero_d(dP_k, 2 * (size_t)nbk * nproj, B.s));
@@ -2008,6 +2069,15 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
             up.add(x.byn.list, &x.d_nl);
             up.add(x.bym.start, &x.d_ms);
             up.add(x.bym.list, &x.d_ml);
+            if (reg_adj) {
+                for (SegTab* t : {&x.sn, &x.sm}) {
+                    up.add(t->seg, &t->d_seg);
+                    if (!t->own.empty()) {
+                        up.add(t->own, &t->d_own);
+                        up.add(t->ostart, &t->d_ostart);
+                    }
+                }
+            }
         }
         up.add(S.gn.start, &S.d_gns);
         up.add(S.gn.list, &S.d_gnl);
@@ -2019,6 +2089,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         cplx<double>* phib_kq = same ? phib_k : phib_k + (size_t)nbk * vol;
         HIP_TRY(launch_zero_d(reinterpret_cast<double*>(phib_k), 2 * (size_t)(nbk + (same ? 0 : nbq)) * vol, B.s));
         HIP_TRY(launch_zero_d(u, std::max(P, 1), B.s));
+        pz_.reset();
         // this set's orbitals (the forward pass left those of the last set in the buffers)
         cplx<double>* phik_c = nullptr;
         cplx<double>* phikq_c = nullptr;
@@ -2040,10 +2111,12 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
             rc = enqueue_pairs<double>(B, Q, K, (int)ik, reinterpret_cast<const cplx<double>*>(phik),
                                        reinterpret_cast<const cplx<double>*>(phikq), p0, np, rre, rim);
             if (rc) return rc;
+            std::optional<ProfScope> pr_(std::in_place, c, S_BW_REST, B.s);
             HIP_TRY(launch_weights(static_cast<const double*>(K.d_epsk), static_cast<const double*>(K.d_epskq),
                                    static_cast<const double*>(K.d_fk), static_cast<const double*>(K.d_fkq), pn, pm,
                                    np, static_cast<const double*>(B.d_om), nw, prefac, aw, lda, B.s));
             HIP_TRY(launch_zero_d(gr, 2 * (size_t)Pc * NGp, B.s));
+            pr_.reset();
             for (int w = 0; w < nw; ++w) {
                 GemmArgs gy{};
                 gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = 1;
@@ -2051,9 +2124,14 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                 gy.Br = Br_ + (size_t)w * NGp * NGp; gy.Bi = Bi_ + (size_t)w * NGp * NGp; gy.sB = 0; gy.bK = 1;
                 gy.bJ = NGp;
                 gy.Cr = Yr; gy.Ci = Yi; gy.sC = 0; gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
-                HIP_TRY(launch_gemm_c64(gy, B.s));
+                {
+                    ProfScope pg_(c, S_BW_GEMM, B.s);
+                    HIP_TRY(launch_gemm_c64(gy, B.s));
+                }
+                ProfScope pw_(c, S_BW_REST, B.s);
                 HIP_TRY(launch_grad_weights(rre, rim, Yr, Yi, NG, NGp, aw, lda, w, cw, gr, gi, dEda, np, B.s));
             }
+            pr_.emplace(c, S_BW_REST, B.s);
             HIP_TRY(launch_pair_eps(dEda, lda, nw, static_cast<const double*>(K.d_epsk),
                                     static_cast<const double*>(K.d_epskq), static_cast<const double*>(K.d_fk),
                                     static_cast<const double*>(K.d_fkq), pn, pm, np,
@@ -2097,19 +2175,37 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                 HIP_TRY(launch_optical_c(gnum, ms, ml, pn, static_cast<const double*>(K.k->C), K.kq->nQ, wq, 1, nm,
                                          dC_kq + 2 * (size_t)x.mlo * K.kq->nQ, B.s));
             }
+            pr_.reset();
+            ProfScope pa_(c, S_BW_PAIRS, B.s);
             HIP_TRY(launch_zadj(gr, gi, NGp, np, g, static_cast<const int32_t*>(Q.d_cs),
                                 static_cast<const int32_t*>(Q.d_cg), static_cast<const int32_t*>(Q.d_ckz),
                                 static_cast<const cplx<double>*>(B.d_tw[2]), tadj, B.s));
-            HIP_TRY(launch_xyadj(tadj, g, ms, ml, pn, reinterpret_cast<const cplx<double>*>(phik), x.mlo, nm, 1,
-                                 static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
-                                 static_cast<const cplx<double>*>(B.d_tw[0]),
-                                 static_cast<const cplx<double>*>(B.d_tw[1]), phib_kq, B.s));
-            HIP_TRY(launch_xyadj(tadj, g, ns, nl, pm, reinterpret_cast<const cplx<double>*>(phikq), x.nlo, nn, 0,
-                                 static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
-                                 static_cast<const cplx<double>*>(B.d_tw[0]),
-                                 static_cast<const cplx<double>*>(B.d_tw[1]), phib_k, B.s));
+            if (reg_adj) {
+                auto side = [&](const SegTab& t, const int32_t* lst, const int32_t* oth, const double* phio, int band0,
+                                int sd, cplx<double>* phib) -> hipError_t {
+                    hipError_t e = launch_xyadj_reg(tadj, g, static_cast<const int32_t*>(t.d_seg), t.nseg, lst, oth,
+                                                    reinterpret_cast<const cplx<double>*>(phio), band0, sd, phib,
+                                                    part, B.s);
+                    if (e != hipSuccess) return e;
+                    return launch_xyadj_reduce(part, vol, static_cast<const int32_t*>(t.d_own),
+                                               static_cast<const int32_t*>(t.d_ostart), (int)t.own.size(), band0,
+                                               phib, B.s);
+                };
+                HIP_TRY(side(x.sm, ml, pn, phik, x.mlo, 1, phib_kq));
+                HIP_TRY(side(x.sn, nl, pm, phikq, x.nlo, 0, phib_k));
+            } else {
+                HIP_TRY(launch_xyadj(tadj, g, ms, ml, pn, reinterpret_cast<const cplx<double>*>(phik), x.mlo, nm, 1,
+                                     static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
+                                     static_cast<const cplx<double>*>(B.d_tw[0]),
+                                     static_cast<const cplx<double>*>(B.d_tw[1]), phib_kq, B.s));
+                HIP_TRY(launch_xyadj(tadj, g, ns, nl, pm, reinterpret_cast<const cplx<double>*>(phikq), x.nlo, nn, 0,
+                                     static_cast<const int32_t*>(Q.d_kx), static_cast<const int32_t*>(Q.d_ky),
+                                     static_cast<const cplx<double>*>(B.d_tw[0]),
+                                     static_cast<const cplx<double>*>(B.d_tw[1]), phib_k, B.s));
+            }
         }
         // energies
+        ProfScope pe_(c, S_BW_REST, B.s);
         HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(S.d_gns), static_cast<const int32_t*>(S.d_gnl), nbk,
                                   1.0, deps_k, B.s));
         HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(S.d_gms), static_cast<const int32_t*>(S.d_gml), nbq,

@@ -71,6 +71,54 @@ def test_adjoint_over_several_set_pairs(rpa, optical):
             assert r < 1e-9, (i, key)
 
 
+@pytest.mark.parametrize("path,chunk", [(0, 0), (0, 24), (1, 24)])
+def test_adjoint_owner_segments(rpa, path, chunk):
+    """Occupied bands with 40 transitions each (16^3 grid, 3 + 40 states, distinct k+q states): the register
+    x-y adjoint (path 0) cuts each band's pairs into segments whose partial sums are added afterwards, also
+    with the pairs spread over chunks of 24; path 1 runs the LDS form on the same inputs. Both against the
+    oracle's reference gradient."""
+    wl = synth.config0(n_occ=3, n_unocc=40, extra_kq=True)
+    s, t = wl.kpoints[0], wl.kq_sets()[0]
+    qp = wl.qpoints[0]
+    gm = oracle.gsphere(wl.A, qp.q, qp.ecut)
+    Q = synth.paw_q_table(wl.paw, wl.A, qp.q, gm)
+    D = synth.paw_d_table(wl.paw)
+    E_ref, g_ref = G.ec_and_grad(wl.A, wl.grid, s, t, gm, Q, wl.paw.offsets, qp.q, wl.omega, wl.omega_weight,
+                                 qp.optical, qp.qhat, D)
+    ks, kqs, qs, fr, _ = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_pair_path(path)
+        ctx.set_chunk_pairs(chunk)
+        ec, g = ctx.ec_backward(ks[0], kqs[0], qs, fr)
+        ctx.check()
+    assert abs(float(ec.cpu()[0]) - E_ref) < 1e-10
+    for key in ["eps_k", "C_k", "P_k", "eps_kq", "C_kq", "P_kq"]:
+        r = _rel(g[key].cpu().numpy(), g_ref[key])
+        print(f"path {path} chunk {chunk} {key}: rel={r:.3e}", flush=True)
+        assert r < 1e-9, key
+
+
+def test_adjoint_stage_profiler(rpa):
+    """The adjoint's stages in the stage profiler: a backward call over 3 + 40 states (120 transitions) in
+    chunks of at most 50 pairs times one inverse, one W(omega) rho product per chunk and frequency, one group
+    of adjoint pair transforms per chunk, and the forward pass's own Cholesky stage."""
+    wl = synth.config0(n_occ=3, n_unocc=40)
+    ks, _, qs, fr, _ = gpu_inputs(rpa, wl)
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        ctx.set_chunk_pairs(50)
+        ctx.ec_backward(ks[0], ks[0], qs, fr)
+        ctx.profile(True)
+        ctx.ec_backward(ks[0], ks[0], qs, fr)
+        prof = ctx.profile_get()
+        ctx.profile(False)
+    print({k: (round(v[0], 3), v[1]) for k, v in prof.items()}, flush=True)
+    assert prof["adjoint_inverse"][1] == 1
+    assert prof["adjoint_gemm"][1] == 3 * fr.nw
+    assert prof["adjoint_pairs"][1] == 3
+    assert prof["adjoint_rest"][1] > 0 and prof["cholesky"][1] == 1 and prof["herk"][1] >= 1
+    assert all(v[0] > 0 for v in prof.values() if v[1])
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_adjoint_matches_reference_gradient(rpa, case):
     wl = CASES[case]()
