@@ -24,6 +24,7 @@ struct PairGeom {
     FftPlan p1, p2, p3;
     int x0, y0;           // grid index of the first kept x / y frequency (the kept sets wrap modulo N)
     int nzc;              // columns that hold sphere entries (the only ones transformed along z)
+    int z0, K3;           // grid index of the sphere's first z frequency and its z extent
 };
 
 // ----------------------------------------------------------------- FFT stages
@@ -70,6 +71,14 @@ template <typename T>
 hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
                              const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, T* rho_re,
                              T* rho_im, hipStream_t s);
+// The z kernel for N3 = 4 M (M a compiled line length) by quads of lanes, keeping only the sphere's z window
+// [z0, z0 + K3) in LDS; same arguments and output as launch_pair_z_reg.
+template <typename T>
+bool pair_z_quad_supported(const PairGeom& g);
+template <typename T>
+hipError_t launch_pair_z_quad(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                              const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, T* rho_re,
+                              T* rho_im, hipStream_t s);
 template <typename T>
 hipError_t launch_pair_z_gather(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
                                 const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz,

@@ -384,6 +384,63 @@ __global__ __launch_bounds__(256) void k_xyadj_reduce(const cplx<T>* __restrict_
     }
 }
 
+// z pass by quads of lanes for N3 = 4 M (M a register length), where a whole FP32 or FP64 line of N3 does
+// not fit one lane's registers: a workgroup of 256 lanes takes 64 held columns of one pair, the quad of lanes
+// 4c..4c+3 transforms column c (lane r the samples z = 4 i + r) and keeps the outputs that fall in the
+// sphere's z window [z0, z0 + K3) in LDS row c; the sphere entries of those columns are then read from LDS,
+// scaled by 1/N and stored.
+constexpr int kZQuadCols = 64;
+
+template <typename T, int N3>
+__global__ __launch_bounds__(4 * kZQuadCols) void k_pair_z_quad(const cplx<T>* __restrict__ tbuf, PairGeom g,
+                                                                const int32_t* __restrict__ zcol,
+                                                                const int32_t* __restrict__ col_start,
+                                                                const int32_t* __restrict__ col_g,
+                                                                const int32_t* __restrict__ col_kz,
+                                                                T* __restrict__ rre, T* __restrict__ rim) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<T>* Z = reinterpret_cast<cplx<T>*>(smem);
+    constexpr int M = N3 / 4, CB = kZQuadCols;
+    const int LDZ = g.K3 + 1, ncols = g.ncols;
+    const size_t p = blockIdx.x;
+    const int c0 = blockIdx.y * CB;
+    const int nc = min(CB, g.nzc - c0);
+    const int l = threadIdx.x, c = l >> 2, r = l & 3;
+    if (c < nc) {
+        const cplx<T>* src = tbuf + p * N3 * ncols + zcol[c0 + c];
+        cplx<T> v[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) v[i] = src[(size_t)(4 * i + r) * ncols];
+        const int s = fft_quad_core<T, N3>(v, r);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            int d = k + M * s - g.z0;
+            if (d < 0) d += N3;
+            if (d < g.K3) Z[c * LDZ + d] = v[k];
+        }
+    }
+    __syncthreads();
+    const Split2<T> invN = split2<T>(1.0 / ((double)g.N1 * g.N2 * N3));
+    const int e0 = col_start[c0], e1 = col_start[c0 + nc];
+    T* ore = rre + p * g.NGp;
+    T* oim = rim + p * g.NGp;
+    for (int i = e0 + l; i < e1; i += 4 * CB) {
+        const int gi = col_g[i];
+        int d = (col_kz[i] >> 16) - g.z0;  // packed (kz << 16) | column
+        if (d < 0) d += N3;
+        const int cc = col_kz[i] & 0xffff;
+        const cplx<T> v = Z[(cc - c0) * LDZ + d];
+        ore[gi] = mulk(v.x, invN);
+        oim[gi] = mulk(v.y, invN);
+    }
+    if (blockIdx.y == 0) {
+        for (int gi = g.NG + l; gi < g.NGp; gi += 4 * CB) {
+            ore[gi] = T(0);
+            oim[gi] = T(0);
+        }
+    }
+}
+
 template <typename T, int N3, int DIR>
 __global__ __launch_bounds__(256) void k_fft_z_reg(cplx<T>* __restrict__ data, long long nlines, int plane,
                                                    const int32_t* __restrict__ cols, int ncols) {
@@ -597,6 +654,47 @@ hipError_t launch_pair_z_reg(const cplx<T>* tbuf, int npairs, const PairGeom& g,
     return hipGetLastError();
 }
 
+template <typename T>
+bool pair_z_quad_supported(const PairGeom& g) {
+    if (g.N3 % 4 != 0 || !reg_size(g.N3 / 4)) return false;
+    if (sizeof(T) == 8 && g.N3 / 4 > 48) return false;  // 48 complex FP64 values per lane at most
+    return g.ncols <= 0xffff && g.K3 >= 1 && g.K3 <= g.N3 && g.z0 >= 0 && g.z0 < g.N3;
+}
+
+namespace {
+template <typename T, int M>
+hipError_t z_quad_case(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                       const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, T* rre, T* rim,
+                       hipStream_t s) {
+    if constexpr (sizeof(T) == 8 && M > 48) {
+        return hipErrorNotSupported;
+    } else {
+        const size_t lds = (size_t)kZQuadCols * (g.K3 + 1) * sizeof(cplx<T>);
+        dim3 grid((unsigned)npairs, (unsigned)((g.nzc + kZQuadCols - 1) / kZQuadCols));
+        hipLaunchKernelGGL((k_pair_z_quad<T, 4 * M>), grid, dim3(4 * kZQuadCols), lds, s, tbuf, g, zcol, col_start,
+                           col_g, col_kz, rre, rim);
+        return hipGetLastError();
+    }
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_pair_z_quad(const cplx<T>* tbuf, int npairs, const PairGeom& g, const int32_t* zcol,
+                              const int32_t* col_start, const int32_t* col_g, const int32_t* col_kz, T* rho_re,
+                              T* rho_im, hipStream_t s) {
+    if (!npairs) return hipSuccess;
+    if (!pair_z_quad_supported<T>(g)) return hipErrorNotSupported;
+    if (g.nzc < 1 || g.nzc > g.ncols) return hipErrorInvalidValue;
+    switch (g.N3 / 4) {
+#define RPA_CASE(L)                                                                                             \
+    case L:                                                                                                     \
+        return z_quad_case<T, L>(tbuf, npairs, g, zcol, col_start, col_g, col_kz, rho_re, rho_im, s);
+        RPA_REG_SIZES(RPA_CASE)
+#undef RPA_CASE
+        default: return hipErrorNotSupported;
+    }
+}
+
 namespace {
 template <int L>
 hipError_t xyadj_case(long long tasks, const cplx<double>* tadj, const PairGeom& g, const int32_t* seg, int nseg,
@@ -651,6 +749,9 @@ hipError_t launch_xyadj_reduce(const cplx<double>* partial, size_t vol, const in
     template hipError_t launch_grid_fft_xy_reg<T>(cplx<T>*, int, int, int, int, int, hipStream_t);                \
     template hipError_t launch_pair_xy_reg<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*, int, \
                                               const PairGeom&, cplx<T>*, hipStream_t);                           \
+    template bool pair_z_quad_supported<T>(const PairGeom&);                                                    \
+    template hipError_t launch_pair_z_quad<T>(const cplx<T>*, int, const PairGeom&, const int32_t*, const int32_t*, \
+                                              const int32_t*, const int32_t*, T*, T*, hipStream_t);              \
     template hipError_t launch_pair_z_reg<T>(const cplx<T>*, int, const PairGeom&, const int32_t*, const int32_t*, \
                                              const int32_t*, const int32_t*, T*, T*, hipStream_t);
 RPA_INST(double)

@@ -451,6 +451,8 @@ int plan_q(rpa_ctx* c, const rpa_qspec* qs, QPlan& P, bool need_coulomb, const i
     for (int i = 0; i < g.K2; ++i) P.ky[i] = ((lo[1] + i) % g.N2 + g.N2) % g.N2;
     g.x0 = P.kx[0];
     g.y0 = P.ky[0];
+    g.K3 = hi[2] - lo[2] + 1;
+    g.z0 = ((lo[2] % g.N3) + g.N3) % g.N3;
     // entries sorted by column (m1, m2); value = G index, (kz << 16) | column
     std::vector<int> order(NG);
     std::vector<int> col(NG);
@@ -1170,6 +1172,7 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     const int32_t* pm = static_cast<const int32_t*>(K.d_pm) + p0;
     const bool reg_xy = c->pair_reg && pair_xy_reg_supported<T>(g);
     const bool reg_z = c->pair_reg && pair_z_reg_supported<T>(g);
+    const bool quad_z = c->pair_reg && !reg_z && pair_z_quad_supported<T>(g);
     if (!skip_xy) {
         ProfScope ps_(c, S_PAIR_XY, B.s);
         if (reg_xy)
@@ -1185,6 +1188,10 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
             HIP_TRY(launch_pair_z_reg<T>(tb, np, g, static_cast<const int32_t*>(Q.d_zc),
                                          static_cast<const int32_t*>(Q.d_zcs), static_cast<const int32_t*>(Q.d_cg),
                                          static_cast<const int32_t*>(Q.d_zckz), rre, rim, B.s));
+        else if (quad_z)
+            HIP_TRY(launch_pair_z_quad<T>(tb, np, g, static_cast<const int32_t*>(Q.d_zc),
+                                          static_cast<const int32_t*>(Q.d_zcs), static_cast<const int32_t*>(Q.d_cg),
+                                          static_cast<const int32_t*>(Q.d_zckz), rre, rim, B.s));
         else
             HIP_TRY(launch_pair_z_gather<T>(tb, np, g, static_cast<const int32_t*>(Q.d_zc),
                                             static_cast<const int32_t*>(Q.d_zcs), static_cast<const int32_t*>(Q.d_cg),

@@ -5,7 +5,8 @@ Same cells, grids, occupations and PAW sizes as the full workloads (9 x 9 x 36 b
   metal slab  - two k-points off Gamma, Fermi-smeared occupations (T = 0.01 Ha), 6 + 24 states,
                 NG = 303;
   uneven batch - eight q-points of the 4 x 4 x 4 mesh with spheres of 252 to 1752 vectors, 4 + 24 states.
-The 40 x 40 x 160 grid runs x and y through the register kernels and z through the LDS passes.
+The 40 x 40 x 160 grid runs x and y through the register kernels and z by quads of lanes (path 0), or all
+three axes through the LDS passes (path 1).
 """
 import numpy as np
 import pytest

@@ -284,6 +284,30 @@ def test_o2box_pair_density_register_path(rpa, prec):
     assert _rel(reg, lds) < tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_slab_pair_density_z_quads(rpa, prec):
+    """The metal-slab grid (40 x 40 x 160, NG = 303): the z pass of 160 points runs by quads of lanes (a
+    whole line does not fit one lane), keeping the sphere's z window; element by element against the
+    oracle, and equal (to rounding) to the LDS passes."""
+    wl = synth.config2(n_below=2, n_above=6, nk=1, target_ng=300)
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    s = wl.kpoints[0]
+    pairs = oracle.pair_list(s.f, s.f)
+    Q = synth.paw_q_table(wl.paw, wl.A, wl.qpoints[0].q, gm)
+    _, ref = oracle.pair_densities(wl.A, wl.grid, s, s, gm, Q, wl.paw.offsets, wl.qpoints[0].optical,
+                                   wl.qpoints[0].qhat, synth.paw_d_table(wl.paw))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        quad = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+        ctx.set_pair_path(1)
+        lds = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    print(f"slab pairs {prec}: {pairs[0].size} pairs, quad rel={_rel(quad, ref):.3e} lds rel={_rel(lds, ref):.3e} "
+          f"quad-lds={_rel(quad, lds):.3e}", flush=True)
+    assert _rel(quad, ref) < tol
+    assert _rel(lds, ref) < tol
+    assert _rel(quad, lds) < tol
+
+
 @pytest.mark.parametrize("iq", [0, 1])
 def test_o2box_reduced_bands(rpa, iq):
     """48^3 grid, ~1500 G-vectors, optical and finite q, with 4 occupied + 40 unoccupied states."""
