@@ -217,6 +217,8 @@ struct GemmArgs {
     const double* Br; const double* Bi; long long sB; long long bK, bJ; int conjB;
     double* Cr; double* Ci; long long sC; long long ldC; double alpha; int beta;
     int lower;           // only entries i >= j of C are needed (a hint: tiles wholly above may be skipped)
+    int ktri;            // A[i][k] = 0 for k < i and B[k][j] = 0 for k < j (both lower-triangular factors of a
+                         // product L^H L): the K loop of a tile starts at its first row or column
 };
 hipError_t launch_gemm_c64(const GemmArgs& g, hipStream_t s);
 // The same product for 1 <= K <= 64 in one round trip to memory (latency-bound shapes of the Cholesky

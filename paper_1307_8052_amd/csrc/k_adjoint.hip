@@ -37,6 +37,9 @@ __global__ __launch_bounds__(256, 3) void k_gemm_c64(GemmArgs g) {
     constexpr int kLd = kTile + 2;
     __shared__ double sAr[2][kGB][kLd], sAi[2][kGB][kLd], sBr[2][kGB][kLd], sBi[2][kGB][kLd];
     const int I = blockIdx.x, J = blockIdx.y, b = blockIdx.z;
+    if (g.lower && J > I) return;  // the whole tile lies above the diagonal
+    // with triangular factors every k below the tile's first row or column contributes zero
+    const int kbeg = g.ktri ? max(I, J) * kTile : 0;
     const double* Ar = g.Ar + (size_t)b * g.sA;
     const double* Ai = g.Ai + (size_t)b * g.sA;
     const double* Br = g.Br + (size_t)b * g.sB;
@@ -90,12 +93,12 @@ __global__ __launch_bounds__(256, 3) void k_gemm_c64(GemmArgs g) {
             sBi[buf][kk][c] = ok ? sb * qi[u] : 0.0;
         }
     };
-    if (g.K > 0) {
-        fetch(0);
-        stash(0, 0);
+    if (kbeg < g.K) {
+        fetch(kbeg);
+        stash(0, kbeg);
     }
     int cur = 0;
-    for (int k0 = 0; k0 < g.K; k0 += kGB) {
+    for (int k0 = kbeg; k0 < g.K; k0 += kGB) {
         __syncthreads();
         const bool more = k0 + kGB < g.K;
         if (more) fetch(k0 + kGB);
@@ -239,21 +242,25 @@ __global__ void k_identity(double* __restrict__ Xr, double* __restrict__ Xi, int
     }
 }
 
-// W = V (1 - Minv) V in place (full matrix), zero outside NG; c_w = dE_up W_w / 2 pi
+// W = V (1 - Minv) V in place, zero outside NG, from the lower triangle of the Hermitian Minv: row block i
+// reads its entries j <= i and writes them and their mirrors (j, i) (the upper part of row j, which row
+// block j does not read); c_w = dE_up W_w / 2 pi
 __global__ void k_build_w(double* __restrict__ Mr, double* __restrict__ Mi, int NG, int NGp,
                           const double* __restrict__ vs) {
     const int i = blockIdx.x, b = blockIdx.y;
-    double* mr = Mr + ((size_t)b * NGp + i) * NGp;
-    double* mi = Mi + ((size_t)b * NGp + i) * NGp;
-    for (int j = threadIdx.x; j < NGp; j += blockDim.x) {
+    double* mr = Mr + (size_t)b * NGp * NGp;
+    double* mi = Mi + (size_t)b * NGp * NGp;
+    for (int j = threadIdx.x; j <= i; j += blockDim.x) {
         double r = 0, im = 0;
         if (i < NG && j < NG) {
             const double s = vs[i] * vs[j];
-            r = s * ((i == j ? 1.0 : 0.0) - mr[j]);
-            im = -s * mi[j];
+            r = s * ((i == j ? 1.0 : 0.0) - mr[(size_t)i * NGp + j]);
+            im = -s * mi[(size_t)i * NGp + j];
         }
-        mr[j] = r;
-        mi[j] = im;
+        mr[(size_t)i * NGp + j] = r;
+        mi[(size_t)i * NGp + j] = im;
+        mr[(size_t)j * NGp + i] = r;
+        mi[(size_t)j * NGp + i] = -im;
     }
 }
 

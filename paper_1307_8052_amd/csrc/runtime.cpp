@@ -2037,6 +2037,10 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         g3.Ar = Xr; g3.Ai = Xi; g3.sA = (long long)NGp * NGp; g3.aI = 1; g3.aK = NGp; g3.conjA = 1;
         g3.Br = Xr; g3.Bi = Xi; g3.sB = (long long)NGp * NGp; g3.bK = NGp; g3.bJ = 1;
         g3.Cr = Br_; g3.Ci = Bi_; g3.sC = (long long)NGp * NGp; g3.ldC = NGp; g3.alpha = 1.0; g3.beta = 0;
+        // X is lower triangular: the lower half of X^H X, with k from the tile's first row (W is built from
+        // that half and mirrored)
+        g3.lower = 1;
+        g3.ktri = 1;
         HIP_TRY(launch_gemm_c64(g3, B.s));
     }
     HIP_TRY(launch_build_w(Br_, Bi_, NG, NGp, nw, static_cast<const double*>(Q.d_vs), B.s));
@@ -2217,13 +2221,31 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                                   1.0, deps_k, B.s));
         HIP_TRY(launch_eps_reduce(u, static_cast<const int32_t*>(S.d_gms), static_cast<const int32_t*>(S.d_gml), nbq,
                                   -1.0, deps_kq, B.s));
-        // coefficients: C_bar = unnormalised forward DFT of phi_bar, read at the plane-wave Miller indices
+        // coefficients: C_bar = unnormalised forward DFT of phi_bar, read at the plane-wave Miller indices:
+        // x and y on every plane, then z on the columns that hold coefficients (register-resident lines
+        // where the axis length has them, LDS passes otherwise)
         for (int side = 0; side < (same ? 1 : 2); ++side) {
             cplx<double>* ph = side == 0 ? phib_k : phib_kq;
             const int nb = side == 0 ? nbk : nbq;
-            for (int ax = 0; ax < 3; ++ax)
-                HIP_TRY(launch_fft_axis<double>(ph, nb, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
-                                                static_cast<const cplx<double>*>(B.d_tw[ax]), -1, B.s));
+            const std::vector<int32_t>& zc = side == 0 ? K.zcolk : K.zcolkq;
+            const int32_t* d_zc = static_cast<const int32_t*>(side == 0 ? K.d_zcolk : K.d_zcolkq);
+            hipError_t e = c->pair_reg ? launch_grid_fft_xy_reg<double>(ph, nb, c->N[0], c->N[1], c->N[2], -1, B.s)
+                                       : hipErrorNotSupported;
+            if (e == hipErrorNotSupported) {
+                for (int ax = 0; ax < 2; ++ax)
+                    HIP_TRY(launch_fft_axis<double>(ph, nb, c->N[0], c->N[1], c->N[2], ax, c->plan[ax],
+                                                    static_cast<const cplx<double>*>(B.d_tw[ax]), -1, B.s));
+            } else {
+                HIP_TRY(e);
+            }
+            e = c->pair_reg ? launch_grid_fft_z_reg<double>(ph, nb, c->N[0], c->N[1], c->N[2], -1, d_zc,
+                                                            (int)zc.size(), B.s)
+                            : hipErrorNotSupported;
+            if (e == hipErrorNotSupported)
+                HIP_TRY(launch_fft_axis<double>(ph, nb, c->N[0], c->N[1], c->N[2], 2, c->plan[2],
+                                                static_cast<const cplx<double>*>(B.d_tw[2]), -1, B.s));
+            else
+                HIP_TRY(e);
         }
         HIP_TRY(launch_gather_c(phib_k, vol, static_cast<const int32_t*>(K.d_mapk), K.k->nQ, nbk, dC_k, B.s));
         // with one state set both roles accumulated into the same phi_bar above
