@@ -77,9 +77,12 @@ __device__ __forceinline__ int fft_quad_core(cplx<T> (&v)[N / 4], int r) {
     RegFft<M, -1, T>::run(v);
 #pragma unroll
     for (int k = 1; k < M; ++k) {
+        // the three lanes' constants split at compile time, then selected by lane
         const int e1 = k % N, e2 = (2 * k) % N, e3 = (3 * k) % N;
-        const double c = r == 1 ? W.c[e1] : r == 2 ? W.c[e2] : W.c[e3];
-        const double sn = r == 1 ? -W.s[e1] : r == 2 ? -W.s[e2] : -W.s[e3];
+        const Split2<T> c1 = split2<T>(W.c[e1]), c2 = split2<T>(W.c[e2]), c3 = split2<T>(W.c[e3]);
+        const Split2<T> s1 = split2<T>(-W.s[e1]), s2 = split2<T>(-W.s[e2]), s3 = split2<T>(-W.s[e3]);
+        const Split2<T> c = r == 1 ? c1 : r == 2 ? c2 : c3;
+        const Split2<T> sn = r == 1 ? s1 : r == 2 ? s2 : s3;
         if (r != 0) v[k] = cmulk(v[k], c, sn);
     }
 #pragma unroll
