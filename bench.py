@@ -469,6 +469,11 @@ def run_qmesh(args, torch, rpa, synth):
 
     batched(args.warmup)
     dt_b, ec_b = batched(args.steps)
+    # stage times of one more batched pass (HIP events around each kernel group; outside the timed region)
+    ctx.profile(True)
+    batched(1)
+    prof = ctx.profile_get()
+    ctx.profile(False)
     # device memory held by the context after the batched call (chi0 sized per class of sphere sizes),
     # against chi0 alone padded to the largest sphere for every q
     used_b = free0 - torch.cuda.mem_get_info()[0]
@@ -491,6 +496,8 @@ def run_qmesh(args, torch, rpa, synth):
                                f"all 64 q-points in one batched call", "precision": prec, "NG": NGs,
                    "pairs_per_q": P, "nw": nw},
         "ms_per_q": ms_b / len(NGs), "ms_per_step_per_q_loop": ms_l, "batched_speedup_vs_loop": ms_l / ms_b,
+        "stage_ms_one_pass": {k: v[0] for k, v in prof.items() if v[1]},
+        "stage_groups_one_pass": {k: v[1] for k, v in prof.items() if v[1]},
         "ec_batched_minus_loop_max_ha": diff, "ec_weighted_sum": float(ec_b[len(NGs)]),
         "device_bytes_after_batched_call": used_b, "chi0_bytes_if_padded_to_largest_sphere": padded_chi,
     }
