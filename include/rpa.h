@@ -366,6 +366,15 @@ int rpa_set_autotune(rpa_ctx* ctx, int enable);
  * q-point's sum into more updates; chi0 is the same up to rounding order.
  * RPA_ERR_INPUT if max_pairs < 0. */
 int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs);
+
+/* Upper bound on the bands m of one pass of the PAW correction's MFMA form
+ * (Eq. n_G_2 factorised per band m: Z_m = Q P'_m, then rho_p += conj(P_n) Z_m
+ * for the pairs of each m). 0 (default): a pass covers every band m of a pair
+ * chunk, or as many as a Z buffer of 2 GiB (an eighth of the cap when one is
+ * set) holds; a chunk whose pairs span more bands runs in several passes over
+ * consecutive pairs. The pair densities do not depend on the bound.
+ * RPA_ERR_INPUT if max_bands < 0. */
+int rpa_set_paw_window(rpa_ctx* ctx, int max_bands);
 int rpa_tune_set(rpa_ctx* ctx, rpa_precision prec, int NG, int variant);
 int rpa_tune_get(rpa_ctx* ctx, rpa_precision prec, int NG, int* variant);
 int rpa_tune_cache_io(rpa_ctx* ctx, const char* path, int save);

@@ -443,6 +443,10 @@ class Context:
         """Upper bound on the pairs of one grouped rank-k update (0: set by the workspace budget)."""
         _check(self._L.rpa_set_chunk_pairs(self._h, int(max_pairs)), self._h)
 
+    def set_paw_window(self, max_bands: int):
+        """Upper bound on the bands m of one pass of the MFMA PAW term (0: set by the Z buffer's size)."""
+        _check(self._L.rpa_set_paw_window(self._h, int(max_bands)), self._h)
+
     def tune_set(self, NG: int, variant: int, precision="split_bf16"):
         _check(self._L.rpa_tune_set(self._h, _prec(precision), int(NG), int(variant)), self._h)
 

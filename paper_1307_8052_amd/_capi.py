@@ -111,6 +111,7 @@ SIGNATURES = {
     "rpa_tune_set": (c_int, [c_void_p, c_int, c_int, c_int]),
     "rpa_set_pair_path": (c_int, [c_void_p, c_int]),
     "rpa_set_chunk_pairs": (c_int, [c_void_p, c_int]),
+    "rpa_set_paw_window": (c_int, [c_void_p, c_int]),
     "rpa_set_autotune": (c_int, [c_void_p, c_int]),
     "rpa_tune_get": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int)]),
     "rpa_tune_cache_io": (c_int, [c_void_p, ctypes.c_char_p, c_int]),

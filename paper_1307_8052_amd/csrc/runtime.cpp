@@ -111,6 +111,7 @@ struct rpa_ctx {
     bool capturing = false;
     bool pair_reg = true;   // register-resident pair transforms where supported
     int max_chunk = 0;      // upper bound on the pairs of one chunk (0: set by the workspace budget alone)
+    int paw_win = 0;        // upper bound on the bands m of one MFMA PAW pass (0: set by the Z buffer's size)
     bool autotune = true;   // split precisions: time the rank-k variants for each new sphere-size bucket
     // arena mode (rpa_ec_noalloc): workspaces are carved from the device scratch instead of hipMalloc'd, and
     // host tables are staged in ordinary host memory instead of a pinned arena
@@ -686,6 +687,7 @@ struct Batch {
     double eta = 0.0;
     int nw_user = 0;
     bool paw_mfma = false;           // set by presize: PAW correction as an MFMA GEMM per band m
+    int paw_mwin = 0;                // set by presize: bands m per MFMA PAW pass (bounds the Z buffer)
     bool share_xy = false;           // several q-points with shared sets: one pair transform per chunk for all
     bool allow_share_xy = true;      // the adjoint keeps one q-point's own box
     int ld = 0;                      // the largest leading dimension of the batch's chi0 / -K matrices
@@ -1009,6 +1011,11 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     rpa_ctx* c = B.c;
     const size_t vol = (size_t)c->N[0] * c->N[1] * c->N[2];
     const size_t el = B.elem();
+    // bytes of the MFMA PAW term's Z buffer at most
+    size_t paw_zcap = (size_t)2 << 30;
+    if (c->cap) paw_zcap = std::min(paw_zcap, c->cap / 8);
+    if (c->arena) paw_zcap = std::min(paw_zcap, c->arena_cap / 8);
+    B.paw_mwin = 0;
     for (auto& K : B.ks) {
         W.drude += K.drude_band.size() * sizeof(double);
         W.phi_k = std::max(W.phi_k, (size_t)K.k->nbands * vol * 2 * el);
@@ -1064,7 +1071,12 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         W.weights = std::max(W.weights, (size_t)std::max(B.nw, 1) * lda * sizeof(double));
         if (nproj > 0) {
             W.paw_y = std::max(W.paw_y, 2 * (size_t)win * nproj * g.NGp * el);
-            W.paw_z = std::max(W.paw_z, 2 * (size_t)mspan * nproj * g.NGp * el);
+            // Z of at most paw_zcap bytes: a chunk whose pairs span more bands m runs the MFMA PAW term over
+            // windows of consecutive pairs with fewer bands
+            const size_t per_m = 2 * (size_t)nproj * g.NGp * el;
+            int mwin = (int)std::max<size_t>(1, std::min<size_t>((size_t)mspan, paw_zcap / per_m));
+            if (c->paw_win > 0) mwin = std::min(mwin, c->paw_win);
+            B.paw_mwin = B.paw_mwin ? std::min(B.paw_mwin, mwin) : mwin;
         }
         if (!B.fp64()) {
             const int NGq = (g.NGp + 127) / 128 * 128;
@@ -1074,9 +1086,14 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         }
         B.ld = std::max(B.ld, Q.ld);
     }
-    // the MFMA PAW term needs Z for every band m of a chunk's span; the factorised VALU form (Y for every
-    // band n) serves the adjoint and spans too wide for that
-    B.paw_mfma = B.allow_paw_mfma && W.paw_z > 0 && W.paw_z <= ((size_t)2 << 30);
+    // the MFMA PAW term needs Z for the bands m of a window (at most paw_mwin of them); the factorised VALU
+    // form (Y for every band n) serves the adjoint
+    if (B.paw_mwin > 0)
+        for (auto& Q : B.qj) {
+            const int nproj = B.poff.empty() ? 0 : B.poff.back();
+            W.paw_z = std::max(W.paw_z, 2 * (size_t)B.paw_mwin * nproj * Q.qp.g.NGp * el);
+        }
+    B.paw_mfma = B.allow_paw_mfma && W.paw_z > 0;
     if (B.paw_mfma) W.paw_y = 0;
     else W.paw_z = 0;
     // per class of q-points with one leading dimension: all real parts, then all imaginary parts, so that
@@ -1200,19 +1217,28 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
     }
     const int nproj = nproj_total(K.k);
     if (nproj > 0 && B.paw_mfma) {
-        int mlo = K.pm[p0], mhi = K.pm[p0];
-        for (int i = p0; i < p0 + np; ++i) {
-            mlo = std::min(mlo, (int)K.pm[i]);
-            mhi = std::max(mhi, (int)K.pm[i]);
-        }
-        const int nm = mhi - mlo + 1;
+        // windows of consecutive pairs whose bands m span at most paw_mwin (one window per chunk unless the
+        // chunk's pairs span more bands than the Z buffer holds)
         T* Zr = static_cast<T*>(buf(B, "paw_z"));
-        T* Zi = Zr + (size_t)nm * nproj * g.NGp;
         ProfScope ps_(c, S_PAW, B.s);
-        HIP_TRY(launch_paw_mfma<T>(static_cast<const double*>(K.k->P), static_cast<const double*>(K.kq->P), nproj, pn,
-                                   pm, np, mlo, nm, static_cast<const int32_t*>(B.d_poff),
-                                   static_cast<const int32_t*>(B.d_qoff), K.k->natoms, nproj,
-                                   static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Zr, Zi, rre, rim, B.s));
+        for (int a = 0; a < np;) {
+            int mlo = K.pm[p0 + a], mhi = mlo, b = a + 1;
+            for (; b < np; ++b) {
+                const int m = K.pm[p0 + b];
+                const int lo = std::min(mlo, m), hi = std::max(mhi, m);
+                if (hi - lo + 1 > B.paw_mwin) break;
+                mlo = lo;
+                mhi = hi;
+            }
+            const int nm = mhi - mlo + 1;
+            T* Zi = Zr + (size_t)nm * nproj * g.NGp;
+            HIP_TRY(launch_paw_mfma<T>(static_cast<const double*>(K.k->P), static_cast<const double*>(K.kq->P), nproj,
+                                       pn + a, pm + a, b - a, mlo, nm, static_cast<const int32_t*>(B.d_poff),
+                                       static_cast<const int32_t*>(B.d_qoff), K.k->natoms, nproj,
+                                       static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Zr, Zi,
+                                       rre + (size_t)a * g.NGp, rim + (size_t)a * g.NGp, B.s));
+            a = b;
+        }
     } else if (nproj > 0) {
         int nlo = K.pn[p0], nhi = K.pn[p0];
         for (int i = p0; i < p0 + np; ++i) {
@@ -2802,6 +2828,14 @@ int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs) {
     if (max_pairs < 0) return fail(RPA_ERR_INPUT, "chunk bound must be >= 0");
     if (ctx->max_chunk != max_pairs) drop_graph(ctx);
     ctx->max_chunk = max_pairs;
+    return RPA_OK;
+}
+
+int rpa_set_paw_window(rpa_ctx* ctx, int max_bands) {
+    if (!ctx) return fail(RPA_ERR_INPUT, "NULL context");
+    if (max_bands < 0) return fail(RPA_ERR_INPUT, "PAW window bound must be >= 0");
+    if (ctx->paw_win != max_bands) drop_graph(ctx);
+    ctx->paw_win = max_bands;
     return RPA_OK;
 }
 

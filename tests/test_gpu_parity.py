@@ -285,6 +285,34 @@ def test_o2box_pair_density_register_path(rpa, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_paw_term_in_band_windows(rpa, prec):
+    """The MFMA PAW term in passes of at most 7 bands m (48^3 grid, NG = 1500, 4 + 40 states): pair
+    densities in the oracle's order (n-major: every pass a run of consecutive pairs) and chi0 in the
+    library's m-major order equal those of one pass per chunk bit for bit, and the pair densities equal
+    the oracle's."""
+    wl = synth.config1(n_occ=4, n_unocc=40, which_q=(1,))
+    ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
+    s = wl.kpoints[0]
+    pairs = oracle.pair_list(s.f, s.f)
+    Q = synth.paw_q_table(wl.paw, wl.A, wl.qpoints[0].q, gm)
+    _, ref = oracle.pair_densities(wl.A, wl.grid, s, s, gm, Q, wl.paw.offsets, wl.qpoints[0].optical,
+                                   wl.qpoints[0].qhat, synth.paw_d_table(wl.paw))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        rho1 = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+        chi1 = ctx.chi0(ks, ks, qs, fr, prec).cpu().numpy()
+        ctx.set_paw_window(7)
+        rho7 = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
+        chi7 = ctx.chi0(ks, ks, qs, fr, prec).cpu().numpy()
+        with pytest.raises(rpa.RpaError):
+            ctx.set_paw_window(-1)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    print(f"paw windows {prec}: rho rel={_rel(rho7, ref):.3e}", flush=True)
+    assert np.array_equal(rho1, rho7)
+    assert np.array_equal(chi1, chi7)
+    assert _rel(rho7, ref) < tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
 def test_slab_pair_density_z_quads(rpa, prec):
     """The metal-slab grid (40 x 40 x 160, NG = 303): the z pass of 160 points runs by quads of lanes (a
     whole line does not fit one lane), keeping the sphere's z window; element by element against the
