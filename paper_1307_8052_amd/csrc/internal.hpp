@@ -116,6 +116,12 @@ hipError_t launch_chi_out_real(const double* Cre, const double* Cim, int ldC, in
 // PAW term as an MFMA GEMM (k_paw.hip): Z_m = Q P'_m for m = m_lo .. m_lo + nslots - 1 into Zr/Zi
 // [nslots][nproj][NGp], then rho[p] += conj(P_k[pn[p]]) Z_{pm[p]} for the npairs pairs (pm within the
 // slots); NGp a multiple of 64
+// The n-factorised MFMA form: rho[perm[f + r]] += P_kq[pm[perm[f + r]]] . Y[n] for the nseg segments
+// (n - n_lo, f, count <= 64) of seg, with Y [n - n_lo][nproj][NGp] from launch_paw_y; NGp a multiple of 64
+template <typename T>
+hipError_t launch_paw_mfma_n(const T* Yr, const T* Yi, int nproj, const double* Pkq, int ldP, const int32_t* pm,
+                             const int32_t* seg, int nseg, const int32_t* perm, int NGp, T* rre, T* rim,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_paw_mfma(const double* Pk, const double* Pkq, int ldP, const int32_t* pn, const int32_t* pm,
                            int npairs, int m_lo, int nslots, const int32_t* proj_off, const int32_t* qoff, int natoms,

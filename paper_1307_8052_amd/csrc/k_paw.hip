@@ -174,6 +174,92 @@ __global__ __launch_bounds__(256) void k_paw_mm(const T* __restrict__ Zr, const 
     }
 }
 
+// The n-factorised form, for chunks whose pairs span fewer bands n than bands m:
+//   Y_n[aj][G] = sum_i conj(P_ni) Q^a_ij(G)             (k_paw_y, once per band n of a chunk)
+//   rho_p[G]  += sum_{aj} P'_{m_p}[aj] Y_{n_p}[aj][G]   (this kernel, K = sum_a Np_a)
+// One workgroup per (64 G-vectors, segment of at most 64 pairs with one band n): seg holds per segment
+// (n - n_lo, first, count) into perm, the chunk's pair indices grouped by n; the B operand Y_n is shared
+// by the segment's rows, the A rows are the pairs' P'_m, and the results go to the pairs' own rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_paw_mm_n(const T* __restrict__ Yr, const T* __restrict__ Yi, int nproj,
+                                                  const double* __restrict__ Pkq, int ldP,
+                                                  const int32_t* __restrict__ pm, const int32_t* __restrict__ seg,
+                                                  const int32_t* __restrict__ perm, int NGp, T* __restrict__ rre,
+                                                  T* __restrict__ rim) {
+    typedef typename Mfma<T>::acc acc_t;
+    __shared__ T sAr[64][kPawKB + 1], sAi[64][kPawKB + 1];
+    __shared__ T sBr[kPawKB][64 + 4], sBi[kPawKB][64 + 4];
+    const int g0 = blockIdx.x * 64;
+    const int ns = seg[3 * blockIdx.y], f = seg[3 * blockIdx.y + 1], nrows = seg[3 * blockIdx.y + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // staging roles: A row ar, k ak .. ak+3; B k-row bk, columns bc .. bc+3
+    const int ar = tid >> 2, ak = (tid & 3) * 4;
+    const int bk = tid >> 4, bc = (tid & 15) * 4;
+    const size_t mA = ar < nrows ? (size_t)pm[perm[f + ar]] : 0;
+    const size_t yb = (size_t)ns * nproj * NGp;
+    acc_t accR[4], accI[4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+        accR[y] = acc_t{0, 0, 0, 0};
+        accI[y] = acc_t{0, 0, 0, 0};
+    }
+    for (int kb = 0; kb < nproj; kb += kPawKB) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = kb + ak + e;
+            double vr = 0.0, vi = 0.0;
+            if (k < nproj && ar < nrows) {
+                vr = Pkq[2 * (mA * ldP + k)];
+                vi = Pkq[2 * (mA * ldP + k) + 1];
+            }
+            sAr[ar][ak + e] = T(vr);
+            sAi[ar][ak + e] = T(vi);
+        }
+        {
+            const int k = kb + bk;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                T vr = T(0), vi = T(0);
+                if (k < nproj) {
+                    const size_t o = yb + (size_t)k * NGp + g0 + bc + e;
+                    vr = Yr[o];
+                    vi = Yi[o];
+                }
+                sBr[bk][bc + e] = vr;
+                sBi[bk][bc + e] = vi;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kPawKB; kk += 4) {
+            const int kr = kk + (lane >> 4), rc = lane & 15;
+            const T a_r = sAr[16 * wave + rc][kr], a_i = sAi[16 * wave + rc][kr];
+            const T a_n = -a_i;
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                // (Ar + i Ai)(Br + i Bi) = Ar Br - Ai Bi + i (Ar Bi + Ai Br)
+                const T b_r = sBr[kr][16 * y + rc], b_i = sBi[kr][16 * y + rc];
+                accR[y] = Mfma<T>::step(a_r, b_r, accR[y]);
+                accR[y] = Mfma<T>::step(a_n, b_i, accR[y]);
+                accI[y] = Mfma<T>::step(a_r, b_i, accI[y]);
+                accI[y] = Mfma<T>::step(a_i, b_r, accI[y]);
+            }
+        }
+    }
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * wave + Mfma<T>::row(lane, r);
+            if (row < nrows) {
+                const size_t o = (size_t)perm[f + row] * NGp + g0 + 16 * y + (lane & 15);
+                rre[o] += accR[y][r];
+                rim[o] += accI[y][r];
+            }
+        }
+}
+
 }  // namespace
 
 template <typename T>
@@ -189,6 +275,23 @@ hipError_t launch_paw_mfma(const double* Pk, const double* Pkq, int ldP, const i
     hipLaunchKernelGGL(k_paw_mm<T>, gm, dim3(256), 0, s, Zr, Zi, nproj, Pk, ldP, pn, pm, npairs, m_lo, NGp, rre, rim);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_paw_mfma_n(const T* Yr, const T* Yi, int nproj, const double* Pkq, int ldP, const int32_t* pm,
+                             const int32_t* seg, int nseg, const int32_t* perm, int NGp, T* rre, T* rim,
+                             hipStream_t s) {
+    if (!nseg || !nproj) return hipSuccess;
+    if (NGp % 64) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(NGp / 64), (unsigned)nseg);
+    hipLaunchKernelGGL(k_paw_mm_n<T>, grid, dim3(256), 0, s, Yr, Yi, nproj, Pkq, ldP, pm, seg, perm, NGp, rre, rim);
+    return hipGetLastError();
+}
+
+template hipError_t launch_paw_mfma_n<float>(const float*, const float*, int, const double*, int, const int32_t*,
+                                             const int32_t*, int, const int32_t*, int, float*, float*, hipStream_t);
+template hipError_t launch_paw_mfma_n<double>(const double*, const double*, int, const double*, int, const int32_t*,
+                                              const int32_t*, int, const int32_t*, int, double*, double*,
+                                              hipStream_t);
 
 template hipError_t launch_paw_mfma<float>(const double*, const double*, int, const int32_t*, const int32_t*, int,
                                            int, int, const int32_t*, const int32_t*, int, int, const double*, int,

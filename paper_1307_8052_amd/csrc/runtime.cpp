@@ -618,6 +618,16 @@ struct KSet {
     void* d_nlist = nullptr;
 };
 
+// The pairs of every chunk of one k set grouped by band n (stable), for the n-factorised MFMA PAW term:
+// perm[p0 + i] is the chunk-local index of its i-th pair in that order, seg holds per segment of at most 64
+// pairs of one band (n - n_lo, first, count), and chunk c's segments are seg[3 s0_c ..], n_lo_c its lowest n.
+struct PawN {
+    std::vector<int32_t> perm, seg;
+    std::vector<int32_t> s0, ns, nlo, nn;   // per chunk
+    void* d_perm = nullptr;
+    void* d_seg = nullptr;
+};
+
 struct QJob {
     const rpa_qspec* qs = nullptr;
     QPlan qp;
@@ -688,6 +698,8 @@ struct Batch {
     int nw_user = 0;
     bool paw_mfma = false;           // set by presize: PAW correction as an MFMA GEMM per band m
     int paw_mwin = 0;                // set by presize: bands m per MFMA PAW pass (bounds the Z buffer)
+    bool paw_nform = false;          // set by presize: the MFMA PAW term factorised per band n (Y_n), not per m
+    std::map<std::pair<int, int>, PawN> pawn;  // (k set, chunk size): pair indices of every chunk grouped by n
     bool share_xy = false;           // several q-points with shared sets: one pair transform per chunk for all
     bool allow_share_xy = true;      // the adjoint keeps one q-point's own box
     int ld = 0;                      // the largest leading dimension of the batch's chi0 / -K matrices
@@ -1016,6 +1028,16 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
     if (c->cap) paw_zcap = std::min(paw_zcap, c->cap / 8);
     if (c->arena) paw_zcap = std::min(paw_zcap, c->arena_cap / 8);
     B.paw_mwin = 0;
+    // bands n and m the pairs of each k set span (the choice of the PAW term's form does not depend on
+    // the chunking, so that a pair's density does not either)
+    int nspan_max = 0, mspan_max = 0;
+    for (auto& K : B.ks) {
+        if (K.pn.empty()) continue;
+        const auto n = std::minmax_element(K.pn.begin(), K.pn.end());
+        const auto m = std::minmax_element(K.pm.begin(), K.pm.end());
+        nspan_max = std::max(nspan_max, *n.second - *n.first + 1);
+        mspan_max = std::max(mspan_max, *m.second - *m.first + 1);
+    }
     for (auto& K : B.ks) {
         W.drude += K.drude_band.size() * sizeof(double);
         W.phi_k = std::max(W.phi_k, (size_t)K.k->nbands * vol * 2 * el);
@@ -1065,6 +1087,7 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
                 mspan = std::max(mspan, mhi - mlo + 1);
             }
         }
+
         W.tbuf = std::max(W.tbuf, (size_t)Pc * g.N3 * g.ncols * 2 * el);
         W.rho = std::max(W.rho, 2 * (size_t)Pc * g.NGp * el);
         const int lda = (Pc + 3) / 4 * 4;
@@ -1086,15 +1109,18 @@ int presize(Batch& B, bool need_ec, bool need_chi, WorkSizes& W) {
         }
         B.ld = std::max(B.ld, Q.ld);
     }
-    // the MFMA PAW term needs Z for the bands m of a window (at most paw_mwin of them); the factorised VALU
-    // form (Y for every band n) serves the adjoint
+    // the MFMA PAW term factorised per band n (Y_n for the bands n of a chunk) where the pairs span fewer
+    // bands n than bands m and Y fits, else per band m (Z_m for the bands of a window, at most paw_mwin of them);
+    // the factorised VALU form (Y for every band n) serves the adjoint
     if (B.paw_mwin > 0)
         for (auto& Q : B.qj) {
             const int nproj = B.poff.empty() ? 0 : B.poff.back();
             W.paw_z = std::max(W.paw_z, 2 * (size_t)B.paw_mwin * nproj * Q.qp.g.NGp * el);
         }
     B.paw_mfma = B.allow_paw_mfma && W.paw_z > 0;
-    if (B.paw_mfma) W.paw_y = 0;
+    B.paw_nform = B.paw_mfma && c->paw_win == 0 && nspan_max <= mspan_max && W.paw_y <= paw_zcap;
+    if (B.paw_nform) W.paw_z = 0;
+    else if (B.paw_mfma) W.paw_y = 0;
     else W.paw_z = 0;
     // per class of q-points with one leading dimension: all real parts, then all imaginary parts, so that
     // matrix b = (q - q0) nw + w of the class sits at b * ld^2 and the E_c stage factorises the class as
@@ -1216,7 +1242,25 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
                                             static_cast<const cplx<T>*>(B.d_tw[2]), rre, rim, B.s));
     }
     const int nproj = nproj_total(K.k);
-    if (nproj > 0 && B.paw_mfma) {
+    if (nproj > 0 && B.paw_nform) {
+        // Y_n for the chunk's bands n, then the GEMM over the chunk's pairs grouped by n
+        const auto it = B.pawn.find(std::make_pair(ik, Q.Pc));
+        const int ci = p0 / Q.Pc;
+        if (it == B.pawn.end() || ci >= (int)it->second.s0.size() || p0 % Q.Pc)
+            return fail(RPA_ERR_SHAPE, "PAW pair tables missing for a chunk");
+        const PawN& PT = it->second;
+        const int nlo = PT.nlo[ci], nn = PT.nn[ci];
+        T* Yre = static_cast<T*>(buf(B, "paw_y"));
+        T* Yim = Yre + (size_t)nn * nproj * g.NGp;
+        ProfScope ps_(c, S_PAW, B.s);
+        HIP_TRY(launch_paw_y<T>(static_cast<const double*>(K.k->P), nproj, static_cast<const int32_t*>(K.d_nlist) + nlo,
+                                nn, static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Yre, Yim,
+                                B.s));
+        HIP_TRY(launch_paw_mfma_n<T>(Yre, Yim, nproj, static_cast<const double*>(K.kq->P), nproj, pm,
+                                     static_cast<const int32_t*>(PT.d_seg) + 3 * (size_t)PT.s0[ci], PT.ns[ci],
+                                     static_cast<const int32_t*>(PT.d_perm) + p0, g.NGp, rre, rim, B.s));
+    } else if (nproj > 0 && B.paw_mfma) {
         // windows of consecutive pairs whose bands m span at most paw_mwin (one window per chunk unless the
         // chunk's pairs span more bands than the Z buffer holds)
         T* Zr = static_cast<T*>(buf(B, "paw_z"));
@@ -1740,6 +1784,49 @@ int check_common(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk
 // plan every (k, q) of a call: validation, tables, one upload, buffer sizes
 // qk (optional, nq + 1 entries): q-point j uses the sets qk[j] .. qk[j+1]-1 of k and kq; without it every
 // q-point uses all nk of them.
+// n-grouped pair tables of the n-factorised MFMA PAW term, one per (k set, chunk size), uploaded beside the
+// call's other tables (before any launch or graph capture)
+int build_pawn(Batch& B, const char* table_buf) {
+    B.pawn.clear();
+    if (!B.paw_nform) return RPA_OK;
+    Upload up;
+    for (auto& Q : B.qj)
+        for (size_t ik = 0; ik < B.ks.size(); ++ik) {
+            if (!Q.uses((int)ik)) continue;
+            const auto key = std::make_pair((int)ik, Q.Pc);
+            if (B.pawn.count(key)) continue;
+            PawN& T = B.pawn[key];
+            const KSet& K = B.ks[ik];
+            const int P = (int)K.pn.size();
+            T.perm.resize(std::max(P, 1));
+            for (int p0 = 0; p0 < P; p0 += Q.Pc) {
+                const int np = std::min(Q.Pc, P - p0);
+                int nlo = K.pn[p0], nhi = nlo;
+                for (int i = p0; i < p0 + np; ++i) {
+                    nlo = std::min(nlo, (int)K.pn[i]);
+                    nhi = std::max(nhi, (int)K.pn[i]);
+                }
+                const int nn = nhi - nlo + 1;
+                std::vector<int32_t> start(nn + 1, 0);
+                for (int i = p0; i < p0 + np; ++i) start[K.pn[i] - nlo + 1]++;
+                for (int b = 0; b < nn; ++b) start[b + 1] += start[b];
+                std::vector<int32_t> fill(start.begin(), start.end() - 1);
+                for (int i = 0; i < np; ++i) T.perm[p0 + fill[K.pn[p0 + i] - nlo]++] = i;
+                T.s0.push_back((int32_t)(T.seg.size() / 3));
+                T.nlo.push_back(nlo);
+                T.nn.push_back(nn);
+                for (int b = 0; b < nn; ++b)
+                    for (int f = start[b]; f < start[b + 1]; f += 64)
+                        T.seg.insert(T.seg.end(), {b, f, std::min(64, start[b + 1] - f)});
+                T.ns.push_back((int32_t)(T.seg.size() / 3) - T.s0.back());
+            }
+            if (T.seg.empty()) T.seg.assign(3, 0);
+            up.add(T.perm, &T.d_perm);
+            up.add(T.seg, &T.d_seg);
+        }
+    return do_upload(B.c, up, B.s, (std::string(table_buf) + "_pawn").c_str());
+}
+
 int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs, int nq,
                bool need_ec, bool need_chi, const char* table_buf, const int32_t* pn = nullptr,
                const int32_t* pm = nullptr, int npairs = -1, const int* qk = nullptr) {
@@ -1849,7 +1936,9 @@ int plan_batch(Batch& B, const rpa_states* k, const rpa_states* kq, int nk, cons
     rc = do_upload(c, up, B.s, table_buf);
     if (rc) return rc;
     WorkSizes W;
-    return presize(B, need_ec, need_chi, W);
+    rc = presize(B, need_ec, need_chi, W);
+    if (rc) return rc;
+    return build_pawn(B, table_buf);
 }
 
 // ------------------------------------------------------------ the adjoint

@@ -285,11 +285,12 @@ def test_o2box_pair_density_register_path(rpa, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
-def test_paw_term_in_band_windows(rpa, prec):
-    """The MFMA PAW term in passes of at most 7 bands m (48^3 grid, NG = 1500, 4 + 40 states): pair
-    densities in the oracle's order (n-major: every pass a run of consecutive pairs) and chi0 in the
-    library's m-major order equal those of one pass per chunk bit for bit, and the pair densities equal
-    the oracle's."""
+def test_paw_term_forms_and_band_windows(rpa, prec):
+    """The PAW term's two MFMA forms (48^3 grid, NG = 1500, 4 + 40 states): factorised per band n (the
+    default here: chunks span 4 bands n and 40 bands m) and per band m, in one pass per chunk (window bound
+    1000) or in passes of at most 7 bands m. Pair densities in the oracle's order (n-major: every pass a
+    run of consecutive pairs) against the oracle for every form; pair densities and chi0 of the m form
+    equal bit for bit whatever the window."""
     wl = synth.config1(n_occ=4, n_unocc=40, which_q=(1,))
     ks, kqs, qs, fr, gm = gpu_inputs(rpa, wl)
     s = wl.kpoints[0]
@@ -297,19 +298,22 @@ def test_paw_term_in_band_windows(rpa, prec):
     Q = synth.paw_q_table(wl.paw, wl.A, wl.qpoints[0].q, gm)
     _, ref = oracle.pair_densities(wl.A, wl.grid, s, s, gm, Q, wl.paw.offsets, wl.qpoints[0].optical,
                                    wl.qpoints[0].qhat, synth.paw_d_table(wl.paw))
+    out = {}
     with rpa.Context(wl.A, wl.grid) as ctx:
-        rho1 = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
-        chi1 = ctx.chi0(ks, ks, qs, fr, prec).cpu().numpy()
-        ctx.set_paw_window(7)
-        rho7 = ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy()
-        chi7 = ctx.chi0(ks, ks, qs, fr, prec).cpu().numpy()
+        for win in (0, 1000, 7):
+            ctx.set_paw_window(win)
+            out[win] = (ctx.pair_density(ks[0], ks[0], qs, pairs[0], pairs[1], prec).cpu().numpy(),
+                        ctx.chi0(ks, ks, qs, fr, prec).cpu().numpy())
         with pytest.raises(rpa.RpaError):
             ctx.set_paw_window(-1)
     tol = 1e-12 if prec == "fp64" else 2e-6
-    print(f"paw windows {prec}: rho rel={_rel(rho7, ref):.3e}", flush=True)
-    assert np.array_equal(rho1, rho7)
-    assert np.array_equal(chi1, chi7)
-    assert _rel(rho7, ref) < tol
+    for win, (rho, chi) in out.items():
+        print(f"paw window {win} {prec}: rho rel={_rel(rho, ref):.3e} chi vs n form "
+              f"{_rel(chi, out[0][1]):.3e}", flush=True)
+        assert _rel(rho, ref) < tol
+        assert _rel(chi, out[0][1]) < (1e-12 if prec == "fp64" else 1e-5)
+    assert np.array_equal(out[1000][0], out[7][0])
+    assert np.array_equal(out[1000][1], out[7][1])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
