@@ -367,12 +367,15 @@ int rpa_set_autotune(rpa_ctx* ctx, int enable);
  * RPA_ERR_INPUT if max_pairs < 0. */
 int rpa_set_chunk_pairs(rpa_ctx* ctx, int max_pairs);
 
-/* Upper bound on the bands m of one pass of the PAW correction's MFMA form
- * (Eq. n_G_2 factorised per band m: Z_m = Q P'_m, then rho_p += conj(P_n) Z_m
- * for the pairs of each m). 0 (default): a pass covers every band m of a pair
- * chunk, or as many as a Z buffer of 2 GiB (an eighth of the cap when one is
- * set) holds; a chunk whose pairs span more bands runs in several passes over
- * consecutive pairs. The pair densities do not depend on the bound.
+/* The PAW correction (Eq. n_G_2) runs on MFMA in one of two factorised forms:
+ * per band n (Y_n = conj(P_n) Q, then rho_p += P'_m . Y_n for the pairs of
+ * each n), chosen by default where the pairs span fewer bands n than bands m
+ * and Y fits 2 GiB (an eighth of the cap when one is set), or per band m
+ * (Z_m = Q P'_m, then rho_p += conj(P_n) . Z_m), in passes over consecutive
+ * pairs whose bands m fit a Z buffer of that size. max_bands > 0 selects the
+ * per-m form with at most max_bands bands m per pass; 0 (default) restores
+ * the automatic choice. Pair densities of one form do not depend on the
+ * bound or the chunking; the two forms agree to rounding.
  * RPA_ERR_INPUT if max_bands < 0. */
 int rpa_set_paw_window(rpa_ctx* ctx, int max_bands);
 int rpa_tune_set(rpa_ctx* ctx, rpa_precision prec, int NG, int variant);

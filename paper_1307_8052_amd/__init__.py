@@ -444,7 +444,8 @@ class Context:
         _check(self._L.rpa_set_chunk_pairs(self._h, int(max_pairs)), self._h)
 
     def set_paw_window(self, max_bands: int):
-        """Upper bound on the bands m of one pass of the MFMA PAW term (0: set by the Z buffer's size)."""
+        """max_bands > 0: the PAW term factorised per band m, at most max_bands bands per pass; 0: the form and
+        the passes chosen automatically (rpa_set_paw_window)."""
         _check(self._L.rpa_set_paw_window(self._h, int(max_bands)), self._h)
 
     def tune_set(self, NG: int, variant: int, precision="split_bf16"):
