@@ -725,7 +725,7 @@ hipError_t launch_xyadj_reg(const cplx<double>* tadj, const PairGeom& g, const i
     if (!nseg) return hipSuccess;
     if (!xyadj_reg_supported(g)) return hipErrorNotSupported;
     const long long tasks = (long long)nseg * g.N3;
-    if (tasks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (tasks * 4 * g.N1 >= (1LL << 32)) return hipErrorInvalidValue;  // grid of at most 2^32 - 1 lanes
     switch (g.N1) {
 #define RPA_CASE(L)                                                                                             \
     case L:                                                                                                     \
