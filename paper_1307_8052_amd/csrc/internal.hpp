@@ -116,6 +116,10 @@ hipError_t launch_chi_out_real(const double* Cre, const double* Cim, int ldC, in
 // PAW term as an MFMA GEMM (k_paw.hip): Z_m = Q P'_m for m = m_lo .. m_lo + nslots - 1 into Zr/Zi
 // [nslots][nproj][NGp], then rho[p] += conj(P_k[pn[p]]) Z_{pm[p]} for the npairs pairs (pm within the
 // slots); NGp a multiple of 64
+// Y_n for n = n_lo .. n_lo + nslots - 1 into Yr/Yi [nslots][nproj][NGp] (eight bands per thread)
+template <typename T>
+hipError_t launch_paw_yn(const double* Pk, int ldP, int n_lo, int nslots, const int32_t* proj_off, const int32_t* qoff,
+                         int natoms, int nproj, const double* Q, int NG, int NGp, T* Yr, T* Yi, hipStream_t s);
 // The n-factorised MFMA form: rho[perm[f + r]] += P_kq[pm[perm[f + r]]] . Y[n] for the nseg segments
 // (n - n_lo, f, count <= 64) of seg, with Y [n - n_lo][nproj][NGp] from launch_paw_y; NGp a multiple of 64
 template <typename T>

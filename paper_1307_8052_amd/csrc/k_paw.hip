@@ -79,6 +79,52 @@ __global__ __launch_bounds__(256) void k_paw_z(const double* __restrict__ Pkq, i
     }
 }
 
+// Y[s][aj][g] for n = n_lo + s: sum_i conj(P[n][a i]) Q[qoff_a + i Np_a + j][g]; zero for g >= NG. As in
+// k_paw_z a thread takes kZSlots consecutive bands n, so each element of Q is read once per kZSlots bands.
+template <typename T>
+__global__ __launch_bounds__(256) void k_paw_yn(const double* __restrict__ Pk, int ldP, int n_lo, int nslots,
+                                                const int32_t* __restrict__ proj_off, const int32_t* __restrict__ qoff,
+                                                int natoms, int nproj, const double* __restrict__ Q, int NG, int NGp,
+                                                T* __restrict__ Yr, T* __restrict__ Yi) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int aj = blockIdx.y;
+    const int s0 = blockIdx.z * kZSlots;
+    if (g >= NGp) return;
+    int a = 0;
+    while (a + 1 < natoms && proj_off[a + 1] <= aj) ++a;
+    const int lo = proj_off[a], np = proj_off[a + 1] - lo, j = aj - lo;
+    const int ns = min(kZSlots, nslots - s0);
+    double sr[kZSlots], si[kZSlots];
+#pragma unroll
+    for (int t = 0; t < kZSlots; ++t) {
+        sr[t] = 0.0;
+        si[t] = 0.0;
+    }
+    if (g < NG) {
+        const double* qcol = Q + 2 * ((size_t)(qoff[a] + j) * NG + g);
+        for (int i = 0; i < np; ++i) {
+            const double qr = qcol[2 * (size_t)i * np * NG], qi = qcol[2 * (size_t)i * np * NG + 1];
+#pragma unroll
+            for (int t = 0; t < kZSlots; ++t) {
+                // slots past the last are clamped to it (computed and not stored)
+                const size_t n = (size_t)(n_lo + s0 + min(t, ns - 1));
+                const double pr = Pk[2 * (n * ldP + lo + i)], pi = Pk[2 * (n * ldP + lo + i) + 1];
+                // conj(p) q
+                sr[t] += pr * qr + pi * qi;
+                si[t] += pr * qi - pi * qr;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kZSlots; ++t) {
+        if (t < ns) {
+            const size_t o = ((size_t)(s0 + t) * nproj + aj) * NGp + g;
+            Yr[o] = T(sr[t]);
+            Yi[o] = T(si[t]);
+        }
+    }
+}
+
 // One workgroup per (64 G-vectors, 64 consecutive pairs of the chunk). The pairs of the window are taken
 // in runs of equal m (one GEMM pass per run: the B operand Z_m is shared by the run's rows); rows outside
 // the run are computed and discarded.
@@ -275,6 +321,21 @@ hipError_t launch_paw_mfma(const double* Pk, const double* Pkq, int ldP, const i
     hipLaunchKernelGGL(k_paw_mm<T>, gm, dim3(256), 0, s, Zr, Zi, nproj, Pk, ldP, pn, pm, npairs, m_lo, NGp, rre, rim);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_paw_yn(const double* Pk, int ldP, int n_lo, int nslots, const int32_t* proj_off, const int32_t* qoff,
+                         int natoms, int nproj, const double* Q, int NG, int NGp, T* Yr, T* Yi, hipStream_t s) {
+    if (!nslots || !nproj) return hipSuccess;
+    dim3 grid((unsigned)((NGp + 255) / 256), (unsigned)nproj, (unsigned)((nslots + kZSlots - 1) / kZSlots));
+    hipLaunchKernelGGL(k_paw_yn<T>, grid, dim3(256), 0, s, Pk, ldP, n_lo, nslots, proj_off, qoff, natoms, nproj, Q, NG,
+                       NGp, Yr, Yi);
+    return hipGetLastError();
+}
+
+template hipError_t launch_paw_yn<float>(const double*, int, int, int, const int32_t*, const int32_t*, int, int,
+                                         const double*, int, int, float*, float*, hipStream_t);
+template hipError_t launch_paw_yn<double>(const double*, int, int, int, const int32_t*, const int32_t*, int, int,
+                                          const double*, int, int, double*, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_paw_mfma_n(const T* Yr, const T* Yi, int nproj, const double* Pkq, int ldP, const int32_t* pm,

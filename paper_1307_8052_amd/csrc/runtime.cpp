@@ -1253,10 +1253,10 @@ int enqueue_pairs(Batch& B, QJob& Q, KSet& K, int ik, const cplx<T>* phik, const
         T* Yre = static_cast<T*>(buf(B, "paw_y"));
         T* Yim = Yre + (size_t)nn * nproj * g.NGp;
         ProfScope ps_(c, S_PAW, B.s);
-        HIP_TRY(launch_paw_y<T>(static_cast<const double*>(K.k->P), nproj, static_cast<const int32_t*>(K.d_nlist) + nlo,
-                                nn, static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
-                                K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Yre, Yim,
-                                B.s));
+        HIP_TRY(launch_paw_yn<T>(static_cast<const double*>(K.k->P), nproj, nlo, nn,
+                                 static_cast<const int32_t*>(B.d_poff), static_cast<const int32_t*>(B.d_qoff),
+                                 K.k->natoms, nproj, static_cast<const double*>(Q.qs->Qpaw), g.NG, g.NGp, Yre, Yim,
+                                 B.s));
         HIP_TRY(launch_paw_mfma_n<T>(Yre, Yim, nproj, static_cast<const double*>(K.kq->P), nproj, pm,
                                      static_cast<const int32_t*>(PT.d_seg) + 3 * (size_t)PT.s0[ci], PT.ns[ci],
                                      static_cast<const int32_t*>(PT.d_perm) + p0, g.NGp, rre, rim, B.s));
