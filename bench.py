@@ -603,7 +603,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); the path "
-              f"shards over pair chunks or q-points with one reduce-scatter of chi0, which this build does not "
+              f"shards over pair chunks or q-points with one reduce-scatter of chi0, which this program does not "
               f"launch.", file=sys.stderr)
         sys.exit(2)
 
