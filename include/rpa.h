@@ -395,8 +395,9 @@ int rpa_check(rpa_ctx* ctx, void* stream);
  * FP16 scales ahead of each rank-k update), "herk" (the rank-k update kernel of
  * chi0 alone, one launch per pair chunk and frequency set), "cholesky" (the
  * whole E_c stage), and for rpa_ec_backward "adjoint_inverse" ((1 - K)^-1 from
- * the Cholesky factor and W(omega)), "adjoint_gemm" (the products W(omega) rho,
- * one per pair chunk and frequency), "adjoint_pairs" (the z and x-y adjoint
+ * the Cholesky factor and W(omega)), "adjoint_gemm" (the products W(omega) rho
+ * of a pair chunk: one batched launch for all frequencies where their products
+ * fit 8 GiB and NG <= 4096, else one per frequency), "adjoint_pairs" (the z and x-y adjoint
  * transforms with the orbital products) or "adjoint_rest" (weights, energies,
  * PAW and optical adjoints, the coefficient transforms).
  * RPA_ERR_INPUT for an unknown stage name. */

@@ -297,6 +297,62 @@ __global__ __launch_bounds__(256) void k_grad_weights(const double* __restrict__
     if (threadIdx.x == 0) dEda[(size_t)w * lda + p] = c * red[0];
 }
 
+// All frequencies at once, from Y [w][pair][NGp] (stride sY between frequencies): per pair p,
+// g_p = sum_w c_w 2 a_p(w) Y_p(w) and dEda[w][p] = c_w Re(rho_p^H Y_p(w)); a thread keeps its kGwPer entries
+// of rho_p and g_p in registers over the frequencies (NG <= 256 kGwPer).
+constexpr int kGwPer = 16;
+__global__ __launch_bounds__(256) void k_grad_weights_all(const double* __restrict__ rr, const double* __restrict__ ri,
+                                                          const double* __restrict__ yr, const double* __restrict__ yi,
+                                                          size_t sY, int NG, int NGp, const double* __restrict__ a,
+                                                          int lda, int nw, const double* __restrict__ cw,
+                                                          double* __restrict__ gr, double* __restrict__ gi,
+                                                          double* __restrict__ dEda) {
+    __shared__ double red[256];
+    const size_t p = blockIdx.x;
+    double xr[kGwPer], xi[kGwPer], hr[kGwPer], hi[kGwPer];
+#pragma unroll
+    for (int e = 0; e < kGwPer; ++e) {
+        const int i = threadIdx.x + 256 * e;
+        xr[e] = i < NG ? rr[p * NGp + i] : 0.0;
+        xi[e] = i < NG ? ri[p * NGp + i] : 0.0;
+        hr[e] = 0.0;
+        hi[e] = 0.0;
+    }
+    for (int w = 0; w < nw; ++w) {
+        const double c = cw[w];
+        const double f = 2.0 * c * a[(size_t)w * lda + p];
+        const double* ywr = yr + (size_t)w * sY + p * NGp;
+        const double* ywi = yi + (size_t)w * sY + p * NGp;
+        double dot = 0.0;
+#pragma unroll
+        for (int e = 0; e < kGwPer; ++e) {
+            const int i = threadIdx.x + 256 * e;
+            if (i < NG) {
+                const double y_r = ywr[i], y_i = ywi[i];
+                dot += xr[e] * y_r + xi[e] * y_i;
+                hr[e] += f * y_r;
+                hi[e] += f * y_i;
+            }
+        }
+        red[threadIdx.x] = dot;
+        __syncthreads();
+        for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dEda[(size_t)w * lda + p] = c * red[0];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < kGwPer; ++e) {
+        const int i = threadIdx.x + 256 * e;
+        if (i < NG) {
+            gr[p * NGp + i] += hr[e];
+            gi[p * NGp + i] += hi[e];
+        }
+    }
+}
+
 // u_p = sum_w dE/da_p(w) da_p(w)/d(e_n - e_m)   (energy gradient per pair, n side +, m side -)
 __global__ void k_pair_eps(const double* __restrict__ dEda, int lda, int nw, const double* __restrict__ epsk,
                            const double* __restrict__ epskq, const double* __restrict__ fk,
@@ -654,6 +710,16 @@ hipError_t launch_grad_weights(const double* rr, const double* ri, const double*
     if (!npairs) return hipSuccess;
     hipLaunchKernelGGL(k_grad_weights, dim3((unsigned)npairs), dim3(256), 0, s, rr, ri, yr, yi, NG, NGp, a, lda, w, cw,
                        gr, gi, dEda);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_weights_all(const double* rr, const double* ri, const double* yr, const double* yi, size_t sY,
+                                   int NG, int NGp, const double* a, int lda, int nw, const double* cw, double* gr,
+                                   double* gi, double* dEda, int npairs, hipStream_t s) {
+    if (!npairs) return hipSuccess;
+    if (NG > 256 * kGwPer) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grad_weights_all, dim3((unsigned)npairs), dim3(256), 0, s, rr, ri, yr, yi, sY, NG, NGp, a, lda,
+                       nw, cw, gr, gi, dEda);
     return hipGetLastError();
 }
 

@@ -2075,7 +2075,10 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         maxphib = std::max(maxphib, (size_t)(nbk + (same ? 0 : nbq)) * vol);
     }
 
-    // buffers (sized for every set)
+    // buffers (sized for every set); the products W(w) rho of all frequencies in one batched GEMM where
+    // they fit 8 GiB and the sphere 4096 entries, else one frequency at a time
+    const size_t ybytes = 2 * (size_t)Pc * NGp * 8;
+    const bool yall = NG <= 4096 && ybytes * nw <= ((size_t)8 << 30) && !c->arena;
     const size_t mat = (size_t)nw * NGp * NGp;
     void *pB, *pX, *pL, *pY, *pG, *pdE, *pu, *pcw, *pZ, *pU, *pgn, *pT, *pPb, *pPart;
     struct NB {
@@ -2084,7 +2087,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         void** p;
     } list[] = {{"bw_B", 2 * mat * 8, &pB}, {"bw_X", 2 * mat * 8, &pX},
                 {"bw_L", (size_t)(NGp / kTile) * 2 * nw * kTile * kTile * 8, &pL},
-                {"bw_Y", 2 * (size_t)Pc * NGp * 8, &pY}, {"bw_g", 2 * (size_t)Pc * NGp * 8, &pG},
+                {"bw_Y", ybytes * (yall ? nw : 1), &pY}, {"bw_g", 2 * (size_t)Pc * NGp * 8, &pG},
                 {"bw_dEda", (size_t)nw * ((Pc + 3) / 4 * 4) * 8, &pdE}, {"bw_u", (size_t)maxP * 8, &pu},
                 {"bw_cw", 64 * 8, &pcw}, {"bw_Z", 4 * (size_t)Pc * std::max(nproj, 1) * 8, &pZ},
                 {"bw_U", 2 * (size_t)maxm * std::max(nproj, 1) * NGp * 8, &pU}, {"bw_gnum", 2 * (size_t)Pc * 8, &pgn},
@@ -2243,7 +2246,21 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                                    np, static_cast<const double*>(B.d_om), nw, prefac, aw, lda, B.s));
             HIP_TRY(launch_zero_d(gr, 2 * (size_t)Pc * NGp, B.s));
             pr_.reset();
-            for (int w = 0; w < nw; ++w) {
+            if (yall) {
+                GemmArgs gy{};
+                gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = nw;
+                gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
+                gy.Br = Br_; gy.Bi = Bi_; gy.sB = (long long)NGp * NGp; gy.bK = 1; gy.bJ = NGp;
+                gy.Cr = Yr; gy.Ci = Yi; gy.sC = (long long)(ybytes / 8); gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
+                {
+                    ProfScope pg_(c, S_BW_GEMM, B.s);
+                    HIP_TRY(launch_gemm_c64(gy, B.s));
+                }
+                ProfScope pw_(c, S_BW_REST, B.s);
+                HIP_TRY(launch_grad_weights_all(rre, rim, Yr, Yi, ybytes / 8, NG, NGp, aw, lda, nw, cw, gr, gi, dEda, np,
+                                                B.s));
+            }
+            for (int w = 0; w < nw && !yall; ++w) {
                 GemmArgs gy{};
                 gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = 1;
                 gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
