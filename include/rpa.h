@@ -317,8 +317,8 @@ int rpa_ec_batched_sets(rpa_ctx* ctx, int nq, const rpa_states* const* k, const 
  * v^1/2 are formed once; then every pair's densities are recomputed chunk by
  * chunk and rho_bar = sum_w c_w 2 a(w) W(w) rho is taken back through the
  * optical row, the PAW term, the pruned pair FFT and the orbital FFT.
- * RPA_ERR_UNSUPPORTED if N1*N2 > 4096, for sets with -df/de at an optical
- * q-point and for sets with a symmetry operation. */
+ * RPA_ERR_UNSUPPORTED if N1*N2 > 4096, for more than 64 frequencies, for sets
+ * with -df/de at an optical q-point and for sets with a symmetry operation. */
 int rpa_ec_backward(rpa_ctx* ctx, const rpa_states* k, const rpa_states* kq, int nk, const rpa_qspec* qs,
                     const rpa_freq* fr, const double* dEc, double* ec_dev, double* deps_k, void* dC_k, void* dP_k,
                     double* deps_kq, void* dC_kq, void* dP_kq, void* stream);

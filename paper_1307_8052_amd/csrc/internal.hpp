@@ -237,13 +237,11 @@ hipError_t launch_gemm_c64_shortk(const GemmArgs& g, hipStream_t s);
 hipError_t launch_identity(double* Xr, double* Xi, int n, int ld, int nb, hipStream_t s);
 hipError_t launch_build_w(double* Mr, double* Mi, int NG, int NGp, int nw, const double* vs, hipStream_t s);
 hipError_t launch_freq_coeffs(const double* dE, const double* ow, int nw, double* cw, hipStream_t s);
-// all nw frequencies in one launch, Y [w] at yr/yi + w sY (NG <= 4096)
+// all nw frequencies in one launch, Y [w] at yr/yi + w sY (nw <= 256)
 hipError_t launch_grad_weights_all(const double* rr, const double* ri, const double* yr, const double* yi, size_t sY,
                                    int NG, int NGp, const double* a, int lda, int nw, const double* cw, double* gr,
                                    double* gi, double* dEda, int npairs, hipStream_t s);
-hipError_t launch_grad_weights(const double* rr, const double* ri, const double* yr, const double* yi, int NG, int NGp,
-                               const double* a, int lda, int w, const double* cw, double* gr, double* gi, double* dEda,
-                               int npairs, hipStream_t s);
+
 hipError_t launch_pair_eps(const double* dEda, int lda, int nw, const double* epsk, const double* epskq,
                            const double* fk, const double* fkq, const int32_t* pn, const int32_t* pm, int npairs,
                            const double* omega, double prefac, double* u, hipStream_t s);

@@ -270,37 +270,12 @@ __global__ void k_freq_coeffs(const double* __restrict__ dE, const double* __res
     if (w < nw) cw[w] = dE[0] * ow[w] / (2.0 * kPi);
 }
 
-// per pair p: g_p += c_w 2 a_p(w) Y_p (Y_p = W rho_p), dEda[w][p] = c_w Re(rho_p^H Y_p)
-__global__ __launch_bounds__(256) void k_grad_weights(const double* __restrict__ rr, const double* __restrict__ ri,
-                                                      const double* __restrict__ yr, const double* __restrict__ yi,
-                                                      int NG, int NGp, const double* __restrict__ a, int lda, int w,
-                                                      const double* __restrict__ cw, double* __restrict__ gr,
-                                                      double* __restrict__ gi, double* __restrict__ dEda) {
-    __shared__ double red[256];
-    const size_t p = blockIdx.x;
-    const double c = cw[w];
-    const double f = 2.0 * c * a[(size_t)w * lda + p];
-    double dot = 0.0;
-    for (int i = threadIdx.x; i < NG; i += blockDim.x) {
-        const size_t o = p * NGp + i;
-        const double y_r = yr[o], y_i = yi[o];
-        dot += rr[o] * y_r + ri[o] * y_i;
-        gr[o] += f * y_r;
-        gi[o] += f * y_i;
-    }
-    red[threadIdx.x] = dot;
-    __syncthreads();
-    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) dEda[(size_t)w * lda + p] = c * red[0];
-}
-
 // All frequencies at once, from Y [w][pair][NGp] (stride sY between frequencies): per pair p,
-// g_p = sum_w c_w 2 a_p(w) Y_p(w) and dEda[w][p] = c_w Re(rho_p^H Y_p(w)); a thread keeps its kGwPer entries
-// of rho_p and g_p in registers over the frequencies (NG <= 256 kGwPer).
+// g_p += sum_w c_w 2 a_p(w) Y_p(w) and dEda[w][p] = c_w Re(rho_p^H Y_p(w)), with Y_p(w) = W(w) rho_p. The
+// sphere goes in segments of 256 kGwPer entries, whose rho_p and g_p a thread keeps in registers over the
+// frequencies; the dot products of the segments add up in LDS (nw <= kGwMaxW).
 constexpr int kGwPer = 16;
+constexpr int kGwMaxW = 256;
 __global__ __launch_bounds__(256) void k_grad_weights_all(const double* __restrict__ rr, const double* __restrict__ ri,
                                                           const double* __restrict__ yr, const double* __restrict__ yi,
                                                           size_t sY, int NG, int NGp, const double* __restrict__ a,
@@ -308,49 +283,54 @@ __global__ __launch_bounds__(256) void k_grad_weights_all(const double* __restri
                                                           double* __restrict__ gr, double* __restrict__ gi,
                                                           double* __restrict__ dEda) {
     __shared__ double red[256];
+    __shared__ double sdot[kGwMaxW];
     const size_t p = blockIdx.x;
-    double xr[kGwPer], xi[kGwPer], hr[kGwPer], hi[kGwPer];
-#pragma unroll
-    for (int e = 0; e < kGwPer; ++e) {
-        const int i = threadIdx.x + 256 * e;
-        xr[e] = i < NG ? rr[p * NGp + i] : 0.0;
-        xi[e] = i < NG ? ri[p * NGp + i] : 0.0;
-        hr[e] = 0.0;
-        hi[e] = 0.0;
-    }
-    for (int w = 0; w < nw; ++w) {
-        const double c = cw[w];
-        const double f = 2.0 * c * a[(size_t)w * lda + p];
-        const double* ywr = yr + (size_t)w * sY + p * NGp;
-        const double* ywi = yi + (size_t)w * sY + p * NGp;
-        double dot = 0.0;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) sdot[w] = 0.0;
+    for (int base = 0; base < NG; base += 256 * kGwPer) {
+        double xr[kGwPer], xi[kGwPer], hr[kGwPer], hi[kGwPer];
 #pragma unroll
         for (int e = 0; e < kGwPer; ++e) {
-            const int i = threadIdx.x + 256 * e;
-            if (i < NG) {
-                const double y_r = ywr[i], y_i = ywi[i];
-                dot += xr[e] * y_r + xi[e] * y_i;
-                hr[e] += f * y_r;
-                hi[e] += f * y_i;
-            }
+            const int i = base + threadIdx.x + 256 * e;
+            xr[e] = i < NG ? rr[p * NGp + i] : 0.0;
+            xi[e] = i < NG ? ri[p * NGp + i] : 0.0;
+            hr[e] = 0.0;
+            hi[e] = 0.0;
         }
-        red[threadIdx.x] = dot;
-        __syncthreads();
-        for (int k = blockDim.x / 2; k > 0; k >>= 1) {
-            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        for (int w = 0; w < nw; ++w) {
+            const double f = 2.0 * cw[w] * a[(size_t)w * lda + p];
+            const double* ywr = yr + (size_t)w * sY + p * NGp;
+            const double* ywi = yi + (size_t)w * sY + p * NGp;
+            double dot = 0.0;
+#pragma unroll
+            for (int e = 0; e < kGwPer; ++e) {
+                const int i = base + threadIdx.x + 256 * e;
+                if (i < NG) {
+                    const double y_r = ywr[i], y_i = ywi[i];
+                    dot += xr[e] * y_r + xi[e] * y_i;
+                    hr[e] += f * y_r;
+                    hi[e] += f * y_i;
+                }
+            }
+            red[threadIdx.x] = dot;
+            __syncthreads();
+            for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+                if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) sdot[w] += red[0];
             __syncthreads();
         }
-        if (threadIdx.x == 0) dEda[(size_t)w * lda + p] = c * red[0];
-        __syncthreads();
-    }
 #pragma unroll
-    for (int e = 0; e < kGwPer; ++e) {
-        const int i = threadIdx.x + 256 * e;
-        if (i < NG) {
-            gr[p * NGp + i] += hr[e];
-            gi[p * NGp + i] += hi[e];
+        for (int e = 0; e < kGwPer; ++e) {
+            const int i = base + threadIdx.x + 256 * e;
+            if (i < NG) {
+                gr[p * NGp + i] += hr[e];
+                gi[p * NGp + i] += hi[e];
+            }
         }
     }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) dEda[(size_t)w * lda + p] = cw[w] * sdot[w];
 }
 
 // u_p = sum_w dE/da_p(w) da_p(w)/d(e_n - e_m)   (energy gradient per pair, n side +, m side -)
@@ -704,20 +684,11 @@ hipError_t launch_freq_coeffs(const double* dE, const double* ow, int nw, double
     return hipGetLastError();
 }
 
-hipError_t launch_grad_weights(const double* rr, const double* ri, const double* yr, const double* yi, int NG, int NGp,
-                               const double* a, int lda, int w, const double* cw, double* gr, double* gi, double* dEda,
-                               int npairs, hipStream_t s) {
-    if (!npairs) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_weights, dim3((unsigned)npairs), dim3(256), 0, s, rr, ri, yr, yi, NG, NGp, a, lda, w, cw,
-                       gr, gi, dEda);
-    return hipGetLastError();
-}
-
 hipError_t launch_grad_weights_all(const double* rr, const double* ri, const double* yr, const double* yi, size_t sY,
                                    int NG, int NGp, const double* a, int lda, int nw, const double* cw, double* gr,
                                    double* gi, double* dEda, int npairs, hipStream_t s) {
     if (!npairs) return hipSuccess;
-    if (NG > 256 * kGwPer) return hipErrorInvalidValue;
+    if (nw > kGwMaxW) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_grad_weights_all, dim3((unsigned)npairs), dim3(256), 0, s, rr, ri, yr, yi, sY, NG, NGp, a, lda,
                        nw, cw, gr, gi, dEda);
     return hipGetLastError();

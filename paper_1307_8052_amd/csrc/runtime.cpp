@@ -2075,10 +2075,12 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         maxphib = std::max(maxphib, (size_t)(nbk + (same ? 0 : nbq)) * vol);
     }
 
-    // buffers (sized for every set); the products W(w) rho of all frequencies in one batched GEMM where
-    // they fit 8 GiB and the sphere 4096 entries, else one frequency at a time
-    const size_t ybytes = 2 * (size_t)Pc * NGp * 8;
-    const bool yall = NG <= 4096 && ybytes * nw <= ((size_t)8 << 30) && !c->arena;
+    // buffers (sized for every set); the products W(w) rho of all frequencies in one batched GEMM per run
+    // of at most kYRows pairs of a chunk (and at most 8 GiB of products)
+    constexpr int kYRows = 4096;
+    const size_t yrow = 2 * (size_t)NGp * 8 * nw;   // bytes of one pair's products, all frequencies
+    const int yrows = (int)std::max<size_t>(1, std::min<size_t>({(size_t)Pc, (size_t)kYRows, ((size_t)8 << 30) / yrow}));
+    const size_t ybytes = 2 * (size_t)yrows * NGp * 8;   // one frequency's products of a run
     const size_t mat = (size_t)nw * NGp * NGp;
     void *pB, *pX, *pL, *pY, *pG, *pdE, *pu, *pcw, *pZ, *pU, *pgn, *pT, *pPb, *pPart;
     struct NB {
@@ -2087,7 +2089,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
         void** p;
     } list[] = {{"bw_B", 2 * mat * 8, &pB}, {"bw_X", 2 * mat * 8, &pX},
                 {"bw_L", (size_t)(NGp / kTile) * 2 * nw * kTile * kTile * 8, &pL},
-                {"bw_Y", ybytes * (yall ? nw : 1), &pY}, {"bw_g", 2 * (size_t)Pc * NGp * 8, &pG},
+                {"bw_Y", ybytes * nw, &pY}, {"bw_g", 2 * (size_t)Pc * NGp * 8, &pG},
                 {"bw_dEda", (size_t)nw * ((Pc + 3) / 4 * 4) * 8, &pdE}, {"bw_u", (size_t)maxP * 8, &pu},
                 {"bw_cw", 64 * 8, &pcw}, {"bw_Z", 4 * (size_t)Pc * std::max(nproj, 1) * 8, &pZ},
                 {"bw_U", 2 * (size_t)maxm * std::max(nproj, 1) * NGp * 8, &pU}, {"bw_gnum", 2 * (size_t)Pc * 8, &pgn},
@@ -2100,7 +2102,7 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
     double* Lb = static_cast<double*>(pL);
     double *Br_ = static_cast<double*>(pB), *Bi_ = Br_ + mat;
     double *Xr = static_cast<double*>(pX), *Xi = Xr + mat;
-    double *Yr = static_cast<double*>(pY), *Yi = Yr + (size_t)Pc * NGp;
+    double *Yr = static_cast<double*>(pY), *Yi = Yr + (size_t)yrows * NGp;
     double *gr = static_cast<double*>(pG), *gi = gr + (size_t)Pc * NGp;
     double* dEda = static_cast<double*>(pdE);
     double* u = static_cast<double*>(pu);
@@ -2246,10 +2248,11 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                                    np, static_cast<const double*>(B.d_om), nw, prefac, aw, lda, B.s));
             HIP_TRY(launch_zero_d(gr, 2 * (size_t)Pc * NGp, B.s));
             pr_.reset();
-            if (yall) {
+            for (int r0 = 0; r0 < np; r0 += yrows) {
+                const int nr = std::min(yrows, np - r0);
                 GemmArgs gy{};
-                gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = nw;
-                gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
+                gy.M = nr; gy.N = NGp; gy.K = NGp; gy.nbatch = nw;
+                gy.Ar = rre + (size_t)r0 * NGp; gy.Ai = rim + (size_t)r0 * NGp; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
                 gy.Br = Br_; gy.Bi = Bi_; gy.sB = (long long)NGp * NGp; gy.bK = 1; gy.bJ = NGp;
                 gy.Cr = Yr; gy.Ci = Yi; gy.sC = (long long)(ybytes / 8); gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
                 {
@@ -2257,22 +2260,9 @@ int backward(Batch& B, const double* dEc, double* ec_dev, const std::vector<BwOu
                     HIP_TRY(launch_gemm_c64(gy, B.s));
                 }
                 ProfScope pw_(c, S_BW_REST, B.s);
-                HIP_TRY(launch_grad_weights_all(rre, rim, Yr, Yi, ybytes / 8, NG, NGp, aw, lda, nw, cw, gr, gi, dEda, np,
-                                                B.s));
-            }
-            for (int w = 0; w < nw && !yall; ++w) {
-                GemmArgs gy{};
-                gy.M = np; gy.N = NGp; gy.K = NGp; gy.nbatch = 1;
-                gy.Ar = rre; gy.Ai = rim; gy.sA = 0; gy.aI = NGp; gy.aK = 1;
-                gy.Br = Br_ + (size_t)w * NGp * NGp; gy.Bi = Bi_ + (size_t)w * NGp * NGp; gy.sB = 0; gy.bK = 1;
-                gy.bJ = NGp;
-                gy.Cr = Yr; gy.Ci = Yi; gy.sC = 0; gy.ldC = NGp; gy.alpha = 1.0; gy.beta = 0;
-                {
-                    ProfScope pg_(c, S_BW_GEMM, B.s);
-                    HIP_TRY(launch_gemm_c64(gy, B.s));
-                }
-                ProfScope pw_(c, S_BW_REST, B.s);
-                HIP_TRY(launch_grad_weights(rre, rim, Yr, Yi, NG, NGp, aw, lda, w, cw, gr, gi, dEda, np, B.s));
+                HIP_TRY(launch_grad_weights_all(rre + (size_t)r0 * NGp, rim + (size_t)r0 * NGp, Yr, Yi, ybytes / 8, NG,
+                                                NGp, aw + r0, lda, nw, cw, gr + (size_t)r0 * NGp,
+                                                gi + (size_t)r0 * NGp, dEda + r0, nr, B.s));
             }
             pr_.emplace(c, S_BW_REST, B.s);
             HIP_TRY(launch_pair_eps(dEda, lda, nw, static_cast<const double*>(K.d_epsk),
@@ -2882,6 +2872,7 @@ int rpa_ec_backward(rpa_ctx* c, const rpa_states* k, const rpa_states* kq, int n
     if (rc) return rc;
     if (!fr || !dEc || !ec_dev || !deps_k || !dC_k) return fail(RPA_ERR_INPUT, "NULL argument");
     if ((long long)c->N[0] * c->N[1] > 16 * 256) return fail(RPA_ERR_UNSUPPORTED, "adjoint needs N1*N2 <= 4096");
+    if (fr->nw > 64) return fail(RPA_ERR_UNSUPPORTED, "the adjoint takes at most 64 frequencies");
     // gradient slots: set i of k (of kq) at the sum of the sizes of sets 0 .. i-1 of k (of kq)
     std::vector<BwOut> outk(nk), outkq(nk);
     size_t ek = 0, ck = 0, pk = 0, eq = 0, cq = 0, pq = 0;

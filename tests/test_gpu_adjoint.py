@@ -120,6 +120,18 @@ def test_adjoint_stage_profiler(rpa):
     assert all(v[0] > 0 for v in prof.values() if v[1])
 
 
+def test_adjoint_rejects_more_than_64_frequencies(rpa):
+    """The adjoint takes at most 64 frequencies: 65 is RPA_ERR_UNSUPPORTED before any launch."""
+    wl = synth.tiny(grid=(8, 8, 8), n_occ=2, n_unocc=4, target_ng=15, nw=8)
+    ks, _, qs, _, _ = gpu_inputs(rpa, wl)
+    x = np.linspace(0.01, 0.99, 65)
+    fr = rpa.Freq(x / (1 - x), np.full(65, 0.01))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        with pytest.raises(rpa.RpaError) as ei:
+            ctx.ec_backward(ks[0], ks[0], qs, fr)
+        assert ei.value.status == -7
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_adjoint_matches_reference_gradient(rpa, case):
     wl = CASES[case]()
