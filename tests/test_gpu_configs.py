@@ -104,6 +104,29 @@ def test_uneven_batch_reduced(rpa):
         assert abs(eager[i] - ref["E"]) < 1e-10
 
 
+def test_uneven_batch_split_graph_replays(rpa):
+    """Split precision on the slab grid in a captured graph (z passes by quads of lanes, the per-n PAW form,
+    per-class chi0 storage): three replays, each after an eager call of another shape on the same context,
+    every replay bit-identical to the eager batch."""
+    wl = synth.config3(n_occ=4, n_unocc=24, nq=4)
+    ks = [rpa.States.from_synth(wl.kpoints[0], wl.paw, "cuda:0")]
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    qspecs = []
+    for qp in wl.qpoints:
+        gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+        qspecs.append(rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight))
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        eager = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16")[0].cpu().numpy().copy()
+        out = None
+        for rep in range(3):
+            ctx.ec(ks, ks, qspecs[rep % len(qspecs)], fr, "split_bf16")
+            out = ctx.ec_batched(ks, ks, qspecs, fr, "split_bf16", use_graph=True, out=out)
+            got = out[0].cpu().numpy().copy()
+            ctx.check()
+            print(f"replay {rep}: {got[:len(qspecs)]}", flush=True)
+            assert np.array_equal(got, eager), rep
+
+
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
 def test_chi0_add_sums_over_k(rpa, slab, prec):
     """rpa_chi0_add one k-point at a time gives the chi0 of rpa_chi0 over both k-points (Eq. chi0's k sum),
