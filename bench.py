@@ -28,7 +28,10 @@ of those same k-points (the whole q-point by default).
 200-3000, on the slab cell at Gamma; one step = E_c of all 64 in one batched
 call, timed against a loop of single-q calls), and --workload grad the
 differentiation form (E_c(q) and its gradient with respect to eigenvalues,
-coefficients and projections of all 16 + 800 states of the O2 box, FP64).
+coefficients and projections of all 16 + 800 states of the O2 box, FP64);
+--workload spin, unfold and realfreq measure the two-channel (spin-polarised)
+O2 box, sets unfolded from the irreducible zone by a symmetry operation, and
+chi0 at real frequencies.
 """
 from __future__ import annotations
 
@@ -579,6 +582,172 @@ def run_grad(args, torch, rpa, synth):
     return out, wl
 
 
+# --------------------------------------------------------------------------------------- next rows
+def _herk_roofline(prof, flops, prec, steps):
+    herk_ms, herk_n = prof["herk"]
+    achieved = flops * steps / (herk_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    return {"kernel": "grouped complex rank-k update of chi0 (" + ("FP64" if prec == "fp64" else
+                                                                    f"split {prec[6:]} hi/lo") + ")",
+            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "avg_launch_ms": herk_ms / max(herk_n, 1), "launches": herk_n}
+
+
+def _timed(ctx, torch, fn, n, profile=False):
+    r = None
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        r = fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.check()
+    prof = ctx.profile_get() if profile else None
+    ctx.profile(False)
+    return dt, r, prof
+
+
+def run_spin(args, torch, rpa, synth):
+    """Spin polarisation (Sec. 2.2: the spin index of Eq. chi0): the O2 box as a triplet, two channels of
+    16 + 1 and 16 - 1 occupied states (f in [0, 1]) out of 816, q = 0.1 x 2pi/12; one step = E_c(q) from
+    chi0 summed over both channels (one call with two state-set pairs)."""
+    dev = "cuda:0"
+    wl = synth.config1(which_q=(1,), spin_moment=2)
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    ks = [rpa.States.from_synth(s, wl.paw, dev) for s in wl.kpoints]
+    qp = wl.qpoints[0]
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    qs = rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight, device=dev)
+    P = [npairs(s, s) for s in wl.kpoints]
+    NG, nw = qs.NG, fr.nw
+    flops = sum(4.0 * NG * NG * p * nw for p in P)
+    ctx = rpa.Context(wl.A, wl.grid, device=0)
+    prec = args.precision
+    _timed(ctx, torch, lambda: ctx.ec(ks, ks, qs, fr, prec), args.warmup)
+    dt, (ec, _), prof = _timed(ctx, torch, lambda: ctx.ec(ks, ks, qs, fr, prec), args.steps, True)
+    _timed(ctx, torch, lambda: ctx.ec(ks, ks, qs, fr, "fp64"), 1)
+    dt64, (ec64, _), _ = _timed(ctx, torch, lambda: ctx.ec(ks, ks, qs, fr, "fp64"), args.steps)
+    out = {
+        "metric": METRIC, "value": flops * args.steps / dt / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"{prec[6:]}x3 MFMA / f32 FFT / f64 log-det",
+        "data": "synthetic",
+        "config": {"workload": "spin-polarised O2 box: 12x12x13 bohr, 48^3 grid, two spin channels of 816 states "
+                               "(17 and 15 occupied, f in [0, 1]), 2x13 PAW projectors, q = 0.1 x 2pi/12, 16 "
+                               "imaginary frequencies; one step = E_c(q) summed over both channels",
+                   "precision": prec, "NG": NG, "pairs_per_channel": P, "nw": nw},
+        "ec_split": float(ec.cpu()[0]), "ec_fp64": float(ec64.cpu()[0]),
+        "ec_split_minus_fp64_ha": float(ec.cpu()[0]) - float(ec64.cpu()[0]),
+        "ms_per_step_fp64": dt64 / args.steps * 1e3, "speedup_vs_fp64": dt64 / dt,
+        "stage_ms": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+        "roofline": _herk_roofline(prof, flops, prec, args.steps),
+    }
+    ctx.close()
+    return out, wl
+
+
+def run_unfold(args, torch, rpa, synth):
+    """Symmetry unfolding (Eq. kmap, Eq. trans_wfs): a simple-cubic crystal (7 bohr, 48^3 grid, seven atoms
+    with s + p projectors) whose k and k+q sets (16 + 400 states) come from the irreducible zone by a
+    three-fold axis with time reversal; one step = E_c(q) from the unfolded sets (transformed plane-wave
+    labels, conjugated coefficients, rotated projections) against the same call on the irreducible sets as
+    they are (no operation), which differs only by the unfolding."""
+    dev = "cuda:0"
+    L = 7.0
+    U = np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]])
+    tr, g0 = 1, (0, 0, 0)
+    A = L * np.eye(3)
+    B = 2 * np.pi * np.linalg.inv(A).T
+    T = synth.cartesian_op(U, A)
+    qf = (0.09, -0.05, 0.07)
+    qv = np.asarray(qf) * 2 * np.pi / L
+    k1 = np.array([0.11, 0.047, 0.023]) * 2 * np.pi / L
+    k = -T @ k1
+    k2 = -(T.T @ (k + qv))
+    w = synth.symmetric_cubic([k1, k2], grid=(48, 48, 48), n_occ=16, n_unocc=400, target_ng=900, q=qf)
+    amap, shift = synth.atom_images(U, w.atoms)
+    D = synth.sp_rotation_blocks(U, A, len(w.atoms))
+    fr = rpa.Freq(w.omega, w.omega_weight)
+    s1, s2 = w.sets
+
+    def lib(s, kpt, sym):
+        op = rpa.SymOp(U, tr, g0, s.kpt, amap, shift, D) if sym else None
+        return rpa.States(s.C, s.miller, s.eps, s.f, s.P, w.paw.offsets, kpt=kpt if sym else s.kpt,
+                          weight=s.weight, device=dev, sym=op)
+    a, b = lib(s1, k, True), lib(s2, k + qv, True)
+    a0, b0 = lib(s1, None, False), lib(s2, None, False)
+    gm = rpa.gsphere(w.A, w.grid, w.qpoint.q, w.qpoint.ecut)
+    qs = rpa.QSpec(w.qpoint.q, gm, synth.paw_q_table(w.paw, w.A, w.qpoint.q, gm), weight=1.0, device=dev)
+    P = npairs(s1, s2)
+    NG, nw = qs.NG, fr.nw
+    flops = 4.0 * NG * NG * P * nw
+    ctx = rpa.Context(w.A, w.grid, device=0)
+    prec = args.precision
+    _timed(ctx, torch, lambda: ctx.ec([a], [b], qs, fr, prec), args.warmup)
+    dt, (ec, _), prof = _timed(ctx, torch, lambda: ctx.ec([a], [b], qs, fr, prec), args.steps, True)
+    _timed(ctx, torch, lambda: ctx.ec([a0], [b0], qs, fr, prec), 1)
+    dt0, _, _ = _timed(ctx, torch, lambda: ctx.ec([a0], [b0], qs, fr, prec), args.steps)
+    ms, ms0 = dt / args.steps * 1e3, dt0 / args.steps * 1e3
+    out = {
+        "metric": METRIC, "value": flops * args.steps / dt / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"{prec[6:]}x3 MFMA / f32 FFT / f64 log-det",
+        "data": "synthetic",
+        "config": {"workload": "symmetry unfolding: simple-cubic crystal 7 bohr, 48^3 grid, 7 atoms x 4 "
+                               "projectors, k and k+q sets of 16+400 states unfolded from the irreducible zone by "
+                               "a three-fold axis with time reversal, 16 imaginary frequencies; one step = E_c(q) "
+                               "from the unfolded sets", "precision": prec, "NG": NG, "pairs": P, "nw": nw},
+        "ec_unfolded": float(ec.cpu()[0]), "ms_per_step_without_unfolding": ms0,
+        "unfolding_ms_per_step": ms - ms0,
+        "stage_ms": {k2_: v[0] / args.steps for k2_, v in prof.items() if v[1]},
+        "roofline": _herk_roofline(prof, flops, prec, args.steps),
+    }
+    ctx.close()
+    return out, w
+
+
+def run_realfreq(args, torch, rpa, synth):
+    """Real frequencies (Sec. 5 outlook: chi0 for TDDFT, GW and BSE): chi0(q, w + i eta) of the O2 box at
+    q = 0.1 x 2pi/12 for 16 frequencies in [0, 1] Ha with eta = 0.01 Ha (two Hermitian updates, Re a and
+    Im a); one step = one rpa_chi0_real call, timed beside rpa_chi0 on the imaginary axis."""
+    dev = "cuda:0"
+    wl = synth.config1(which_q=(1,))
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    ks = [rpa.States.from_synth(s, wl.paw, dev) for s in wl.kpoints]
+    qp = wl.qpoints[0]
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    qs = rpa.QSpec(qp.q, gm, synth.paw_q_table(wl.paw, wl.A, qp.q, gm), weight=qp.weight, device=dev)
+    P = npairs(wl.kpoints[0], wl.kpoints[0])
+    NG = qs.NG
+    om = np.linspace(0.0, 1.0, 16)
+    eta = 0.01
+    flops = 2 * 4.0 * NG * NG * P * om.size
+    ctx = rpa.Context(wl.A, wl.grid, device=0)
+    prec = args.precision
+    _timed(ctx, torch, lambda: ctx.chi0_real(ks, ks, qs, om, eta, prec), args.warmup)
+    dt, _, prof = _timed(ctx, torch, lambda: ctx.chi0_real(ks, ks, qs, om, eta, prec), args.steps, True)
+    _timed(ctx, torch, lambda: ctx.chi0(ks, ks, qs, fr, prec), 1)
+    dti, _, _ = _timed(ctx, torch, lambda: ctx.chi0(ks, ks, qs, fr, prec), args.steps)
+    out = {
+        "metric": METRIC, "value": flops * args.steps / dt / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"{prec[6:]}x3 MFMA / f32 FFT",
+        "data": "synthetic",
+        "config": {"workload": "real frequencies: O2 box (12x12x13 bohr, 48^3 grid, 16+800 states, 2x13 PAW "
+                               "projectors), q = 0.1 x 2pi/12, 16 frequencies w in [0, 1] Ha, eta = 0.01 Ha; one "
+                               "step = chi0(q, w + i eta) of all frequencies", "precision": prec, "NG": NG,
+                   "pairs": P, "nw": int(om.size)},
+        "value_counts": "two Hermitian updates per frequency (Re a and Im a): 8 NG^2 P nw",
+        "ms_per_step_imaginary_axis_chi0": dti / args.steps * 1e3,
+        "stage_ms": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+        "roofline": _herk_roofline(prof, flops, prec, args.steps),
+    }
+    ctx.close()
+    return out, wl
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--oracle-sample":
         _oracle_sample(sys.argv[2])
@@ -590,7 +759,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8, help="timed steps (slab: one k-point each)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="slab", choices=["slab", "o2box", "qmesh", "grad"])
+    ap.add_argument("--workload", default="slab", choices=["slab", "o2box", "qmesh", "grad", "spin", "unfold",
+                                                           "realfreq"])
     ap.add_argument("--qmesh-bands", type=int, nargs=2, default=(8, 60), metavar=("OCC", "UNOCC"),
                     help="qmesh: occupied and empty states at Gamma (the full form is 60 1500)")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "split_fp16"])
@@ -623,6 +793,14 @@ def main():
     elif args.workload == "grad":
         out, wl = run_grad(args, torch, rpa, synth)
         band_stride, label = 16, "gradient at O2-in-box size, q = 0.1"
+    elif args.workload in ("spin", "unfold", "realfreq"):
+        run = {"spin": run_spin, "unfold": run_unfold, "realfreq": run_realfreq}[args.workload]
+        out, wl = run(args, torch, rpa, synth)
+        band_stride, label = 4, "spin-polarised O2 box, up channel, q = 0.1"
+        # the oracle baseline of these lines: the spin channel's chi0 build (the unfolded and real-frequency
+        # lines report their comparison calls instead)
+        if args.workload != "spin":
+            args.no_cpu_baseline = True
     else:
         out, wl = run_o2box(args, torch, rpa, synth)
         band_stride, label = 4, "O2-in-box q-point 0"
