@@ -29,9 +29,9 @@ of those same k-points (the whole q-point by default).
 call, timed against a loop of single-q calls), and --workload grad the
 differentiation form (E_c(q) and its gradient with respect to eigenvalues,
 coefficients and projections of all 16 + 800 states of the O2 box, FP64);
---workload spin, unfold and realfreq measure the two-channel (spin-polarised)
-O2 box, sets unfolded from the irreducible zone by a symmetry operation, and
-chi0 at real frequencies.
+--workload spin, unfold, realfreq and metalq0 measure the two-channel
+(spin-polarised) O2 box, sets unfolded from the irreducible zone by a symmetry
+operation, chi0 at real frequencies, and the metal slab's q -> 0 head.
 """
 from __future__ import annotations
 
@@ -748,6 +748,48 @@ def run_realfreq(args, torch, rpa, synth):
     return out, wl
 
 
+def run_metalq0(args, torch, rpa, synth):
+    """The metallic q -> 0 head (Sec. 2.2 with Fermi-smeared bands): one k-point of the metal slab (120 +
+    3000 states, T = 0.01 Ha) at the optical q-point (q -> 0 along x, the optical row of every pair and the
+    intraband head from -df/de) against the same k-point at q = 0.1 x 2pi/9; one step = that k-point's chi0
+    contribution."""
+    dev = "cuda:0"
+    wl = synth.config2(device=dev)
+    ks, qs1, fr = slab_inputs(rpa, wl, dev)
+    q0 = np.zeros(3)
+    gm0 = rpa.gsphere(wl.A, wl.grid, q0, wl.qpoints[0].ecut)
+    qs0 = rpa.QSpec(q0, gm0, synth.paw_q_table(wl.paw, wl.A, q0, gm0), optical=True, qhat=(1.0, 0.0, 0.0),
+                    Dpaw=synth.paw_d_table(wl.paw), weight=1.0, device=dev)
+    P = npairs(wl.kpoints[0], wl.kpoints[0])
+    NG, nw = qs0.NG, fr.nw
+    flops = 4.0 * NG * NG * P * nw
+    ctx = rpa.Context(wl.A, wl.grid, device=0)
+    prec = args.precision
+    step0 = lambda: ctx.chi0([ks[0]], [ks[0]], qs0, fr, prec)
+    step1 = lambda: ctx.chi0([ks[0]], [ks[0]], qs1, fr, prec)
+    _timed(ctx, torch, step0, args.warmup)
+    dt, chi, prof = _timed(ctx, torch, step0, args.steps, True)
+    del chi
+    _timed(ctx, torch, step1, 1)
+    dt1, chi1, _ = _timed(ctx, torch, step1, args.steps)
+    del chi1
+    out = {
+        "metric": METRIC, "value": flops * args.steps / dt / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"{prec[6:]}x3 MFMA / f32 FFT",
+        "data": "synthetic",
+        "config": {"workload": "metallic q -> 0: metal slab (9x9x36 bohr, 40x40x160 grid, 120+3000 Fermi-smeared "
+                               "states, T = 0.01 Ha, 20x18 PAW projectors), k-point 0 at the optical q-point "
+                               "(qhat = x, intraband head from -df/de), 16 imaginary frequencies; one step = that "
+                               "k-point's chi0", "precision": prec, "NG": NG, "pairs": P, "nw": nw},
+        "ms_per_step_at_q_0.1": dt1 / args.steps * 1e3,
+        "stage_ms": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+        "roofline": _herk_roofline(prof, flops, prec, args.steps),
+    }
+    ctx.close()
+    return out, wl
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--oracle-sample":
         _oracle_sample(sys.argv[2])
@@ -760,7 +802,7 @@ def main():
     ap.add_argument("--steps", type=int, default=8, help="timed steps (slab: one k-point each)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="slab", choices=["slab", "o2box", "qmesh", "grad", "spin", "unfold",
-                                                           "realfreq"])
+                                                           "realfreq", "metalq0"])
     ap.add_argument("--qmesh-bands", type=int, nargs=2, default=(8, 60), metavar=("OCC", "UNOCC"),
                     help="qmesh: occupied and empty states at Gamma (the full form is 60 1500)")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "split_fp16"])
@@ -793,8 +835,9 @@ def main():
     elif args.workload == "grad":
         out, wl = run_grad(args, torch, rpa, synth)
         band_stride, label = 16, "gradient at O2-in-box size, q = 0.1"
-    elif args.workload in ("spin", "unfold", "realfreq"):
-        run = {"spin": run_spin, "unfold": run_unfold, "realfreq": run_realfreq}[args.workload]
+    elif args.workload in ("spin", "unfold", "realfreq", "metalq0"):
+        run = {"spin": run_spin, "unfold": run_unfold, "realfreq": run_realfreq,
+               "metalq0": run_metalq0}[args.workload]
         out, wl = run(args, torch, rpa, synth)
         band_stride, label = 4, "spin-polarised O2 box, up channel, q = 0.1"
         # the oracle baseline of these lines: the spin channel's chi0 build (the unfolded and real-frequency
