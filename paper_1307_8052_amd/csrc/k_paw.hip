@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_paw_mm(const T* __restrict__ Zr, const 
 }
 
 // The n-factorised form, for chunks whose pairs span fewer bands n than bands m:
-//   Y_n[aj][G] = sum_i conj(P_ni) Q^a_ij(G)             (k_paw_y, once per band n of a chunk)
+//   Y_n[aj][G] = sum_i conj(P_ni) Q^a_ij(G)             (k_paw_yn, once per band n of a chunk)
 //   rho_p[G]  += sum_{aj} P'_{m_p}[aj] Y_{n_p}[aj][G]   (this kernel, K = sum_a Np_a)
 // One workgroup per (64 G-vectors, segment of at most 64 pairs with one band n): seg holds per segment
 // (n - n_lo, first, count) into perm, the chunk's pair indices grouped by n; the B operand Y_n is shared

@@ -1,4 +1,6 @@
-"""The metal-slab and uneven-batch workload shapes at reduced band counts, through the C ABI.
+"""The metal-slab and uneven-batch workload shapes, through the C ABI: at reduced band counts against the
+oracle, and the metal slab at full size (split against FP64 over one k-point, sampled pair densities
+against the oracle).
 
 Same cells, grids, occupations and PAW sizes as the full workloads (9 x 9 x 36 bohr, 40 x 40 x 160 grid,
 20 atoms x 18 projectors), with fewer states so that the FP64 oracle finishes in seconds:
@@ -8,9 +10,12 @@ Same cells, grids, occupations and PAW sizes as the full workloads (9 x 9 x 36 b
 The 40 x 40 x 160 grid runs x and y through the register kernels and z by quads of lanes (path 0), or all
 three axes through the LDS passes (path 1).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from helpers import gpu_inputs, oracle_q
 
@@ -193,3 +198,49 @@ def test_metal_slab_full_size_one_kpoint(rpa):
     print(f"slab k0: E_fp64={e64:.12f} E_split={es:.12f} diff={es - e64:.3e} chi rel={diff:.3e}", flush=True)
     assert abs(es - e64) < 1e-6
     assert diff < 2e-4
+
+
+# bands of the full metal-slab set (120 + 3000 states) sampled for the pair densities: deep, mid and top
+# occupied states, the partly occupied ones at the Fermi level (f from 1.98 to 0.1) and far empty ones
+SLAB_BANDS = [0, 60, 117, 119, 120, 121, 125, 140, 600, 3119]
+
+
+@pytest.fixture(scope="module")
+def slab_full_k0(rpa):
+    """One k-point of the metal slab at full size: 120 + 3000 Fermi-smeared states on the 40 x 40 x 160
+    grid, NG = 4011, 20 x 18 projectors; the library's state set and sphere, and the oracle's pair
+    densities for every pair of SLAB_BANDS with f_n - f_m above the pair threshold (Eq. n_G_2, Sec. 2.2),
+    computed from those bands alone."""
+    dev = "cuda:0"
+    wl = synth.config2(nk=1, device=dev)
+    s, qp = wl.kpoints[0], wl.qpoints[0]
+    gm = rpa.gsphere(wl.A, wl.grid, qp.q, qp.ecut)
+    ref_g = oracle.gsphere(wl.A, qp.q, qp.ecut)
+    assert np.array_equal(gm, ref_g) and len(gm) == 4011
+    Q = synth.paw_q_table(wl.paw, wl.A, qp.q, ref_g)
+    keep = np.asarray(SLAB_BANDS)
+    sub = dataclasses.replace(s, C=np.ascontiguousarray(s.C[keep]), eps=s.eps[keep].copy(), f=s.f[keep].copy(),
+                              P=np.ascontiguousarray(s.P[keep]), dfde=None)
+    pairs, rho = oracle.pair_densities(wl.A, wl.grid, sub, sub, ref_g, Q, wl.paw.offsets)
+    qs = rpa.QSpec(qp.q, gm, Q, weight=qp.weight, device=dev)
+    st = rpa.States.from_synth(s, wl.paw, dev)
+    return dict(A=wl.A, grid=wl.grid, qs=qs, st=st, pn=keep[pairs[0]], pm=keep[pairs[1]], rho=rho, f=s.f)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_metal_slab_full_size_pair_density_sample(rpa, slab_full_k0, prec, path):
+    """Pair densities of the full-size metal slab (all 3120 states resident, NG = 4011, 20 x 18 projectors)
+    for sampled pairs, element by element against the oracle: z by quads of lanes (path 0) and the LDS
+    passes (path 1); FP64 transforms to 1e-12 and the FP32 transforms of the split path to 2e-6 of
+    max |rho|, the bounds of every other grid."""
+    d = slab_full_k0
+    pn, pm = d["pn"], d["pm"]
+    assert len(pn) >= 30 and np.any((d["f"][pn] < 2.0 - 1e-3) & (d["f"][pm] > 1e-3))
+    with rpa.Context(d["A"], d["grid"]) as ctx:
+        ctx.set_pair_path(path)
+        rho = ctx.pair_density(d["st"], d["st"], d["qs"], pn, pm, prec).cpu().numpy()
+        ctx.check()
+    r = _rel(rho, d["rho"])
+    print(f"slab full {prec} path {path}: pairs={len(pn)} NG={rho.shape[1]} rel={r:.3e}", flush=True)
+    assert r < (1e-12 if prec == "fp64" else 2e-6)
