@@ -224,7 +224,8 @@ def slab_full_k0(rpa):
     pairs, rho = oracle.pair_densities(wl.A, wl.grid, sub, sub, ref_g, Q, wl.paw.offsets)
     qs = rpa.QSpec(qp.q, gm, Q, weight=qp.weight, device=dev)
     st = rpa.States.from_synth(s, wl.paw, dev)
-    return dict(A=wl.A, grid=wl.grid, qs=qs, st=st, pn=keep[pairs[0]], pm=keep[pairs[1]], rho=rho, f=s.f)
+    return dict(wl=wl, A=wl.A, grid=wl.grid, gm=ref_g, Q=Q, qs=qs, st=st, sub=sub, pn=keep[pairs[0]],
+                pm=keep[pairs[1]], rho=rho, f=s.f)
 
 
 @pytest.mark.parametrize("path", [0, 1])
@@ -244,3 +245,29 @@ def test_metal_slab_full_size_pair_density_sample(rpa, slab_full_k0, prec, path)
     r = _rel(rho, d["rho"])
     print(f"slab full {prec} path {path}: pairs={len(pn)} NG={rho.shape[1]} rel={r:.3e}", flush=True)
     assert r < (1e-12 if prec == "fp64" else 2e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+def test_metal_slab_full_size_chi0_sampled_block(rpa, slab_full_k0, prec):
+    """chi0 at the slab's full sphere (NG = 4011: 63 tiles of 64 with a ragged last one, 16 frequencies)
+    from the pairs of SLAB_BANDS, on a block of sampled G-vectors (the first and last 64 and 200 spread
+    between): the oracle computes chi0 on that G list alone (chi0(G, G') needs only rho(G) and rho(G')),
+    the library the whole matrix; FP64 to 1e-12, split to 2e-4 of the block's largest element."""
+    d = slab_full_k0
+    wl, gm, NG = d["wl"], d["gm"], len(d["gm"])
+    sel = np.unique(np.concatenate([np.arange(64), np.linspace(0, NG - 1, 200).astype(np.int64),
+                                    np.arange(NG - 64, NG)]))
+    ref = oracle.chi0_q(wl.A, wl.grid, [d["sub"]], [d["sub"]], gm[sel], d["Q"][:, sel], wl.paw.offsets,
+                        wl.omega)
+    st = rpa.States.from_synth(d["sub"], wl.paw, "cuda:0")
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    idx = torch.as_tensor(sel, device="cuda:0")
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        chi = ctx.chi0([st], [st], d["qs"], fr, prec)
+        ctx.check()
+        blk = chi.index_select(1, idx).index_select(2, idx).cpu().numpy()
+        del chi
+    r = _rel(blk, ref)
+    print(f"slab full chi0 {prec}: pairs={len(d['pn'])} NG={NG} block={len(sel)} rel={r:.3e}", flush=True)
+    assert np.max(np.abs(ref)) > 0
+    assert r < (1e-12 if prec == "fp64" else 2e-4)
