@@ -503,6 +503,9 @@ def run_qmesh(args, torch, rpa, synth):
         "stage_groups_one_pass": {k: v[1] for k, v in prof.items() if v[1]},
         "ec_batched_minus_loop_max_ha": diff, "ec_weighted_sum": float(ec_b[len(NGs)]),
         "device_bytes_after_batched_call": used_b, "chi0_bytes_if_padded_to_largest_sphere": padded_chi,
+        "roofline": dict(_herk_roofline(prof, flops, prec, 1),
+                         measured_on="the profiled batched pass after the timed ones (HIP events on the launch "
+                                     "stream around each rank-k launch)"),
     }
     ctx.close()
     return out, wl
