@@ -271,3 +271,56 @@ def test_metal_slab_full_size_chi0_sampled_block(rpa, slab_full_k0, prec):
     print(f"slab full chi0 {prec}: pairs={len(d['pn'])} NG={NG} block={len(sel)} rel={r:.3e}", flush=True)
     assert np.max(np.abs(ref)) > 0
     assert r < (1e-12 if prec == "fp64" else 2e-4)
+
+
+def test_metal_slab_full_size_optical_head_sampled_block(rpa, slab_full_k0):
+    """The metallic q -> 0 head at full slab size (Sec. 2.2 with Fermi-smeared bands): the bands of
+    SLAB_BANDS with their -df/de, at the optical q-point along x (the q = 0 sphere, the nabla tables of the
+    20 x 18 projectors): chi0 on a block of sampled G-vectors that holds G = 0 against the oracle's chi0 on
+    that G list; the head (with the intraband term), the wings and the body each to 1e-12 (FP64) and 2e-4
+    (split) of their own largest element."""
+    d = slab_full_k0
+    wl = d["wl"]
+    s = wl.kpoints[0]
+    keep = np.asarray(SLAB_BANDS)
+    assert s.dfde is not None
+    sub = dataclasses.replace(d["sub"], dfde=s.dfde[keep].copy())
+    assert np.max(sub.dfde) > 1.0
+    q0, qhat = np.zeros(3), np.array([1.0, 0.0, 0.0])
+    ecut = wl.qpoints[0].ecut
+    gm = rpa.gsphere(wl.A, wl.grid, q0, ecut)
+    ref_g = oracle.gsphere(wl.A, q0, ecut)
+    assert np.array_equal(gm, ref_g)
+    NG = len(gm)
+    zero = int(np.nonzero(np.all(ref_g == 0, axis=1))[0][0])
+    sel = np.unique(np.concatenate([[zero], np.arange(64), np.linspace(0, NG - 1, 200).astype(np.int64),
+                                    np.arange(NG - 64, NG)]))
+    Q = synth.paw_q_table(wl.paw, wl.A, q0, ref_g)
+    D = synth.paw_d_table(wl.paw)
+    ref = oracle.chi0_q(wl.A, wl.grid, [sub], [sub], ref_g[sel], Q[:, sel], wl.paw.offsets, wl.omega,
+                        optical=True, qhat=qhat, Dtab=D)
+    qs = rpa.QSpec(q0, gm, Q, optical=True, qhat=qhat, Dpaw=D, device="cuda:0")
+    st = rpa.States.from_synth(sub, wl.paw, "cuda:0")
+    fr = rpa.Freq(wl.omega, wl.omega_weight)
+    idx = torch.as_tensor(sel, device="cuda:0")
+    z = int(np.nonzero(sel == zero)[0][0])
+    out = {}
+    with rpa.Context(wl.A, wl.grid) as ctx:
+        for prec in ("fp64", "split_bf16"):
+            chi = ctx.chi0([st], [st], qs, fr, prec)
+            ctx.check()
+            out[prec] = chi.index_select(1, idx).index_select(2, idx).cpu().numpy()
+            del chi
+    # the intraband head outweighs the rest of the block by four orders: head, wings (G = 0 row and column)
+    # and body are each compared with their own largest element
+    body = np.ones(len(sel), dtype=bool)
+    body[z] = False
+    parts = {"head": lambda c: c[:, z, z], "wings": lambda c: np.concatenate([c[:, z, body], c[:, body, z]], axis=1),
+             "body": lambda c: c[:, body][:, :, body]}
+    for name, part in parts.items():
+        r64, rs = _rel(part(out["fp64"]), part(ref)), _rel(part(out["split_bf16"]), part(ref))
+        print(f"slab full optical {name}: NG={NG} block={len(sel)} max={np.max(np.abs(part(ref))):.3e} "
+              f"fp64 rel={r64:.3e} split rel={rs:.3e}", flush=True)
+        assert np.max(np.abs(part(ref))) > 0
+        assert r64 < 1e-12
+        assert rs < 2e-4
