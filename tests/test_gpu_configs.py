@@ -176,7 +176,8 @@ def test_spin_polarised_o2box_reduced(rpa, iq):
 def test_metal_slab_full_size_one_kpoint(rpa):
     """The metal slab at full size (120 + 3000 Fermi-smeared states, NG = 4011, 20 x 18 projectors, 16
     frequencies), k-point 0 alone: split-precision E_c of that k-point's chi0 within 1e-6 Ha of the FP64
-    path (the FP64 path itself is pinned to the oracle at full O2-box size and at every reduced size), chi0
+    path (the FP64 path itself is pinned to the oracle at full O2-box size, at every reduced size and, on
+    sampled pairs and G-vectors, at this size: the tests below), chi0
     of the two paths within the split tolerance, about 20 chunks of the split kernel's accumulate branch."""
     dev = "cuda:0"
     wl = synth.config2(device=dev)
